@@ -1,0 +1,270 @@
+"""Pins for the oracle's BACA / H-BACA against what the paper and the
+mathematics fix: special cases the paper names (d = 1 is ACA, d = n is a
+QRCP interpolative decomposition, n_b = 1 is plain BACA), exact recovery of
+low-rank products, exact merge algebra, the interpolation property of the
+LRID update, invariances, a LAPACK-free Jacobi SVD brute force, and the
+paper's complexity estimates."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.baca import baca_leaf
+from oracle.entries import EntrySource
+from oracle.splitmix import first_column_block
+from workloads import generators as G
+
+
+def _points(m, n, dim, gap, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.random((m, dim))
+    Y = rng.random((n, dim))
+    Y[:, 0] += gap
+    return (X[G.kd_order(X, 4)], Y[G.kd_order(Y, 4)])
+
+
+def _src(kind, m, n, seed=0, **kw):
+    if kind == "lowrank":
+        rng = np.random.default_rng(seed)
+        r = kw.get("rank", 5)
+        wl = dict(entry=4, G1=rng.standard_normal((m, r)),
+                  G2=rng.standard_normal((r, n)),
+                  spike_lin=np.zeros(0, np.int64), spike_val=np.zeros(0))
+        return EntrySource(wl)
+    X, Y = _points(m, n, 3, kw.get("gap", 2.0), seed)
+    if kind == "gauss":
+        return EntrySource(dict(entry=1, X=X, Y=Y, h=kw.get("h", 0.5), gauss_c=1.0))
+    if kind == "laplace":
+        return EntrySource(dict(entry=2, X=X, Y=Y))
+    if kind == "helmholtz":
+        X[:, 2] = 0.0
+        Y[:, 2] = 1.0
+        Y[:, 0] -= kw.get("gap", 2.0)
+        return EntrySource(dict(entry=3, X=X, Y=Y, wavenumber=kw.get("k", 20.0)))
+    raise KeyError(kind)
+
+
+def _leaf_block(src):
+    return lambda I, J: src.block(I, J)
+
+
+# ---------------------------------------------------------------- P4 -------
+@pytest.mark.parametrize("kind", ["gauss", "laplace", "helmholtz"])
+def test_d1_is_aca(kind):
+    """BACA with d = 1 reduces exactly to ACA (Section "Blocked Adaptive
+    Cross Approximation")."""
+    m, n = 60, 50
+    src = _src(kind, m, n, seed=11)
+    eps = 1e-6
+    J1 = first_column_block(77, 0, n, 1)
+    res = baca_leaf(_leaf_block(src), m, n, 1, eps, J1)
+    U, V, piv = oracle.aca(_leaf_block(src), m, n, eps, int(J1[0]))
+    assert len(res.iters) == len(piv)
+    for it, (i, j) in zip(res.iters, piv):
+        assert it["dk"] == 1
+        assert it["I"].tolist() == [i] and it["J"].tolist() == [j]
+    A1 = res.U @ res.V
+    A2 = U @ V
+    assert np.linalg.norm(A1 - A2) <= 1e-13 * np.linalg.norm(A2)
+
+
+# ---------------------------------------------------------------- P5 -------
+@pytest.mark.parametrize("kind", ["gauss", "helmholtz"])
+def test_full_block_is_qrcp_id(kind):
+    """With d >= max(m0, n0) BACA makes one iteration and returns the
+    QRCP-based interpolative decomposition A(:,S) A(:,S)^+ A."""
+    m, n = 24, 30
+    src = _src(kind, m, n, seed=5)
+    A = src.dense()
+    eps = 1e-6
+    d = 40
+    J1 = first_column_block(9, 0, n, d)
+    res = baca_leaf(_leaf_block(src), m, n, d, eps, J1)
+    assert len(res.iters) == 1
+    S = res.iters[0]["J"]
+    # independent: greedy columns by least-squares residual norms on the
+    # row-restricted cross block, then the projector by lstsq
+    I = np.sort(res.iters[0]["I"])
+    assert S.size == res.rank
+    B = A[:, S]
+    proj = B @ np.linalg.lstsq(B, A, rcond=None)[0]
+    assert np.linalg.norm(res.U @ res.V - proj) <= 1e-9 * np.linalg.norm(A)
+    assert I.size <= min(m, n)
+
+
+# ---------------------------------------------------------------- P7 -------
+@pytest.mark.parametrize("kind", ["gauss", "laplace", "helmholtz", "lowrank"])
+def test_interpolation_on_selected_columns(kind):
+    """LRID interpolates: the residual vanishes on every selected column
+    J_k(Jbar) (eq. (9) with W(:,Jbar) = Q1 T11)."""
+    m, n = 80, 70
+    src = _src(kind, m, n, seed=3, rank=12)
+    A = src.dense()
+    res = baca_leaf(_leaf_block(src), m, n, 6, 1e-8, first_column_block(1, 0, n, 6))
+    cols = np.concatenate([it["J"] for it in res.iters])
+    assert len(set(cols.tolist())) == cols.size
+    E = A[:, cols] - res.U @ res.V[:, cols]
+    assert np.max(np.abs(E)) <= 1e3 * np.finfo(float).eps * np.max(np.abs(A))
+
+
+# ---------------------------------------------------------------- P2, P3 ---
+@pytest.mark.parametrize("r0", [1, 7, 30])
+@pytest.mark.parametrize("leaf", [200, 60])
+def test_exact_recovery_of_low_rank_products(r0, leaf):
+    m = n = 200
+    src = _src("lowrank", m, n, seed=r0, rank=r0)
+    res = oracle.hbaca(src, m, n, 1e-10, 8, leaf, seed=123)
+    A = src.dense()
+    assert res.rank == r0
+    assert np.linalg.norm(A - res.dense()) <= 1e-12 * np.linalg.norm(A)
+
+
+def test_zero_matrix_gives_rank_zero():
+    m, n = 50, 40
+    wl = dict(entry=4, G1=np.zeros((m, 1)), G2=np.zeros((1, n)),
+              spike_lin=np.zeros(0, np.int64), spike_val=np.zeros(0))
+    res = oracle.hbaca(EntrySource(wl), m, n, 1e-6, 4, 16, seed=1)
+    assert res.rank == 0
+    assert res.U.shape == (m, 0) and res.V.shape == (0, n)
+
+
+def test_rank_one_is_exact():
+    m, n = 64, 48
+    src = _src("lowrank", m, n, seed=2, rank=1)
+    res = oracle.hbaca(src, m, n, 1e-8, 4, 16, seed=1)
+    A = src.dense()
+    assert res.rank == 1
+    assert np.linalg.norm(A - res.dense()) <= 1e-13 * np.linalg.norm(A)
+
+
+# ---------------------------------------------------------------- P8 -------
+def test_power_of_two_scaling_is_exact():
+    m, n = 90, 80
+    src = _src("gauss", m, n, seed=4)
+    A = src.dense()
+    wl = dict(entry=4, G1=A, G2=np.eye(n), spike_lin=np.zeros(0, np.int64),
+              spike_val=np.zeros(0))
+    wl2 = dict(wl, G1=A * 2.0 ** 37)
+    r1 = oracle.hbaca(EntrySource(wl), m, n, 1e-6, 4, 30, seed=8)
+    r2 = oracle.hbaca(EntrySource(wl2), m, n, 1e-6, 4, 30, seed=8)
+    assert r1.rank == r2.rank
+    for b in r1.leaf_info:
+        a, c = r1.leaf_info[b], r2.leaf_info[b]
+        assert [it["I"].tolist() for it in a["iters"]] == [it["I"].tolist() for it in c["iters"]]
+        assert [it["J"].tolist() for it in a["iters"]] == [it["J"].tolist() for it in c["iters"]]
+    assert np.array_equal(r1.S * 2.0 ** 37, r2.S)
+
+
+# ---------------------------------------------------------------- P9 -------
+@pytest.mark.parametrize("kind", ["gauss", "helmholtz"])
+def test_merge_algebra_is_exact(kind):
+    """Merging exact leaf SVDs (from the Jacobi brute force) with a tiny eps
+    reproduces the singular values of the whole matrix (eqs. (14)-(15) are
+    exact algebra)."""
+    m, n = 64, 56
+    src = _src(kind, m, n, seed=6, h=1.5)
+    A = src.dense()
+    L = 2
+    rows = oracle.cluster_tree(m, L)[L]
+    cols = oracle.cluster_tree(n, L)[L]
+    leaves = {}
+    for t, (ra, rs) in enumerate(rows):
+        for v, (ca, cs) in enumerate(cols):
+            U, s, V = oracle.jacobi_svd(A[ra:ra + rs, ca:ca + cs])
+            leaves[(t, v)] = (U, s, V.conj().T)
+    U, S, V = oracle.merge_tree(leaves, L, 1e-15)
+    s_ref = oracle.jacobi_svd(A)[1]
+    k = S.size
+    assert np.allclose(S, s_ref[:k], rtol=0, atol=1e-12 * s_ref[0])
+    assert np.linalg.norm((U * S) @ V - A) <= 1e-12 * np.linalg.norm(A)
+    assert np.allclose(U.conj().T @ U, np.eye(k), atol=1e-12)
+    assert np.allclose(V @ V.conj().T, np.eye(k), atol=1e-12)
+
+
+# ---------------------------------------------------------------- P10 ------
+def test_single_leaf_is_baca_plus_recompression():
+    m, n = 70, 60
+    src = _src("gauss", m, n, seed=9)
+    res = oracle.hbaca(src, m, n, 1e-6, 8, 100, seed=5)
+    assert res.L == 0
+    leaf = baca_leaf(_leaf_block(src), m, n, 8, 1e-6, first_column_block(5, 0, n, 8))
+    U, S, V = oracle.recompress(leaf.U, leaf.V, 1e-6)
+    assert np.array_equal(S, res.S)
+    assert np.array_equal(U, res.U) and np.array_equal(V, res.V)
+
+
+# ---------------------------------------------------------------- P1 -------
+CASES = [(kind, L, seed) for kind in ("gauss", "laplace", "helmholtz", "lowrank")
+         for L in (0, 1, 2) for seed in (0, 1)]
+
+
+@pytest.mark.parametrize("kind,L,seed", CASES)
+def test_bruteforce_accuracy_and_rank(kind, L, seed):
+    """Against the Jacobi SVD of the whole (tiny) matrix.
+
+    The eps-rank truncation of an exact SVD already leaves a Frobenius error
+    e_opt(r) = sqrt(sum_{j>r} sigma_j^2) that can exceed eps ||A||_F, so the
+    accuracy gate is relative to it: ||A - A~||_F <= 3 e_opt(r_A) + eps ||A||_F.
+    The spectral error obeys ||A - A~||_2 <= (2L + 2) eps sigma_1 (one
+    truncation per leaf stage and per merge step; the paper reports that
+    merges add only slight error).  The rank satisfies Weyl's bracket
+    sigma_{r+1}(A) <= ||A - A~||_2."""
+    m, n = 96, 80
+    leaf = {0: 96, 1: 48, 2: 24}[L]
+    eps = {"lowrank": 1e-8}.get(kind, 1e-4)
+    src = _src(kind, m, n, seed=seed, rank=15, h=0.4)
+    A = src.dense()
+    res = oracle.hbaca(src, m, n, eps, 4, leaf, seed=31 + seed)
+    assert res.L == L
+    s = oracle.jacobi_svd(A)[1]
+    rA = oracle.eps_rank(s, eps)
+    e_opt = np.sqrt(np.sum(s[rA:] ** 2))
+    E = A - res.dense()
+    eF = np.linalg.norm(E)
+    e2 = oracle.jacobi_svd(E)[1][0]
+    assert eF <= 3 * e_opt + eps * np.linalg.norm(A), (eF, e_opt)
+    assert e2 <= (2 * L + 2) * eps * s[0], (e2, eps * s[0])
+    r = res.rank
+    if r < s.size:
+        assert s[r] <= e2 * (1 + 1e-10) + 1e-14 * s[0]
+    assert abs(r - rA) <= 2 + rA // 10
+
+
+# ---------------------------------------------------------------- P11 ------
+def _slope(x, y):
+    return np.polyfit(np.log(x), np.log(y), 1)[0]
+
+
+def test_baca_cost_scales_as_n_r_squared():
+    """eq. (16): c_BACA = O(n r^2) for d <= r."""
+    d = 4
+    r0 = 16
+    ns = [200, 400, 800]
+    costs = []
+    for n in ns:
+        src = _src("lowrank", n, n, seed=1, rank=r0)
+        res = baca_leaf(_leaf_block(src), n, n, d, 1e-10, first_column_block(1, 0, n, d))
+        costs.append(res.ops["resid_flops"] + res.ops["norm_flops"])
+    assert abs(_slope(ns, costs) - 1.0) <= 0.15
+    # the r^2 law is asymptotic in r/d (the sum over ceil(r/d) iterations
+    # gives (r + d)^2): take d = 2 so r/d spans 8..32
+    rs = [16, 32, 64]
+    costs = []
+    for r in rs:
+        src = _src("lowrank", 600, 600, seed=2, rank=r)
+        res = baca_leaf(_leaf_block(src), 600, 600, 2, 1e-10,
+                        first_column_block(1, 0, 600, 2))
+        costs.append(res.ops["resid_flops"] + res.ops["norm_flops"])
+    assert abs(_slope(rs, costs) - 2.0) <= 0.3
+
+
+def test_merge_cost_constant_rank_grows_like_sqrt_nb():
+    """eq. (18) with s_l = r: c_m = n r^2 sum_l 2^(L-l) = n r^2 (sqrt(n_b) - 1)."""
+    n = 512
+    src = _src("lowrank", n, n, seed=3, rank=10)
+    ratios = []
+    for L in (1, 2, 3, 4):
+        res = oracle.hbaca(src, n, n, 1e-10, 8, n >> L, seed=2)
+        assert res.L == L
+        ratios.append(res.ops["merge_flops"] / ((1 << L) - 1))
+    ratios = np.array(ratios)
+    assert ratios.max() / ratios.min() <= 1.3
