@@ -1,0 +1,196 @@
+/*
+ * hbaca.h -- C ABI of the MI355X (gfx950) H-BACA library.
+ *
+ * H-BACA computes a truncated SVD  A ~ U diag(sigma) V^H  of an m x n matrix
+ * whose entries are evaluated on demand in O(1) each (the paper's problem
+ * statement, Abstract and Algorithm 3).  The matrix is split by two L-level
+ * binary cluster trees into 4^L leaf blocks; every leaf is compressed by
+ * blocked adaptive cross approximation (BACA, Algorithm 2) followed by an SVD
+ * re-compression (Section "Blocked Adaptive Cross Approximation"), and the
+ * leaf factors are merged level by level by truncated SVDs (Algorithm 3,
+ * eqs. (14)-(15)).
+ *
+ * Conventions used by every call:
+ *  - All array arguments are DEVICE pointers (HIP), except where a comment
+ *    says "host".  Matrices are column-major; point sets are row-major
+ *    (point i occupies dim consecutive doubles).
+ *  - Rows and columns are assumed already ordered so that contiguous index
+ *    ranges are geometric clusters (the paper applies the method to a
+ *    KD-permuted matrix); the library never reorders.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  The
+ *    compress calls synchronise that stream before returning, because the
+ *    output ranks size the results.
+ *  - The caller owns every input.  Results are owned by the library until
+ *    hb_result_free().  On error *out is set to NULL and nothing leaks.
+ *  - No exception or HIP error crosses the ABI: HIP failures map to
+ *    HB_EDEVICE; hb_status_string() gives a text for every status.
+ *  - Calls on distinct results and streams may run concurrently.
+ */
+#ifndef HBACA_H
+#define HBACA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HB_OK = 0,
+  HB_EINVAL = -1,       /* invalid argument (null pointer, size, tolerance...) */
+  HB_ENOMEM = -2,       /* device allocation failed */
+  HB_EDEVICE = -3,      /* a HIP call or kernel launch failed */
+  HB_ERANKCAP = -4,     /* a leaf needed more than params->rank_cap columns */
+  HB_ENONFINITE = -5,   /* NaN or Inf in a scalar parameter */
+  HB_EUNSUPPORTED = -6  /* size outside what the kernels are built for */
+} hb_status;
+
+/* Entry functions A(i, j) for row point x_i and column point y_j. */
+typedef enum {
+  HB_K_GAUSS = 1,          /* exp(-|x - y|^2 / (gauss_c h^2)), real; the
+                              paper's Gaussian kernel has gauss_c = 2 */
+  HB_K_LAPLACE = 2,        /* 1 / |x - y|, real */
+  HB_K_HELMHOLTZ3D = 3,    /* exp(i k |x - y|) / (4 pi |x - y|), complex */
+  HB_K_LOWRANK_SPIKES = 4  /* (G1 G2)(i, j) + spike(i, j), real: the paper's
+                              product-of-random kernel plus sparse entries */
+} hb_entry_fn;
+
+typedef enum {
+  HB_PREC_FP64 = 0   /* every step in FP64 (complex: FP64 pairs) */
+} hb_precision;
+
+typedef struct {
+  int32_t dim;        /* point dimension (1..8); ignored by LOWRANK_SPIKES */
+  double h;           /* Gaussian width h > 0 */
+  double gauss_c;     /* Gaussian normalisation c > 0 */
+  double wavenumber;  /* Helmholtz k > 0 */
+  /* LOWRANK_SPIKES only (device arrays): G1 is m x lr_rank row-major, G2 is
+     lr_rank x n row-major; spike_lin holds n_spikes sorted linear indices
+     i * n + j with values spike_val. */
+  int32_t lr_rank;
+  const double* lr_G1;
+  const double* lr_G2;
+  int32_t n_spikes;
+  const int64_t* spike_lin;
+  const double* spike_val;
+  /* Seed of the random first column block J_1 of every leaf (Algorithm 2,
+     first line).  Leaf b = t * 2^L + v (row cluster t, column cluster v)
+     draws min(d, n0) distinct leaf-local columns by a partial Fisher-Yates
+     shuffle driven by SplitMix64 started at seed + b * 0x632BE59BD9B4E019.
+     In the batched call block p uses seed + p. */
+  uint64_t seed;
+  int32_t precision;   /* hb_precision */
+  int32_t rank_cap;    /* max BACA rank per leaf; 0 = min(m0, n0) */
+  int32_t record_tape; /* keep per-leaf pivots, d_k, nu, mu for hb_result_leaf_tape */
+  int32_t stop_after;  /* diagnostics: 0 full H-BACA; 1 stop after the leaf
+                          BACA (blocks = leaves, A_leaf ~ U Vh^H, sigma = 1);
+                          2 stop after the leaf SVD re-compression */
+} hb_params;
+
+typedef struct hb_result hb_result; /* opaque */
+
+typedef struct {
+  int32_t n_blocks;          /* output blocks (problems, or leaves if stop_after > 0) */
+  int32_t n_leaves;
+  int32_t levels_max;        /* max L over the problems */
+  int32_t leaf_rank_baca_max;
+  int32_t leaf_rank_max;     /* after re-compression */
+  int32_t iters_max;
+  int64_t iters_total;
+  int32_t step_rank_max[64]; /* max rank after merge step s (s = 0: leaves;
+                                odd: horizontal, even > 0: vertical) */
+  int32_t n_steps;
+  double ms_setup, ms_baca, ms_recompress, ms_merge, ms_total;  /* device time */
+  double entries_evaluated;  /* matrix entries computed by the leaf BACA */
+  double resid_bytes;        /* algorithmic HBM bytes of the BACA residual
+                                passes: U and V streamed once per iteration */
+  double resid_flops;        /* 2 phi d r (m0 + n0) summed over iterations */
+} hb_stats;
+
+/*
+ * H-BACA of one m x n matrix (Algorithm 3).
+ *   entry_fn_id  hb_entry_fn
+ *   params       kernel parameters and options (host struct, required)
+ *   points_row   m x dim row points (device); NULL for LOWRANK_SPIKES
+ *   points_col   n x dim column points (device); NULL for LOWRANK_SPIKES
+ *   tol          relative tolerance eps of every truncation, 0 < tol < 1
+ *   d            BACA block size (1..32)
+ *   leaf         target leaf size; L = smallest level count with
+ *                leaf * 2^L >= max(m, n), lowered until 2^L <= min(m, n)
+ * Leaves larger than 2048 in either dimension return HB_EUNSUPPORTED.
+ */
+hb_status hbaca_compress(int entry_fn_id, const hb_params* params, const double* points_row,
+                         const double* points_col, int64_t m, int64_t n, double tol, int32_t d,
+                         int32_t leaf, void* stream, hb_result** out);
+
+/*
+ * Independent H-BACA of nblocks matrices in one pass: all their leaves run in
+ * one leaf-kernel launch and every merge step of all blocks is one batch.
+ * Block p has rows points_row[row_off[p] .. row_off[p] + row_cnt[p]) and
+ * columns points_col[col_off[p] ...]; the offset/count arrays are HOST
+ * arrays of nblocks entries.  LOWRANK_SPIKES is not accepted here.
+ */
+hb_status hbaca_compress_batched(int entry_fn_id, const hb_params* params, int64_t nblocks,
+                                 const double* points_row, const int64_t* row_off,
+                                 const int64_t* row_cnt, const double* points_col,
+                                 const int64_t* col_off, const int64_t* col_cnt, double tol,
+                                 int32_t d, int32_t leaf, void* stream, hb_result** out);
+
+/* Number of output blocks, and rank / rows / columns of one of them
+   (-1 on a bad handle or index). */
+int64_t hb_result_nblocks(const hb_result* res);
+int64_t hb_result_rank(const hb_result* res, int64_t block);
+int64_t hb_result_rows(const hb_result* res, int64_t block);
+int64_t hb_result_cols(const hb_result* res, int64_t block);
+/* 1 if the factors are complex (interleaved FP64 pairs), 0 if real FP64. */
+int32_t hb_result_is_complex(const hb_result* res);
+
+/*
+ * Copy block `block`: U (rows x r), sigma (r) and Vh (cols x r), all
+ * column-major DEVICE buffers of the result's scalar type (sigma is real
+ * FP64), such that A_block ~ U diag(sigma) Vh^H.  Any pointer may be NULL.
+ * Asynchronous on `stream`.
+ */
+hb_status hb_result_copy(const hb_result* res, int64_t block, void* U, double* sigma, void* Vh,
+                         void* stream);
+
+/* Statistics of the call (host struct). */
+hb_status hb_result_stats(const hb_result* res, hb_stats* out);
+
+/*
+ * Leaf descriptors (host, 12 int64 per leaf, in leaf order: block-major,
+ * then b = t * 2^L + v):
+ *   block, t, v, row0, col0, m0, n0, rank_baca, rank_leaf, iterations,
+ *   status, tape_len
+ */
+int64_t hb_result_nleaves(const hb_result* res);
+hb_status hb_result_leaf_info(const hb_result* res, int64_t leaf, int64_t* info12);
+
+/*
+ * Pivot tape of one leaf (needs params->record_tape): rows[c] and cols[c],
+ * c < rank_baca, are the leaf-local rows I_k(1:d_k) and columns J_k(Jbar) in
+ * the order their cross blocks were appended; dk[k], nu[k], mu[k] for each
+ * iteration k < iterations (an iteration that ends with d_k = 0 is included).
+ * Host buffers sized from hb_result_leaf_info; any pointer may be NULL.
+ */
+hb_status hb_result_leaf_tape(const hb_result* res, int64_t leaf, int32_t* rows, int32_t* cols,
+                              int32_t* dk, double* nu, double* mu);
+
+/*
+ * Untimed check: sum over rows i = 0, stride, 2 stride, ... of
+ * |A(i,j) - (U diag(sigma) Vh^H)(i,j)|^2 and of |A(i,j)|^2, every column j,
+ * with A re-evaluated on the device in FP64 (host outputs).  The problem's
+ * own entry function and points are used; for a batched result `block`
+ * selects the problem.
+ */
+hb_status hb_result_error(const hb_result* res, int64_t block, int64_t row_stride, double* err2,
+                          double* ref2, void* stream);
+
+void hb_result_free(hb_result* res);
+const char* hb_status_string(hb_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HBACA_H */

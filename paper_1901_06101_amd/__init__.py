@@ -1,0 +1,193 @@
+"""H-BACA on MI355X: hierarchical blocked adaptive cross approximation.
+
+Python front end of libhbaca.so.  ``compress`` and ``compress_batched`` take
+torch tensors that already live on the GPU and return a ``Result`` whose
+factors come back as torch tensors:  A ~ U diag(S) Vh^H.
+
+There is no CPU path: if the HIP library or the GPU is missing the calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _binding as B
+from ._binding import (HB_K_GAUSS, HB_K_HELMHOLTZ3D, HB_K_LAPLACE,  # noqa: F401
+                       HB_K_LOWRANK_SPIKES, HBACAError, HbParams, HbStats, load)
+
+__all__ = ["compress", "compress_batched", "Result", "require_gpu", "params", "load",
+           "HBACAError", "HB_K_GAUSS", "HB_K_LAPLACE", "HB_K_HELMHOLTZ3D",
+           "HB_K_LOWRANK_SPIKES"]
+
+
+def require_gpu():
+    """Raise unless a GPU and the built library are both present."""
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("H-BACA needs a ROCm GPU (torch.cuda.is_available() is False)")
+    load()
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def params(dim=3, h=1.0, gauss_c=1.0, wavenumber=0.0, seed=0, rank_cap=0, record_tape=0,
+           stop_after=0, G1=None, G2=None, spike_lin=None, spike_val=None) -> dict:
+    return dict(dim=dim, h=h, gauss_c=gauss_c, wavenumber=wavenumber, seed=seed,
+                rank_cap=rank_cap, record_tape=record_tape, stop_after=stop_after, G1=G1,
+                G2=G2, spike_lin=spike_lin, spike_val=spike_val)
+
+
+def _hb_params(p: dict, keep: list) -> HbParams:
+    hp = HbParams()
+    hp.dim = int(p.get("dim", 3))
+    hp.h = float(p.get("h", 1.0))
+    hp.gauss_c = float(p.get("gauss_c", 1.0))
+    hp.wavenumber = float(p.get("wavenumber", 0.0))
+    G1, G2 = p.get("G1"), p.get("G2")
+    if G1 is not None:
+        keep += [G1, G2]
+        hp.lr_rank = int(G1.shape[1])
+        hp.lr_G1 = G1.data_ptr()
+        hp.lr_G2 = G2.data_ptr()
+    sl, sv = p.get("spike_lin"), p.get("spike_val")
+    if sl is not None and sl.numel() > 0:
+        keep += [sl, sv]
+        hp.n_spikes = int(sl.numel())
+        hp.spike_lin = sl.data_ptr()
+        hp.spike_val = sv.data_ptr()
+    hp.seed = int(p.get("seed", 0)) & ((1 << 64) - 1)
+    hp.precision = int(p.get("precision", 0))
+    hp.rank_cap = int(p.get("rank_cap", 0))
+    hp.record_tape = int(p.get("record_tape", 0))
+    hp.stop_after = int(p.get("stop_after", 0))
+    return hp
+
+
+class Result:
+    """Owns an hb_result handle; frees it on close() or garbage collection."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep
+        self._lib = load()
+
+    def close(self):
+        if self._h:
+            self._lib.hb_result_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nblocks(self):
+        return int(self._lib.hb_result_nblocks(self._h))
+
+    @property
+    def is_complex(self):
+        return bool(self._lib.hb_result_is_complex(self._h))
+
+    def rank(self, block=0):
+        return int(self._lib.hb_result_rank(self._h, block))
+
+    def shape(self, block=0):
+        return (int(self._lib.hb_result_rows(self._h, block)),
+                int(self._lib.hb_result_cols(self._h, block)))
+
+    def factors(self, block=0):
+        """(U, S, Vh) as torch tensors on the GPU with A ~ U diag(S) Vh^H."""
+        import torch
+        m, n = self.shape(block)
+        r = self.rank(block)
+        dt = torch.complex128 if self.is_complex else torch.float64
+        dev = torch.device("cuda")
+        Ub = torch.empty((r, m), dtype=dt, device=dev)   # column-major m x r
+        Vb = torch.empty((r, n), dtype=dt, device=dev)
+        S = torch.empty((r,), dtype=torch.float64, device=dev)
+        if r > 0:
+            B._check(self._lib.hb_result_copy(self._h, block, _ptr(Ub), _ptr(S), _ptr(Vb),
+                                              _stream()), "hb_result_copy")
+        return Ub.T, S, Vb.T
+
+    def stats(self):
+        st = HbStats()
+        B._check(self._lib.hb_result_stats(self._h, C.byref(st)), "hb_result_stats")
+        return st.as_dict()
+
+    @property
+    def nleaves(self):
+        return int(self._lib.hb_result_nleaves(self._h))
+
+    def leaf_info(self, leaf):
+        buf = (C.c_int64 * 12)()
+        B._check(self._lib.hb_result_leaf_info(self._h, leaf, buf), "hb_result_leaf_info")
+        keys = ("block", "t", "v", "row0", "col0", "m0", "n0", "rank_baca", "rank_leaf",
+                "iters", "status", "tape_len")
+        return dict(zip(keys, [int(x) for x in buf]))
+
+    def leaf_tape(self, leaf):
+        info = self.leaf_info(leaf)
+        n = info["rank_baca"]
+        it = info["iters"]
+        rows = np.zeros(max(n, 1), np.int32)
+        cols = np.zeros(max(n, 1), np.int32)
+        dk = np.zeros(max(it, 1), np.int32)
+        nu = np.zeros(max(it, 1), np.float64)
+        mu = np.zeros(max(it, 1), np.float64)
+        B._check(self._lib.hb_result_leaf_tape(
+            self._h, leaf, rows.ctypes.data_as(C.c_void_p), cols.ctypes.data_as(C.c_void_p),
+            dk.ctypes.data_as(C.c_void_p), nu.ctypes.data_as(C.c_void_p),
+            mu.ctypes.data_as(C.c_void_p)), "hb_result_leaf_tape")
+        return dict(rows=rows[:n], cols=cols[:n], dk=dk[:it], nu=nu[:it], mu=mu[:it])
+
+    def error(self, block=0, row_stride=1):
+        """(sum |A - A~|^2, sum |A|^2) over rows 0, stride, ... (device FP64)."""
+        e = C.c_double()
+        a = C.c_double()
+        B._check(self._lib.hb_result_error(self._h, block, row_stride, C.byref(e), C.byref(a),
+                                           _stream()), "hb_result_error")
+        return e.value, a.value
+
+
+def compress(entry: int, p: dict, X, Y, m: int, n: int, tol: float, d: int, leaf: int) -> Result:
+    """H-BACA of an m x n kernel matrix (points X: m x dim, Y: n x dim, float64
+    CUDA tensors; None for the low-rank-plus-spikes kernel)."""
+    lib = load()
+    keep = [X, Y]
+    hp = _hb_params(p, keep)
+    out = C.c_void_p()
+    st = lib.hbaca_compress(int(entry), C.byref(hp), _ptr(X), _ptr(Y), int(m), int(n),
+                            float(tol), int(d), int(leaf), _stream(), C.byref(out))
+    B._check(st, "hbaca_compress")
+    return Result(out, keep)
+
+
+def compress_batched(entry: int, p: dict, X, row_off, row_cnt, Y, col_off, col_cnt, tol: float,
+                     d: int, leaf: int) -> Result:
+    """Independent H-BACA of many blocks in one pass (offsets/counts: host
+    integer sequences)."""
+    lib = load()
+    keep = [X, Y]
+    hp = _hb_params(p, keep)
+    nb = len(row_off)
+    arr = [np.ascontiguousarray(np.asarray(a, dtype=np.int64)) for a in
+           (row_off, row_cnt, col_off, col_cnt)]
+    ptrs = [a.ctypes.data_as(C.POINTER(C.c_int64)) for a in arr]
+    out = C.c_void_p()
+    st = lib.hbaca_compress_batched(int(entry), C.byref(hp), nb, _ptr(X), ptrs[0], ptrs[1],
+                                    _ptr(Y), ptrs[2], ptrs[3], float(tol), int(d), int(leaf),
+                                    _stream(), C.byref(out))
+    B._check(st, "hbaca_compress_batched")
+    return Result(out, keep)

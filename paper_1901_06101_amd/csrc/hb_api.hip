@@ -1,0 +1,1704 @@
+// Host orchestration of H-BACA (Algorithm 3) behind the C ABI in hbaca.h.
+//
+// One call runs, on one stream:
+//   setup      cluster trees, leaf descriptors, first column blocks (SplitMix64)
+//   leaf BACA  one launch of the leaf kernel over every leaf of every problem
+//   leaf SVD   TSQR of U and V^H, M = R_U R_V^H, Jacobi SVD, Q applied to X, Y
+//   merges     for l = 1..L: horizontal merges, then vertical merges, each a
+//              batch over all blocks of all problems (TSQR, SVD, block GEMM)
+// The host reads back only ranks (to size the next step) and small records.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hbaca.h"
+#include "hb_common.h"
+#include "hb_entries.h"
+#include "hb_internal.h"
+#include "hb_merge.h"
+
+namespace {
+
+// ------------------------------------------------------------------ errors --
+struct HbError {
+  hb_status st;
+};
+#define HB_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) throw HbError{HB_EDEVICE};   \
+  } while (0)
+#define HB_LAUNCH(call)                                \
+  do {                                                 \
+    int e_ = (call);                                   \
+    if (e_ == -1) throw HbError{HB_EUNSUPPORTED};      \
+    if (e_ != 0) throw HbError{HB_EDEVICE};            \
+  } while (0)
+
+// --------------------------------------------------------- device memory ---
+static void keep_pool_memory() {
+  // keep freed stream-ordered allocations in the pool across calls
+  static bool done = false;
+  if (done) return;
+  int dev = 0;
+  hipMemPool_t pool;
+  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  done = true;
+}
+
+struct DevMem {
+  std::vector<void*> ptrs;
+  hipStream_t st = nullptr;
+  bool sync_free = false;  // results outlive the caller's stream
+  void* alloc(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    void* p = nullptr;
+    if (hipMallocAsync(&p, bytes, st) != hipSuccess || p == nullptr) throw HbError{HB_ENOMEM};
+    ptrs.push_back(p);
+    return p;
+  }
+  template <typename T> T* get(size_t n) { return (T*)alloc(n * sizeof(T)); }
+  // one allocation carved into 256-byte aligned pieces
+  std::vector<char*> carve(const std::vector<size_t>& sizes) {
+    size_t tot = 0;
+    std::vector<size_t> off(sizes.size());
+    for (size_t i = 0; i < sizes.size(); ++i) {
+      off[i] = tot;
+      tot += (std::max<size_t>(sizes[i], 1) + 255) & ~(size_t)255;
+    }
+    char* base = (char*)alloc(tot);
+    std::vector<char*> out(sizes.size());
+    for (size_t i = 0; i < sizes.size(); ++i) out[i] = base + off[i];
+    return out;
+  }
+  void release() {
+    if (sync_free && !ptrs.empty()) (void)hipDeviceSynchronize();
+    for (void* p : ptrs) (void)hipFreeAsync(p, sync_free ? nullptr : st);
+    if (sync_free && !ptrs.empty()) (void)hipStreamSynchronize(nullptr);
+    ptrs.clear();
+  }
+  ~DevMem() { release(); }
+};
+
+template <typename T>
+static T* upload(DevMem& mem, const std::vector<T>& v, hipStream_t st) {
+  T* d = mem.get<T>(v.size() ? v.size() : 1);
+  if (!v.empty()) HB_HIP(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return d;
+}
+
+// ------------------------------------------------------------ SplitMix64 ---
+// J_1 of leaf b: SplitMix64 (Steele, Lea and Flood 2014) from
+// seed + b * 0x632BE59BD9B4E019, partial Fisher-Yates over 0..n0-1.
+static void first_column_block(uint64_t seed, uint64_t b, int n0, int d, int32_t* out) {
+  const int q = std::min(d, n0);
+  uint64_t s = seed + b * 0x632BE59BD9B4E019ull;
+  std::vector<int32_t> perm(n0);
+  for (int i = 0; i < n0; ++i) perm[i] = i;
+  for (int t = 0; t < q; ++t) {
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const int j = t + (int)(z % (uint64_t)(n0 - t));
+    std::swap(perm[t], perm[j]);
+  }
+  for (int t = 0; t < q; ++t) out[t] = perm[t];
+}
+
+// ------------------------------------------------------------ trees --------
+static int tree_levels(int64_t m, int64_t n, int64_t leaf) {
+  int L = 0;
+  const int64_t big = std::max(m, n);
+  while (leaf * ((int64_t)1 << L) < big) ++L;
+  while (L > 0 && ((int64_t)1 << L) > std::min(m, n)) --L;
+  return L;
+}
+
+struct Node {
+  int64_t off, size;
+};
+static std::vector<std::vector<Node>> cluster_tree(int64_t size, int L) {
+  std::vector<std::vector<Node>> lv(1, std::vector<Node>{{0, size}});
+  for (int l = 0; l < L; ++l) {
+    std::vector<Node> nx;
+    for (const Node& nd : lv.back()) {
+      const int64_t h = (nd.size + 1) / 2;
+      nx.push_back({nd.off, h});
+      nx.push_back({nd.off + h, nd.size - h});
+    }
+    lv.push_back(nx);
+  }
+  return lv;
+}
+
+// ------------------------------------------------------------ kernels ------
+__global__ void aos_to_soa_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                  int64_t npts, int dim) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npts) return;
+  for (int c = 0; c < dim; ++c) dst[(int64_t)c * npts + i] = src[i * dim + c];
+}
+
+// M = R_U R_V^H for one leaf: R_U (pu x r), R_V (pv x r) from TSQR top nodes.
+template <typename T>
+__global__ void rrh_kernel(const QRNodeDev* __restrict__ topU, const QRNodeDev* __restrict__ topV,
+                           const T* __restrict__ store, const T* __restrict__ alpha,
+                           T* const* __restrict__ Mout) {
+  const QRNodeDev A = topU[blockIdx.x];
+  const QRNodeDev B = topV[blockIdx.x];
+  const int pu = A.steps, pv = B.steps, r = A.k;
+  T* M = Mout[blockIdx.x];
+  for (int e = threadIdx.x; e < pu * pv; e += blockDim.x) {
+    const int i = e % pu, j = e / pu;
+    T acc = sc_zero<T>();
+    // R_U(i, t) nonzero for t >= i; R_V(j, t) nonzero for t >= j
+    for (int t = max(i, j); t < r; ++t) {
+      const T a = (i < t) ? store[A.store + (int64_t)t * 256 + i] : alpha[A.ab + t];
+      const T b = (j < t) ? store[B.store + (int64_t)t * 256 + j] : alpha[B.ab + t];
+      sc_fma(acc, a, sc_conj(b));
+    }
+    M[e] = acc;  // column-major pu x pv
+  }
+}
+
+// Sums of |A - U S Vh^H|^2 and |A|^2 over rows i = stride * blockIdx.y... one
+// workgroup per (row, column tile); partial sums per workgroup.
+template <typename T>
+__global__ void error_kernel(EntryDev E, int64_t row_base, int64_t col_base, int64_t m, int64_t n,
+                             const T* __restrict__ U, const double* __restrict__ S,
+                             const T* __restrict__ Vh, int r, int64_t stride, int64_t nrows_s,
+                             double* __restrict__ part) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double e2 = 0.0, a2 = 0.0;
+  if (j < n) {
+    double yj[HB_MAXDIM];
+    for (int q = 0; q < HB_MAXDIM; ++q) yj[q] = q < E.dim ? E.Y[(int64_t)q * E.ldy + col_base + j] : 0.0;
+    for (int64_t rr = blockIdx.y; rr < nrows_s; rr += gridDim.y) {
+      const int64_t i = rr * stride;
+      double xi[HB_MAXDIM];
+      for (int q = 0; q < HB_MAXDIM; ++q) xi[q] = q < E.dim ? E.X[(int64_t)q * E.ldx + row_base + i] : 0.0;
+      const T a = eval_entry<T>(E, row_base + i, col_base + j, xi, yj);
+      T ap = sc_zero<T>();
+      for (int t = 0; t < r; ++t)
+        sc_fma(ap, sc_scale(U[(int64_t)t * m + i], S[t]), sc_conj(Vh[(int64_t)t * n + j]));
+      e2 += sc_abs2(sc_sub(a, ap));
+      a2 += sc_abs2(a);
+    }
+  }
+  __shared__ double r1[256], r2[256];
+  r1[threadIdx.x] = e2;
+  r2[threadIdx.x] = a2;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      r1[threadIdx.x] += r1[threadIdx.x + s];
+      r2[threadIdx.x] += r2[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * (blockIdx.y * gridDim.x + blockIdx.x)] = r1[0];
+    part[2 * (blockIdx.y * gridDim.x + blockIdx.x) + 1] = r2[0];
+  }
+}
+
+// ------------------------------------------------------------ structures ---
+struct Block {  // compressed block A_b ~ U diag(S) Vh^H on the device
+  int64_t m = 0, n = 0;
+  int r = 0;
+  void* U = nullptr;   // m x r, ld m
+  void* Vh = nullptr;  // n x r, ld n
+  double* S = nullptr; // r
+};
+
+struct Problem {
+  int64_t m, n, row_base, col_base;
+  int L;
+  uint64_t seed;
+  std::vector<std::vector<Node>> rt, ct;
+  Block root;
+};
+
+struct LeafHost {
+  int problem, t, v;
+  int64_t row0, col0;
+  int m0, n0;
+  int rank_baca = 0, rank_leaf = 0, iters = 0, status = 0;
+  std::vector<int32_t> tape_rows, tape_cols, it_dk;
+  std::vector<double> it_nu, it_mu;
+};
+
+}  // namespace
+
+struct hb_result {
+  int scalar = 0;  // 0 real, 1 complex
+  int entry = 0;
+  EntryDev E{};
+  std::vector<Problem> problems;
+  std::vector<LeafHost> leaves;
+  std::vector<Block> out_blocks;  // what hb_result_copy returns
+  DevMem keep;                     // device memory owned by the result
+  hb_stats stats{};
+};
+
+namespace {
+
+static size_t scalar_bytes(int scalar) { return scalar == 1 ? 16 : 8; }
+
+// ------------------------------------------------- batched truncated SVDs ---
+// A "merge job" computes the truncated SVD of B = [P1 diag(S1), P2 diag(S2)]
+// (rows x k) and applies it:  Pnew = Q X_r,  Onew = blockdiag(O1, O2) Y_r.
+// With O1 == nullptr (leaf re-compression) the job is the SVD re-compression
+// of U Vh^H instead (see run_recompress).
+struct MergeJob {
+  int64_t rows;           // rows of P1, P2
+  const void* P1; int r1; const double* S1;
+  const void* P2; int r2; const double* S2;
+  const void* O1; int64_t n1;  // O1: n1 x r1
+  const void* O2; int64_t n2;
+  Block* outP_owner;  // filled: rank, S, P (as out->U or out->Vh), O
+  bool p_is_u;        // true: P side is U (horizontal), false: P side is Vh
+};
+
+struct TreeBuild {
+  std::vector<std::vector<QRNodeDev>> levels;  // per level, all trees concatenated
+  std::vector<int> top_level, top_index;       // per matrix
+  std::vector<int> kmat;                       // per matrix
+  size_t store_elems = 0;
+  int ab_elems = 0;
+};
+
+// Builds TSQR trees for a list of tall matrices given by their level-0 sources.
+static void build_trees(const std::vector<QRNodeDev>& mats, const std::vector<int64_t>& rows,
+                        TreeBuild& tb) {
+  const int MC = 256;
+  const size_t nm = mats.size();
+  tb.top_level.assign(nm, -1);
+  tb.top_index.assign(nm, -1);
+  tb.kmat.assign(nm, 0);
+  std::vector<std::vector<int>> cur(nm);  // node indices at the current level per matrix
+  tb.levels.clear();
+  tb.levels.emplace_back();
+  for (size_t a = 0; a < nm; ++a) {
+    const int k = mats[a].k;
+    tb.kmat[a] = k;
+    if (k == 0 || rows[a] == 0) continue;
+    for (int64_t r0 = 0; r0 < rows[a]; r0 += MC) {
+      QRNodeDev nd = mats[a];
+      nd.row0 = mats[a].row0 + r0;
+      nd.rows = (int)std::min<int64_t>(MC, rows[a] - r0);
+      nd.steps = std::min(nd.rows, k);
+      nd.level0 = 1;
+      nd.store = (int64_t)tb.store_elems;
+      tb.store_elems += (size_t)MC * k;
+      nd.ab = tb.ab_elems;
+      tb.ab_elems += k;
+      cur[a].push_back((int)tb.levels[0].size());
+      tb.levels[0].push_back(nd);
+    }
+  }
+  int lev = 0;
+  while (true) {
+    bool any = false;
+    std::vector<QRNodeDev> next;
+    for (size_t a = 0; a < nm; ++a) {
+      if (cur[a].empty()) continue;
+      if (cur[a].size() == 1) {
+        if (tb.top_level[a] < 0) {
+          tb.top_level[a] = lev;
+          tb.top_index[a] = cur[a][0];
+        }
+        cur[a].clear();
+        continue;
+      }
+      any = true;
+      const int k = tb.kmat[a];
+      const int g = std::max(2, MC / k);
+      std::vector<int> nxt;
+      for (size_t c0 = 0; c0 < cur[a].size(); c0 += g) {
+        const int nc = (int)std::min<size_t>(g, cur[a].size() - c0);
+        int rws = 0;
+        for (int c = 0; c < nc; ++c) rws += tb.levels[lev][cur[a][c0 + c]].steps;
+        QRNodeDev nd{};
+        nd.rows = rws;
+        nd.k = k;
+        nd.steps = std::min(rws, k);
+        nd.level0 = 0;
+        nd.child0 = cur[a][c0];
+        nd.nchild = nc;
+        nd.store = (int64_t)tb.store_elems;
+        tb.store_elems += (size_t)MC * k;
+        nd.ab = tb.ab_elems;
+        tb.ab_elems += k;
+        nxt.push_back((int)next.size());
+        next.push_back(nd);
+      }
+      cur[a] = nxt;
+    }
+    if (!any) break;
+    tb.levels.push_back(next);
+    ++lev;
+  }
+}
+
+struct Engine {
+  hipStream_t st;
+  int scalar;
+  double eps;
+  DevMem& tmp;
+
+  Engine(hipStream_t s, int sc, double e, DevMem& t) : st(s), scalar(sc), eps(e), tmp(t) {}
+
+  size_t sb() const { return scalar_bytes(scalar); }
+
+  // Factor trees; returns device copies of each level's nodes.
+  struct Factored {
+    TreeBuild tb;
+    std::vector<QRNodeDev*> dlev;
+    void* store = nullptr;
+    void* alpha = nullptr;
+    double* beta = nullptr;
+  };
+
+  void factor(const std::vector<QRNodeDev>& mats, const std::vector<int64_t>& rows, Factored& F) {
+    build_trees(mats, rows, F.tb);
+    int kmax = 1;
+    for (int k : F.tb.kmat) kmax = std::max(kmax, k);
+    const int kv = hbk::tsqr_kmax_for(scalar, kmax);
+    if (kv < 0) throw HbError{HB_EUNSUPPORTED};
+    F.store = tmp.alloc(std::max<size_t>(F.tb.store_elems, 1) * sb());
+    F.alpha = tmp.alloc(std::max(F.tb.ab_elems, 1) * sb());
+    F.beta = tmp.get<double>(std::max(F.tb.ab_elems, 1));
+    F.dlev.clear();
+    for (auto& lv : F.tb.levels) F.dlev.push_back(upload(tmp, lv, st));
+    for (size_t l = 0; l < F.tb.levels.size(); ++l) {
+      HB_LAUNCH(hbk::tsqr_factor_launch(scalar, kv, F.dlev[l], (int)F.tb.levels[l].size(),
+                                        l ? F.dlev[l - 1] : nullptr, F.store, F.alpha, F.beta,
+                                        st));
+    }
+  }
+
+  // Zout(matrix a) = Q_a [Zin_a; 0]  (Zin_a: steps_top x r_a, ld ldin_a;
+  // Zout_a: rows_a x r_a, ld ldout_a)
+  // Q Z for any number of columns: groups of at most kcap columns
+  void apply(const Factored& F, const std::vector<const void*>& zin, const std::vector<int64_t>& ldin,
+             const std::vector<int>& rr, const std::vector<void*>& zout,
+             const std::vector<int64_t>& ldout) {
+    const int kcap = scalar == 0 ? 128 : 64;
+    int rmax = 0;
+    for (int r : rr) rmax = std::max(rmax, r);
+    if (rmax <= kcap) {
+      apply_cols(F, zin, ldin, rr, zout, ldout);
+      return;
+    }
+    for (int c0 = 0; c0 < rmax; c0 += kcap) {
+      std::vector<const void*> zi(zin.size(), nullptr);
+      std::vector<void*> zo(zout.size(), nullptr);
+      std::vector<int> rc(rr.size(), 0);
+      for (size_t a = 0; a < rr.size(); ++a) {
+        rc[a] = std::max(0, std::min(kcap, rr[a] - c0));
+        if (rc[a] == 0) continue;
+        zi[a] = (const char*)zin[a] + (size_t)c0 * ldin[a] * sb();
+        zo[a] = (char*)zout[a] + (size_t)c0 * ldout[a] * sb();
+      }
+      apply_cols(F, zi, ldin, rc, zo, ldout);
+    }
+  }
+
+  void apply_cols(const Factored& F, const std::vector<const void*>& zin,
+                  const std::vector<int64_t>& ldin, const std::vector<int>& rr,
+                  const std::vector<void*>& zout, const std::vector<int64_t>& ldout) {
+    const auto& tb = F.tb;
+    const int nlev = (int)tb.levels.size();
+    const size_t nm = tb.kmat.size();
+    int rmax = 1;
+    for (size_t a = 0; a < nm; ++a) rmax = std::max(rmax, rr[a]);
+    const int kv = hbk::tsqr_kmax_for(scalar, rmax);
+    if (kv < 0) throw HbError{HB_EUNSUPPORTED};
+    // map node -> (matrix) and the input/output of every node, top down
+    std::vector<std::vector<int>> owner(nlev);
+    for (int l = 0; l < nlev; ++l) owner[l].assign(tb.levels[l].size(), -1);
+    for (size_t a = 0; a < nm; ++a) {
+      if (tb.top_level[a] < 0) continue;
+      // walk down marking ownership
+      std::vector<int> cur{tb.top_index[a]};
+      for (int l = tb.top_level[a]; l >= 0; --l) {
+        std::vector<int> nx;
+        for (int id : cur) {
+          owner[l][id] = (int)a;
+          if (l > 0)
+            for (int c = 0; c < tb.levels[l][id].nchild; ++c) nx.push_back(tb.levels[l][id].child0 + c);
+        }
+        cur = nx;
+      }
+    }
+    // per node Zin pointer/ld and Zout pointer/ld
+    std::vector<std::vector<const void*>> nin(nlev);
+    std::vector<std::vector<int64_t>> nldin(nlev);
+    for (int l = 0; l < nlev; ++l) {
+      nin[l].assign(tb.levels[l].size(), nullptr);
+      nldin[l].assign(tb.levels[l].size(), 0);
+    }
+    for (size_t a = 0; a < nm; ++a)
+      if (tb.top_level[a] >= 0 && rr[a] > 0) {
+        nin[tb.top_level[a]][tb.top_index[a]] = zin[a];
+        nldin[tb.top_level[a]][tb.top_index[a]] = ldin[a];
+      }
+    for (int l = nlev - 1; l >= 0; --l) {
+      std::vector<QRApplyDev> jobs;
+      std::vector<char*> lbuf;
+      if (l > 0) {
+        std::vector<size_t> sz;
+        for (size_t id = 0; id < tb.levels[l].size(); ++id) {
+          const int a = owner[l][id];
+          sz.push_back((a < 0 || rr[a] == 0) ? 0 : (size_t)tb.levels[l][id].rows * rr[a] * sb());
+        }
+        lbuf = tmp.carve(sz);
+      }
+      for (size_t id = 0; id < tb.levels[l].size(); ++id) {
+        const int a = owner[l][id];
+        if (a < 0 || rr[a] == 0) continue;
+        const QRNodeDev& nd = tb.levels[l][id];
+        QRApplyDev J{};
+        J.rows = nd.rows;
+        J.steps = nd.steps;
+        J.r = rr[a];
+        J.store = nd.store;
+        J.ab = nd.ab;
+        J.Zin = nin[l][id];
+        J.ldin = nldin[l][id];
+        if (l == 0) {
+          // rows [row0 - base, ...) of the destination
+          const int64_t base = tb.levels[0][id].row0;  // absolute row in the source
+          (void)base;
+          J.Zout = (char*)zout[a] + 0;  // patched below with the chunk offset
+          J.ldout = ldout[a];
+        } else {
+          void* buf = lbuf[id];
+          J.Zout = buf;
+          J.ldout = nd.rows;
+          int off = 0;
+          for (int c = 0; c < nd.nchild; ++c) {
+            const int cid = nd.child0 + c;
+            nin[l - 1][cid] = (const char*)buf + (size_t)off * sb();
+            nldin[l - 1][cid] = nd.rows;
+            off += tb.levels[l - 1][cid].steps;
+          }
+        }
+        jobs.push_back(J);
+      }
+      if (l == 0) {
+        // level-0 chunks write rows [chunk offset, ...) of their matrix
+        size_t j = 0;
+        std::vector<int64_t> first_row(nm, -1);
+        for (size_t id = 0; id < tb.levels[0].size(); ++id) {
+          const int a = owner[0][id];
+          if (a >= 0 && first_row[a] < 0) first_row[a] = tb.levels[0][id].row0;
+        }
+        for (size_t id = 0; id < tb.levels[0].size(); ++id) {
+          const int a = owner[0][id];
+          if (a < 0 || rr[a] == 0) continue;
+          const int64_t off = tb.levels[0][id].row0 - first_row[a];
+          jobs[j].Zout = (char*)zout[a] + (size_t)off * sb();
+          ++j;
+        }
+      }
+      if (!jobs.empty()) {
+        QRApplyDev* dj = upload(tmp, jobs, st);
+        HB_LAUNCH(hbk::tsqr_apply_launch(scalar, kv, dj, (int)jobs.size(), F.store, F.beta, st));
+      }
+    }
+  }
+};
+
+// Runs a batch of truncated SVDs of R matrices (explicit or TSQR tops).
+struct SvdOut {
+  void* Xr;
+  void* Yr;
+  double* S;
+  int32_t* rank;
+  int p, k;
+};
+
+static void run_svds(Engine& E, std::vector<SVDJobDev>& jobs, const void* store, const void* alpha,
+                     std::vector<SvdOut>& outs, std::vector<int>& ranks_host) {
+  const size_t nj = jobs.size();
+  outs.assign(nj, SvdOut{});
+  if (nj == 0) {
+    ranks_host.clear();
+    return;
+  }
+  int32_t* dr = E.tmp.get<int32_t>(nj);
+  int kmax = 0, pmax = 0;
+  std::vector<size_t> sz;
+  for (size_t a = 0; a < nj; ++a) {
+    const size_t p = jobs[a].p, k = jobs[a].k;
+    kmax = std::max(kmax, (int)k);
+    pmax = std::max(pmax, (int)p);
+    sz.push_back(p * k * E.sb());
+    sz.push_back(k * k * E.sb());
+    sz.push_back(k * 8);
+    sz.push_back(k * 4);
+    sz.push_back(p * k * E.sb());
+    sz.push_back(k * k * E.sb());
+  }
+  std::vector<char*> bufs = E.tmp.carve(sz);
+  for (size_t a = 0; a < nj; ++a) {
+    SVDJobDev& J = jobs[a];
+    J.A = bufs[6 * a + 0];
+    J.Y = bufs[6 * a + 1];
+    J.S = (double*)bufs[6 * a + 2];
+    J.perm = (int32_t*)bufs[6 * a + 3];
+    J.rank = dr + a;
+    J.Xr = bufs[6 * a + 4];
+    J.Yr = bufs[6 * a + 5];
+    outs[a] = SvdOut{J.Xr, J.Yr, J.S, J.rank, J.p, J.k};
+  }
+  SVDJobDev* dj = upload(E.tmp, jobs, E.st);
+  HB_LAUNCH(hbk::svd_launch(E.scalar, dj, (int)nj, kmax, pmax, store, alpha, E.eps, E.st));
+  std::vector<int32_t> rh(nj);
+  HB_HIP(hipMemcpyAsync(rh.data(), dr, nj * sizeof(int32_t), hipMemcpyDeviceToHost, E.st));
+  HB_HIP(hipStreamSynchronize(E.st));
+  ranks_host.assign(rh.begin(), rh.end());
+}
+
+// Truncated SVD of the horizontal (p_is_u) or vertical concatenation of two
+// blocks, for a batch of pairs.  Results are allocated in `out_mem`.
+static void run_merges_direct(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_mem) {
+  const size_t nj = jobs.size();
+  std::vector<QRNodeDev> mats;
+  std::vector<int64_t> rows;
+  std::vector<size_t> midx(nj, (size_t)-1);
+  for (size_t a = 0; a < nj; ++a) {
+    MergeJob& J = jobs[a];
+    Block& B = *J.outP_owner;
+    const int k = J.r1 + J.r2;
+    if (J.p_is_u) {
+      B.m = J.rows;
+      B.n = J.n1 + J.n2;
+    } else {
+      B.n = J.rows;
+      B.m = J.n1 + J.n2;
+    }
+    B.r = 0;
+    if (k == 0) continue;
+    QRNodeDev nd{};
+    nd.k = k;
+    nd.P1 = J.P1; nd.ld1 = J.rows; nd.n1 = J.r1; nd.S1 = J.S1;
+    nd.P2 = J.P2; nd.ld2 = J.rows; nd.n2 = J.r2; nd.S2 = J.S2;
+    nd.row0 = 0;
+    midx[a] = mats.size();
+    mats.push_back(nd);
+    rows.push_back(J.rows);
+  }
+  Engine::Factored F;
+  E.factor(mats, rows, F);
+  std::vector<SVDJobDev> sj;
+  for (size_t a = 0; a < mats.size(); ++a) {
+    const QRNodeDev& top = F.tb.levels[F.tb.top_level[a]][F.tb.top_index[a]];
+    SVDJobDev J{};
+    J.p = top.steps;
+    J.k = top.k;
+    J.from_node = 1;
+    J.store = top.store;
+    J.ab = top.ab;
+    sj.push_back(J);
+  }
+  std::vector<SvdOut> so;
+  std::vector<int> rk;
+  run_svds(E, sj, F.store, F.alpha, so, rk);
+  // allocate outputs
+  std::vector<const void*> zin;
+  std::vector<int64_t> ldin, ldout;
+  std::vector<int> rr;
+  std::vector<void*> zout;
+  std::vector<BlockGemmDev> gj;
+  int64_t max_rows = 0;
+  int max_rin = 0;
+  std::vector<size_t> osz;
+  for (size_t a = 0; a < nj; ++a) {
+    MergeJob& J = jobs[a];
+    const int r = midx[a] == (size_t)-1 ? 0 : rk[midx[a]];
+    osz.push_back((size_t)J.rows * r * E.sb());
+    osz.push_back((size_t)(J.n1 + J.n2) * r * E.sb());
+    osz.push_back((size_t)r * 8);
+  }
+  std::vector<char*> ob = out_mem.carve(osz);
+  for (size_t a = 0; a < nj; ++a) {
+    MergeJob& J = jobs[a];
+    Block& B = *J.outP_owner;
+    if (midx[a] == (size_t)-1) continue;
+    const size_t i = midx[a];
+    const int r = rk[i];
+    B.r = r;
+    if (r == 0) continue;
+    const int64_t prow = J.rows, orow = J.n1 + J.n2;
+    void* P = ob[3 * a];
+    void* O = ob[3 * a + 1];
+    B.S = (double*)ob[3 * a + 2];
+    HB_HIP(hipMemcpyAsync(B.S, so[i].S, r * sizeof(double), hipMemcpyDeviceToDevice, E.st));
+    if (J.p_is_u) {
+      B.U = P;
+      B.Vh = O;
+    } else {
+      B.Vh = P;
+      B.U = O;
+    }
+    zin.push_back(so[i].Xr);
+    ldin.push_back(so[i].p);
+    rr.push_back(r);
+    zout.push_back(P);
+    ldout.push_back(prow);
+    BlockGemmDev g{};
+    g.A1 = J.O1; g.lda1 = J.n1; g.n1 = (int)J.n1; g.r1 = J.r1;
+    g.A2 = J.O2; g.lda2 = J.n2; g.n2 = (int)J.n2; g.r2 = J.r2;
+    g.Y = so[i].Yr; g.ldy = so[i].k; g.r = r;
+    g.C = O; g.ldc = orow;
+    gj.push_back(g);
+    max_rows = std::max(max_rows, orow);
+    max_rin = std::max(max_rin, J.r1 + J.r2);
+  }
+  // Q [X_r; 0] for every matrix with a nonzero rank (zeros for rank 0 are skipped)
+  std::vector<int> rr_all(mats.size(), 0);
+  std::vector<const void*> zin_all(mats.size(), nullptr);
+  std::vector<int64_t> ldin_all(mats.size(), 1), ldout_all(mats.size(), 1);
+  std::vector<void*> zout_all(mats.size(), nullptr);
+  {
+    size_t c = 0;
+    for (size_t a = 0; a < nj; ++a) {
+      if (midx[a] == (size_t)-1) continue;
+      const size_t i = midx[a];
+      if (rk[i] == 0) continue;
+      rr_all[i] = rr[c];
+      zin_all[i] = zin[c];
+      ldin_all[i] = ldin[c];
+      zout_all[i] = zout[c];
+      ldout_all[i] = ldout[c];
+      ++c;
+    }
+  }
+  E.apply(F, zin_all, ldin_all, rr_all, zout_all, ldout_all);
+  if (!gj.empty()) {
+    BlockGemmDev* dg = upload(E.tmp, gj, E.st);
+    HB_LAUNCH(hbk::block_gemm_launch(E.scalar, dg, (int)gj.size(), (int)max_rows, max_rin, E.st));
+  }
+}
+
+// Merges wider than the register TSQR: the larger block P_a (orthonormal) is
+// kept as a basis, the other is orthogonalised against it twice (block
+// classical Gram-Schmidt with re-orthogonalisation) and only that projection
+// goes through TSQR.  R = [P_a, Q_b]^H B is assembled explicitly.
+static void run_merges_split(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_mem) {
+  const size_t nj = jobs.size();
+  if (nj == 0) return;
+  const size_t sb = E.sb();
+  struct S {
+    bool a_first;
+    const void *Pa, *Pb;
+    int ra, rb;
+  };
+  std::vector<S> sp(nj);
+  for (size_t a = 0; a < nj; ++a) {
+    MergeJob& J = jobs[a];
+    Block& B = *J.outP_owner;
+    if (J.p_is_u) {
+      B.m = J.rows;
+      B.n = J.n1 + J.n2;
+    } else {
+      B.n = J.rows;
+      B.m = J.n1 + J.n2;
+    }
+    B.r = 0;
+    S& x = sp[a];
+    x.a_first = J.r1 >= J.r2;
+    x.Pa = x.a_first ? J.P1 : J.P2;
+    x.Pb = x.a_first ? J.P2 : J.P1;
+    x.ra = x.a_first ? J.r1 : J.r2;
+    x.rb = x.a_first ? J.r2 : J.r1;
+  }
+  // ---- projections W = (I - P_a P_a^H)^2 P_b,  M + M2 = P_a^H P_b
+  std::vector<size_t> sz;
+  for (size_t a = 0; a < nj; ++a) {
+    const int64_t m = jobs[a].rows;
+    const int64_t nch = (m + 31) / 32;
+    const size_t mm = (size_t)sp[a].ra * sp[a].rb * sb;
+    sz.push_back((size_t)m * sp[a].rb * sb);  // W
+    sz.push_back(mm);                         // M
+    sz.push_back(mm);                         // M2
+    sz.push_back((size_t)nch * mm);           // partials
+  }
+  std::vector<char*> bf = E.tmp.carve(sz);
+  std::vector<AhbJobDev> a1, a2;
+  std::vector<TallGemmDev> g1, g2;
+  int maxch = 1, maxka = 1, maxkb = 1;
+  int64_t maxm = 1;
+  for (size_t a = 0; a < nj; ++a) {
+    if (sp[a].rb == 0) continue;
+    const int64_t m = jobs[a].rows;
+    AhbJobDev h{};
+    h.A = sp[a].Pa;
+    h.B = sp[a].Pb;
+    h.m = m;
+    h.ka = sp[a].ra;
+    h.kb = sp[a].rb;
+    h.part = bf[4 * a + 3];
+    h.out = bf[4 * a + 1];
+    h.nchunk = (int)((m + 31) / 32);
+    a1.push_back(h);
+    h.B = bf[4 * a];
+    h.out = bf[4 * a + 2];
+    a2.push_back(h);
+    TallGemmDev g{};
+    g.Cin = sp[a].Pb;
+    g.A = sp[a].Pa;
+    g.B = bf[4 * a + 1];
+    g.C = bf[4 * a];
+    g.m = m;
+    g.lda = m;
+    g.ldb = sp[a].ra;
+    g.ldc = m;
+    g.ka = sp[a].ra;
+    g.nc = sp[a].rb;
+    g.sgn = -1.0;
+    g1.push_back(g);
+    g.Cin = bf[4 * a];
+    g.B = bf[4 * a + 2];
+    g2.push_back(g);
+    maxch = std::max(maxch, h.nchunk);
+    maxka = std::max(maxka, h.ka);
+    maxkb = std::max(maxkb, h.kb);
+    maxm = std::max(maxm, m);
+  }
+  if (!a1.empty()) {
+    AhbJobDev* d1 = upload(E.tmp, a1, E.st);
+    AhbJobDev* d2 = upload(E.tmp, a2, E.st);
+    TallGemmDev* e1 = upload(E.tmp, g1, E.st);
+    TallGemmDev* e2 = upload(E.tmp, g2, E.st);
+    HB_LAUNCH(hbk::ahb_launch(E.scalar, d1, (int)a1.size(), maxch, maxka, maxkb, E.st));
+    HB_LAUNCH(hbk::tall_gemm_launch(E.scalar, e1, (int)g1.size(), maxm, maxka, E.st));
+    HB_LAUNCH(hbk::ahb_launch(E.scalar, d2, (int)a2.size(), maxch, maxka, maxkb, E.st));
+    HB_LAUNCH(hbk::tall_gemm_launch(E.scalar, e2, (int)g2.size(), maxm, maxka, E.st));
+  }
+  // ---- TSQR of the projections
+  std::vector<QRNodeDev> mats;
+  std::vector<int64_t> rows;
+  std::vector<int> midx(nj, -1);
+  for (size_t a = 0; a < nj; ++a) {
+    if (sp[a].rb == 0) continue;
+    QRNodeDev nd{};
+    nd.k = sp[a].rb;
+    nd.P1 = bf[4 * a];
+    nd.ld1 = jobs[a].rows;
+    nd.n1 = sp[a].rb;
+    nd.P2 = bf[4 * a];
+    nd.ld2 = jobs[a].rows;
+    nd.n2 = 0;
+    midx[a] = (int)mats.size();
+    mats.push_back(nd);
+    rows.push_back(jobs[a].rows);
+  }
+  Engine::Factored F;
+  E.factor(mats, rows, F);
+  // ---- explicit R and its SVD
+  std::vector<SplitRDev> rj(nj);
+  std::vector<SVDJobDev> sj(nj);
+  std::vector<size_t> rsz(nj);
+  std::vector<int> pb(nj, 0);
+  for (size_t a = 0; a < nj; ++a) {
+    if (midx[a] >= 0) {
+      const QRNodeDev& top = F.tb.levels[F.tb.top_level[midx[a]]][F.tb.top_index[midx[a]]];
+      pb[a] = top.steps;
+      rj[a].store = top.store;
+      rj[a].ab = top.ab;
+    }
+    rsz[a] = (size_t)(sp[a].ra + pb[a]) * (jobs[a].r1 + jobs[a].r2) * sb;
+  }
+  std::vector<char*> rbuf = E.tmp.carve(rsz);
+  for (size_t a = 0; a < nj; ++a) {
+    SplitRDev& x = rj[a];
+    x.S1 = jobs[a].S1;
+    x.S2 = jobs[a].S2;
+    x.M = bf[4 * a + 1];
+    x.M2 = bf[4 * a + 2];
+    x.r1 = jobs[a].r1;
+    x.r2 = jobs[a].r2;
+    x.ra = sp[a].ra;
+    x.rb = sp[a].rb;
+    x.pb = pb[a];
+    x.a_first = sp[a].a_first ? 1 : 0;
+    x.R = rbuf[a];
+    SVDJobDev J{};
+    J.p = sp[a].ra + pb[a];
+    J.k = jobs[a].r1 + jobs[a].r2;
+    J.from_node = 0;
+    J.R = rbuf[a];
+    sj[a] = J;
+  }
+  SplitRDev* drj = upload(E.tmp, rj, E.st);
+  HB_LAUNCH(hbk::split_r_launch(E.scalar, drj, (int)nj, F.store, F.alpha, E.st));
+  std::vector<SvdOut> so;
+  std::vector<int> rk;
+  run_svds(E, sj, F.store, F.alpha, so, rk);
+  // ---- outputs
+  std::vector<size_t> osz;
+  for (size_t a = 0; a < nj; ++a) {
+    const int r = rk[a];
+    osz.push_back((size_t)jobs[a].rows * r * sb);
+    osz.push_back((size_t)(jobs[a].n1 + jobs[a].n2) * r * sb);
+    osz.push_back((size_t)r * 8);
+  }
+  std::vector<char*> ob = out_mem.carve(osz);
+  std::vector<int> rr(mats.size(), 0);
+  std::vector<const void*> zin(mats.size(), nullptr);
+  std::vector<int64_t> ldin(mats.size(), 1), ldout(mats.size(), 1);
+  std::vector<void*> zout(mats.size(), nullptr);
+  std::vector<TallGemmDev> gadd;
+  std::vector<BlockGemmDev> gj;
+  int64_t max_rows = 0, maxm2 = 1;
+  int max_rin = 0, maxka2 = 1;
+  for (size_t a = 0; a < nj; ++a) {
+    MergeJob& J = jobs[a];
+    Block& B = *J.outP_owner;
+    const int r = rk[a];
+    B.r = r;
+    if (r == 0) continue;
+    void* P = ob[3 * a];
+    void* O = ob[3 * a + 1];
+    B.S = (double*)ob[3 * a + 2];
+    HB_HIP(hipMemcpyAsync(B.S, so[a].S, r * sizeof(double), hipMemcpyDeviceToDevice, E.st));
+    if (J.p_is_u) {
+      B.U = P;
+      B.Vh = O;
+    } else {
+      B.Vh = P;
+      B.U = O;
+    }
+    const int p = sp[a].ra + pb[a];
+    bool wrote = false;
+    if (midx[a] >= 0 && pb[a] > 0) {
+      const int i = midx[a];
+      rr[i] = r;
+      zin[i] = (const char*)so[a].Xr + (size_t)sp[a].ra * sb;
+      ldin[i] = p;
+      zout[i] = P;
+      ldout[i] = J.rows;
+      wrote = true;
+    }
+    TallGemmDev g{};
+    g.Cin = wrote ? P : nullptr;
+    g.A = sp[a].Pa;
+    g.B = so[a].Xr;
+    g.C = P;
+    g.m = J.rows;
+    g.lda = J.rows;
+    g.ldb = p;
+    g.ldc = J.rows;
+    g.ka = sp[a].ra;
+    g.nc = r;
+    g.sgn = 1.0;
+    gadd.push_back(g);
+    maxm2 = std::max(maxm2, J.rows);
+    maxka2 = std::max(maxka2, sp[a].ra);
+    BlockGemmDev bg{};
+    bg.A1 = J.O1; bg.lda1 = J.n1; bg.n1 = (int)J.n1; bg.r1 = J.r1;
+    bg.A2 = J.O2; bg.lda2 = J.n2; bg.n2 = (int)J.n2; bg.r2 = J.r2;
+    bg.Y = so[a].Yr; bg.ldy = so[a].k; bg.r = r;
+    bg.C = O; bg.ldc = J.n1 + J.n2;
+    gj.push_back(bg);
+    max_rows = std::max<int64_t>(max_rows, J.n1 + J.n2);
+    max_rin = std::max(max_rin, J.r1 + J.r2);
+  }
+  if (!mats.empty()) E.apply(F, zin, ldin, rr, zout, ldout);
+  if (!gadd.empty()) {
+    TallGemmDev* dg = upload(E.tmp, gadd, E.st);
+    HB_LAUNCH(hbk::tall_gemm_launch(E.scalar, dg, (int)gadd.size(), maxm2, maxka2, E.st));
+  }
+  if (!gj.empty()) {
+    BlockGemmDev* dg = upload(E.tmp, gj, E.st);
+    HB_LAUNCH(hbk::block_gemm_launch(E.scalar, dg, (int)gj.size(), (int)max_rows, max_rin, E.st));
+  }
+}
+
+static void run_merges(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_mem) {
+  const int kcap = E.scalar == 0 ? 128 : 64;
+  std::vector<MergeJob> direct, split;
+  for (auto& J : jobs) {
+    const int k = J.r1 + J.r2;
+    if (k <= kcap) direct.push_back(J);
+    else if (std::min(J.r1, J.r2) <= kcap) split.push_back(J);
+    else throw HbError{HB_EUNSUPPORTED};
+  }
+  run_merges_direct(E, direct, out_mem);
+  run_merges_split(E, split, out_mem);
+}
+
+// SVD re-compression of BACA leaves: U (m0 x r), Vh (n0 x r) -> truncated SVD.
+struct RecJob {
+  const void* U;
+  const void* Vh;
+  int64_t m0, n0;
+  int r;
+  Block* out;
+};
+
+static void run_recompress(Engine& E, std::vector<RecJob>& jobs, DevMem& out_mem) {
+  const size_t nj = jobs.size();
+  std::vector<QRNodeDev> mats;
+  std::vector<int64_t> rows;
+  std::vector<size_t> live;
+  for (size_t a = 0; a < nj; ++a) {
+    Block& B = *jobs[a].out;
+    B.m = jobs[a].m0;
+    B.n = jobs[a].n0;
+    B.r = 0;
+    if (jobs[a].r == 0) continue;
+    live.push_back(a);
+    for (int side = 0; side < 2; ++side) {
+      QRNodeDev nd{};
+      nd.k = jobs[a].r;
+      nd.P1 = side == 0 ? jobs[a].U : jobs[a].Vh;
+      nd.ld1 = side == 0 ? jobs[a].m0 : jobs[a].n0;
+      nd.n1 = jobs[a].r;
+      nd.P2 = nd.P1;
+      nd.ld2 = nd.ld1;
+      nd.n2 = 0;
+      mats.push_back(nd);
+      rows.push_back(side == 0 ? jobs[a].m0 : jobs[a].n0);
+    }
+  }
+  if (live.empty()) return;
+  Engine::Factored F;
+  E.factor(mats, rows, F);
+  const size_t nl = live.size();
+  std::vector<QRNodeDev> topU(nl), topV(nl);
+  std::vector<void*> Mptr(nl);
+  std::vector<SVDJobDev> sj(nl);
+  for (size_t i = 0; i < nl; ++i) {
+    topU[i] = F.tb.levels[F.tb.top_level[2 * i]][F.tb.top_index[2 * i]];
+    topV[i] = F.tb.levels[F.tb.top_level[2 * i + 1]][F.tb.top_index[2 * i + 1]];
+    const int pu = topU[i].steps, pv = topV[i].steps;
+    Mptr[i] = nullptr;
+    (void)pu;
+    (void)pv;
+    SVDJobDev J{};
+    J.p = pu;
+    J.k = pv;
+    J.from_node = 0;
+    J.R = Mptr[i];
+    sj[i] = J;
+  }
+  {
+    std::vector<size_t> msz;
+    for (size_t i = 0; i < nl; ++i) msz.push_back((size_t)topU[i].steps * topV[i].steps * E.sb());
+    std::vector<char*> mb = E.tmp.carve(msz);
+    for (size_t i = 0; i < nl; ++i) {
+      Mptr[i] = mb[i];
+      sj[i].R = mb[i];
+    }
+  }
+  QRNodeDev* dU = upload(E.tmp, topU, E.st);
+  QRNodeDev* dV = upload(E.tmp, topV, E.st);
+  void** dM = upload(E.tmp, Mptr, E.st);
+  if (E.scalar == 0)
+    hipLaunchKernelGGL((rrh_kernel<double>), dim3(nl), dim3(256), 0, E.st, dU, dV,
+                       (const double*)F.store, (const double*)F.alpha, (double* const*)dM);
+  else
+    hipLaunchKernelGGL((rrh_kernel<hb_cplx>), dim3(nl), dim3(256), 0, E.st, dU, dV,
+                       (const hb_cplx*)F.store, (const hb_cplx*)F.alpha, (hb_cplx* const*)dM);
+  HB_HIP(hipGetLastError());
+  std::vector<SvdOut> so;
+  std::vector<int> rk;
+  run_svds(E, sj, F.store, F.alpha, so, rk);
+  std::vector<int> rr(mats.size(), 0);
+  std::vector<const void*> zin(mats.size(), nullptr);
+  std::vector<int64_t> ldin(mats.size(), 1), ldout(mats.size(), 1);
+  std::vector<void*> zout(mats.size(), nullptr);
+  std::vector<size_t> osz;
+  for (size_t i = 0; i < nl; ++i) {
+    const RecJob& J = jobs[live[i]];
+    osz.push_back((size_t)J.m0 * rk[i] * E.sb());
+    osz.push_back((size_t)J.n0 * rk[i] * E.sb());
+    osz.push_back((size_t)rk[i] * 8);
+  }
+  std::vector<char*> ob = out_mem.carve(osz);
+  for (size_t i = 0; i < nl; ++i) {
+    RecJob& J = jobs[live[i]];
+    Block& B = *J.out;
+    const int r = rk[i];
+    B.r = r;
+    if (r == 0) continue;
+    B.U = ob[3 * i];
+    B.Vh = ob[3 * i + 1];
+    B.S = (double*)ob[3 * i + 2];
+    HB_HIP(hipMemcpyAsync(B.S, so[i].S, r * sizeof(double), hipMemcpyDeviceToDevice, E.st));
+    rr[2 * i] = r;
+    zin[2 * i] = so[i].Xr;
+    ldin[2 * i] = so[i].p;
+    zout[2 * i] = B.U;
+    ldout[2 * i] = J.m0;
+    rr[2 * i + 1] = r;
+    zin[2 * i + 1] = so[i].Yr;
+    ldin[2 * i + 1] = so[i].k;
+    zout[2 * i + 1] = B.Vh;
+    ldout[2 * i + 1] = J.n0;
+  }
+  E.apply(F, zin, ldin, rr, zout, ldout);
+}
+
+// ------------------------------------------------------------ the driver ---
+struct CallSpec {
+  int entry;
+  const hb_params* prm;
+  const double* X;  // row points (AoS)
+  const double* Y;
+  int64_t nx, ny;   // total points
+  std::vector<int64_t> roff, rcnt, coff, ccnt;
+  double tol;
+  int d, leaf;
+  hipStream_t st;
+  bool batched;
+};
+
+static float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.0f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  return ms;
+}
+
+static hb_status validate(const CallSpec& c) {
+  const hb_params* p = c.prm;
+  if (!p) return HB_EINVAL;
+  if (!(c.tol > 0.0 && c.tol < 1.0)) return std::isfinite(c.tol) ? HB_EINVAL : HB_ENONFINITE;
+  if (c.d < 1 || c.leaf < 1) return HB_EINVAL;
+  if (c.d > 32) return HB_EUNSUPPORTED;
+  if (p->precision != HB_PREC_FP64) return HB_EUNSUPPORTED;
+  if (p->stop_after < 0 || p->stop_after > 2 || p->rank_cap < 0) return HB_EINVAL;
+  for (size_t b = 0; b < c.rcnt.size(); ++b) {
+    if (c.rcnt[b] < 1 || c.ccnt[b] < 1 || c.roff[b] < 0 || c.coff[b] < 0) return HB_EINVAL;
+    if (c.roff[b] + c.rcnt[b] > c.nx || c.coff[b] + c.ccnt[b] > c.ny) return HB_EINVAL;
+  }
+  switch (c.entry) {
+    case HB_K_GAUSS:
+      if (!std::isfinite(p->h) || !std::isfinite(p->gauss_c)) return HB_ENONFINITE;
+      if (!(p->h > 0.0) || !(p->gauss_c > 0.0)) return HB_EINVAL;
+      [[fallthrough]];
+    case HB_K_LAPLACE:
+    case HB_K_HELMHOLTZ3D:
+      if (c.entry == HB_K_HELMHOLTZ3D) {
+        if (!std::isfinite(p->wavenumber)) return HB_ENONFINITE;
+        if (!(p->wavenumber > 0.0)) return HB_EINVAL;
+      }
+      if (p->dim < 1 || p->dim > HB_MAXDIM) return HB_EINVAL;
+      if (!c.X || !c.Y) return HB_EINVAL;
+      break;
+    case HB_K_LOWRANK_SPIKES:
+      if (c.batched) return HB_EINVAL;
+      if (p->lr_rank < 1 || !p->lr_G1 || !p->lr_G2) return HB_EINVAL;
+      if (p->n_spikes < 0 || (p->n_spikes > 0 && (!p->spike_lin || !p->spike_val))) return HB_EINVAL;
+      break;
+    default:
+      return HB_EINVAL;
+  }
+  return HB_OK;
+}
+
+static hb_status run(const CallSpec& c, hb_result** out) {
+  if (!out) return HB_EINVAL;
+  *out = nullptr;
+  hb_status vs = validate(c);
+  if (vs != HB_OK) return vs;
+  const hb_params& P = *c.prm;
+  std::unique_ptr<hb_result> R(new (std::nothrow) hb_result());
+  if (!R) return HB_ENOMEM;
+  hipStream_t st = c.st;
+  keep_pool_memory();
+  R->keep.st = st;
+  R->keep.sync_free = true;
+  DevMem tmp;
+  tmp.st = st;
+  hipEvent_t ev[6];
+  for (auto& e : ev) HB_HIP(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]);
+    }
+  } evg{ev};
+  HB_HIP(hipEventRecord(ev[0], st));
+
+  const int scalar = c.entry == HB_K_HELMHOLTZ3D ? 1 : 0;
+  R->scalar = scalar;
+  R->entry = c.entry;
+  const size_t sbytes = scalar_bytes(scalar);
+
+  // ---- entry description (SoA points owned by the result)
+  EntryDev E{};
+  E.kind = c.entry;
+  if (c.entry == HB_K_LOWRANK_SPIKES) {
+    E.dim = 0;
+    E.G1 = P.lr_G1;
+    E.G2 = P.lr_G2;
+    E.r0 = P.lr_rank;
+    E.n_glob = c.ny;
+    E.spike_lin = P.spike_lin;
+    E.spike_val = P.spike_val;
+    E.nspk = P.n_spikes;
+  } else {
+    E.dim = P.dim;
+    double* Xs = R->keep.get<double>((size_t)c.nx * P.dim);
+    double* Ys = R->keep.get<double>((size_t)c.ny * P.dim);
+    hipLaunchKernelGGL(aos_to_soa_kernel, dim3((c.nx + 255) / 256), dim3(256), 0, st, c.X, Xs,
+                       c.nx, P.dim);
+    hipLaunchKernelGGL(aos_to_soa_kernel, dim3((c.ny + 255) / 256), dim3(256), 0, st, c.Y, Ys,
+                       c.ny, P.dim);
+    HB_HIP(hipGetLastError());
+    E.X = Xs;
+    E.Y = Ys;
+    E.ldx = c.nx;
+    E.ldy = c.ny;
+    E.neg_inv_ch2 = c.entry == HB_K_GAUSS ? -1.0 / (P.gauss_c * P.h * P.h) : 0.0;
+    E.wavenumber = P.wavenumber;
+  }
+  R->E = E;
+
+  // ---- problems, trees, leaves
+  const size_t np = c.rcnt.size();
+  R->problems.resize(np);
+  int Lmax = 0;
+  for (size_t p = 0; p < np; ++p) {
+    Problem& pr = R->problems[p];
+    pr.m = c.rcnt[p];
+    pr.n = c.ccnt[p];
+    pr.row_base = c.roff[p];
+    pr.col_base = c.coff[p];
+    pr.L = tree_levels(pr.m, pr.n, c.leaf);
+    pr.seed = P.seed + (c.batched ? (uint64_t)p : 0ull);
+    pr.rt = cluster_tree(pr.m, pr.L);
+    pr.ct = cluster_tree(pr.n, pr.L);
+    Lmax = std::max(Lmax, pr.L);
+    const int nb = 1 << pr.L;
+    for (int t = 0; t < nb; ++t)
+      for (int v = 0; v < nb; ++v) {
+        LeafHost lf;
+        lf.problem = (int)p;
+        lf.t = t;
+        lf.v = v;
+        lf.row0 = pr.row_base + pr.rt[pr.L][t].off;
+        lf.col0 = pr.col_base + pr.ct[pr.L][v].off;
+        lf.m0 = (int)pr.rt[pr.L][t].size;
+        lf.n0 = (int)pr.ct[pr.L][v].size;
+        R->leaves.push_back(lf);
+      }
+  }
+  const size_t nleaves = R->leaves.size();
+  int maxdim = 0;
+  for (auto& lf : R->leaves) maxdim = std::max(maxdim, std::max(lf.m0, lf.n0));
+  if (maxdim > 2048) return HB_EUNSUPPORTED;
+  const int dmax = c.d <= 8 ? 8 : (c.d <= 16 ? 16 : 32);
+  const int rpt = (maxdim + 511) / 512;
+  int rpt_v = rpt <= 1 ? 1 : (rpt <= 2 ? 2 : 4);
+  if (scalar == 1 && ((dmax == 16 && rpt_v > 2) || (dmax == 32 && rpt_v > 1))) return HB_EUNSUPPORTED;
+  if (scalar == 0 && dmax == 32 && rpt_v > 2) return HB_EUNSUPPORTED;
+
+  // ---- leaf descriptors; largest leaves first
+  std::vector<int> order(nleaves);
+  for (size_t i = 0; i < nleaves; ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (int64_t)R->leaves[a].m0 * R->leaves[a].n0 > (int64_t)R->leaves[b].m0 * R->leaves[b].n0;
+  });
+  std::vector<BacaLeafDev> ld(nleaves);
+  std::vector<int32_t> j1;
+  int64_t uo = 0, vo = 0, co = 0, ro = 0;
+  int32_t tapeo = 0, ito = 0;
+  std::vector<int> caps(nleaves);
+  for (size_t s = 0; s < nleaves; ++s) {
+    const LeafHost& lf = R->leaves[order[s]];
+    const Problem& pr = R->problems[lf.problem];
+    BacaLeafDev& L = ld[s];
+    std::memset(&L, 0, sizeof(L));
+    L.m0 = lf.m0;
+    L.n0 = lf.n0;
+    L.row0 = lf.row0;
+    L.col0 = lf.col0;
+    int cap = std::min(lf.m0, lf.n0);
+    if (P.rank_cap > 0) cap = std::min(cap, P.rank_cap);
+    caps[s] = cap;
+    L.cap = cap;
+    L.u_off = uo;
+    uo += (int64_t)lf.m0 * cap;
+    L.v_off = vo;
+    vo += (int64_t)lf.n0 * cap;
+    L.c_off = co;
+    co += (int64_t)lf.m0 * dmax;
+    L.r_off = ro;
+    ro += (int64_t)lf.n0 * dmax;
+    L.tape_off = tapeo;
+    tapeo += cap;
+    L.it_off = ito;
+    ito += cap + 1;
+    L.j1_off = (int32_t)j1.size();
+    L.nj1 = std::min(c.d, lf.n0);
+    const uint64_t b = (uint64_t)lf.t * ((uint64_t)1 << pr.L) + (uint64_t)lf.v;
+    std::vector<int32_t> jj(L.nj1);
+    first_column_block(pr.seed, b, lf.n0, c.d, jj.data());
+    j1.insert(j1.end(), jj.begin(), jj.end());
+  }
+  DevMem baca_mem;
+  baca_mem.st = st;
+  BacaArgs A{};
+  A.leaves = upload(tmp, ld, st);
+  A.out = tmp.get<BacaOutDev>(nleaves);
+  A.E = E;
+  A.U = baca_mem.alloc((size_t)std::max<int64_t>(uo, 1) * sbytes);
+  A.V = baca_mem.alloc((size_t)std::max<int64_t>(vo, 1) * sbytes);
+  A.C = tmp.alloc((size_t)std::max<int64_t>(co, 1) * sbytes);
+  A.R = tmp.alloc((size_t)std::max<int64_t>(ro, 1) * sbytes);
+  A.j1 = upload(tmp, j1, st);
+  A.tape_rows = tmp.get<int32_t>(std::max(tapeo, 1));
+  A.tape_cols = tmp.get<int32_t>(std::max(tapeo, 1));
+  A.it_dk = tmp.get<int32_t>(std::max(ito, 1));
+  A.it_nu = tmp.get<double>(std::max(ito, 1));
+  A.it_mu = tmp.get<double>(std::max(ito, 1));
+  A.eps = c.tol;
+  A.nleaves = (int32_t)nleaves;
+  HB_HIP(hipEventRecord(ev[1], st));
+  HB_LAUNCH(hbk::baca_launch(scalar, dmax, rpt_v, A, st));
+  HB_HIP(hipEventRecord(ev[2], st));
+  std::vector<BacaOutDev> bo(nleaves);
+  HB_HIP(hipMemcpyAsync(bo.data(), A.out, nleaves * sizeof(BacaOutDev), hipMemcpyDeviceToHost, st));
+  std::vector<int32_t> h_rows, h_cols, h_dk;
+  std::vector<double> h_nu, h_mu;
+  if (P.record_tape) {
+    h_rows.resize(tapeo);
+    h_cols.resize(tapeo);
+    h_dk.resize(ito);
+    h_nu.resize(ito);
+    h_mu.resize(ito);
+    HB_HIP(hipMemcpyAsync(h_rows.data(), A.tape_rows, tapeo * 4, hipMemcpyDeviceToHost, st));
+    HB_HIP(hipMemcpyAsync(h_cols.data(), A.tape_cols, tapeo * 4, hipMemcpyDeviceToHost, st));
+    HB_HIP(hipMemcpyAsync(h_dk.data(), A.it_dk, ito * 4, hipMemcpyDeviceToHost, st));
+    HB_HIP(hipMemcpyAsync(h_nu.data(), A.it_nu, ito * 8, hipMemcpyDeviceToHost, st));
+    HB_HIP(hipMemcpyAsync(h_mu.data(), A.it_mu, ito * 8, hipMemcpyDeviceToHost, st));
+  }
+  HB_HIP(hipStreamSynchronize(st));
+  hb_stats& S = R->stats;
+  S.n_leaves = (int32_t)nleaves;
+  S.n_blocks = (int32_t)np;
+  S.levels_max = Lmax;
+  for (size_t s = 0; s < nleaves; ++s) {
+    LeafHost& lf = R->leaves[order[s]];
+    lf.rank_baca = bo[s].rank;
+    lf.iters = bo[s].iters;
+    lf.status = bo[s].status;
+    if (bo[s].status != 0) return HB_ERANKCAP;
+    if (P.record_tape) {
+      lf.tape_rows.assign(h_rows.begin() + ld[s].tape_off, h_rows.begin() + ld[s].tape_off + lf.rank_baca);
+      lf.tape_cols.assign(h_cols.begin() + ld[s].tape_off, h_cols.begin() + ld[s].tape_off + lf.rank_baca);
+      lf.it_dk.assign(h_dk.begin() + ld[s].it_off, h_dk.begin() + ld[s].it_off + lf.iters);
+      lf.it_nu.assign(h_nu.begin() + ld[s].it_off, h_nu.begin() + ld[s].it_off + lf.iters);
+      lf.it_mu.assign(h_mu.begin() + ld[s].it_off, h_mu.begin() + ld[s].it_off + lf.iters);
+    }
+    S.leaf_rank_baca_max = std::max(S.leaf_rank_baca_max, lf.rank_baca);
+    S.iters_max = std::max(S.iters_max, lf.iters);
+    S.iters_total += lf.iters;
+  }
+  // algorithmic counters of the residual passes (iteration k streams r_{k-1}
+  // columns of U and V once and evaluates d (m0 + n0) entries)
+  {
+    const double phi = scalar ? 4.0 : 1.0;
+    if (P.record_tape) {
+      for (size_t s = 0; s < nleaves; ++s) {
+        const LeafHost& lf = R->leaves[order[s]];
+        int r = 0;
+        for (int k = 0; k < lf.iters; ++k) {
+          const double mn = (double)lf.m0 + lf.n0;
+          S.resid_bytes += (double)sbytes * r * mn;
+          S.resid_flops += 2.0 * phi * std::min(c.d, lf.n0) * r * mn;
+          S.entries_evaluated += (double)std::min(c.d, lf.n0) * mn;
+          r += lf.it_dk[k];
+        }
+      }
+    }
+  }
+  // the leaf BACA factors as blocks (stop_after == 1)
+  std::vector<Block> leafblk(nleaves);
+  for (size_t s = 0; s < nleaves; ++s) {
+    const int li = order[s];
+    Block& b = leafblk[li];
+    b.m = ld[s].m0;
+    b.n = ld[s].n0;
+    b.r = bo[s].rank;
+    b.U = (char*)A.U + (size_t)ld[s].u_off * sbytes;
+    b.Vh = (char*)A.V + (size_t)ld[s].v_off * sbytes;
+  }
+  Engine Eng(st, scalar, c.tol, tmp);
+  if (P.stop_after == 1) {
+    // keep the BACA arena in the result; blocks are leaves with sigma = 1
+    for (void* p : baca_mem.ptrs) R->keep.ptrs.push_back(p);
+    baca_mem.ptrs.clear();
+    int maxr = 1;
+    for (auto& b : leafblk) maxr = std::max(maxr, b.r);
+    std::vector<double> ones(maxr, 1.0);
+    double* dones = upload(R->keep, ones, st);
+    for (auto& b : leafblk) b.S = dones;
+    R->out_blocks = leafblk;
+    S.n_blocks = (int32_t)nleaves;
+    HB_HIP(hipEventRecord(ev[3], st));
+    HB_HIP(hipEventRecord(ev[4], st));
+  } else {
+    // ---- leaf SVD re-compression
+    DevMem lvl_mem;
+    lvl_mem.st = st;
+    std::vector<Block> cur(nleaves);
+    std::vector<RecJob> rj;
+    for (size_t i = 0; i < nleaves; ++i)
+      rj.push_back(RecJob{leafblk[i].U, leafblk[i].Vh, leafblk[i].m, leafblk[i].n, leafblk[i].r, &cur[i]});
+    run_recompress(Eng, rj, lvl_mem);
+    baca_mem.release();
+    HB_HIP(hipEventRecord(ev[3], st));
+    for (size_t i = 0; i < nleaves; ++i) {
+      R->leaves[i].rank_leaf = cur[i].r;
+      S.leaf_rank_max = std::max(S.leaf_rank_max, cur[i].r);
+    }
+    S.step_rank_max[0] = S.leaf_rank_max;
+    if (P.stop_after == 2) {
+      for (void* p : lvl_mem.ptrs) R->keep.ptrs.push_back(p);
+      lvl_mem.ptrs.clear();
+      R->out_blocks = cur;
+      S.n_blocks = (int32_t)nleaves;
+    } else {
+      // ---- merges: per problem a map (t, v) -> block at the current depth
+      std::vector<std::vector<Block>> blk(np);
+      std::vector<int> depth(np);
+      {
+        size_t i = 0;
+        for (size_t p = 0; p < np; ++p) {
+          const int nb = 1 << R->problems[p].L;
+          blk[p].assign(cur.begin() + i, cur.begin() + i + (size_t)nb * nb);
+          depth[p] = R->problems[p].L;
+          i += (size_t)nb * nb;
+        }
+      }
+      DevMem* prev_mem = &lvl_mem;
+      std::vector<std::unique_ptr<DevMem>> mems;
+      int step = 0;
+      for (int l = 1; l <= Lmax; ++l) {
+        // horizontal: (tau_i, nu) from (tau_i, nu_1) and (tau_i, nu_2)
+        std::unique_ptr<DevMem> hm(new DevMem());
+        hm->st = st;
+        std::vector<std::vector<Block>> hb(np);
+        std::vector<MergeJob> jobs;
+        for (size_t p = 0; p < np; ++p) {
+          if (depth[p] < 1) continue;
+          const int nbc = 1 << depth[p];
+          const int nbp = nbc / 2;
+          hb[p].assign((size_t)nbc * nbp, Block{});
+          for (int ti = 0; ti < nbc; ++ti)
+            for (int v = 0; v < nbp; ++v) {
+              const Block& b1 = blk[p][(size_t)ti * nbc + 2 * v];
+              const Block& b2 = blk[p][(size_t)ti * nbc + 2 * v + 1];
+              MergeJob J{};
+              J.rows = b1.m;
+              J.P1 = b1.U; J.r1 = b1.r; J.S1 = b1.S;
+              J.P2 = b2.U; J.r2 = b2.r; J.S2 = b2.S;
+              J.O1 = b1.Vh; J.n1 = b1.n;
+              J.O2 = b2.Vh; J.n2 = b2.n;
+              J.p_is_u = true;
+              J.outP_owner = &hb[p][(size_t)ti * nbp + v];
+              jobs.push_back(J);
+            }
+        }
+        run_merges(Eng, jobs, *hm);
+        int mx = 0;
+        for (auto& J : jobs) mx = std::max(mx, J.outP_owner->r);
+        S.step_rank_max[std::min(++step, 63)] = mx;
+        prev_mem->release();
+        // vertical: (tau, nu) from (tau_1, nu) and (tau_2, nu)
+        std::unique_ptr<DevMem> vm(new DevMem());
+        vm->st = st;
+        jobs.clear();
+        std::vector<std::vector<Block>> vb(np);
+        for (size_t p = 0; p < np; ++p) {
+          if (depth[p] < 1) continue;
+          const int nbc = 1 << depth[p];
+          const int nbp = nbc / 2;
+          vb[p].assign((size_t)nbp * nbp, Block{});
+          for (int t = 0; t < nbp; ++t)
+            for (int v = 0; v < nbp; ++v) {
+              const Block& b1 = hb[p][(size_t)(2 * t) * nbp + v];
+              const Block& b2 = hb[p][(size_t)(2 * t + 1) * nbp + v];
+              MergeJob J{};
+              J.rows = b1.n;
+              J.P1 = b1.Vh; J.r1 = b1.r; J.S1 = b1.S;
+              J.P2 = b2.Vh; J.r2 = b2.r; J.S2 = b2.S;
+              J.O1 = b1.U; J.n1 = b1.m;
+              J.O2 = b2.U; J.n2 = b2.m;
+              J.p_is_u = false;
+              J.outP_owner = &vb[p][(size_t)t * nbp + v];
+              jobs.push_back(J);
+            }
+        }
+        run_merges(Eng, jobs, *vm);
+        mx = 0;
+        for (auto& J : jobs) mx = std::max(mx, J.outP_owner->r);
+        S.step_rank_max[std::min(++step, 63)] = mx;
+        hm->release();
+        for (size_t p = 0; p < np; ++p)
+          if (depth[p] >= 1) {
+            blk[p] = vb[p];
+            depth[p] -= 1;
+          }
+        mems.push_back(std::move(vm));
+        prev_mem = mems.back().get();
+        if (mems.size() > 1) mems.front()->release();
+        tmp.release();
+      }
+      S.n_steps = step + 1;
+      // roots: keep their memory
+      for (auto& m : mems)
+        for (void* p : m->ptrs) R->keep.ptrs.push_back(p);
+      for (auto& m : mems) m->ptrs.clear();
+      if (mems.empty()) {
+        for (void* p : lvl_mem.ptrs) R->keep.ptrs.push_back(p);
+        lvl_mem.ptrs.clear();
+      }
+      for (size_t p = 0; p < np; ++p) {
+        R->problems[p].root = blk[p][0];
+        R->out_blocks.push_back(blk[p][0]);
+      }
+    }
+    HB_HIP(hipEventRecord(ev[4], st));
+  }
+  HB_HIP(hipEventRecord(ev[5], st));
+  HB_HIP(hipStreamSynchronize(st));
+  S.ms_setup = elapsed(ev[0], ev[1]);
+  S.ms_baca = elapsed(ev[1], ev[2]);
+  S.ms_recompress = elapsed(ev[2], ev[3]);
+  S.ms_merge = elapsed(ev[3], ev[4]);
+  S.ms_total = elapsed(ev[0], ev[5]);
+  tmp.release();
+  *out = R.release();
+  return HB_OK;
+}
+
+static hb_status guarded(const CallSpec& c, hb_result** out) {
+  try {
+    return run(c, out);
+  } catch (const HbError& e) {
+    if (out) *out = nullptr;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    if (out) *out = nullptr;
+    return HB_ENOMEM;
+  } catch (...) {
+    if (out) *out = nullptr;
+    return HB_EDEVICE;
+  }
+}
+
+}  // namespace
+
+// ============================================================== C ABI =======
+extern "C" {
+
+hb_status hbaca_compress(int entry_fn_id, const hb_params* params, const double* points_row,
+                         const double* points_col, int64_t m, int64_t n, double tol, int32_t d,
+                         int32_t leaf, void* stream, hb_result** out) {
+  if (out) *out = nullptr;
+  if (!out || m < 1 || n < 1) return HB_EINVAL;
+  CallSpec c;
+  c.entry = entry_fn_id;
+  c.prm = params;
+  c.X = points_row;
+  c.Y = points_col;
+  c.nx = m;
+  c.ny = n;
+  c.roff = {0};
+  c.rcnt = {m};
+  c.coff = {0};
+  c.ccnt = {n};
+  c.tol = tol;
+  c.d = d;
+  c.leaf = leaf;
+  c.st = (hipStream_t)stream;
+  c.batched = false;
+  return guarded(c, out);
+}
+
+hb_status hbaca_compress_batched(int entry_fn_id, const hb_params* params, int64_t nblocks,
+                                 const double* points_row, const int64_t* row_off,
+                                 const int64_t* row_cnt, const double* points_col,
+                                 const int64_t* col_off, const int64_t* col_cnt, double tol,
+                                 int32_t d, int32_t leaf, void* stream, hb_result** out) {
+  if (out) *out = nullptr;
+  if (!out || nblocks < 1 || !row_off || !row_cnt || !col_off || !col_cnt) return HB_EINVAL;
+  CallSpec c;
+  c.entry = entry_fn_id;
+  c.prm = params;
+  c.X = points_row;
+  c.Y = points_col;
+  c.nx = 0;
+  c.ny = 0;
+  for (int64_t b = 0; b < nblocks; ++b) {
+    c.roff.push_back(row_off[b]);
+    c.rcnt.push_back(row_cnt[b]);
+    c.coff.push_back(col_off[b]);
+    c.ccnt.push_back(col_cnt[b]);
+    c.nx = std::max(c.nx, row_off[b] + row_cnt[b]);
+    c.ny = std::max(c.ny, col_off[b] + col_cnt[b]);
+  }
+  c.tol = tol;
+  c.d = d;
+  c.leaf = leaf;
+  c.st = (hipStream_t)stream;
+  c.batched = true;
+  return guarded(c, out);
+}
+
+int64_t hb_result_nblocks(const hb_result* r) { return r ? (int64_t)r->out_blocks.size() : -1; }
+int64_t hb_result_rank(const hb_result* r, int64_t b) {
+  if (!r || b < 0 || b >= (int64_t)r->out_blocks.size()) return -1;
+  return r->out_blocks[b].r;
+}
+int64_t hb_result_rows(const hb_result* r, int64_t b) {
+  if (!r || b < 0 || b >= (int64_t)r->out_blocks.size()) return -1;
+  return r->out_blocks[b].m;
+}
+int64_t hb_result_cols(const hb_result* r, int64_t b) {
+  if (!r || b < 0 || b >= (int64_t)r->out_blocks.size()) return -1;
+  return r->out_blocks[b].n;
+}
+int32_t hb_result_is_complex(const hb_result* r) { return r ? r->scalar : -1; }
+
+hb_status hb_result_copy(const hb_result* r, int64_t b, void* U, double* sigma, void* Vh,
+                         void* stream) {
+  if (!r || b < 0 || b >= (int64_t)r->out_blocks.size()) return HB_EINVAL;
+  const Block& B = r->out_blocks[b];
+  if (B.r == 0) return HB_OK;
+  const size_t sb = scalar_bytes(r->scalar);
+  hipStream_t st = (hipStream_t)stream;
+  if (U && hipMemcpyAsync(U, B.U, (size_t)B.m * B.r * sb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return HB_EDEVICE;
+  if (Vh && hipMemcpyAsync(Vh, B.Vh, (size_t)B.n * B.r * sb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return HB_EDEVICE;
+  if (sigma && hipMemcpyAsync(sigma, B.S, (size_t)B.r * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return HB_EDEVICE;
+  return HB_OK;
+}
+
+hb_status hb_result_stats(const hb_result* r, hb_stats* out) {
+  if (!r || !out) return HB_EINVAL;
+  *out = r->stats;
+  return HB_OK;
+}
+
+int64_t hb_result_nleaves(const hb_result* r) { return r ? (int64_t)r->leaves.size() : -1; }
+
+hb_status hb_result_leaf_info(const hb_result* r, int64_t leaf, int64_t* info) {
+  if (!r || !info || leaf < 0 || leaf >= (int64_t)r->leaves.size()) return HB_EINVAL;
+  const LeafHost& L = r->leaves[leaf];
+  const Problem& P = r->problems[L.problem];
+  info[0] = L.problem;
+  info[1] = L.t;
+  info[2] = L.v;
+  info[3] = L.row0 - P.row_base;
+  info[4] = L.col0 - P.col_base;
+  info[5] = L.m0;
+  info[6] = L.n0;
+  info[7] = L.rank_baca;
+  info[8] = L.rank_leaf;
+  info[9] = L.iters;
+  info[10] = L.status;
+  info[11] = (int64_t)L.tape_rows.size();
+  return HB_OK;
+}
+
+hb_status hb_result_leaf_tape(const hb_result* r, int64_t leaf, int32_t* rows, int32_t* cols,
+                              int32_t* dk, double* nu, double* mu) {
+  if (!r || leaf < 0 || leaf >= (int64_t)r->leaves.size()) return HB_EINVAL;
+  const LeafHost& L = r->leaves[leaf];
+  if (L.tape_rows.size() != (size_t)L.rank_baca) return HB_EINVAL;  // no tape recorded
+  if (rows) std::memcpy(rows, L.tape_rows.data(), L.tape_rows.size() * 4);
+  if (cols) std::memcpy(cols, L.tape_cols.data(), L.tape_cols.size() * 4);
+  if (dk) std::memcpy(dk, L.it_dk.data(), L.it_dk.size() * 4);
+  if (nu) std::memcpy(nu, L.it_nu.data(), L.it_nu.size() * 8);
+  if (mu) std::memcpy(mu, L.it_mu.data(), L.it_mu.size() * 8);
+  return HB_OK;
+}
+
+hb_status hb_result_error(const hb_result* r, int64_t b, int64_t stride, double* err2, double* ref2,
+                          void* stream) {
+  if (!r || !err2 || !ref2 || stride < 1 || b < 0 || b >= (int64_t)r->out_blocks.size())
+    return HB_EINVAL;
+  try {
+    const Block& B = r->out_blocks[b];
+    int64_t rb = 0, cb = 0;
+    if (r->out_blocks.size() == r->problems.size()) {
+      rb = r->problems[b].row_base;
+      cb = r->problems[b].col_base;
+    } else {
+      rb = r->leaves[b].row0;
+      cb = r->leaves[b].col0;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    DevMem mem;
+    mem.st = st;
+    const int64_t nrows_s = (B.m + stride - 1) / stride;
+    dim3 grid((unsigned)((B.n + 255) / 256), (unsigned)std::min<int64_t>(nrows_s, 64));
+    double* part = mem.get<double>((size_t)2 * grid.x * grid.y);
+    const double* S = B.S;
+    if (r->scalar == 0)
+      hipLaunchKernelGGL((error_kernel<double>), grid, dim3(256), 0, st, r->E, rb, cb, B.m, B.n,
+                         (const double*)B.U, S, (const double*)B.Vh, B.r, stride, nrows_s, part);
+    else
+      hipLaunchKernelGGL((error_kernel<hb_cplx>), grid, dim3(256), 0, st, r->E, rb, cb, B.m, B.n,
+                         (const hb_cplx*)B.U, S, (const hb_cplx*)B.Vh, B.r, stride, nrows_s, part);
+    HB_HIP(hipGetLastError());
+    std::vector<double> h((size_t)2 * grid.x * grid.y);
+    HB_HIP(hipMemcpyAsync(h.data(), part, h.size() * 8, hipMemcpyDeviceToHost, st));
+    HB_HIP(hipStreamSynchronize(st));
+    double e = 0, a = 0;
+    for (size_t i = 0; i < h.size(); i += 2) {
+      e += h[i];
+      a += h[i + 1];
+    }
+    *err2 = e;
+    *ref2 = a;
+    return HB_OK;
+  } catch (const HbError& e) {
+    return e.st;
+  }
+}
+
+void hb_result_free(hb_result* r) {
+  if (!r) return;
+  (void)hipDeviceSynchronize();
+  delete r;
+}
+
+const char* hb_status_string(hb_status s) {
+  switch (s) {
+    case HB_OK: return "ok";
+    case HB_EINVAL: return "invalid argument";
+    case HB_ENOMEM: return "device allocation failed";
+    case HB_EDEVICE: return "HIP call or kernel launch failed";
+    case HB_ERANKCAP: return "a leaf needed more columns than rank_cap";
+    case HB_ENONFINITE: return "non-finite scalar parameter";
+    case HB_EUNSUPPORTED: return "size or option outside the built kernels";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

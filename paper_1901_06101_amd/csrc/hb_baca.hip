@@ -1,0 +1,652 @@
+// Blocked adaptive cross approximation of one leaf per workgroup
+// (Algorithm 2 of the paper, with its LRID, LRnorm and LRnormUp functions).
+//
+// Layout and work split (512 threads = 8 wave64s per leaf):
+//  * the factors live in HBM: U (m0 x cap) and Vh = V^H (n0 x cap), both
+//    column-major, so a wave reading one column touches consecutive rows;
+//  * the residual column block C_k = A(:, J_k) - U V(:, J_k) is computed with
+//    one thread per row (RPT rows per thread), V(:, J_k) staged through LDS in
+//    tiles; it is written once to HBM scratch (U_k and W_k gather from it) and
+//    kept in registers as the QRCP panel that picks I_k (eq. (6));
+//  * the residual row block R_k = A(I_k, :) - U(I_k, :) V is computed with one
+//    thread per column and never leaves registers: it feeds V_k (eq. (9))
+//    and the QRCP panel that picks J_{k+1} (eq. (7));
+//  * QRCP(W_k, eps) (eq. (8)) runs in one wave, one column per lane;
+//  * the norm estimates (eqs. (11)-(13)) use the Gram blocks
+//    [U, U_k]^H U_k and [Vh, Vh_k]^H Vh_k, accumulated from LDS-staged row
+//    chunks with 4x2 register blocking and a deterministic cross-wave sum.
+//
+// Pivot choice follows the oracle's reading of QR(., d): exact trailing norms
+// after each Householder step, largest first, ties to the lowest index.
+#include "hb_common.h"
+#include "hb_entries.h"
+#include "hb_internal.h"
+
+namespace {
+
+constexpr int NT = 512;
+constexpr int NW = NT / HB_WAVE;
+
+template <typename T, int DMAX>
+struct GramCfg {
+  static constexpr int CB = DMAX / 2;       // column blocks of 2
+  static constexpr int TB = HB_WAVE / CB;   // row blocks of 4
+  static constexpr int GT = 4 * TB;         // t-tile width
+  static constexpr int GCH = 16;            // rows per staged chunk
+};
+
+// G[tt * DMAX + c] = sum_i conj(X(i, t0 + tt)) * X(i, k0 + c), tt < tw, c < dk.
+// X is column-major with leading dimension ld and `nrows` rows.  The result
+// lands in sG (GT x DMAX).  All threads of the block must call it.
+template <typename T, int DMAX>
+__device__ void gram_tile(const T* __restrict__ X, int64_t ld, int nrows, int t0, int tw, int k0,
+                          int dk, T* sXs, T* sKs, T* sG) {
+  using C = GramCfg<T, DMAX>;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tb = lane % C::TB, cb = lane / C::TB;
+  T acc[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = sc_zero<T>();
+#pragma unroll 1
+  for (int i0 = 0; i0 < nrows; i0 += C::GCH) {
+    __syncthreads();
+    for (int e = tid; e < C::GCH * C::GT; e += NT) {
+      const int ii = e % C::GCH, tt = e / C::GCH, i = i0 + ii;
+      sXs[ii * C::GT + tt] = (i < nrows && tt < tw) ? X[(int64_t)(t0 + tt) * ld + i] : sc_zero<T>();
+    }
+    for (int e = tid; e < C::GCH * DMAX; e += NT) {
+      const int ii = e % C::GCH, c = e / C::GCH, i = i0 + ii;
+      sKs[ii * DMAX + c] = (i < nrows && c < dk) ? X[(int64_t)(k0 + c) * ld + i] : sc_zero<T>();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < C::GCH / NW; ++q) {
+      const int ii = wid * (C::GCH / NW) + q;
+      T xa[4], kb[2];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) xa[a] = sXs[ii * C::GT + 4 * tb + a];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) kb[b] = sKs[ii * DMAX + 2 * cb + b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) sc_cfma(acc[a][b], xa[a], kb[b]);
+    }
+  }
+  // deterministic cross-wave sum: wave 0 writes, waves 1..7 add in order
+  for (int w = 0; w < NW; ++w) {
+    __syncthreads();
+    if (wid == w) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int idx = (4 * tb + a) * DMAX + 2 * cb + b;
+          sG[idx] = (w == 0) ? acc[a][b] : sc_add(sG[idx], acc[a][b]);
+        }
+    }
+  }
+  __syncthreads();
+}
+
+// Upper Cholesky factor in place (G = T^H T, T stored over G's upper part);
+// returns false on a pivot <= 0.  Single thread.
+template <typename T, int DMAX>
+__device__ bool chol_upper(T* G, int n) {
+  for (int j = 0; j < n; ++j) {
+    double s = sc_re(G[j * DMAX + j]);
+    for (int k = 0; k < j; ++k) s -= sc_abs2(G[k * DMAX + j]);
+    if (!(s > 0.0)) return false;
+    const double d = sqrt(s);
+    G[j * DMAX + j] = sc_real<T>(d);
+    for (int c = j + 1; c < n; ++c) {
+      T v = G[j * DMAX + c];
+      for (int k = 0; k < j; ++k) v = sc_sub(v, sc_cmul(G[k * DMAX + j], G[k * DMAX + c]));
+      G[j * DMAX + c] = sc_scale(v, 1.0 / d);
+    }
+  }
+  return true;
+}
+
+// Greedy QRCP pivot selection over a register-resident panel (Algorithm 2,
+// lines selecting I_k and J_{k+1}).  Each thread owns RPT candidates (index
+// tid + s * NT) with panel vectors x[s][0..nrow).  `excl[idx] != 0` removes a
+// candidate.  Writes the nsel chosen indices to out[].  Destroys x.
+template <typename T, int DMAX, int RPT>
+__device__ void qrcp_select(T (&x)[RPT][DMAX], int ncand_total, const unsigned char* excl,
+                            int nrow, int nsel, int* out, T* sPiv, double (*redv)[NW],
+                            int (*redi)[NW]) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  bool picked[RPT];
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) picked[s] = false;
+#pragma unroll 1
+  for (int st = 0; st < nsel; ++st) {
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int i = tid + s * NT;
+      if (i < ncand_total && excl[i] == 0 && !picked[s]) {
+        double nv = 0.0;
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c)
+          if (c >= st && c < nrow) nv += sc_abs2(x[s][c]);
+        if (nv > bv || (nv == bv && i < bi)) {
+          bv = nv;
+          bi = i;
+        }
+      }
+    }
+    wave_argmax(bv, bi);
+    if (lane == 0) {
+      redv[st & 1][wid] = bv;
+      redi[st & 1][wid] = bi;
+    }
+    __syncthreads();
+    bv = redv[st & 1][0];
+    bi = redi[st & 1][0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      const double ov = redv[st & 1][w];
+      const int oi = redi[st & 1][w];
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      if (tid + s * NT == bi) {
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c)
+          if (c >= st && c < nrow) sPiv[c] = x[s][c];
+        picked[s] = true;
+      }
+    }
+    if (tid == 0) out[st] = bi;
+    __syncthreads();
+    // Householder reflector of the pivot's trailing part, applied to the rest
+    double sig2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < DMAX; ++c)
+      if (c >= st && c < nrow) sig2 += sc_abs2(sPiv[c]);
+    const double sigma = sqrt(sig2);
+    if (sigma > 0.0 && st + 1 < nsel) {
+      const T x0 = sPiv[st];
+      const double a0 = sqrt(sc_abs2(x0));
+      const T alpha = sc_scale(sc_phase(x0), -sigma);
+      const double beta = 1.0 / (sigma * (sigma + a0));
+      const T v0 = sc_sub(x0, alpha);
+#pragma unroll
+      for (int s = 0; s < RPT; ++s) {
+        const int i = tid + s * NT;
+        if (i < ncand_total && excl[i] == 0 && !picked[s]) {
+          T w = sc_zero<T>();
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c)
+            if (c >= st && c < nrow) sc_cfma(w, c == st ? v0 : sPiv[c], x[s][c]);
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c)
+            if (c >= st && c < nrow) sc_axpy_neg(x[s][c], beta, c == st ? v0 : sPiv[c], w);
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int DMAX, int RPT>
+__global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
+  using C = GramCfg<T, DMAX>;
+  constexpr int TILE = 32;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const BacaLeafDev L = A.leaves[blockIdx.x];
+  const int m0 = L.m0, n0 = L.n0, cap = L.cap;
+  const int rmax = min(m0, n0);
+  T* __restrict__ U = (T*)A.U + L.u_off;
+  T* __restrict__ Vh = (T*)A.V + L.v_off;
+  T* __restrict__ Cg = (T*)A.C + L.c_off;
+  T* __restrict__ Rg = (T*)A.R + L.r_off;
+  const double eps = A.eps;
+  const int dim = A.E.dim;
+
+  __shared__ int sJ[DMAX], sI[DMAX], sJbar[DMAX];
+  __shared__ int sDK, sNJ;
+  __shared__ unsigned char used_r[NT * RPT], used_c[NT * RPT];
+  __shared__ double redv[2][NW];
+  __shared__ int redi[2][NW];
+  __shared__ double redd[NW];
+  __shared__ T sPiv[DMAX];
+  __shared__ T sRefl[DMAX * DMAX];
+  __shared__ double sBeta[DMAX];
+  __shared__ T sTm[DMAX * DMAX];
+  __shared__ double sTabs[DMAX];
+  __shared__ double sPts[DMAX * HB_MAXDIM];
+  __shared__ T sTile[DMAX * TILE];
+  __shared__ T sXs[C::GCH * C::GT];
+  __shared__ T sKs[C::GCH * DMAX];
+  __shared__ T sG[C::GT * DMAX];
+  __shared__ T sGU[C::GT * DMAX];
+  __shared__ T sGUd[DMAX * DMAX];
+  __shared__ T sGVd[DMAX * DMAX];
+  __shared__ double sScal[2];
+
+  for (int i = tid; i < NT * RPT; i += NT) {
+    used_r[i] = 0;
+    used_c[i] = 0;
+  }
+  if (tid < DMAX) sJ[tid] = (tid < L.nj1) ? A.j1[L.j1_off + tid] : 0;
+  if (tid == 0) sNJ = L.nj1;
+  __syncthreads();
+
+  double mu2 = 0.0;
+  int r = 0, iter = 0, status = 0;
+
+  while (true) {
+    const int nJ = sNJ;
+    if (r + min(nJ, m0 - r) > cap) {
+      status = 1;
+      break;
+    }
+    // ------------------------------------------------ C_k = A(:,J) - U V(:,J)
+    if (tid < nJ * dim) {
+      const int c = tid / dim, q = tid % dim;
+      sPts[c * HB_MAXDIM + q] = A.E.Y[(int64_t)q * A.E.ldy + L.col0 + sJ[c]];
+    }
+    __syncthreads();
+    // entries A(:, J_k) straight to the scratch block
+#pragma unroll 1
+    for (int s = 0; s < RPT; ++s) {
+      const int i = tid + s * NT;
+      if (i < m0) {
+        double xi[HB_MAXDIM];
+#pragma unroll
+        for (int q = 0; q < HB_MAXDIM; ++q)
+          xi[q] = q < dim ? A.E.X[(int64_t)q * A.E.ldx + L.row0 + i] : 0.0;
+#pragma unroll 1
+        for (int c = 0; c < nJ; ++c)
+          Cg[(int64_t)c * m0 + i] =
+              eval_entry<T>(A.E, L.row0 + i, L.col0 + sJ[c], xi, &sPts[c * HB_MAXDIM]);
+      }
+    }
+    T x[RPT][DMAX];
+#pragma unroll
+    for (int s = 0; s < RPT; ++s)
+#pragma unroll
+      for (int c = 0; c < DMAX; ++c) x[s][c] = sc_zero<T>();
+    for (int t0 = 0; t0 < r; t0 += TILE) {
+      const int tw = min(TILE, r - t0);
+      __syncthreads();
+      for (int e = tid; e < nJ * TILE; e += NT) {
+        const int c = e / TILE, tt = e % TILE;
+        sTile[c * TILE + tt] =
+            tt < tw ? sc_conj(Vh[(int64_t)(t0 + tt) * n0 + sJ[c]]) : sc_zero<T>();
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < RPT; ++s) {
+        const int i = tid + s * NT;
+        if (i < m0) {
+#pragma unroll 2
+          for (int tt = 0; tt < tw; ++tt) {
+            const T u = U[(int64_t)(t0 + tt) * m0 + i];
+#pragma unroll
+            for (int c = 0; c < DMAX; ++c)
+              if (c < nJ) sc_fma(x[s][c], u, sTile[c * TILE + tt]);
+          }
+        }
+      }
+    }
+    // C_k = A(:, J_k) - U V(:, J_k); the panel is its conjugate transpose
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int i = tid + s * NT;
+      if (i < m0) {
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) {
+          if (c < nJ) {
+            const T cv = sc_sub(Cg[(int64_t)c * m0 + i], x[s][c]);
+            Cg[(int64_t)c * m0 + i] = cv;
+            x[s][c] = sc_conj(cv);
+          }
+        }
+      }
+    }
+    // ------------------------------------------------ I_k = QR(C^H, d) (eq. (6))
+    const int nI = min(nJ, m0 - r);
+    qrcp_select<T, DMAX, RPT>(x, m0, used_r, nJ, nI, sI, sPiv, redv, redi);
+    // (the last select step ends with a barrier, so sI is visible)
+
+    // ------------------------------------------------ R_k = A(I,:) - U(I,:) V
+    if (tid < nI * dim) {
+      const int c = tid / dim, q = tid % dim;
+      sPts[c * HB_MAXDIM + q] = A.E.X[(int64_t)q * A.E.ldx + L.row0 + sI[c]];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int s = 0; s < RPT; ++s) {
+      const int j = tid + s * NT;
+      if (j < n0) {
+        double yj[HB_MAXDIM];
+#pragma unroll
+        for (int q = 0; q < HB_MAXDIM; ++q)
+          yj[q] = q < dim ? A.E.Y[(int64_t)q * A.E.ldy + L.col0 + j] : 0.0;
+#pragma unroll 1
+        for (int c = 0; c < nI; ++c)
+          Rg[(int64_t)c * n0 + j] =
+              eval_entry<T>(A.E, L.row0 + sI[c], L.col0 + j, &sPts[c * HB_MAXDIM], yj);
+      }
+    }
+    {
+      T y[RPT][DMAX];
+#pragma unroll
+      for (int s = 0; s < RPT; ++s)
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) y[s][c] = sc_zero<T>();
+      for (int t0 = 0; t0 < r; t0 += TILE) {
+        const int tw = min(TILE, r - t0);
+        __syncthreads();
+        for (int e = tid; e < nI * TILE; e += NT) {
+          const int c = e / TILE, tt = e % TILE;
+          sTile[c * TILE + tt] = tt < tw ? U[(int64_t)(t0 + tt) * m0 + sI[c]] : sc_zero<T>();
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < RPT; ++s) {
+          const int j = tid + s * NT;
+          if (j < n0) {
+#pragma unroll 2
+            for (int tt = 0; tt < tw; ++tt) {
+              const T vc = sc_conj(Vh[(int64_t)(t0 + tt) * n0 + j]);
+#pragma unroll
+              for (int c = 0; c < DMAX; ++c)
+                if (c < nI) sc_fma(y[s][c], sTile[c * TILE + tt], vc);
+            }
+          }
+        }
+      }
+      // R_k = A(I_k, :) - U(I_k, :) V, kept transposed in the scratch block
+#pragma unroll
+      for (int s = 0; s < RPT; ++s) {
+        const int j = tid + s * NT;
+        if (j < n0) {
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c)
+            if (c < nI) Rg[(int64_t)c * n0 + j] = sc_sub(Rg[(int64_t)c * n0 + j], y[s][c]);
+        }
+      }
+    }
+    // ------------------------------------------------ W_k and QR(W_k, eps) (eq. (8))
+    if (wid == 0) {
+      T w[DMAX];
+      bool rem = lane < nJ;
+#pragma unroll
+      for (int c = 0; c < DMAX; ++c)
+        w[c] = (lane < nJ && c < nI) ? Cg[(int64_t)lane * m0 + sI[c]] : sc_zero<T>();
+      const int q = min(nI, nJ);
+#pragma unroll 1
+      for (int st = 0; st < q; ++st) {
+        double bv = -1.0;
+        if (rem) {
+          bv = 0.0;
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c)
+            if (c >= st && c < nI) bv += sc_abs2(w[c]);
+        }
+        int bi = rem ? lane : 0x7fffffff;
+        wave_argmax(bv, bi);
+        const int p = bi;
+        // the pivot column's entries are broadcast from lane p on use
+        double sig2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) {
+          const T pc = sc_shfl(w[c], p);
+          if (c >= st && c < nI) sig2 += sc_abs2(pc);
+        }
+        const double sigma = sqrt(sig2);
+        T x0 = sc_zero<T>();
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) {
+          const T pc = sc_shfl(w[c], p);
+          if (c == st) x0 = pc;
+        }
+        T alpha = sc_zero<T>();
+        double beta = 0.0;
+        if (sigma > 0.0) {
+          alpha = sc_scale(sc_phase(x0), -sigma);
+          beta = 1.0 / (sigma * (sigma + sqrt(sc_abs2(x0))));
+        }
+        const T v0 = sc_sub(x0, alpha);
+        {
+          T ww = sc_zero<T>();
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) {
+            const T pc = sc_shfl(w[c], p);
+            if (c >= st && c < nI) sc_cfma(ww, c == st ? v0 : pc, w[c]);
+          }
+          const bool upd = rem && lane != p && beta != 0.0;
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) {
+            const T pc = sc_shfl(w[c], p);
+            if (upd && c >= st && c < nI) sc_axpy_neg(w[c], beta, c == st ? v0 : pc, ww);
+            if (lane == 0 && c >= st && c < nI) sRefl[st * DMAX + c] = (c == st) ? v0 : pc;
+          }
+        }
+        if (lane == p) {
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) {
+            if (c == st) w[c] = alpha;
+            if (c > st) w[c] = sc_zero<T>();
+          }
+          rem = false;
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c)
+            if (c <= st) sTm[c * DMAX + st] = w[c];
+        }
+        if (lane == 0) {
+          sBeta[st] = beta;
+          sTabs[st] = sigma;
+          sJbar[st] = p;
+        }
+      }
+      if (lane == 0) {
+        int dk = 0;
+        if (q > 0 && sTabs[0] > 0.0)
+          while (dk < q && sTabs[dk] >= eps * sTabs[0]) ++dk;
+        sDK = dk;
+      }
+    }
+    __syncthreads();
+    const int dk = sDK;
+    if (dk == 0) {
+      if (tid == 0) {
+        A.it_dk[L.it_off + iter] = 0;
+        A.it_nu[L.it_off + iter] = 0.0;
+        A.it_mu[L.it_off + iter] = sqrt(mu2);
+      }
+      ++iter;
+      break;
+    }
+    // ------------------------------------------------ V_k = T11^-1 Q1^H R_k (eq. (9))
+#pragma unroll 1
+    for (int s = 0; s < RPT; ++s) {
+      const int j = tid + s * NT;
+      if (j < n0) {
+        T z[DMAX];
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) z[c] = c < nI ? Rg[(int64_t)c * n0 + j] : sc_zero<T>();
+#pragma unroll 1
+        for (int st = 0; st < dk; ++st) {
+          T ww = sc_zero<T>();
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c)
+            if (c >= st && c < nI) sc_cfma(ww, sRefl[st * DMAX + c], z[c]);
+          const double beta = sBeta[st];
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c)
+            if (c >= st && c < nI) sc_axpy_neg(z[c], beta, sRefl[st * DMAX + c], ww);
+        }
+#pragma unroll
+        for (int cc = DMAX - 1; cc >= 0; --cc) {
+          if (cc < dk) {
+            T sum = z[cc];
+#pragma unroll
+            for (int e = cc + 1; e < DMAX; ++e)
+              if (e < dk) sum = sc_sub(sum, sc_mul(sTm[cc * DMAX + e], z[e]));
+            z[cc] = sc_div(sum, sTm[cc * DMAX + cc]);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c)
+          if (c < dk) Vh[(int64_t)(r + c) * n0 + j] = sc_conj(z[c]);
+      }
+    }
+    // ------------------------------------------------ U_k = C_k(:, Jbar)
+#pragma unroll 1
+    for (int s = 0; s < RPT; ++s) {
+      const int i = tid + s * NT;
+      if (i < m0) {
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c)
+          if (c < dk) U[(int64_t)(r + c) * m0 + i] = Cg[(int64_t)sJbar[c] * m0 + i];
+      }
+    }
+    // ------------------------------------------------ pivots (eq. (10)) and exclusions
+    if (tid < dk) {
+      A.tape_rows[L.tape_off + r + tid] = sI[tid];
+      A.tape_cols[L.tape_off + r + tid] = sJ[sJbar[tid]];
+    }
+    if (tid < nJ) used_c[sJ[tid]] = 2;  // the whole current J leaves the next candidates
+    __syncthreads();
+    if (tid < dk) {
+      used_c[sJ[sJbar[tid]]] = 1;
+      used_r[sI[tid]] = 1;
+    }
+    // ------------------------------------------------ LRnorm / LRnormUp (eqs. (11)-(13))
+    double cross = 0.0;
+    const int ntot = r + dk;
+    for (int t0 = 0; t0 < ntot; t0 += C::GT) {
+      const int tw = min(C::GT, ntot - t0);
+      gram_tile<T, DMAX>(U, m0, m0, t0, tw, r, dk, sXs, sKs, sGU);
+      gram_tile<T, DMAX>(Vh, n0, n0, t0, tw, r, dk, sXs, sKs, sG);
+      double part = 0.0;
+      for (int e = tid; e < C::GT * DMAX; e += NT) {
+        const int tt = e / DMAX, c = e % DMAX, t = t0 + tt;
+        if (tt < tw && c < dk) {
+          if (t < r) {
+            part += sc_re(sc_mulc(sGU[e], sG[e]));
+          } else {
+            sGUd[(t - r) * DMAX + c] = sGU[e];
+            sGVd[(t - r) * DMAX + c] = sG[e];
+          }
+        }
+      }
+      cross += block_sum<NT>(part, redd);
+    }
+    if (tid == 0) {
+      // sGUd / sGVd hold U_k^H U_k and Vh_k^H Vh_k (dk x dk, Hermitian)
+      double fb = 0.0;  // tr(G_U G_V): the breakdown fallback
+      for (int a = 0; a < dk; ++a)
+        for (int b = 0; b < dk; ++b) fb += sc_re(sc_mulc(sGUd[a * DMAX + b], sGVd[a * DMAX + b]));
+      const bool ok1 = chol_upper<T, DMAX>(sGUd, dk);
+      const bool ok2 = ok1 && chol_upper<T, DMAX>(sGVd, dk);
+      double nu2;
+      if (ok1 && ok2) {
+        // ||T1 T2^H||_F^2 with T1, T2 upper triangular
+        nu2 = 0.0;
+        for (int a = 0; a < dk; ++a)
+          for (int b = 0; b < dk; ++b) {
+            T s = sc_zero<T>();
+            const int k0 = a > b ? a : b;
+            for (int k = k0; k < dk; ++k) sc_fma(s, sGUd[a * DMAX + k], sc_conj(sGVd[b * DMAX + k]));
+            nu2 += sc_abs2(s);
+          }
+      } else {
+        nu2 = fb > 0.0 ? fb : 0.0;
+      }
+      sScal[0] = sqrt(nu2);
+      const double m2 = mu2 + nu2 + 2.0 * cross;
+      sScal[1] = m2 > 0.0 ? m2 : 0.0;
+    }
+    __syncthreads();
+    const double nu = sScal[0];
+    mu2 = sScal[1];
+    if (tid == 0) {
+      A.it_dk[L.it_off + iter] = dk;
+      A.it_nu[L.it_off + iter] = nu;
+      A.it_mu[L.it_off + iter] = sqrt(mu2);
+    }
+    ++iter;
+    r += dk;
+    // ------------------------------------------------ stopping test
+    int cnt = 0;
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int j = tid + s * NT;
+      if (j < n0 && used_c[j] == 0) ++cnt;
+    }
+    const int npc = (int)(block_sum<NT>((double)cnt, redd) + 0.5);
+    const bool stop = (nu < eps * sqrt(mu2)) || npc == 0 || r >= rmax;
+    if (stop) break;
+    // ------------------------------------------------ J_{k+1} = QR(R_k, d) (eq. (7))
+    const int nsel = min(nI, npc);
+    {
+      T y[RPT][DMAX];
+#pragma unroll
+      for (int s = 0; s < RPT; ++s) {
+        const int j = tid + s * NT;
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c)
+          y[s][c] = (j < n0 && c < nI) ? Rg[(int64_t)c * n0 + j] : sc_zero<T>();
+      }
+      qrcp_select<T, DMAX, RPT>(y, n0, used_c, nI, nsel, sJ, sPiv, redv, redi);
+    }
+    for (int i = tid; i < NT * RPT; i += NT)
+      if (used_c[i] == 2) used_c[i] = 0;
+    if (tid == 0) sNJ = nsel;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    BacaOutDev o;
+    o.rank = r;
+    o.iters = iter;
+    o.status = status;
+    o.pad = 0;
+    o.mu = sqrt(mu2);
+    A.out[blockIdx.x] = o;
+  }
+}
+
+}  // namespace
+
+namespace hbk {
+
+template <typename T, int DMAX, int RPT>
+static int launch_one(const BacaArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((baca_leaf_kernel<T, DMAX, RPT>), dim3(a.nleaves), dim3(NT), 0, st, a);
+  return (int)hipGetLastError();
+}
+
+int baca_launch(int scalar, int dmax, int rpt, const BacaArgs& a, hipStream_t st) {
+  if (a.nleaves == 0) return 0;
+#ifdef HB_ONLY_VARIANT
+#define HB_CASE(S, TY, D, R) \
+  if (HB_ONLY_VARIANT == S * 1000 + D * 10 + R && scalar == S && dmax == D && rpt == R) \
+    return launch_one<TY, D, R>(a, st);
+#else
+#define HB_CASE(S, TY, D, R) \
+  if (scalar == S && dmax == D && rpt == R) return launch_one<TY, D, R>(a, st);
+#endif
+  HB_CASE(0, double, 8, 1) HB_CASE(0, double, 8, 2) HB_CASE(0, double, 8, 4)
+  HB_CASE(0, double, 16, 1) HB_CASE(0, double, 16, 2) HB_CASE(0, double, 16, 4)
+  HB_CASE(0, double, 32, 1) HB_CASE(0, double, 32, 2)
+  HB_CASE(1, hb_cplx, 8, 1) HB_CASE(1, hb_cplx, 8, 2) HB_CASE(1, hb_cplx, 8, 4)
+  HB_CASE(1, hb_cplx, 16, 1) HB_CASE(1, hb_cplx, 16, 2)
+  HB_CASE(1, hb_cplx, 32, 1)
+#undef HB_CASE
+  return -1;
+}
+
+}  // namespace hbk

@@ -1,0 +1,139 @@
+// Kernels behind the SVD re-compression of BACA leaves and the hierarchical
+// merges (Algorithm 3; eqs. (14)-(15)).  Every step computes a truncated SVD
+// of a tall block B = [P1 diag(S1), P2 diag(S2)] (or a plain tall factor) as
+// Householder QR of B, then the SVD of the small triangular factor.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// A node of a tall-skinny QR (TSQR) tree.  Level-0 nodes hold up to MC rows
+// of B; a higher node stacks the R factors of up to MC / k children.
+struct QRNodeDev {
+  int32_t rows;    // stacked input rows (<= MC)
+  int32_t k;       // columns of B
+  int32_t steps;   // Householder steps = min(rows, k) = rows of this node's R
+  int32_t level0;  // 1: rows come from B, 0: rows come from child R factors
+  // level 0: B(row0 + i, j) = j < n1 ? P1(row0+i, j) * S1[j] : P2(row0+i, j-n1) * S2[j-n1]
+  const void* P1;
+  const void* P2;
+  const double* S1;  // may be null (scale 1)
+  const double* S2;
+  int64_t ld1, ld2, row0;
+  int32_t n1, n2;
+  // level > 0
+  int32_t child0, nchild;
+  // this node's storage: MC x k tile (column-major, ld MC) holding R above the
+  // diagonal and the reflectors on and below it; alpha = diag(R); beta
+  int64_t store;  // element offset into the tile arena
+  int32_t ab;     // offset into the alpha / beta arrays (k entries)
+  int32_t pad;
+};
+
+// Applying the tree's Q to Z = [Zin; 0]: one node per entry.
+struct QRApplyDev {
+  int32_t rows, steps, r;  // node rows, reflector count, columns of Z
+  int32_t pad;
+  int64_t store;
+  int32_t ab;
+  int32_t pad2;
+  const void* Zin;  // steps x r (column-major, ld ldin)
+  void* Zout;       // rows x r (column-major, ld ldout)
+  int64_t ldin, ldout;
+};
+
+// One small SVD: R (p x k) read from a TSQR top node or given explicitly.
+struct SVDJobDev {
+  int32_t p, k;       // R is p x k
+  int32_t from_node;  // 1: R from a TSQR node (store/ab), 0: explicit R
+  int32_t pad;
+  int64_t store;
+  int32_t ab;
+  int32_t pad2;
+  const void* R;   // explicit R, column-major ld p
+  void* A;         // workspace p x k (becomes X S), column-major ld p
+  void* Y;         // k x k right singular vectors (column-major, ld k)
+  double* S;       // k singular values (sorted descending on return)
+  int32_t* perm;   // k: sorted position -> column
+  int32_t* rank;   // eps-rank (output)
+  void* Xr;        // p x k output: X columns in sorted order (ld p)
+  void* Yr;        // k x k output: Y columns in sorted order (ld k)
+};
+
+// C(row, c) = sum_t A_b(row, t) * Y(t0_b + t, c) for the two diagonal blocks
+// of blockdiag(A1, A2) * Y (the "other side" of a merge).
+struct BlockGemmDev {
+  const void* A1;
+  const void* A2;
+  int64_t lda1, lda2;
+  int32_t n1, n2;  // rows of A1, A2
+  int32_t r1, r2;  // columns of A1, A2 (rows of the two Y blocks)
+  const void* Y;   // (r1 + r2) x r, column-major ld ldy
+  int64_t ldy;
+  int32_t r;
+  int32_t pad;
+  void* C;  // (n1 + n2) x r, column-major ld ldc
+  int64_t ldc;
+};
+
+// Partial products of a tall A^H B over a chunk of rows (the projection of a
+// merge whose second block is orthogonalised against the first).
+struct AhbJobDev {
+  const void* A;  // m x ka, ld m
+  const void* B;  // m x kb, ld m
+  int64_t m;
+  int32_t ka, kb;
+  void* part;     // nchunk x ka x kb partial sums (column-major ka x kb each)
+  void* out;      // ka x kb result (column-major)
+  int32_t nchunk;
+  int32_t pad;
+};
+
+// C = Cin + sgn * A * B with A tall (m x ka) and B small (ka x nc).
+struct TallGemmDev {
+  const void* Cin;  // m x nc, ld ldc (may equal C)
+  const void* A;    // m x ka, ld lda
+  const void* B;    // ka x nc, ld ldb
+  void* C;          // m x nc, ld ldc
+  int64_t m, lda, ldb, ldc;
+  int32_t ka, nc;
+  double sgn;
+};
+
+// R of a split merge.  The block "a" (orthonormal P_a, r_a columns) is kept
+// as a basis; block "b" is projected: P_b = P_a (M + M2) + Q_b R_b.  Rows of R
+// follow the basis [P_a, Q_b]; columns follow B = [P1 diag(S1), P2 diag(S2)].
+struct SplitRDev {
+  const double* S1;
+  const double* S2;
+  const void* M;   // r_a x r_b
+  const void* M2;  // r_a x r_b
+  int32_t r1, r2;
+  int32_t ra, rb, pb;
+  int32_t a_first;  // 1: block a is the first block
+  int64_t store;    // TSQR top node of the projected block (R_b), if pb > 0
+  int32_t ab;
+  int32_t pad2;
+  void* R;          // (ra + pb) x (r1 + r2), column-major
+};
+
+namespace hbk {
+// scalar: 0 double, 1 complex double
+int ahb_launch(int scalar, const AhbJobDev* jobs_dev, int njobs, int max_chunks, int max_ka,
+               int max_kb, hipStream_t st);
+int tall_gemm_launch(int scalar, const TallGemmDev* jobs_dev, int njobs, int64_t max_m,
+                     int max_ka, hipStream_t st);
+int split_r_launch(int scalar, const SplitRDev* jobs_dev, int njobs, const void* store,
+                   const void* alpha, hipStream_t st);
+int tsqr_factor_launch(int scalar, int kmax, const QRNodeDev* nodes_dev, int nnodes,
+                       const QRNodeDev* level_below_dev, void* store, void* alpha,
+                       double* beta, hipStream_t st);
+int tsqr_apply_launch(int scalar, int kmax, const QRApplyDev* jobs_dev, int njobs,
+                      const void* store, const double* beta, hipStream_t st);
+int svd_launch(int scalar, const SVDJobDev* jobs_dev, int njobs, int kmax_batch, int pmax_batch,
+               const void* store, const void* alpha, double eps, hipStream_t st);
+int block_gemm_launch(int scalar, const BlockGemmDev* jobs_dev, int njobs, int max_rows,
+                      int max_r, hipStream_t st);
+int tsqr_mc(int scalar, int kmax);
+int tsqr_kmax_for(int scalar, int k);
+}  // namespace hbk

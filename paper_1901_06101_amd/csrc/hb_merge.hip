@@ -1,0 +1,679 @@
+// Tall-skinny Householder QR (TSQR), one-sided Jacobi SVD and block
+// products used by the SVD re-compression of BACA leaves and the
+// hierarchical merges (Algorithm 3, eqs. (14)-(15)).
+//
+// TSQR: B (rows x k) is cut into chunks of MC = 256 rows; each chunk is
+// factored by one workgroup with the chunk held in registers (thread (j, q)
+// owns column j, rows q, q + NQ, ...; the NQ threads of a column are adjacent
+// lanes, so column norms and reflector dot products reduce with shuffles and
+// each Householder step needs a single barrier).  The R factors of up to
+// MC / k chunks are stacked and factored again, up to one root R.  Q is kept
+// implicitly as the reflectors of every node; Q Z is applied top-down.
+#include "hb_common.h"
+#include "hb_merge.h"
+
+#include <algorithm>
+
+namespace {
+
+constexpr int MC_ALL = 256;
+
+template <typename T>
+__device__ inline T node_R(const T* store, const T* alpha, const QRNodeDev& N, int i, int j) {
+  // R(i, j) of a factored node (i < steps, j < k)
+  if (i < j) return store[N.store + (int64_t)j * MC_ALL + i];
+  if (i == j) return alpha[N.ab + j];
+  return sc_zero<T>();
+}
+
+template <typename T, int KMAX, int NQ, int SEG>
+__global__ __launch_bounds__(KMAX* NQ) void tsqr_factor_kernel(const QRNodeDev* __restrict__ nodes,
+                                                              const QRNodeDev* __restrict__ below,
+                                                              T* __restrict__ store,
+                                                              T* __restrict__ alpha,
+                                                              double* __restrict__ beta) {
+  static_assert(NQ * SEG == MC_ALL, "chunk height");
+  constexpr int MC = MC_ALL;
+  const QRNodeDev N = nodes[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int q = tid % NQ, j = tid / NQ;
+  const int k = N.k, rows = N.rows, steps = N.steps;
+  __shared__ T sV[2][MC];
+  __shared__ double sB[2];
+
+  T x[SEG];
+#pragma unroll
+  for (int s = 0; s < SEG; ++s) x[s] = sc_zero<T>();
+  if (N.level0) {
+    if (j < k) {
+      const T* P;
+      int64_t ld;
+      int jj;
+      const double* S;
+      if (j < N.n1) {
+        P = (const T*)N.P1; ld = N.ld1; jj = j; S = N.S1;
+      } else {
+        P = (const T*)N.P2; ld = N.ld2; jj = j - N.n1; S = N.S2;
+      }
+      const double sc = S ? S[jj] : 1.0;
+#pragma unroll
+      for (int s = 0; s < SEG; ++s) {
+        const int rho = s * NQ + q;
+        if (rho < rows) x[s] = sc_scale(P[(int64_t)jj * ld + N.row0 + rho], sc);
+      }
+    }
+  } else if (j < k) {
+    int off = 0;
+    for (int c = 0; c < N.nchild; ++c) {
+      const QRNodeDev Cn = below[N.child0 + c];
+      const int pc = Cn.steps;
+#pragma unroll
+      for (int s = 0; s < SEG; ++s) {
+        const int rho = s * NQ + q;
+        if (rho >= off && rho < off + pc) x[s] = node_R<T>(store, alpha, Cn, rho - off, j);
+      }
+      off += pc;
+    }
+  }
+
+  int buf = 0;
+  for (int st = 0; st < steps; ++st) {
+    if (j == st) {
+      double part = 0.0;
+      T xs0 = sc_zero<T>();
+#pragma unroll
+      for (int s = 0; s < SEG; ++s) {
+        const int rho = s * NQ + q;
+        if (rho >= st) part += sc_abs2(x[s]);
+        if (rho == st) xs0 = x[s];
+      }
+      const double sig2 = group_sum<NQ>(part);
+      const T x0 = group_sum_sc<NQ>(xs0);
+      const double sigma = sqrt(sig2);
+      T al = sc_zero<T>();
+      double be = 0.0;
+      if (sigma > 0.0) {
+        al = sc_scale(sc_phase(x0), -sigma);
+        be = 1.0 / (sigma * (sigma + sqrt(sc_abs2(x0))));
+      }
+      const T v0 = sc_sub(x0, al);
+#pragma unroll
+      for (int s = 0; s < SEG; ++s) {
+        const int rho = s * NQ + q;
+        if (rho == st) x[s] = v0;
+        sV[buf][rho] = rho >= st ? x[s] : sc_zero<T>();
+      }
+      if (q == 0) {
+        sB[buf] = be;
+        alpha[N.ab + st] = al;
+        beta[N.ab + st] = be;
+      }
+    }
+    __syncthreads();
+    if (j > st && j < k) {
+      const double be = sB[buf];
+      if (be != 0.0) {
+        T w = sc_zero<T>();
+#pragma unroll
+        for (int s = 0; s < SEG; ++s) {
+          const int rho = s * NQ + q;
+          if (rho >= st) sc_cfma(w, sV[buf][rho], x[s]);
+        }
+        w = group_sum_sc<NQ>(w);
+#pragma unroll
+        for (int s = 0; s < SEG; ++s) {
+          const int rho = s * NQ + q;
+          if (rho >= st) sc_axpy_neg(x[s], be, sV[buf][rho], w);
+        }
+      }
+    }
+    buf ^= 1;
+  }
+  if (j < k) {
+#pragma unroll
+    for (int s = 0; s < SEG; ++s) store[N.store + (int64_t)j * MC + s * NQ + q] = x[s];
+  }
+}
+
+template <typename T, int KMAX, int NQ, int SEG>
+__global__ __launch_bounds__(KMAX* NQ) void tsqr_apply_kernel(const QRApplyDev* __restrict__ jobs,
+                                                             const T* __restrict__ store,
+                                                             const double* __restrict__ beta) {
+  constexpr int MC = MC_ALL;
+  constexpr int NTH = KMAX * NQ;
+  const QRApplyDev J = jobs[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int q = tid % NQ, j = tid / NQ;
+  const int rows = J.rows, steps = J.steps, r = J.r;
+  const T* Zin = (const T*)J.Zin;
+  T* Zout = (T*)J.Zout;
+  __shared__ T sV[2][MC];
+  __shared__ double sB[2];
+  T z[SEG];
+#pragma unroll
+  for (int s = 0; s < SEG; ++s) {
+    const int rho = s * NQ + q;
+    z[s] = (j < r && rho < steps) ? Zin[(int64_t)j * J.ldin + rho] : sc_zero<T>();
+  }
+  int buf = 0;
+  for (int st = steps - 1; st >= 0; --st) {
+    for (int e = tid; e < MC; e += NTH)
+      sV[buf][e] = (e >= st && e < rows) ? store[J.store + (int64_t)st * MC + e] : sc_zero<T>();
+    if (tid == 0) sB[buf] = beta[J.ab + st];
+    __syncthreads();
+    if (j < r) {
+      const double be = sB[buf];
+      if (be != 0.0) {
+        T w = sc_zero<T>();
+#pragma unroll
+        for (int s = 0; s < SEG; ++s) {
+          const int rho = s * NQ + q;
+          if (rho >= st) sc_cfma(w, sV[buf][rho], z[s]);
+        }
+        w = group_sum_sc<NQ>(w);
+#pragma unroll
+        for (int s = 0; s < SEG; ++s) {
+          const int rho = s * NQ + q;
+          if (rho >= st) sc_axpy_neg(z[s], be, sV[buf][rho], w);
+        }
+      }
+    }
+    buf ^= 1;
+  }
+  if (j < r) {
+#pragma unroll
+    for (int s = 0; s < SEG; ++s) {
+      const int rho = s * NQ + q;
+      if (rho < rows) Zout[(int64_t)j * J.ldout + rho] = z[s];
+    }
+  }
+}
+
+// ------------------------------------------------------------- Jacobi SVD --
+// One-sided (Hestenes) Jacobi on the columns of R (p x k) with the classic
+// round-robin pairing: k/2 disjoint column pairs per round, each rotated by
+// a group of G lanes.  Column norms are recomputed at the start of every
+// sweep and updated in closed form after each rotation (a' = a - t|g|,
+// b' = b + t|g|), so a pair costs one dot product.  Sweeps end when no pair
+// has |a_i^H a_j| > tol sqrt(|a_i|^2 |a_j|^2).  R and V live in LDS when they
+// fit (the common case), otherwise in the HBM workspace.
+constexpr int SVD_NT = 512;
+
+template <typename T, int G>
+__device__ void jacobi_rounds(T* A, int lda, T* Y, int ldy, int p, int k, int K, double tol,
+                              double* nrm, int* sRot) {
+  const int tid = threadIdx.x;
+  const int grp = tid / G, gl = tid % G;
+  constexpr int ngrp = SVD_NT / G;
+  const int npairs = K / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    // fresh column norms
+    for (int j = grp; j < k; j += ngrp) {
+      double s2 = 0.0;
+      for (int i = gl; i < p; i += G) s2 += sc_abs2(A[(int64_t)j * lda + i]);
+      s2 = group_sum<G>(s2);
+      if (gl == 0) nrm[j] = s2;
+    }
+    if (tid == 0) *sRot = 0;
+    __syncthreads();
+    for (int t = 0; t < K - 1; ++t) {
+      for (int pi = grp; pi < npairs; pi += ngrp) {
+        int a, b;
+        if (pi == 0) {
+          a = 0;
+          b = 1 + (t % (K - 1));
+        } else {
+          a = 1 + (t + pi) % (K - 1);
+          b = 1 + (t - pi + (K - 1)) % (K - 1);
+        }
+        if (a > b) {
+          const int tmp = a; a = b; b = tmp;
+        }
+        if (b >= k) continue;  // padding column of an odd k (uniform in the group)
+        T* xa = A + (int64_t)a * lda;
+        T* xb = A + (int64_t)b * lda;
+        T g = sc_zero<T>();
+        for (int i = gl; i < p; i += G) sc_cfma(g, xa[i], xb[i]);
+        g = group_sum_sc<G, T>(g);
+        const double al = nrm[a], bt = nrm[b];
+        const double ag = sqrt(sc_abs2(g));
+        if (ag > 0.0 && ag > tol * sqrt(al * bt)) {
+          const T ph = sc_scale(g, 1.0 / ag);
+          const double zeta = (bt - al) / (2.0 * ag);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+          for (int i = gl; i < p; i += G) {
+            const T u = xa[i];
+            const T v = sc_mulc(xb[i], ph);  // y * conj(phase)
+            xa[i] = sc_sub(sc_scale(u, c), sc_scale(v, s));
+            xb[i] = sc_add(sc_scale(u, s), sc_scale(v, c));
+          }
+          T* ya = Y + (int64_t)a * ldy;
+          T* yb = Y + (int64_t)b * ldy;
+          for (int i = gl; i < k; i += G) {
+            const T u = ya[i];
+            const T v = sc_mulc(yb[i], ph);
+            ya[i] = sc_sub(sc_scale(u, c), sc_scale(v, s));
+            yb[i] = sc_add(sc_scale(u, s), sc_scale(v, c));
+          }
+          if (gl == 0) {
+            nrm[a] = fmax(al - tt * ag, 0.0);
+            nrm[b] = bt + tt * ag;
+            *sRot = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    const int rot = *sRot;
+    __syncthreads();
+    if (!rot) break;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict__ jobs,
+                                                     const T* __restrict__ store,
+                                                     const T* __restrict__ alpha, double eps,
+                                                     int lds_mode) {
+  const SVDJobDev Jb = jobs[blockIdx.x];
+  const int p = Jb.p, k = Jb.k, tid = threadIdx.x;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ int sRot;
+  __shared__ double sS[512];
+  __shared__ double sN[512];
+  // lds_mode: 2 = R and V in LDS, 1 = R in LDS, 0 = both in HBM
+  T* A = lds_mode >= 1 ? (T*)smem_raw : (T*)Jb.A;
+  T* Y = lds_mode == 2 ? (T*)smem_raw + (size_t)p * k : (T*)Jb.Y;
+  QRNodeDev N;
+  N.store = Jb.store;
+  N.ab = Jb.ab;
+  for (int e = tid; e < p * k; e += SVD_NT) {
+    const int i = e % p, j = e / p;
+    A[e] = Jb.from_node ? node_R<T>(store, alpha, N, i, j) : ((const T*)Jb.R)[e];
+  }
+  for (int e = tid; e < k * k; e += SVD_NT) {
+    const int i = e % k, j = e / k;
+    Y[e] = sc_real<T>(i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  const int K = k + (k & 1);
+  const double tol = 4.0e-16 * (p > 4 ? (double)p : 4.0);
+  if (k >= 2) {
+    const int npairs = K / 2;
+    if (npairs * 32 <= SVD_NT) jacobi_rounds<T, 32>(A, p, Y, k, p, k, K, tol, sN, &sRot);
+    else if (npairs * 16 <= SVD_NT) jacobi_rounds<T, 16>(A, p, Y, k, p, k, K, tol, sN, &sRot);
+    else if (npairs * 8 <= SVD_NT) jacobi_rounds<T, 8>(A, p, Y, k, p, k, K, tol, sN, &sRot);
+    else if (npairs * 4 <= SVD_NT) jacobi_rounds<T, 4>(A, p, Y, k, p, k, K, tol, sN, &sRot);
+    else jacobi_rounds<T, 2>(A, p, Y, k, p, k, K, tol, sN, &sRot);
+  }
+  // column norms, descending order (ties by index), eps-rank
+  for (int j = tid; j < k; j += SVD_NT) {
+    double s2 = 0.0;
+    for (int i = 0; i < p; ++i) s2 += sc_abs2(A[(int64_t)j * p + i]);
+    sS[j] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int j = tid; j < k; j += SVD_NT) {
+    const double sj = sS[j];
+    int pos = 0;
+    for (int i = 0; i < k; ++i) {
+      const double si = sS[i];
+      if (si > sj || (si == sj && i < j)) ++pos;
+    }
+    Jb.perm[pos] = j;
+    Jb.S[pos] = sj;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double s1 = k > 0 ? Jb.S[0] : 0.0;
+    int r = 0;
+    if (s1 > 0.0)
+      while (r < k && Jb.S[r] >= eps * s1) ++r;
+    *Jb.rank = r;
+  }
+  T* Xr = (T*)Jb.Xr;
+  T* Yr = (T*)Jb.Yr;
+  for (int e = tid; e < p * k; e += SVD_NT) {
+    const int i = e % p, pos = e / p;
+    const int j = Jb.perm[pos];
+    const double sj = Jb.S[pos];
+    Xr[e] = sj > 0.0 ? sc_scale(A[(int64_t)j * p + i], 1.0 / sj) : sc_zero<T>();
+  }
+  for (int e = tid; e < k * k; e += SVD_NT) {
+    const int i = e % k, pos = e / k;
+    Yr[e] = Y[(int64_t)Jb.perm[pos] * k + i];
+  }
+}
+
+// ------------------------------------------------------------ block GEMM ---
+constexpr int BG_NT = 256;
+constexpr int BG_CT = 16;
+
+template <typename T>
+__global__ __launch_bounds__(BG_NT) void block_gemm_kernel(const BlockGemmDev* __restrict__ jobs,
+                                                           int ymax) {
+  const BlockGemmDev Jb = jobs[blockIdx.y];
+  const int row = blockIdx.x * BG_NT + threadIdx.x;
+  const int nrows = Jb.n1 + Jb.n2;
+  extern __shared__ unsigned char smem_raw[];
+  T* sY = (T*)smem_raw;  // (r1 + r2) x BG_CT
+  const int rin = Jb.r1 + Jb.r2;
+  if ((int)(blockIdx.x * BG_NT) >= nrows) return;
+  const bool first = row < Jb.n1;
+  const T* Ab = first ? (const T*)Jb.A1 : (const T*)Jb.A2;
+  const int64_t lda = first ? Jb.lda1 : Jb.lda2;
+  const int rowb = first ? row : row - Jb.n1;
+  const int t0 = first ? 0 : Jb.r1;
+  const int tn = first ? Jb.r1 : Jb.r2;
+  const T* Yg = (const T*)Jb.Y;
+  T* Cg = (T*)Jb.C;
+  for (int c0 = 0; c0 < Jb.r; c0 += BG_CT) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < rin * BG_CT; e += BG_NT) {
+      const int t = e % rin, cc = e / rin;
+      sY[t * BG_CT + cc] = (c0 + cc < Jb.r) ? Yg[(int64_t)(c0 + cc) * Jb.ldy + t] : sc_zero<T>();
+    }
+    __syncthreads();
+    if (row < nrows) {
+      T acc[BG_CT];
+#pragma unroll
+      for (int cc = 0; cc < BG_CT; ++cc) acc[cc] = sc_zero<T>();
+      for (int t = 0; t < tn; ++t) {
+        const T a = Ab[(int64_t)t * lda + rowb];
+#pragma unroll
+        for (int cc = 0; cc < BG_CT; ++cc) sc_fma(acc[cc], a, sY[(t0 + t) * BG_CT + cc]);
+      }
+#pragma unroll
+      for (int cc = 0; cc < BG_CT; ++cc)
+        if (c0 + cc < Jb.r) Cg[(int64_t)(c0 + cc) * Jb.ldc + row] = acc[cc];
+    }
+  }
+}
+
+
+// ------------------------------------------- split merge (block CGS2) -----
+constexpr int AHB_RC = 32;   // rows per chunk
+constexpr int AHB_NT = 256;
+
+template <typename T>
+__global__ __launch_bounds__(AHB_NT) void ahb_partial_kernel(const AhbJobDev* __restrict__ jobs) {
+  const AhbJobDev J = jobs[blockIdx.y];
+  const int c = blockIdx.x;
+  if (c >= J.nchunk) return;
+  const int ka = J.ka, kb = J.kb;
+  const int64_t i0 = (int64_t)c * AHB_RC;
+  const int nr = (int)min<int64_t>(AHB_RC, J.m - i0);
+  extern __shared__ unsigned char smem_raw[];
+  T* sA = (T*)smem_raw;              // AHB_RC x ka (row-major)
+  T* sB = sA + (size_t)AHB_RC * ka;  // AHB_RC x kb
+  const T* A = (const T*)J.A;
+  const T* B = (const T*)J.B;
+  for (int e = threadIdx.x; e < AHB_RC * ka; e += AHB_NT) {
+    const int ii = e % AHB_RC, t = e / AHB_RC;
+    sA[ii * ka + t] = ii < nr ? A[(int64_t)t * J.m + i0 + ii] : sc_zero<T>();
+  }
+  for (int e = threadIdx.x; e < AHB_RC * kb; e += AHB_NT) {
+    const int ii = e % AHB_RC, t = e / AHB_RC;
+    sB[ii * kb + t] = ii < nr ? B[(int64_t)t * J.m + i0 + ii] : sc_zero<T>();
+  }
+  __syncthreads();
+  T* part = (T*)J.part + (size_t)c * ka * kb;
+  for (int o = threadIdx.x; o < ka * kb; o += AHB_NT) {
+    const int a = o % ka, b = o / ka;
+    T acc = sc_zero<T>();
+    for (int ii = 0; ii < AHB_RC; ++ii) sc_cfma(acc, sA[ii * ka + a], sB[ii * kb + b]);
+    part[o] = acc;
+  }
+}
+
+template <typename T>
+__global__ void ahb_reduce_kernel(const AhbJobDev* __restrict__ jobs) {
+  const AhbJobDev J = jobs[blockIdx.y];
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = J.ka * J.kb;
+  if (o >= n) return;
+  const T* part = (const T*)J.part;
+  T acc = sc_zero<T>();
+  for (int c = 0; c < J.nchunk; ++c) acc = sc_add(acc, part[(size_t)c * n + o]);
+  ((T*)J.out)[o] = acc;
+}
+
+constexpr int TG_NT = 256;
+constexpr int TG_CT = 16;
+
+template <typename T>
+__global__ __launch_bounds__(TG_NT) void tall_gemm_kernel(const TallGemmDev* __restrict__ jobs) {
+  const TallGemmDev J = jobs[blockIdx.y];
+  const int64_t row = (int64_t)blockIdx.x * TG_NT + threadIdx.x;
+  if ((int64_t)blockIdx.x * TG_NT >= J.m) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* sB = (T*)smem_raw;  // ka x TG_CT
+  const T* A = (const T*)J.A;
+  const T* Bm = (const T*)J.B;
+  const T* Cin = (const T*)J.Cin;
+  T* Cm = (T*)J.C;
+  for (int c0 = 0; c0 < J.nc; c0 += TG_CT) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < J.ka * TG_CT; e += TG_NT) {
+      const int t = e % J.ka, cc = e / J.ka;
+      sB[t * TG_CT + cc] = (c0 + cc < J.nc) ? Bm[(int64_t)(c0 + cc) * J.ldb + t] : sc_zero<T>();
+    }
+    __syncthreads();
+    if (row < J.m) {
+      T acc[TG_CT];
+#pragma unroll
+      for (int cc = 0; cc < TG_CT; ++cc) acc[cc] = sc_zero<T>();
+      for (int t = 0; t < J.ka; ++t) {
+        const T a = A[(int64_t)t * J.lda + row];
+#pragma unroll
+        for (int cc = 0; cc < TG_CT; ++cc) sc_fma(acc[cc], a, sB[t * TG_CT + cc]);
+      }
+#pragma unroll
+      for (int cc = 0; cc < TG_CT; ++cc) {
+        if (c0 + cc < J.nc) {
+          const int64_t idx = (int64_t)(c0 + cc) * J.ldc + row;
+          const T base = Cin ? Cin[idx] : sc_zero<T>();
+          Cm[idx] = sc_add(base, sc_scale(acc[cc], J.sgn));
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void split_r_kernel(const SplitRDev* __restrict__ jobs, const T* __restrict__ store,
+                               const T* __restrict__ alpha) {
+  const SplitRDev J = jobs[blockIdx.x];
+  const int r1 = J.r1, ra = J.ra, rb = J.rb, p = J.ra + J.pb, k = J.r1 + J.r2;
+  T* R = (T*)J.R;
+  const T* M = (const T*)J.M;
+  const T* M2 = (const T*)J.M2;
+  QRNodeDev N;
+  N.store = J.store;
+  N.ab = J.ab;
+  for (int e = threadIdx.x; e < p * k; e += blockDim.x) {
+    const int i = e % p, j = e / p;
+    const bool first = j < r1;
+    const int jj = first ? j : j - r1;
+    const double sc = first ? J.S1[jj] : J.S2[jj];
+    const bool in_a = (first == (J.a_first != 0));
+    T v = sc_zero<T>();
+    if (in_a) {
+      if (i == jj) v = sc_real<T>(sc);
+    } else if (i < ra) {
+      v = sc_scale(sc_add(M[(int64_t)jj * ra + i], M2[(int64_t)jj * ra + i]), sc);
+    } else {
+      v = sc_scale(node_R<T>(store, alpha, N, i - ra, jj), sc);
+    }
+    (void)rb;
+    R[e] = v;
+  }
+}
+}  // namespace
+
+namespace hbk {
+
+int tsqr_mc(int, int) { return MC_ALL; }
+
+int tsqr_kmax_for(int scalar, int k) {
+  if (k <= 16) return 16;
+  if (k <= 32) return 32;
+  if (k <= 64) return 64;
+  if (scalar == 0 && k <= 128) return 128;
+  return -1;
+}
+
+template <typename T, int KMAX, int NQ, int SEG>
+static int fac(const QRNodeDev* nodes, int n, const QRNodeDev* below, void* store, void* alpha,
+               double* beta, hipStream_t st) {
+  hipLaunchKernelGGL((tsqr_factor_kernel<T, KMAX, NQ, SEG>), dim3(n), dim3(KMAX * NQ), 0, st,
+                     nodes, below, (T*)store, (T*)alpha, beta);
+  return (int)hipGetLastError();
+}
+
+int tsqr_factor_launch(int scalar, int kmax, const QRNodeDev* nodes, int n,
+                       const QRNodeDev* below, void* store, void* alpha, double* beta,
+                       hipStream_t st) {
+  if (n == 0) return 0;
+  if (scalar == 0) {
+    if (kmax == 16) return fac<double, 16, 32, 8>(nodes, n, below, store, alpha, beta, st);
+    if (kmax == 32) return fac<double, 32, 16, 16>(nodes, n, below, store, alpha, beta, st);
+    if (kmax == 64) return fac<double, 64, 8, 32>(nodes, n, below, store, alpha, beta, st);
+    if (kmax == 128) return fac<double, 128, 4, 64>(nodes, n, below, store, alpha, beta, st);
+  } else {
+    if (kmax == 16) return fac<hb_cplx, 16, 32, 8>(nodes, n, below, store, alpha, beta, st);
+    if (kmax == 32) return fac<hb_cplx, 32, 16, 16>(nodes, n, below, store, alpha, beta, st);
+    if (kmax == 64) return fac<hb_cplx, 64, 8, 32>(nodes, n, below, store, alpha, beta, st);
+  }
+  return -1;
+}
+
+template <typename T, int KMAX, int NQ, int SEG>
+static int app(const QRApplyDev* jobs, int n, const void* store, const double* beta,
+               hipStream_t st) {
+  hipLaunchKernelGGL((tsqr_apply_kernel<T, KMAX, NQ, SEG>), dim3(n), dim3(KMAX * NQ), 0, st,
+                     jobs, (const T*)store, beta);
+  return (int)hipGetLastError();
+}
+
+int tsqr_apply_launch(int scalar, int kmax, const QRApplyDev* jobs, int n, const void* store,
+                      const double* beta, hipStream_t st) {
+  if (n == 0) return 0;
+  if (scalar == 0) {
+    if (kmax == 16) return app<double, 16, 32, 8>(jobs, n, store, beta, st);
+    if (kmax == 32) return app<double, 32, 16, 16>(jobs, n, store, beta, st);
+    if (kmax == 64) return app<double, 64, 8, 32>(jobs, n, store, beta, st);
+    if (kmax == 128) return app<double, 128, 4, 64>(jobs, n, store, beta, st);
+  } else {
+    if (kmax == 16) return app<hb_cplx, 16, 32, 8>(jobs, n, store, beta, st);
+    if (kmax == 32) return app<hb_cplx, 32, 16, 16>(jobs, n, store, beta, st);
+    if (kmax == 64) return app<hb_cplx, 64, 8, 32>(jobs, n, store, beta, st);
+  }
+  return -1;
+}
+
+int svd_launch(int scalar, const SVDJobDev* jobs, int n, int kmax_batch, int pmax_batch,
+               const void* store, const void* alpha, double eps, hipStream_t st) {
+  if (n == 0) return 0;
+  if (kmax_batch > 512) return -1;
+  const size_t sb = scalar == 0 ? 8 : 16;
+  const size_t lds_cap = 150 * 1024;
+  const size_t a_bytes = (size_t)pmax_batch * kmax_batch * sb;
+  const size_t y_bytes = (size_t)kmax_batch * kmax_batch * sb;
+  int mode = 0;
+  size_t sh = 0;
+  if (a_bytes + y_bytes <= lds_cap) {
+    mode = 2;
+    sh = a_bytes + y_bytes;
+  } else if (a_bytes <= lds_cap) {
+    mode = 1;
+    sh = a_bytes;
+  }
+  if (scalar == 0) {
+    if (sh > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)svd_kernel<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((svd_kernel<double>), dim3(n), dim3(SVD_NT), sh, st, jobs,
+                       (const double*)store, (const double*)alpha, eps, mode);
+  } else {
+    if (sh > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)svd_kernel<hb_cplx>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((svd_kernel<hb_cplx>), dim3(n), dim3(SVD_NT), sh, st, jobs,
+                       (const hb_cplx*)store, (const hb_cplx*)alpha, eps, mode);
+  }
+  return (int)hipGetLastError();
+}
+
+int block_gemm_launch(int scalar, const BlockGemmDev* jobs, int n, int max_rows, int max_rin,
+                      hipStream_t st) {
+  if (n == 0 || max_rows == 0) return 0;
+  dim3 grid((max_rows + BG_NT - 1) / BG_NT, n);
+  const size_t sh = (size_t)max_rin * BG_CT * (scalar == 0 ? 8 : 16);
+  if (sh > 160 * 1024) return -1;
+  if (scalar == 0)
+    hipLaunchKernelGGL((block_gemm_kernel<double>), grid, dim3(BG_NT), sh, st, jobs, max_rin);
+  else
+    hipLaunchKernelGGL((block_gemm_kernel<hb_cplx>), grid, dim3(BG_NT), sh, st, jobs, max_rin);
+  return (int)hipGetLastError();
+}
+
+int ahb_launch(int scalar, const AhbJobDev* jobs, int n, int max_chunks, int max_ka, int max_kb,
+               hipStream_t st) {
+  if (n == 0) return 0;
+  const size_t sb = scalar == 0 ? 8 : 16;
+  const size_t sh = (size_t)AHB_RC * (max_ka + max_kb) * sb;
+  if (sh > 150 * 1024) return -1;
+  dim3 g1(max_chunks, n);
+  dim3 g2((max_ka * max_kb + 255) / 256, n);
+  if (scalar == 0) {
+    if (sh > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)ahb_partial_kernel<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((ahb_partial_kernel<double>), g1, dim3(AHB_NT), sh, st, jobs);
+    hipLaunchKernelGGL((ahb_reduce_kernel<double>), g2, dim3(256), 0, st, jobs);
+  } else {
+    if (sh > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)ahb_partial_kernel<hb_cplx>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((ahb_partial_kernel<hb_cplx>), g1, dim3(AHB_NT), sh, st, jobs);
+    hipLaunchKernelGGL((ahb_reduce_kernel<hb_cplx>), g2, dim3(256), 0, st, jobs);
+  }
+  return (int)hipGetLastError();
+}
+
+int tall_gemm_launch(int scalar, const TallGemmDev* jobs, int n, int64_t max_m, int max_ka,
+                     hipStream_t st) {
+  if (n == 0 || max_m == 0) return 0;
+  const size_t sb = scalar == 0 ? 8 : 16;
+  const size_t sh = (size_t)std::max(max_ka, 1) * TG_CT * sb;
+  if (sh > 150 * 1024) return -1;
+  dim3 g((unsigned)((max_m + TG_NT - 1) / TG_NT), n);
+  if (scalar == 0) {
+    if (sh > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)tall_gemm_kernel<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((tall_gemm_kernel<double>), g, dim3(TG_NT), sh, st, jobs);
+  } else {
+    if (sh > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)tall_gemm_kernel<hb_cplx>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((tall_gemm_kernel<hb_cplx>), g, dim3(TG_NT), sh, st, jobs);
+  }
+  return (int)hipGetLastError();
+}
+
+int split_r_launch(int scalar, const SplitRDev* jobs, int n, const void* store, const void* alpha,
+                   hipStream_t st) {
+  if (n == 0) return 0;
+  if (scalar == 0)
+    hipLaunchKernelGGL((split_r_kernel<double>), dim3(n), dim3(256), 0, st, jobs,
+                       (const double*)store, (const double*)alpha);
+  else
+    hipLaunchKernelGGL((split_r_kernel<hb_cplx>), dim3(n), dim3(256), 0, st, jobs,
+                       (const hb_cplx*)store, (const hb_cplx*)alpha);
+  return (int)hipGetLastError();
+}
+
+}  // namespace hbk
