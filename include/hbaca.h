@@ -84,7 +84,14 @@ typedef struct {
   int32_t record_tape; /* keep per-leaf pivots, d_k, nu, mu for hb_result_leaf_tape */
   int32_t stop_after;  /* diagnostics: 0 full H-BACA; 1 stop after the leaf
                           BACA (blocks = leaves, A_leaf ~ U Vh^H, sigma = 1);
-                          2 stop after the leaf SVD re-compression */
+                          2 stop after the leaf SVD re-compression;
+                          2 + s stop after merge step s (odd s: horizontal,
+                          even s: vertical); blocks in row-major grid order */
+  int32_t diag_panel;  /* diagnostics: 0 default; > 0 merges wider than this
+                          many columns use the column-panel QR with panels of
+                          this width (1..128 real, 1..64 complex) */
+  int32_t diag_svd_storage; /* diagnostics: 0 default; 1 keep the small SVD's
+                          matrices in HBM; 2 R in LDS, V in HBM */
 } hb_params;
 
 typedef struct hb_result hb_result; /* opaque */
@@ -105,6 +112,8 @@ typedef struct {
   double resid_bytes;        /* algorithmic HBM bytes of the BACA residual
                                 passes: U and V streamed once per iteration */
   double resid_flops;        /* 2 phi d r (m0 + n0) summed over iterations */
+  int32_t svd_sweeps_max;    /* most Jacobi sweeps taken by one small SVD */
+  int32_t pad;
 } hb_stats;
 
 /*

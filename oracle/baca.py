@@ -32,6 +32,10 @@ Readings where the paper is silent or garbled:
   reaches min(m0, n0) (the paper's loop bound).
 * Complex matrices: every transpose is a conjugate transpose and the cross
   term of eq. (13) takes the real part.
+
+Instrumentation (no effect on the arithmetic): every iteration records its
+pivots, d_k, nu, mu and the trailing norms of the row picks (sel_I) and of
+the column picks that chose the next block (sel_J).
 """
 from __future__ import annotations
 
@@ -145,7 +149,8 @@ def baca_leaf(block, m0: int, n0: int, d: int, eps: float, J1: np.ndarray,
         if dk == 0:
             if record:
                 iters.append(dict(I=np.zeros(0, np.int64), J=np.zeros(0, np.int64),
-                                  dk=0, nu=0.0, mu=float(np.sqrt(mu2)), r=r))
+                                  dk=0, nu=0.0, mu=float(np.sqrt(mu2)), r=r,
+                                  sel_I=np.abs(selI.tdiag), sel_J=np.zeros(0)))
             break
         jbar = full.piv[:dk]
         Uk = C[:, jbar]
@@ -165,11 +170,14 @@ def baca_leaf(block, m0: int, n0: int, d: int, eps: float, J1: np.ndarray,
         mu = float(np.sqrt(mu2))
         if record:
             iters.append(dict(I=I[:dk].copy(), J=J[jbar].copy(), dk=dk, nu=nu,
-                              mu=mu, r=U.shape[1]))
+                              mu=mu, r=U.shape[1], sel_I=np.abs(selI.tdiag),
+                              sel_J=np.zeros(0)))
         # (8) stopping test, then the next column block (eq. (7))
         if nu < eps * mu or Pc.size == 0 or U.shape[1] >= rmax:
             break
         selJ = qrcp(R[:, Pc], d)
+        if record:
+            iters[-1]["sel_J"] = np.abs(selJ.tdiag)
         ops["qrcp_flops"] += 4 * phi * I.size * Pc.size * selJ.piv.size
         J = Pc[selJ.piv]
     return LeafResult(U, V, iters, ops)

@@ -40,10 +40,12 @@ def _stream():
 
 
 def params(dim=3, h=1.0, gauss_c=1.0, wavenumber=0.0, seed=0, rank_cap=0, record_tape=0,
-           stop_after=0, G1=None, G2=None, spike_lin=None, spike_val=None) -> dict:
+           stop_after=0, G1=None, G2=None, spike_lin=None, spike_val=None, diag_panel=0,
+           diag_svd_storage=0) -> dict:
     return dict(dim=dim, h=h, gauss_c=gauss_c, wavenumber=wavenumber, seed=seed,
                 rank_cap=rank_cap, record_tape=record_tape, stop_after=stop_after, G1=G1,
-                G2=G2, spike_lin=spike_lin, spike_val=spike_val)
+                G2=G2, spike_lin=spike_lin, spike_val=spike_val, diag_panel=diag_panel,
+                diag_svd_storage=diag_svd_storage)
 
 
 def _hb_params(p: dict, keep: list) -> HbParams:
@@ -69,6 +71,8 @@ def _hb_params(p: dict, keep: list) -> HbParams:
     hp.rank_cap = int(p.get("rank_cap", 0))
     hp.record_tape = int(p.get("record_tape", 0))
     hp.stop_after = int(p.get("stop_after", 0))
+    hp.diag_panel = int(p.get("diag_panel", 0))
+    hp.diag_svd_storage = int(p.get("diag_svd_storage", 0))
     return hp
 
 

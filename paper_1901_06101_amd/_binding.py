@@ -42,6 +42,8 @@ class HbParams(C.Structure):
         ("rank_cap", C.c_int32),
         ("record_tape", C.c_int32),
         ("stop_after", C.c_int32),
+        ("diag_panel", C.c_int32),
+        ("diag_svd_storage", C.c_int32),
     ]
 
 
@@ -64,6 +66,8 @@ class HbStats(C.Structure):
         ("entries_evaluated", C.c_double),
         ("resid_bytes", C.c_double),
         ("resid_flops", C.c_double),
+        ("svd_sweeps_max", C.c_int32),
+        ("pad", C.c_int32),
     ]
 
     def as_dict(self):

@@ -359,7 +359,13 @@ struct Engine {
   double eps;
   DevMem& tmp;
 
+  int panel = 0;        // merge panel width (0: the TSQR tile)
+  int svd_sweeps_max = 0;
+  int svd_storage = 0;  // forced SVD storage mode (diagnostics)
+
   Engine(hipStream_t s, int sc, double e, DevMem& t) : st(s), scalar(sc), eps(e), tmp(t) {}
+
+  int kcap() const { return panel > 0 ? panel : (scalar == 0 ? 128 : 64); }
 
   size_t sb() const { return scalar_bytes(scalar); }
 
@@ -393,18 +399,22 @@ struct Engine {
   // Zout(matrix a) = Q_a [Zin_a; 0]  (Zin_a: steps_top x r_a, ld ldin_a;
   // Zout_a: rows_a x r_a, ld ldout_a)
   // Q Z for any number of columns: groups of at most kcap columns
+  // Q Z for any number of columns: groups of at most kcap columns.  With
+  // `ztr`, rows beyond each node's steps come from the trailing block
+  // (rows - steps_top rows, ld ldtr) instead of zeros.
   void apply(const Factored& F, const std::vector<const void*>& zin, const std::vector<int64_t>& ldin,
              const std::vector<int>& rr, const std::vector<void*>& zout,
-             const std::vector<int64_t>& ldout) {
+             const std::vector<int64_t>& ldout, const std::vector<const void*>* ztr = nullptr,
+             const std::vector<int64_t>* ldtr = nullptr) {
     const int kcap = scalar == 0 ? 128 : 64;
     int rmax = 0;
     for (int r : rr) rmax = std::max(rmax, r);
     if (rmax <= kcap) {
-      apply_cols(F, zin, ldin, rr, zout, ldout);
+      apply_cols(F, zin, ldin, rr, zout, ldout, ztr, ldtr);
       return;
     }
     for (int c0 = 0; c0 < rmax; c0 += kcap) {
-      std::vector<const void*> zi(zin.size(), nullptr);
+      std::vector<const void*> zi(zin.size(), nullptr), zt(zin.size(), nullptr);
       std::vector<void*> zo(zout.size(), nullptr);
       std::vector<int> rc(rr.size(), 0);
       for (size_t a = 0; a < rr.size(); ++a) {
@@ -412,14 +422,140 @@ struct Engine {
         if (rc[a] == 0) continue;
         zi[a] = (const char*)zin[a] + (size_t)c0 * ldin[a] * sb();
         zo[a] = (char*)zout[a] + (size_t)c0 * ldout[a] * sb();
+        if (ztr && (*ztr)[a]) zt[a] = (const char*)(*ztr)[a] + (size_t)c0 * (*ldtr)[a] * sb();
       }
-      apply_cols(F, zi, ldin, rc, zo, ldout);
+      apply_cols(F, zi, ldin, rc, zo, ldout, ztr ? &zt : nullptr, ldtr);
+    }
+  }
+
+  // per node: offset of its trailing rows in the matrix's trailing block
+  static std::vector<std::vector<int64_t>> trailing_offsets(const TreeBuild& tb,
+                                                            const std::vector<std::vector<int>>& owner) {
+    const int nlev = (int)tb.levels.size();
+    std::vector<std::vector<int64_t>> off(nlev);
+    std::vector<int64_t> cur(tb.kmat.size(), 0);
+    for (int l = 0; l < nlev; ++l) {
+      off[l].assign(tb.levels[l].size(), 0);
+      for (size_t id = 0; id < tb.levels[l].size(); ++id) {
+        const int a = owner[l][id];
+        if (a < 0) continue;
+        off[l][id] = cur[a];
+        cur[a] += tb.levels[l][id].rows - tb.levels[l][id].steps;
+      }
+    }
+    return off;
+  }
+
+  static std::vector<std::vector<int>> owners(const TreeBuild& tb) {
+    const int nlev = (int)tb.levels.size();
+    std::vector<std::vector<int>> owner(nlev);
+    for (int l = 0; l < nlev; ++l) owner[l].assign(tb.levels[l].size(), -1);
+    for (size_t a = 0; a < tb.kmat.size(); ++a) {
+      if (tb.top_level[a] < 0) continue;
+      std::vector<int> cur{tb.top_index[a]};
+      for (int l = tb.top_level[a]; l >= 0; --l) {
+        std::vector<int> nx;
+        for (int id : cur) {
+          owner[l][id] = (int)a;
+          if (l > 0)
+            for (int c = 0; c < tb.levels[l][id].nchild; ++c) nx.push_back(tb.levels[l][id].child0 + c);
+        }
+        cur = nx;
+      }
+    }
+    return owner;
+  }
+
+  // Q^H Z bottom-up through every tree: Z (rows_a x kk_a, ld ldin) -> the top
+  // node's first steps rows into top (ld ldtop) and the remaining rows into
+  // the trailing block trail (rows_a - steps_top rows, ld ldtrail).
+  void apply_h(const Factored& F, const std::vector<const void*>& zin,
+               const std::vector<int64_t>& ldin, const std::vector<int>& kk,
+               const std::vector<void*>& top, const std::vector<int64_t>& ldtop,
+               const std::vector<void*>& trail, const std::vector<int64_t>& ldtrail) {
+    const auto& tb = F.tb;
+    const int nlev = (int)tb.levels.size();
+    const size_t nm = tb.kmat.size();
+    int kmx = 1;
+    for (size_t a = 0; a < nm; ++a) kmx = std::max(kmx, kk[a]);
+    const int kv = hbk::tsqr_kmax_for(scalar, kmx);
+    if (kv < 0) throw HbError{HB_EUNSUPPORTED};
+    auto owner = owners(tb);
+    auto toff = trailing_offsets(tb, owner);
+    // stacked input buffers of levels >= 1
+    std::vector<std::vector<char*>> sbuf(nlev);
+    for (int l = 1; l < nlev; ++l) {
+      std::vector<size_t> sz;
+      for (size_t id = 0; id < tb.levels[l].size(); ++id) {
+        const int a = owner[l][id];
+        sz.push_back(a < 0 ? 0 : (size_t)tb.levels[l][id].rows * kk[a] * sb());
+      }
+      sbuf[l] = tmp.carve(sz);
+    }
+    // parent of every node and the child's row offset in the parent's stack
+    std::vector<std::vector<int>> par(nlev), poff(nlev);
+    for (int l = 0; l < nlev; ++l) {
+      par[l].assign(tb.levels[l].size(), -1);
+      poff[l].assign(tb.levels[l].size(), 0);
+    }
+    for (int l = 1; l < nlev; ++l)
+      for (size_t id = 0; id < tb.levels[l].size(); ++id) {
+        int off = 0;
+        const QRNodeDev& nd = tb.levels[l][id];
+        for (int c = 0; c < nd.nchild; ++c) {
+          par[l - 1][nd.child0 + c] = (int)id;
+          poff[l - 1][nd.child0 + c] = off;
+          off += tb.levels[l - 1][nd.child0 + c].steps;
+        }
+      }
+    std::vector<int64_t> first_row(nm, -1);
+    for (size_t id = 0; id < tb.levels[0].size(); ++id) {
+      const int a = owner[0][id];
+      if (a >= 0 && first_row[a] < 0) first_row[a] = tb.levels[0][id].row0;
+    }
+    for (int l = 0; l < nlev; ++l) {
+      std::vector<QRApplyHDev> jobs;
+      for (size_t id = 0; id < tb.levels[l].size(); ++id) {
+        const int a = owner[l][id];
+        if (a < 0 || kk[a] == 0) continue;
+        const QRNodeDev& nd = tb.levels[l][id];
+        QRApplyHDev J{};
+        J.rows = nd.rows;
+        J.steps = nd.steps;
+        J.r = kk[a];
+        J.store = nd.store;
+        J.ab = nd.ab;
+        if (l == 0) {
+          J.Zin = (const char*)zin[a] + (size_t)(nd.row0 - first_row[a]) * sb();
+          J.ldin = ldin[a];
+        } else {
+          J.Zin = sbuf[l][id];
+          J.ldin = nd.rows;
+        }
+        const bool is_top = (l == tb.top_level[a] && (int)id == tb.top_index[a]);
+        if (is_top) {
+          J.Zup = top[a];
+          J.ldup = ldtop[a];
+        } else {
+          const int pid = par[l][id];
+          J.Zup = sbuf[l + 1][pid] + (size_t)poff[l][id] * sb();
+          J.ldup = tb.levels[l + 1][pid].rows;
+        }
+        J.Ztr = (char*)trail[a] + (size_t)toff[l][id] * sb();
+        J.ldtr = ldtrail[a];
+        jobs.push_back(J);
+      }
+      if (!jobs.empty()) {
+        QRApplyHDev* dj = upload(tmp, jobs, st);
+        HB_LAUNCH(hbk::tsqr_applyh_launch(scalar, kv, dj, (int)jobs.size(), F.store, F.beta, st));
+      }
     }
   }
 
   void apply_cols(const Factored& F, const std::vector<const void*>& zin,
                   const std::vector<int64_t>& ldin, const std::vector<int>& rr,
-                  const std::vector<void*>& zout, const std::vector<int64_t>& ldout) {
+                  const std::vector<void*>& zout, const std::vector<int64_t>& ldout,
+                  const std::vector<const void*>* ztr, const std::vector<int64_t>* ldtr) {
     const auto& tb = F.tb;
     const int nlev = (int)tb.levels.size();
     const size_t nm = tb.kmat.size();
@@ -444,6 +580,7 @@ struct Engine {
         cur = nx;
       }
     }
+    auto tofs = trailing_offsets(tb, owner);
     // per node Zin pointer/ld and Zout pointer/ld
     std::vector<std::vector<const void*>> nin(nlev);
     std::vector<std::vector<int64_t>> nldin(nlev);
@@ -479,6 +616,10 @@ struct Engine {
         J.ab = nd.ab;
         J.Zin = nin[l][id];
         J.ldin = nldin[l][id];
+        if (ztr && (*ztr)[a]) {
+          J.Ztr = (const char*)(*ztr)[a] + (size_t)tofs[l][id] * sb();
+          J.ldtr = (*ldtr)[a];
+        }
         if (l == 0) {
           // rows [row0 - base, ...) of the destination
           const int64_t base = tb.levels[0][id].row0;  // absolute row in the source
@@ -540,15 +681,14 @@ static void run_svds(Engine& E, std::vector<SVDJobDev>& jobs, const void* store,
     ranks_host.clear();
     return;
   }
-  int32_t* dr = E.tmp.get<int32_t>(nj);
+  int32_t* dr = E.tmp.get<int32_t>(2 * nj);
   int kmax = 0, pmax = 0;
   std::vector<size_t> sz;
   for (size_t a = 0; a < nj; ++a) {
     const size_t p = jobs[a].p, k = jobs[a].k;
     kmax = std::max(kmax, (int)k);
     pmax = std::max(pmax, (int)p);
-    sz.push_back(p * k * E.sb());
-    sz.push_back(k * k * E.sb());
+    sz.push_back(p * k * E.sb());   // HBM workspace (used when R exceeds LDS)
     sz.push_back(k * 8);
     sz.push_back(k * 4);
     sz.push_back(p * k * E.sb());
@@ -557,21 +697,30 @@ static void run_svds(Engine& E, std::vector<SVDJobDev>& jobs, const void* store,
   std::vector<char*> bufs = E.tmp.carve(sz);
   for (size_t a = 0; a < nj; ++a) {
     SVDJobDev& J = jobs[a];
-    J.A = bufs[6 * a + 0];
-    J.Y = bufs[6 * a + 1];
-    J.S = (double*)bufs[6 * a + 2];
-    J.perm = (int32_t*)bufs[6 * a + 3];
-    J.rank = dr + a;
-    J.Xr = bufs[6 * a + 4];
-    J.Yr = bufs[6 * a + 5];
+    J.A = bufs[5 * a + 0];
+    J.S = (double*)bufs[5 * a + 1];
+    J.perm = (int32_t*)bufs[5 * a + 2];
+    J.rank = dr + 2 * a;
+    J.Xr = bufs[5 * a + 3];
+    J.Yr = bufs[5 * a + 4];
     outs[a] = SvdOut{J.Xr, J.Yr, J.S, J.rank, J.p, J.k};
   }
   SVDJobDev* dj = upload(E.tmp, jobs, E.st);
-  HB_LAUNCH(hbk::svd_launch(E.scalar, dj, (int)nj, kmax, pmax, store, alpha, E.eps, E.st));
-  std::vector<int32_t> rh(nj);
-  HB_HIP(hipMemcpyAsync(rh.data(), dr, nj * sizeof(int32_t), hipMemcpyDeviceToHost, E.st));
+  HB_LAUNCH(hbk::svd_launch(E.scalar, dj, (int)nj, kmax, pmax, store, alpha, E.eps, E.st, E.svd_storage));
+  std::vector<int32_t> rh(2 * nj);
+  HB_HIP(hipMemcpyAsync(rh.data(), dr, 2 * nj * sizeof(int32_t), hipMemcpyDeviceToHost, E.st));
   HB_HIP(hipStreamSynchronize(E.st));
-  ranks_host.assign(rh.begin(), rh.end());
+  ranks_host.resize(nj);
+  for (size_t a = 0; a < nj; ++a) {
+    ranks_host[a] = rh[2 * a];
+    E.svd_sweeps_max = std::max(E.svd_sweeps_max, (int)rh[2 * a + 1]);
+  }
+}
+
+static void copy_sigmas(Engine& E, const std::vector<CopyDev>& cp) {
+  if (cp.empty()) return;
+  CopyDev* d = upload(E.tmp, cp, E.st);
+  HB_LAUNCH(hbk::copy_list_launch(d, (int)cp.size(), E.st));
 }
 
 // Truncated SVD of the horizontal (p_is_u) or vertical concatenation of two
@@ -636,6 +785,7 @@ static void run_merges_direct(Engine& E, std::vector<MergeJob>& jobs, DevMem& ou
     osz.push_back((size_t)r * 8);
   }
   std::vector<char*> ob = out_mem.carve(osz);
+  std::vector<CopyDev> scp;
   for (size_t a = 0; a < nj; ++a) {
     MergeJob& J = jobs[a];
     Block& B = *J.outP_owner;
@@ -648,7 +798,7 @@ static void run_merges_direct(Engine& E, std::vector<MergeJob>& jobs, DevMem& ou
     void* P = ob[3 * a];
     void* O = ob[3 * a + 1];
     B.S = (double*)ob[3 * a + 2];
-    HB_HIP(hipMemcpyAsync(B.S, so[i].S, r * sizeof(double), hipMemcpyDeviceToDevice, E.st));
+    scp.push_back(CopyDev{so[i].S, B.S, (int64_t)r * 8});
     if (J.p_is_u) {
       B.U = P;
       B.Vh = O;
@@ -689,6 +839,7 @@ static void run_merges_direct(Engine& E, std::vector<MergeJob>& jobs, DevMem& ou
       ++c;
     }
   }
+  copy_sigmas(E, scp);
   E.apply(F, zin_all, ldin_all, rr_all, zout_all, ldout_all);
   if (!gj.empty()) {
     BlockGemmDev* dg = upload(E.tmp, gj, E.st);
@@ -696,20 +847,19 @@ static void run_merges_direct(Engine& E, std::vector<MergeJob>& jobs, DevMem& ou
   }
 }
 
-// Merges wider than the register TSQR: the larger block P_a (orthonormal) is
-// kept as a basis, the other is orthogonalised against it twice (block
-// classical Gram-Schmidt with re-orthogonalisation) and only that projection
-// goes through TSQR.  R = [P_a, Q_b]^H B is assembled explicitly.
-static void run_merges_split(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_mem) {
+// Merges wider than the register TSQR tile: Householder QR of B by column
+// panels (communication-avoiding QR).  Panel p is factored by TSQR; the Q^H
+// of its tree is applied bottom-up to every later panel, whose top rows
+// become the coupling block R_{p,j} and whose other rows form the next
+// working matrix.  Q [X_r; 0] is applied top-down panel by panel with the
+// trailing rows of the later panels re-injected.
+static void run_merges_caqr(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_mem) {
   const size_t nj = jobs.size();
   if (nj == 0) return;
   const size_t sb = E.sb();
-  struct S {
-    bool a_first;
-    const void *Pa, *Pb;
-    int ra, rb;
-  };
-  std::vector<S> sp(nj);
+  const int kcap = E.kcap();
+  std::vector<int> q(nj), kk(nj);
+  int qmax = 0;
   for (size_t a = 0; a < nj; ++a) {
     MergeJob& J = jobs[a];
     Block& B = *J.outP_owner;
@@ -721,137 +871,150 @@ static void run_merges_split(Engine& E, std::vector<MergeJob>& jobs, DevMem& out
       B.m = J.n1 + J.n2;
     }
     B.r = 0;
-    S& x = sp[a];
-    x.a_first = J.r1 >= J.r2;
-    x.Pa = x.a_first ? J.P1 : J.P2;
-    x.Pb = x.a_first ? J.P2 : J.P1;
-    x.ra = x.a_first ? J.r1 : J.r2;
-    x.rb = x.a_first ? J.r2 : J.r1;
+    kk[a] = J.r1 + J.r2;
+    q[a] = (kk[a] + kcap - 1) / kcap;
+    qmax = std::max(qmax, q[a]);
   }
-  // ---- projections W = (I - P_a P_a^H)^2 P_b,  M + M2 = P_a^H P_b
-  std::vector<size_t> sz;
-  for (size_t a = 0; a < nj; ++a) {
-    const int64_t m = jobs[a].rows;
-    const int64_t nch = (m + 31) / 32;
-    const size_t mm = (size_t)sp[a].ra * sp[a].rb * sb;
-    sz.push_back((size_t)m * sp[a].rb * sb);  // W
-    sz.push_back(mm);                         // M
-    sz.push_back(mm);                         // M2
-    sz.push_back((size_t)nch * mm);           // partials
-  }
-  std::vector<char*> bf = E.tmp.carve(sz);
-  std::vector<AhbJobDev> a1, a2;
-  std::vector<TallGemmDev> g1, g2;
-  int maxch = 1, maxka = 1, maxkb = 1;
-  int64_t maxm = 1;
-  for (size_t a = 0; a < nj; ++a) {
-    if (sp[a].rb == 0) continue;
-    const int64_t m = jobs[a].rows;
-    AhbJobDev h{};
-    h.A = sp[a].Pa;
-    h.B = sp[a].Pb;
-    h.m = m;
-    h.ka = sp[a].ra;
-    h.kb = sp[a].rb;
-    h.part = bf[4 * a + 3];
-    h.out = bf[4 * a + 1];
-    h.nchunk = (int)((m + 31) / 32);
-    a1.push_back(h);
-    h.B = bf[4 * a];
-    h.out = bf[4 * a + 2];
-    a2.push_back(h);
-    TallGemmDev g{};
-    g.Cin = sp[a].Pb;
-    g.A = sp[a].Pa;
-    g.B = bf[4 * a + 1];
-    g.C = bf[4 * a];
-    g.m = m;
-    g.lda = m;
-    g.ldb = sp[a].ra;
-    g.ldc = m;
-    g.ka = sp[a].ra;
-    g.nc = sp[a].rb;
-    g.sgn = -1.0;
-    g1.push_back(g);
-    g.Cin = bf[4 * a];
-    g.B = bf[4 * a + 2];
-    g2.push_back(g);
-    maxch = std::max(maxch, h.nchunk);
-    maxka = std::max(maxka, h.ka);
-    maxkb = std::max(maxkb, h.kb);
-    maxm = std::max(maxm, m);
-  }
-  if (!a1.empty()) {
-    AhbJobDev* d1 = upload(E.tmp, a1, E.st);
-    AhbJobDev* d2 = upload(E.tmp, a2, E.st);
-    TallGemmDev* e1 = upload(E.tmp, g1, E.st);
-    TallGemmDev* e2 = upload(E.tmp, g2, E.st);
-    HB_LAUNCH(hbk::ahb_launch(E.scalar, d1, (int)a1.size(), maxch, maxka, maxkb, E.st));
-    HB_LAUNCH(hbk::tall_gemm_launch(E.scalar, e1, (int)g1.size(), maxm, maxka, E.st));
-    HB_LAUNCH(hbk::ahb_launch(E.scalar, d2, (int)a2.size(), maxch, maxka, maxkb, E.st));
-    HB_LAUNCH(hbk::tall_gemm_launch(E.scalar, e2, (int)g2.size(), maxm, maxka, E.st));
-  }
-  // ---- TSQR of the projections
-  std::vector<QRNodeDev> mats;
-  std::vector<int64_t> rows;
-  std::vector<int> midx(nj, -1);
-  for (size_t a = 0; a < nj; ++a) {
-    if (sp[a].rb == 0) continue;
-    QRNodeDev nd{};
-    nd.k = sp[a].rb;
-    nd.P1 = bf[4 * a];
-    nd.ld1 = jobs[a].rows;
-    nd.n1 = sp[a].rb;
-    nd.P2 = bf[4 * a];
-    nd.ld2 = jobs[a].rows;
-    nd.n2 = 0;
-    midx[a] = (int)mats.size();
-    mats.push_back(nd);
-    rows.push_back(jobs[a].rows);
-  }
-  Engine::Factored F;
-  E.factor(mats, rows, F);
-  // ---- explicit R and its SVD
-  std::vector<SplitRDev> rj(nj);
-  std::vector<SVDJobDev> sj(nj);
-  std::vector<size_t> rsz(nj);
-  std::vector<int> pb(nj, 0);
-  for (size_t a = 0; a < nj; ++a) {
-    if (midx[a] >= 0) {
-      const QRNodeDev& top = F.tb.levels[F.tb.top_level[midx[a]]][F.tb.top_index[midx[a]]];
-      pb[a] = top.steps;
-      rj[a].store = top.store;
-      rj[a].ab = top.ab;
+  auto pw = [&](size_t a, int p) { return std::min(kcap, kk[a] - p * kcap); };
+  // materialised B = [P1 S1, P2 S2]
+  std::vector<size_t> bsz(nj);
+  for (size_t a = 0; a < nj; ++a) bsz[a] = (size_t)jobs[a].rows * kk[a] * sb;
+  std::vector<char*> Bm = E.tmp.carve(bsz);
+  {
+    std::vector<ConcatDev> cj(nj);
+    int64_t mm = 0;
+    for (size_t a = 0; a < nj; ++a) {
+      const MergeJob& J = jobs[a];
+      cj[a] = ConcatDev{J.P1, J.P2, J.S1, J.S2, J.rows, J.r1, J.r2, Bm[a]};
+      mm = std::max(mm, J.rows);
     }
-    rsz[a] = (size_t)(sp[a].ra + pb[a]) * (jobs[a].r1 + jobs[a].r2) * sb;
+    ConcatDev* d = upload(E.tmp, cj, E.st);
+    HB_LAUNCH(hbk::concat_launch(E.scalar, d, (int)nj, mm, 0, E.st));
   }
-  std::vector<char*> rbuf = E.tmp.carve(rsz);
+  // working matrices of every panel: pointer + ld (rows of the working set)
+  std::vector<std::vector<const void*>> pin(nj);
+  std::vector<int64_t> wrows(nj);
   for (size_t a = 0; a < nj; ++a) {
-    SplitRDev& x = rj[a];
-    x.S1 = jobs[a].S1;
-    x.S2 = jobs[a].S2;
-    x.M = bf[4 * a + 1];
-    x.M2 = bf[4 * a + 2];
-    x.r1 = jobs[a].r1;
-    x.r2 = jobs[a].r2;
-    x.ra = sp[a].ra;
-    x.rb = sp[a].rb;
-    x.pb = pb[a];
-    x.a_first = sp[a].a_first ? 1 : 0;
-    x.R = rbuf[a];
+    wrows[a] = jobs[a].rows;
+    pin[a].resize(q[a]);
+    for (int p = 0; p < q[a]; ++p) pin[a][p] = Bm[a] + (size_t)p * kcap * jobs[a].rows * sb;
+  }
+  std::vector<std::vector<int64_t>> rows_at(nj);   // working rows when panel p is factored
+  std::vector<std::vector<int>> stepsp(nj);        // R rows contributed by panel p
+  std::vector<std::unique_ptr<Engine::Factored>> Fp(qmax);
+  std::vector<std::vector<int>> midx(qmax, std::vector<int>(nj, -1));
+  // R rows: panel p starts at row sum(stepsp[<p]); allocate R after all panels
+  // are known - but coupling blocks are written during the sweep, so size R by
+  // its upper bound (sum of panel widths) and compact rows later.
+  std::vector<size_t> rsz(nj);
+  for (size_t a = 0; a < nj; ++a) rsz[a] = (size_t)kk[a] * kk[a] * sb;
+  std::vector<char*> Rbuf = E.tmp.carve(rsz);  // kk x kk, ld kk (rows beyond P stay unused)
+  {
+    size_t tot = 0;
+    for (size_t a = 0; a < nj; ++a) tot += (rsz[a] + 255) & ~(size_t)255;
+    HB_LAUNCH(hbk::zero_fill_launch(Rbuf[0], tot, E.st));
+  }
+  std::vector<int64_t> roff(nj, 0);            // current R row offset
+  for (int p = 0; p < qmax; ++p) {
+    std::vector<QRNodeDev> mats;
+    std::vector<int64_t> rows;
+    for (size_t a = 0; a < nj; ++a) {
+      if (p >= q[a]) continue;
+      if (wrows[a] == 0) {  // no rows left: this panel adds no R rows
+        rows_at[a].push_back(0);
+        stepsp[a].push_back(0);
+        continue;
+      }
+      QRNodeDev nd{};
+      nd.k = pw(a, p);
+      nd.P1 = pin[a][p];
+      nd.ld1 = wrows[a];
+      nd.n1 = nd.k;
+      nd.P2 = pin[a][p];
+      nd.ld2 = wrows[a];
+      midx[p][a] = (int)mats.size();
+      mats.push_back(nd);
+      rows.push_back(wrows[a]);
+    }
+    Fp[p].reset(new Engine::Factored());
+    Engine::Factored& F = *Fp[p];
+    if (mats.empty()) continue;
+    E.factor(mats, rows, F);
+    // R_pp into R, coupling blocks of later panels, next working matrices
+    std::vector<RCopyDev> rc;
+    for (size_t a = 0; a < nj; ++a) {
+      if (midx[p][a] < 0) continue;
+      const int i = midx[p][a];
+      const QRNodeDev& top = F.tb.levels[F.tb.top_level[i]][F.tb.top_index[i]];
+      rows_at[a].push_back(wrows[a]);
+      stepsp[a].push_back(top.steps);
+      RCopyDev c{};
+      c.store = top.store;
+      c.ab = top.ab;
+      c.p = top.steps;
+      c.k = top.k;
+      c.dst = Rbuf[a] + ((size_t)p * kcap * kk[a] + roff[a]) * sb;
+      c.ld = kk[a];
+      rc.push_back(c);
+    }
+    RCopyDev* drc = upload(E.tmp, rc, E.st);
+    HB_LAUNCH(hbk::rcopy_launch(E.scalar, drc, (int)rc.size(), F.store, F.alpha, E.st));
+    // later panels
+    for (int j = p + 1; j < qmax; ++j) {
+      std::vector<const void*> zin(mats.size(), nullptr);
+      std::vector<int64_t> ldin(mats.size(), 1), ldtop(mats.size(), 1), ldtr(mats.size(), 1);
+      std::vector<int> kj(mats.size(), 0);
+      std::vector<void*> top(mats.size(), nullptr), trail(mats.size(), nullptr);
+      std::vector<size_t> tsz(mats.size(), 0);
+      std::vector<size_t> who;
+      for (size_t a = 0; a < nj; ++a)
+        if (midx[p][a] >= 0 && j < q[a]) who.push_back(a);
+      if (who.empty()) continue;
+      for (size_t a : who) {
+        const int i = midx[p][a];
+        tsz[i] = (size_t)(wrows[a] - stepsp[a][p]) * pw(a, j) * sb;
+      }
+      std::vector<char*> tb = E.tmp.carve(tsz);
+      for (size_t a : who) {
+        const int i = midx[p][a];
+        kj[i] = pw(a, j);
+        zin[i] = pin[a][j];
+        ldin[i] = wrows[a];
+        top[i] = Rbuf[a] + ((size_t)j * kcap * kk[a] + roff[a]) * sb;
+        ldtop[i] = kk[a];
+        trail[i] = tb[i];
+        ldtr[i] = wrows[a] - stepsp[a][p];
+      }
+      E.apply_h(F, zin, ldin, kj, top, ldtop, trail, ldtr);
+      for (size_t a : who) pin[a][j] = tb[midx[p][a]];
+    }
+    for (size_t a = 0; a < nj; ++a)
+      if (midx[p][a] >= 0) {
+        roff[a] += stepsp[a][p];
+        wrows[a] -= stepsp[a][p];
+      }
+  }
+  // compact R (P x k, P = sum of panel steps) and its SVD
+  std::vector<SVDJobDev> sj(nj);
+  std::vector<size_t> csz(nj);
+  for (size_t a = 0; a < nj; ++a) csz[a] = (size_t)std::max<int64_t>(roff[a], 1) * kk[a] * sb;
+  std::vector<char*> Rc = E.tmp.carve(csz);
+  std::vector<RCompactDev> rcj(nj);
+  for (size_t a = 0; a < nj; ++a) {
+    rcj[a] = RCompactDev{Rbuf[a], kk[a], Rc[a], (int)roff[a], kk[a]};
     SVDJobDev J{};
-    J.p = sp[a].ra + pb[a];
-    J.k = jobs[a].r1 + jobs[a].r2;
+    J.p = (int)roff[a];
+    J.k = kk[a];
     J.from_node = 0;
-    J.R = rbuf[a];
+    J.R = Rc[a];
     sj[a] = J;
   }
-  SplitRDev* drj = upload(E.tmp, rj, E.st);
-  HB_LAUNCH(hbk::split_r_launch(E.scalar, drj, (int)nj, F.store, F.alpha, E.st));
+  RCompactDev* drcj = upload(E.tmp, rcj, E.st);
+  HB_LAUNCH(hbk::rcompact_launch(E.scalar, drcj, (int)nj, E.st));
   std::vector<SvdOut> so;
   std::vector<int> rk;
-  run_svds(E, sj, F.store, F.alpha, so, rk);
-  // ---- outputs
+  run_svds(E, sj, nullptr, nullptr, so, rk);
+  // outputs
   std::vector<size_t> osz;
   for (size_t a = 0; a < nj; ++a) {
     const int r = rk[a];
@@ -860,57 +1023,28 @@ static void run_merges_split(Engine& E, std::vector<MergeJob>& jobs, DevMem& out
     osz.push_back((size_t)r * 8);
   }
   std::vector<char*> ob = out_mem.carve(osz);
-  std::vector<int> rr(mats.size(), 0);
-  std::vector<const void*> zin(mats.size(), nullptr);
-  std::vector<int64_t> ldin(mats.size(), 1), ldout(mats.size(), 1);
-  std::vector<void*> zout(mats.size(), nullptr);
-  std::vector<TallGemmDev> gadd;
   std::vector<BlockGemmDev> gj;
-  int64_t max_rows = 0, maxm2 = 1;
-  int max_rin = 0, maxka2 = 1;
+  int64_t max_rows = 0;
+  int max_rin = 0;
+  std::vector<char*> P(nj, nullptr);
+  std::vector<CopyDev> scp;
   for (size_t a = 0; a < nj; ++a) {
     MergeJob& J = jobs[a];
     Block& B = *J.outP_owner;
     const int r = rk[a];
     B.r = r;
     if (r == 0) continue;
-    void* P = ob[3 * a];
+    P[a] = ob[3 * a];
     void* O = ob[3 * a + 1];
     B.S = (double*)ob[3 * a + 2];
-    HB_HIP(hipMemcpyAsync(B.S, so[a].S, r * sizeof(double), hipMemcpyDeviceToDevice, E.st));
+    scp.push_back(CopyDev{so[a].S, B.S, (int64_t)r * 8});
     if (J.p_is_u) {
-      B.U = P;
+      B.U = P[a];
       B.Vh = O;
     } else {
-      B.Vh = P;
+      B.Vh = P[a];
       B.U = O;
     }
-    const int p = sp[a].ra + pb[a];
-    bool wrote = false;
-    if (midx[a] >= 0 && pb[a] > 0) {
-      const int i = midx[a];
-      rr[i] = r;
-      zin[i] = (const char*)so[a].Xr + (size_t)sp[a].ra * sb;
-      ldin[i] = p;
-      zout[i] = P;
-      ldout[i] = J.rows;
-      wrote = true;
-    }
-    TallGemmDev g{};
-    g.Cin = wrote ? P : nullptr;
-    g.A = sp[a].Pa;
-    g.B = so[a].Xr;
-    g.C = P;
-    g.m = J.rows;
-    g.lda = J.rows;
-    g.ldb = p;
-    g.ldc = J.rows;
-    g.ka = sp[a].ra;
-    g.nc = r;
-    g.sgn = 1.0;
-    gadd.push_back(g);
-    maxm2 = std::max(maxm2, J.rows);
-    maxka2 = std::max(maxka2, sp[a].ra);
     BlockGemmDev bg{};
     bg.A1 = J.O1; bg.lda1 = J.n1; bg.n1 = (int)J.n1; bg.r1 = J.r1;
     bg.A2 = J.O2; bg.lda2 = J.n2; bg.n2 = (int)J.n2; bg.r2 = J.r2;
@@ -920,10 +1054,49 @@ static void run_merges_split(Engine& E, std::vector<MergeJob>& jobs, DevMem& out
     max_rows = std::max<int64_t>(max_rows, J.n1 + J.n2);
     max_rin = std::max(max_rin, J.r1 + J.r2);
   }
-  if (!mats.empty()) E.apply(F, zin, ldin, rr, zout, ldout);
-  if (!gadd.empty()) {
-    TallGemmDev* dg = upload(E.tmp, gadd, E.st);
-    HB_LAUNCH(hbk::tall_gemm_launch(E.scalar, dg, (int)gadd.size(), maxm2, maxka2, E.st));
+  copy_sigmas(E, scp);
+  // forward: Z_p = T_p [X_r(rows of panel p); Z_{p+1}]
+  std::vector<const void*> znext(nj, nullptr);
+  std::vector<int64_t> ldnext(nj, 1);
+  for (int p = qmax - 1; p >= 0; --p) {
+    Engine::Factored& F = *Fp[p];
+    const size_t nm = F.tb.kmat.size();
+    if (nm == 0) continue;
+    std::vector<const void*> zin(nm, nullptr), ztr(nm, nullptr);
+    std::vector<int64_t> ldin(nm, 1), ldout(nm, 1), ldtr(nm, 1);
+    std::vector<int> rr(nm, 0);
+    std::vector<void*> zout(nm, nullptr);
+    std::vector<size_t> zsz(nm, 0);
+    for (size_t a = 0; a < nj; ++a) {
+      const int i = midx[p][a];
+      if (i < 0 || rk[a] == 0) continue;
+      if (p > 0) zsz[i] = (size_t)rows_at[a][p] * rk[a] * sb;
+    }
+    std::vector<char*> zb = E.tmp.carve(zsz);
+    int64_t rof = 0;
+    for (size_t a = 0; a < nj; ++a) {
+      const int i = midx[p][a];
+      if (i < 0 || rk[a] == 0) continue;
+      int64_t r0 = 0;
+      for (int pp = 0; pp < p; ++pp) r0 += stepsp[a][pp];
+      (void)rof;
+      rr[i] = rk[a];
+      zin[i] = (const char*)so[a].Xr + (size_t)r0 * sb;
+      ldin[i] = so[a].p;
+      zout[i] = p == 0 ? (void*)P[a] : (void*)zb[i];
+      ldout[i] = rows_at[a][p];
+      if (p + 1 < q[a]) {
+        ztr[i] = znext[a];
+        ldtr[i] = ldnext[a];
+      }
+    }
+    E.apply(F, zin, ldin, rr, zout, ldout, &ztr, &ldtr);
+    for (size_t a = 0; a < nj; ++a) {
+      const int i = midx[p][a];
+      if (i < 0 || rk[a] == 0) continue;
+      znext[a] = zout[i];
+      ldnext[a] = rows_at[a][p];
+    }
   }
   if (!gj.empty()) {
     BlockGemmDev* dg = upload(E.tmp, gj, E.st);
@@ -932,16 +1105,16 @@ static void run_merges_split(Engine& E, std::vector<MergeJob>& jobs, DevMem& out
 }
 
 static void run_merges(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_mem) {
-  const int kcap = E.scalar == 0 ? 128 : 64;
+  const int kcap = E.kcap();
   std::vector<MergeJob> direct, split;
   for (auto& J : jobs) {
     const int k = J.r1 + J.r2;
     if (k <= kcap) direct.push_back(J);
-    else if (std::min(J.r1, J.r2) <= kcap) split.push_back(J);
+    else if (k <= 512) split.push_back(J);
     else throw HbError{HB_EUNSUPPORTED};
   }
   run_merges_direct(E, direct, out_mem);
-  run_merges_split(E, split, out_mem);
+  run_merges_caqr(E, split, out_mem);
 }
 
 // SVD re-compression of BACA leaves: U (m0 x r), Vh (n0 x r) -> truncated SVD.
@@ -985,16 +1158,17 @@ static void run_recompress(Engine& E, std::vector<RecJob>& jobs, DevMem& out_mem
   std::vector<QRNodeDev> topU(nl), topV(nl);
   std::vector<void*> Mptr(nl);
   std::vector<SVDJobDev> sj(nl);
+  // The SVD is taken of M^H = R_V R_U^H: Jacobi's accurate (orthonormal to the
+  // sweep tolerance) side then lands on V^H, which the first horizontal
+  // merge uses as an orthonormal basis; U's side is R^H X / S.
   for (size_t i = 0; i < nl; ++i) {
     topU[i] = F.tb.levels[F.tb.top_level[2 * i]][F.tb.top_index[2 * i]];
     topV[i] = F.tb.levels[F.tb.top_level[2 * i + 1]][F.tb.top_index[2 * i + 1]];
     const int pu = topU[i].steps, pv = topV[i].steps;
     Mptr[i] = nullptr;
-    (void)pu;
-    (void)pv;
     SVDJobDev J{};
-    J.p = pu;
-    J.k = pv;
+    J.p = pv;
+    J.k = pu;
     J.from_node = 0;
     J.R = Mptr[i];
     sj[i] = J;
@@ -1008,8 +1182,8 @@ static void run_recompress(Engine& E, std::vector<RecJob>& jobs, DevMem& out_mem
       sj[i].R = mb[i];
     }
   }
-  QRNodeDev* dU = upload(E.tmp, topU, E.st);
-  QRNodeDev* dV = upload(E.tmp, topV, E.st);
+  QRNodeDev* dU = upload(E.tmp, topV, E.st);  // first factor of M^H
+  QRNodeDev* dV = upload(E.tmp, topU, E.st);
   void** dM = upload(E.tmp, Mptr, E.st);
   if (E.scalar == 0)
     hipLaunchKernelGGL((rrh_kernel<double>), dim3(nl), dim3(256), 0, E.st, dU, dV,
@@ -1033,6 +1207,7 @@ static void run_recompress(Engine& E, std::vector<RecJob>& jobs, DevMem& out_mem
     osz.push_back((size_t)rk[i] * 8);
   }
   std::vector<char*> ob = out_mem.carve(osz);
+  std::vector<CopyDev> scp;
   for (size_t i = 0; i < nl; ++i) {
     RecJob& J = jobs[live[i]];
     Block& B = *J.out;
@@ -1042,18 +1217,20 @@ static void run_recompress(Engine& E, std::vector<RecJob>& jobs, DevMem& out_mem
     B.U = ob[3 * i];
     B.Vh = ob[3 * i + 1];
     B.S = (double*)ob[3 * i + 2];
-    HB_HIP(hipMemcpyAsync(B.S, so[i].S, r * sizeof(double), hipMemcpyDeviceToDevice, E.st));
+    scp.push_back(CopyDev{so[i].S, B.S, (int64_t)r * 8});
+    // M^H = X S Y^H  =>  M = Y S X^H: U side from Y, V side from X
     rr[2 * i] = r;
-    zin[2 * i] = so[i].Xr;
-    ldin[2 * i] = so[i].p;
+    zin[2 * i] = so[i].Yr;
+    ldin[2 * i] = so[i].k;
     zout[2 * i] = B.U;
     ldout[2 * i] = J.m0;
     rr[2 * i + 1] = r;
-    zin[2 * i + 1] = so[i].Yr;
-    ldin[2 * i + 1] = so[i].k;
+    zin[2 * i + 1] = so[i].Xr;
+    ldin[2 * i + 1] = so[i].p;
     zout[2 * i + 1] = B.Vh;
     ldout[2 * i + 1] = J.n0;
   }
+  copy_sigmas(E, scp);
   E.apply(F, zin, ldin, rr, zout, ldout);
 }
 
@@ -1084,7 +1261,10 @@ static hb_status validate(const CallSpec& c) {
   if (c.d < 1 || c.leaf < 1) return HB_EINVAL;
   if (c.d > 32) return HB_EUNSUPPORTED;
   if (p->precision != HB_PREC_FP64) return HB_EUNSUPPORTED;
-  if (p->stop_after < 0 || p->stop_after > 2 || p->rank_cap < 0) return HB_EINVAL;
+  if (p->stop_after < 0 || p->stop_after > 2 + 2 * 30 || p->rank_cap < 0) return HB_EINVAL;
+  if (p->diag_panel < 0 || p->diag_panel > 128 || p->diag_svd_storage < 0 ||
+      p->diag_svd_storage > 2)
+    return HB_EINVAL;
   for (size_t b = 0; b < c.rcnt.size(); ++b) {
     if (c.rcnt[b] < 1 || c.ccnt[b] < 1 || c.roff[b] < 0 || c.coff[b] < 0) return HB_EINVAL;
     if (c.roff[b] + c.rcnt[b] > c.nx || c.coff[b] + c.ccnt[b] > c.ny) return HB_EINVAL;
@@ -1344,6 +1524,8 @@ static hb_status run(const CallSpec& c, hb_result** out) {
     b.Vh = (char*)A.V + (size_t)ld[s].v_off * sbytes;
   }
   Engine Eng(st, scalar, c.tol, tmp);
+  Eng.panel = P.diag_panel;
+  Eng.svd_storage = P.diag_svd_storage;
   if (P.stop_after == 1) {
     // keep the BACA arena in the result; blocks are leaves with sigma = 1
     for (void* p : baca_mem.ptrs) R->keep.ptrs.push_back(p);
@@ -1424,6 +1606,18 @@ static hb_status run(const CallSpec& c, hb_result** out) {
         int mx = 0;
         for (auto& J : jobs) mx = std::max(mx, J.outP_owner->r);
         S.step_rank_max[std::min(++step, 63)] = mx;
+        if (P.stop_after == 2 + step) {  // diagnostics: blocks after this step
+          for (size_t p = 0; p < np; ++p)
+            for (auto& b : hb[p]) R->out_blocks.push_back(b);
+          for (void* q : hm->ptrs) R->keep.ptrs.push_back(q);
+          hm->ptrs.clear();
+          for (auto& m : mems)
+            for (void* q : m->ptrs) R->keep.ptrs.push_back(q);
+          for (auto& m : mems) m->ptrs.clear();
+          for (void* q : prev_mem->ptrs) R->keep.ptrs.push_back(q);
+          prev_mem->ptrs.clear();
+          break;
+        }
         prev_mem->release();
         // vertical: (tau, nu) from (tau_1, nu) and (tau_2, nu)
         std::unique_ptr<DevMem> vm(new DevMem());
@@ -1454,6 +1648,18 @@ static hb_status run(const CallSpec& c, hb_result** out) {
         mx = 0;
         for (auto& J : jobs) mx = std::max(mx, J.outP_owner->r);
         S.step_rank_max[std::min(++step, 63)] = mx;
+        if (P.stop_after == 2 + step) {  // diagnostics: blocks after this step
+          for (size_t p = 0; p < np; ++p)
+            for (auto& b : vb[p]) R->out_blocks.push_back(b);
+          for (void* q : vm->ptrs) R->keep.ptrs.push_back(q);
+          vm->ptrs.clear();
+          for (void* q : hm->ptrs) R->keep.ptrs.push_back(q);
+          hm->ptrs.clear();
+          for (auto& m : mems)
+            for (void* q : m->ptrs) R->keep.ptrs.push_back(q);
+          for (auto& m : mems) m->ptrs.clear();
+          break;
+        }
         hm->release();
         for (size_t p = 0; p < np; ++p)
           if (depth[p] >= 1) {
@@ -1466,6 +1672,11 @@ static hb_status run(const CallSpec& c, hb_result** out) {
         tmp.release();
       }
       S.n_steps = step + 1;
+      if (P.stop_after > 2) {
+        S.n_blocks = (int32_t)R->out_blocks.size();
+        HB_HIP(hipEventRecord(ev[4], st));
+        goto finish;
+      }
       // roots: keep their memory
       for (auto& m : mems)
         for (void* p : m->ptrs) R->keep.ptrs.push_back(p);
@@ -1481,6 +1692,8 @@ static hb_status run(const CallSpec& c, hb_result** out) {
     }
     HB_HIP(hipEventRecord(ev[4], st));
   }
+finish:
+  S.svd_sweeps_max = Eng.svd_sweeps_max;
   HB_HIP(hipEventRecord(ev[5], st));
   HB_HIP(hipStreamSynchronize(st));
   S.ms_setup = elapsed(ev[0], ev[1]);

@@ -30,7 +30,8 @@ struct QRNodeDev {
   int32_t pad;
 };
 
-// Applying the tree's Q to Z = [Zin; 0]: one node per entry.
+// Applying the tree's Q to Z = [Zin; Ztr] (Ztr = 0 when null): one node per
+// entry.  Zin holds the node's first `steps` rows, Ztr its remaining rows.
 struct QRApplyDev {
   int32_t rows, steps, r;  // node rows, reflector count, columns of Z
   int32_t pad;
@@ -40,6 +41,34 @@ struct QRApplyDev {
   const void* Zin;  // steps x r (column-major, ld ldin)
   void* Zout;       // rows x r (column-major, ld ldout)
   int64_t ldin, ldout;
+  const void* Ztr;  // (rows - steps) x r, ld ldtr, or null
+  int64_t ldtr;
+};
+
+// Applying the tree's Q^H bottom-up: the node's rows x r input is reflected;
+// its first `steps` rows go up (to the parent's stacked input, or to the
+// coupling block R_12 at the top), the others to the trailing block.
+struct QRApplyHDev {
+  int32_t rows, steps, r;
+  int32_t pad;
+  int64_t store;
+  int32_t ab;
+  int32_t pad2;
+  const void* Zin;  // rows x r, ld ldin
+  void* Zup;        // steps x r, ld ldup
+  void* Ztr;        // (rows - steps) x r, ld ldtr
+  int64_t ldin, ldup, ldtr;
+};
+
+// B = [P1 diag(S1), P2 diag(S2)] materialised (column-major, ld ldb).
+struct ConcatDev {
+  const void* P1;
+  const void* P2;
+  const double* S1;
+  const double* S2;
+  int64_t m;
+  int32_t n1, n2;
+  void* B;
 };
 
 // One small SVD: R (p x k) read from a TSQR top node or given explicitly.
@@ -51,13 +80,20 @@ struct SVDJobDev {
   int32_t ab;
   int32_t pad2;
   const void* R;   // explicit R, column-major ld p
-  void* A;         // workspace p x k (becomes X S), column-major ld p
-  void* Y;         // k x k right singular vectors (column-major, ld k)
+  void* A;         // workspace p x k (becomes X S) when it does not fit in LDS
   double* S;       // k singular values (sorted descending on return)
   int32_t* perm;   // k: sorted position -> column
-  int32_t* rank;   // eps-rank (output)
-  void* Xr;        // p x k output: X columns in sorted order (ld p)
-  void* Yr;        // k x k output: Y columns in sorted order (ld k)
+  int32_t* rank;   // out: [0] eps-rank r, [1] Jacobi sweeps used
+  void* Xr;        // p x k output: left singular vectors, sorted (ld p)
+  void* Yr;        // k x k output: first r columns = right singular vectors
+                   // R^H X_r diag(1/S_r) (ld k)
+};
+
+// Batched device-to-device copies (one workgroup per entry).
+struct CopyDev {
+  const void* src;
+  void* dst;
+  int64_t bytes;  // multiple of 8
 };
 
 // C(row, c) = sum_t A_b(row, t) * Y(t0_b + t, c) for the two diagonal blocks
@@ -117,8 +153,31 @@ struct SplitRDev {
   void* R;          // (ra + pb) x (r1 + r2), column-major
 };
 
+// Copy of a TSQR top node's R (p x k) into a column-major block (ld ld).
+struct RCopyDev {
+  int64_t store;
+  int32_t ab;
+  int32_t p, k;
+  int32_t pad;
+  void* dst;
+  int64_t ld;
+};
+
+// dst (P x k, ld P) = rows 0..P-1 of src (ld ld_src).
+struct RCompactDev {
+  const void* src;
+  int64_t ld_src;
+  void* dst;
+  int32_t P, k;
+};
+
 namespace hbk {
 // scalar: 0 double, 1 complex double
+int copy_list_launch(const CopyDev* jobs_dev, int njobs, hipStream_t st);
+int rcopy_launch(int scalar, const RCopyDev* jobs_dev, int njobs, const void* store,
+                 const void* alpha, hipStream_t st);
+int rcompact_launch(int scalar, const RCompactDev* jobs_dev, int njobs, hipStream_t st);
+int zero_fill_launch(void* ptr, size_t bytes, hipStream_t st);
 int ahb_launch(int scalar, const AhbJobDev* jobs_dev, int njobs, int max_chunks, int max_ka,
                int max_kb, hipStream_t st);
 int tall_gemm_launch(int scalar, const TallGemmDev* jobs_dev, int njobs, int64_t max_m,
@@ -131,9 +190,14 @@ int tsqr_factor_launch(int scalar, int kmax, const QRNodeDev* nodes_dev, int nno
 int tsqr_apply_launch(int scalar, int kmax, const QRApplyDev* jobs_dev, int njobs,
                       const void* store, const double* beta, hipStream_t st);
 int svd_launch(int scalar, const SVDJobDev* jobs_dev, int njobs, int kmax_batch, int pmax_batch,
-               const void* store, const void* alpha, double eps, hipStream_t st);
+               const void* store, const void* alpha, double eps, hipStream_t st,
+               int force_storage = 0);
 int block_gemm_launch(int scalar, const BlockGemmDev* jobs_dev, int njobs, int max_rows,
                       int max_r, hipStream_t st);
+int tsqr_applyh_launch(int scalar, int kmax, const QRApplyHDev* jobs_dev, int njobs,
+                       const void* store, const double* beta, hipStream_t st);
+int concat_launch(int scalar, const ConcatDev* jobs_dev, int njobs, int64_t max_m, int max_k,
+                  hipStream_t st);
 int tsqr_mc(int scalar, int kmax);
 int tsqr_kmax_for(int scalar, int k);
 }  // namespace hbk

@@ -149,11 +149,17 @@ __global__ __launch_bounds__(KMAX* NQ) void tsqr_apply_kernel(const QRApplyDev* 
   T* Zout = (T*)J.Zout;
   __shared__ T sV[2][MC];
   __shared__ double sB[2];
+  const T* Ztr = (const T*)J.Ztr;
   T z[SEG];
 #pragma unroll
   for (int s = 0; s < SEG; ++s) {
     const int rho = s * NQ + q;
-    z[s] = (j < r && rho < steps) ? Zin[(int64_t)j * J.ldin + rho] : sc_zero<T>();
+    T v = sc_zero<T>();
+    if (j < r) {
+      if (rho < steps) v = Zin[(int64_t)j * J.ldin + rho];
+      else if (Ztr && rho < rows) v = Ztr[(int64_t)j * J.ldtr + (rho - steps)];
+    }
+    z[s] = v;
   }
   int buf = 0;
   for (int st = steps - 1; st >= 0; --st) {
@@ -189,24 +195,140 @@ __global__ __launch_bounds__(KMAX* NQ) void tsqr_apply_kernel(const QRApplyDev* 
   }
 }
 
+
+template <typename T, int KMAX, int NQ, int SEG>
+__global__ __launch_bounds__(KMAX* NQ) void tsqr_applyh_kernel(const QRApplyHDev* __restrict__ jobs,
+                                                              const T* __restrict__ store,
+                                                              const double* __restrict__ beta) {
+  constexpr int MC = MC_ALL;
+  constexpr int NTH = KMAX * NQ;
+  const QRApplyHDev J = jobs[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int q = tid % NQ, j = tid / NQ;
+  const int rows = J.rows, steps = J.steps, r = J.r;
+  const T* Zin = (const T*)J.Zin;
+  __shared__ T sV[2][MC];
+  __shared__ double sB[2];
+  T z[SEG];
+#pragma unroll
+  for (int s = 0; s < SEG; ++s) {
+    const int rho = s * NQ + q;
+    z[s] = (j < r && rho < rows) ? Zin[(int64_t)j * J.ldin + rho] : sc_zero<T>();
+  }
+  int buf = 0;
+  for (int st = 0; st < steps; ++st) {
+    for (int e = tid; e < MC; e += NTH)
+      sV[buf][e] = (e >= st && e < rows) ? store[J.store + (int64_t)st * MC + e] : sc_zero<T>();
+    if (tid == 0) sB[buf] = beta[J.ab + st];
+    __syncthreads();
+    if (j < r) {
+      const double be = sB[buf];
+      if (be != 0.0) {
+        T w = sc_zero<T>();
+#pragma unroll
+        for (int s = 0; s < SEG; ++s) {
+          const int rho = s * NQ + q;
+          if (rho >= st) sc_cfma(w, sV[buf][rho], z[s]);
+        }
+        w = group_sum_sc<NQ>(w);
+#pragma unroll
+        for (int s = 0; s < SEG; ++s) {
+          const int rho = s * NQ + q;
+          if (rho >= st) sc_axpy_neg(z[s], be, sV[buf][rho], w);
+        }
+      }
+    }
+    buf ^= 1;
+  }
+  if (j < r) {
+    T* Zup = (T*)J.Zup;
+    T* Ztr = (T*)J.Ztr;
+#pragma unroll
+    for (int s = 0; s < SEG; ++s) {
+      const int rho = s * NQ + q;
+      if (rho < steps) Zup[(int64_t)j * J.ldup + rho] = z[s];
+      else if (rho < rows) Ztr[(int64_t)j * J.ldtr + (rho - steps)] = z[s];
+    }
+  }
+}
+
+template <typename T>
+__global__ void concat_kernel(const ConcatDev* __restrict__ jobs) {
+  const ConcatDev J = jobs[blockIdx.y];
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= J.m) return;
+  const T* P1 = (const T*)J.P1;
+  const T* P2 = (const T*)J.P2;
+  T* B = (T*)J.B;
+  for (int j = 0; j < J.n1; ++j)
+    B[(int64_t)j * J.m + row] = sc_scale(P1[(int64_t)j * J.m + row], J.S1 ? J.S1[j] : 1.0);
+  for (int j = 0; j < J.n2; ++j)
+    B[(int64_t)(J.n1 + j) * J.m + row] = sc_scale(P2[(int64_t)j * J.m + row], J.S2 ? J.S2[j] : 1.0);
+}
+
+
+template <typename T>
+__global__ void rcopy_kernel(const RCopyDev* __restrict__ jobs, const T* __restrict__ store,
+                             const T* __restrict__ alpha) {
+  const RCopyDev J = jobs[blockIdx.x];
+  QRNodeDev N;
+  N.store = J.store;
+  N.ab = J.ab;
+  T* dst = (T*)J.dst;
+  for (int e = threadIdx.x; e < J.p * J.k; e += blockDim.x) {
+    const int i = e % J.p, j = e / J.p;
+    dst[(int64_t)j * J.ld + i] = node_R<T>(store, alpha, N, i, j);
+  }
+}
+
+template <typename T>
+__global__ void rcompact_kernel(const RCompactDev* __restrict__ jobs) {
+  const RCompactDev J = jobs[blockIdx.x];
+  const T* src = (const T*)J.src;
+  T* dst = (T*)J.dst;
+  for (int e = threadIdx.x; e < J.P * J.k; e += blockDim.x) {
+    const int i = e % J.P, j = e / J.P;
+    dst[e] = src[(int64_t)j * J.ld_src + i];
+  }
+}
+
+__global__ void zero_fill_kernel(uint64_t* p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+
+__global__ void copy_list_kernel(const CopyDev* __restrict__ jobs) {
+  const CopyDev J = jobs[blockIdx.x];
+  const int64_t n = J.bytes / 8;
+  const uint64_t* src = (const uint64_t*)J.src;
+  uint64_t* dst = (uint64_t*)J.dst;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
 // ------------------------------------------------------------- Jacobi SVD --
 // One-sided (Hestenes) Jacobi on the columns of R (p x k) with the classic
 // round-robin pairing: k/2 disjoint column pairs per round, each rotated by
 // a group of G lanes.  Column norms are recomputed at the start of every
-// sweep and updated in closed form after each rotation (a' = a - t|g|,
-// b' = b + t|g|), so a pair costs one dot product.  Sweeps end when no pair
-// has |a_i^H a_j| > tol sqrt(|a_i|^2 |a_j|^2).  R and V live in LDS when they
-// fit (the common case), otherwise in the HBM workspace.
+// sweep and the two norms of a rotated pair are accumulated while it is
+// rotated, so a pair costs one dot product.  Sweeps end when no pair has
+// |a_i^H a_j| > tol |a_i| |a_j|; a column whose norm is below the rounding
+// level of R (1e-16 sqrt(p) ||R||_F) takes no part.  The rotation tangent is
+// evaluated without overflow for large zeta.  R lives in LDS when it fits,
+// otherwise in the HBM workspace.  The rotations are not accumulated: the
+// normalised final columns are the left singular vectors X (orthonormal to
+// the sweep tolerance) and the kept right vectors follow as R^H X_r / S_r.
 constexpr int SVD_NT = 512;
 
 template <typename T, int G>
-__device__ void jacobi_rounds(T* A, int lda, T* Y, int ldy, int p, int k, int K, double tol,
-                              double* nrm, int* sRot) {
+__device__ int jacobi_rounds(T* A, int lda, int p, int k, int K, double tol, double negl,
+                             double* nrm, int* sRot) {
   const int tid = threadIdx.x;
   const int grp = tid / G, gl = tid % G;
   constexpr int ngrp = SVD_NT / G;
   const int npairs = K / 2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  int sweep = 0;
+  for (; sweep < 60; ++sweep) {
     // fresh column norms
     for (int j = grp; j < k; j += ngrp) {
       double s2 = 0.0;
@@ -230,35 +352,41 @@ __device__ void jacobi_rounds(T* A, int lda, T* Y, int ldy, int p, int k, int K,
           const int tmp = a; a = b; b = tmp;
         }
         if (b >= k) continue;  // padding column of an odd k (uniform in the group)
+        const double al = nrm[a], bt = nrm[b];
+        // a column below the rounding level of R cannot move any singular
+        // value that a truncation can see: leave it alone
+        if (al <= negl || bt <= negl) continue;
         T* xa = A + (int64_t)a * lda;
         T* xb = A + (int64_t)b * lda;
         T g = sc_zero<T>();
         for (int i = gl; i < p; i += G) sc_cfma(g, xa[i], xb[i]);
         g = group_sum_sc<G, T>(g);
-        const double al = nrm[a], bt = nrm[b];
         const double ag = sqrt(sc_abs2(g));
-        if (ag > 0.0 && ag > tol * sqrt(al * bt)) {
+        if (ag > tol * sqrt(al) * sqrt(bt)) {
           const T ph = sc_scale(g, 1.0 / ag);
           const double zeta = (bt - al) / (2.0 * ag);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double az = fabs(zeta);
+          // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), without overflow
+          const double den = az > 1.0 ? az * (1.0 + sqrt(1.0 + (1.0 / az) * (1.0 / az)))
+                                      : az + sqrt(1.0 + az * az);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / den;
           const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+          double na = 0.0, nb = 0.0;
           for (int i = gl; i < p; i += G) {
             const T u = xa[i];
             const T v = sc_mulc(xb[i], ph);  // y * conj(phase)
-            xa[i] = sc_sub(sc_scale(u, c), sc_scale(v, s));
-            xb[i] = sc_add(sc_scale(u, s), sc_scale(v, c));
+            const T u2 = sc_sub(sc_scale(u, c), sc_scale(v, s));
+            const T v2 = sc_add(sc_scale(u, s), sc_scale(v, c));
+            xa[i] = u2;
+            xb[i] = v2;
+            na += sc_abs2(u2);
+            nb += sc_abs2(v2);
           }
-          T* ya = Y + (int64_t)a * ldy;
-          T* yb = Y + (int64_t)b * ldy;
-          for (int i = gl; i < k; i += G) {
-            const T u = ya[i];
-            const T v = sc_mulc(yb[i], ph);
-            ya[i] = sc_sub(sc_scale(u, c), sc_scale(v, s));
-            yb[i] = sc_add(sc_scale(u, s), sc_scale(v, c));
-          }
+          na = group_sum<G>(na);
+          nb = group_sum<G>(nb);
           if (gl == 0) {
-            nrm[a] = fmax(al - tt * ag, 0.0);
-            nrm[b] = bt + tt * ag;
+            nrm[a] = na;
+            nrm[b] = nb;
             *sRot = 1;
           }
         }
@@ -269,6 +397,7 @@ __device__ void jacobi_rounds(T* A, int lda, T* Y, int ldy, int p, int k, int K,
     __syncthreads();
     if (!rot) break;
   }
+  return sweep + 1;
 }
 
 template <typename T>
@@ -282,30 +411,36 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
   __shared__ int sRot;
   __shared__ double sS[512];
   __shared__ double sN[512];
-  // lds_mode: 2 = R and V in LDS, 1 = R in LDS, 0 = both in HBM
-  T* A = lds_mode >= 1 ? (T*)smem_raw : (T*)Jb.A;
-  T* Y = lds_mode == 2 ? (T*)smem_raw + (size_t)p * k : (T*)Jb.Y;
+  __shared__ double sRed[SVD_NT / 64];
+  // lds_mode: 1 = R in LDS, 0 = R in the HBM workspace
+  T* A = lds_mode == 1 ? (T*)smem_raw : (T*)Jb.A;
   QRNodeDev N;
   N.store = Jb.store;
   N.ab = Jb.ab;
-  for (int e = tid; e < p * k; e += SVD_NT) {
-    const int i = e % p, j = e / p;
-    A[e] = Jb.from_node ? node_R<T>(store, alpha, N, i, j) : ((const T*)Jb.R)[e];
-  }
-  for (int e = tid; e < k * k; e += SVD_NT) {
-    const int i = e % k, j = e / k;
-    Y[e] = sc_real<T>(i == j ? 1.0 : 0.0);
-  }
+  auto Rat = [&](int i, int j) -> T {
+    return Jb.from_node ? node_R<T>(store, alpha, N, i, j) : ((const T*)Jb.R)[(int64_t)j * p + i];
+  };
+  for (int e = tid; e < p * k; e += SVD_NT) A[e] = Rat(e % p, e / p);
   __syncthreads();
   const int K = k + (k & 1);
   const double tol = 4.0e-16 * (p > 4 ? (double)p : 4.0);
+  // squared Frobenius norm of R, for the negligible-column level
+  double f2 = 0.0;
+  for (int e = tid; e < p * k; e += SVD_NT) f2 += sc_abs2(A[e]);
+  f2 = wave_sum(f2);
+  if ((tid & 63) == 0) sRed[tid >> 6] = f2;
+  __syncthreads();
+  f2 = 0.0;
+  for (int w = 0; w < SVD_NT / 64; ++w) f2 += sRed[w];
+  const double negl = 1.0e-32 * (double)(p > 1 ? p : 1) * f2;
+  int sweeps = 0;
   if (k >= 2) {
     const int npairs = K / 2;
-    if (npairs * 32 <= SVD_NT) jacobi_rounds<T, 32>(A, p, Y, k, p, k, K, tol, sN, &sRot);
-    else if (npairs * 16 <= SVD_NT) jacobi_rounds<T, 16>(A, p, Y, k, p, k, K, tol, sN, &sRot);
-    else if (npairs * 8 <= SVD_NT) jacobi_rounds<T, 8>(A, p, Y, k, p, k, K, tol, sN, &sRot);
-    else if (npairs * 4 <= SVD_NT) jacobi_rounds<T, 4>(A, p, Y, k, p, k, K, tol, sN, &sRot);
-    else jacobi_rounds<T, 2>(A, p, Y, k, p, k, K, tol, sN, &sRot);
+    if (npairs * 32 <= SVD_NT) sweeps = jacobi_rounds<T, 32>(A, p, p, k, K, tol, negl, sN, &sRot);
+    else if (npairs * 16 <= SVD_NT) sweeps = jacobi_rounds<T, 16>(A, p, p, k, K, tol, negl, sN, &sRot);
+    else if (npairs * 8 <= SVD_NT) sweeps = jacobi_rounds<T, 8>(A, p, p, k, K, tol, negl, sN, &sRot);
+    else if (npairs * 4 <= SVD_NT) sweeps = jacobi_rounds<T, 4>(A, p, p, k, K, tol, negl, sN, &sRot);
+    else sweeps = jacobi_rounds<T, 2>(A, p, p, k, K, tol, negl, sN, &sRot);
   }
   // column norms, descending order (ties by index), eps-rank
   for (int j = tid; j < k; j += SVD_NT) {
@@ -323,26 +458,36 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
     }
     Jb.perm[pos] = j;
     Jb.S[pos] = sj;
+    sN[pos] = sj;
   }
   __syncthreads();
+  __shared__ int sR;
   if (tid == 0) {
-    const double s1 = k > 0 ? Jb.S[0] : 0.0;
+    const double s1 = k > 0 ? sN[0] : 0.0;
     int r = 0;
     if (s1 > 0.0)
-      while (r < k && Jb.S[r] >= eps * s1) ++r;
-    *Jb.rank = r;
+      while (r < k && sN[r] >= eps * s1) ++r;
+    sR = r;
+    Jb.rank[0] = r;
+    Jb.rank[1] = sweeps;
   }
+  __syncthreads();
+  const int r = sR;
   T* Xr = (T*)Jb.Xr;
   T* Yr = (T*)Jb.Yr;
   for (int e = tid; e < p * k; e += SVD_NT) {
     const int i = e % p, pos = e / p;
     const int j = Jb.perm[pos];
-    const double sj = Jb.S[pos];
+    const double sj = sN[pos];
     Xr[e] = sj > 0.0 ? sc_scale(A[(int64_t)j * p + i], 1.0 / sj) : sc_zero<T>();
   }
-  for (int e = tid; e < k * k; e += SVD_NT) {
+  __syncthreads();
+  // right singular vectors of the kept part: Y_r = R^H X_r diag(1 / S_r)
+  for (int e = tid; e < k * r; e += SVD_NT) {
     const int i = e % k, pos = e / k;
-    Yr[e] = Y[(int64_t)Jb.perm[pos] * k + i];
+    T acc = sc_zero<T>();
+    for (int t = 0; t < p; ++t) sc_cfma(acc, Rat(t, i), Xr[(int64_t)pos * p + t]);
+    Yr[(int64_t)pos * k + i] = sc_scale(acc, 1.0 / sN[pos]);
   }
 }
 
@@ -574,22 +719,16 @@ int tsqr_apply_launch(int scalar, int kmax, const QRApplyDev* jobs, int n, const
 }
 
 int svd_launch(int scalar, const SVDJobDev* jobs, int n, int kmax_batch, int pmax_batch,
-               const void* store, const void* alpha, double eps, hipStream_t st) {
+               const void* store, const void* alpha, double eps, hipStream_t st,
+               int force_storage) {
   if (n == 0) return 0;
   if (kmax_batch > 512) return -1;
   const size_t sb = scalar == 0 ? 8 : 16;
   const size_t lds_cap = 150 * 1024;
   const size_t a_bytes = (size_t)pmax_batch * kmax_batch * sb;
-  const size_t y_bytes = (size_t)kmax_batch * kmax_batch * sb;
-  int mode = 0;
-  size_t sh = 0;
-  if (a_bytes + y_bytes <= lds_cap) {
-    mode = 2;
-    sh = a_bytes + y_bytes;
-  } else if (a_bytes <= lds_cap) {
-    mode = 1;
-    sh = a_bytes;
-  }
+  int mode = a_bytes <= lds_cap ? 1 : 0;
+  if (force_storage == 1) mode = 0;
+  const size_t sh = mode == 1 ? a_bytes : 0;
   if (scalar == 0) {
     if (sh > 64 * 1024)
       (void)hipFuncSetAttribute((const void*)svd_kernel<double>,
@@ -673,6 +812,78 @@ int split_r_launch(int scalar, const SplitRDev* jobs, int n, const void* store, 
   else
     hipLaunchKernelGGL((split_r_kernel<hb_cplx>), dim3(n), dim3(256), 0, st, jobs,
                        (const hb_cplx*)store, (const hb_cplx*)alpha);
+  return (int)hipGetLastError();
+}
+
+
+template <typename T, int KMAX, int NQ, int SEG>
+static int apph(const QRApplyHDev* jobs, int n, const void* store, const double* beta,
+                hipStream_t st) {
+  hipLaunchKernelGGL((tsqr_applyh_kernel<T, KMAX, NQ, SEG>), dim3(n), dim3(KMAX * NQ), 0, st,
+                     jobs, (const T*)store, beta);
+  return (int)hipGetLastError();
+}
+
+int tsqr_applyh_launch(int scalar, int kmax, const QRApplyHDev* jobs, int n, const void* store,
+                       const double* beta, hipStream_t st) {
+  if (n == 0) return 0;
+  if (scalar == 0) {
+    if (kmax == 16) return apph<double, 16, 32, 8>(jobs, n, store, beta, st);
+    if (kmax == 32) return apph<double, 32, 16, 16>(jobs, n, store, beta, st);
+    if (kmax == 64) return apph<double, 64, 8, 32>(jobs, n, store, beta, st);
+    if (kmax == 128) return apph<double, 128, 4, 64>(jobs, n, store, beta, st);
+  } else {
+    if (kmax == 16) return apph<hb_cplx, 16, 32, 8>(jobs, n, store, beta, st);
+    if (kmax == 32) return apph<hb_cplx, 32, 16, 16>(jobs, n, store, beta, st);
+    if (kmax == 64) return apph<hb_cplx, 64, 8, 32>(jobs, n, store, beta, st);
+  }
+  return -1;
+}
+
+int concat_launch(int scalar, const ConcatDev* jobs, int n, int64_t max_m, int, hipStream_t st) {
+  if (n == 0 || max_m == 0) return 0;
+  dim3 g((unsigned)((max_m + 255) / 256), n);
+  if (scalar == 0)
+    hipLaunchKernelGGL((concat_kernel<double>), g, dim3(256), 0, st, jobs);
+  else
+    hipLaunchKernelGGL((concat_kernel<hb_cplx>), g, dim3(256), 0, st, jobs);
+  return (int)hipGetLastError();
+}
+
+
+int rcopy_launch(int scalar, const RCopyDev* jobs, int n, const void* store, const void* alpha,
+                 hipStream_t st) {
+  if (n == 0) return 0;
+  if (scalar == 0)
+    hipLaunchKernelGGL((rcopy_kernel<double>), dim3(n), dim3(256), 0, st, jobs,
+                       (const double*)store, (const double*)alpha);
+  else
+    hipLaunchKernelGGL((rcopy_kernel<hb_cplx>), dim3(n), dim3(256), 0, st, jobs,
+                       (const hb_cplx*)store, (const hb_cplx*)alpha);
+  return (int)hipGetLastError();
+}
+
+int rcompact_launch(int scalar, const RCompactDev* jobs, int n, hipStream_t st) {
+  if (n == 0) return 0;
+  if (scalar == 0)
+    hipLaunchKernelGGL((rcompact_kernel<double>), dim3(n), dim3(256), 0, st, jobs);
+  else
+    hipLaunchKernelGGL((rcompact_kernel<hb_cplx>), dim3(n), dim3(256), 0, st, jobs);
+  return (int)hipGetLastError();
+}
+
+int zero_fill_launch(void* ptr, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 8;
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(zero_fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     (uint64_t*)ptr, n);
+  return (int)hipGetLastError();
+}
+
+
+int copy_list_launch(const CopyDev* jobs, int n, hipStream_t st) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(copy_list_kernel, dim3(n), dim3(64), 0, st, jobs);
   return (int)hipGetLastError();
 }
 

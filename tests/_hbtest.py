@@ -1,0 +1,120 @@
+"""Shared helpers of the GPU parity tests: run the HIP path through the C ABI
+and the CPU oracle on the same seeded inputs and compare them."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import oracle
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def device_inputs(wl):
+    import torch
+    dev = torch.device("cuda")
+    X = torch.tensor(wl["X"], device=dev) if wl.get("X") is not None else None
+    Y = torch.tensor(wl["Y"], device=dev) if wl.get("Y") is not None else None
+    return X, Y
+
+
+def gpu_params(hb, wl, **kw):
+    import torch
+    dim = wl["X"].shape[1] if wl.get("X") is not None else 0
+    p = hb.params(dim=dim, h=wl.get("h", 0.0), gauss_c=wl.get("gauss_c", 1.0),
+                  wavenumber=wl.get("wavenumber", 0.0), seed=wl["seed"], **kw)
+    if wl["entry"] == 4:
+        dev = torch.device("cuda")
+        p["G1"] = torch.tensor(wl["G1"], device=dev)
+        p["G2"] = torch.tensor(wl["G2"], device=dev)
+        p["spike_lin"] = torch.tensor(np.asarray(wl["spike_lin"], np.int64), device=dev)
+        p["spike_val"] = torch.tensor(np.asarray(wl["spike_val"], np.float64), device=dev)
+    return p
+
+
+def run_gpu(hb, wl, **kw):
+    X, Y = device_inputs(wl)
+    p = gpu_params(hb, wl, **kw)
+    return hb.compress(wl["entry"], p, X, Y, wl["m"], wl["n"], wl["tol"], wl["d"], wl["leaf"])
+
+
+def run_oracle(wl, keep_leaf_factors=False):
+    src = oracle.EntrySource(wl)
+    return src, oracle.hbaca(src, wl["m"], wl["n"], wl["tol"], wl["d"], wl["leaf"], wl["seed"],
+                             keep_leaf_factors=keep_leaf_factors)
+
+
+def factors_np(res, block=0):
+    U, S, Vh = res.factors(block)
+    return U.cpu().numpy(), S.cpu().numpy(), Vh.cpu().numpy()
+
+
+def lowrank_diff(X1, Y1, X2, Y2):
+    """||X1 Y1^H - X2 Y2^H||_F without forming the products (QR of the
+    stacked factors, then the small core)."""
+    Xs = np.hstack([X1, -X2])
+    Ys = np.hstack([Y1, Y2])
+    if Xs.shape[1] == 0:
+        return 0.0
+    _, R1 = np.linalg.qr(Xs)
+    _, R2 = np.linalg.qr(Ys)
+    return float(np.linalg.norm(R1 @ R2.conj().T))
+
+
+def recon_norm(X, Y):
+    if X.shape[1] == 0:
+        return 0.0
+    _, R1 = np.linalg.qr(X)
+    _, R2 = np.linalg.qr(Y)
+    return float(np.linalg.norm(R1 @ R2.conj().T))
+
+
+NOISE = 1e-12
+PICK_NOISE = 1e-11
+
+
+def _determined(norms):
+    """A QRCP pick is unique only while its trailing norm is well above the
+    rounding level of its panel."""
+    norms = np.asarray(norms)
+    return norms.size == 0 or norms.min() > PICK_NOISE * norms.max()
+
+
+def compare_tape(gtape, ginfo, oinfo):
+    """Compare one leaf's GPU pivot tape with the oracle's iterations.
+
+    Iterations are compared in order while their pivots are unique: d_k,
+    I_k(1:d_k) and J_k(Jbar) must then be equal.  Comparison stops at the
+    first iteration whose row picks, or the column picks that produced its
+    block J_k, were made among rounding-level trailing norms (an exactly
+    low-rank residual), and a terminating iteration with nu < 1e-12 mu is
+    never compared: in both cases several choices are equally valid.
+    Returns None or a text describing the first difference."""
+    its = oinfo["iters"]
+    gdk = list(int(x) for x in gtape["dk"])
+    odk = [it["dk"] for it in its]
+    nk = 0
+    for k, it in enumerate(its):
+        if not _determined(it["sel_I"]):
+            break
+        if k > 0 and not _determined(its[k - 1]["sel_J"]):
+            break
+        if it["dk"] > 0 and it["nu"] < NOISE * max(it["mu"], 1e-300) and k == len(its) - 1:
+            break
+        nk += 1
+    if gdk[:nk] != odk[:nk]:
+        return f"d_k differ: gpu {gdk} oracle {odk}"
+    r = int(sum(odk[:nk]))
+    orows = np.concatenate([it["I"] for it in its[:nk]]) if nk else np.zeros(0, np.int64)
+    ocols = np.concatenate([it["J"] for it in its[:nk]]) if nk else np.zeros(0, np.int64)
+    if not np.array_equal(gtape["rows"][:r], orows):
+        return "row pivots differ"
+    if not np.array_equal(gtape["cols"][:r], ocols):
+        return "column pivots differ"
+    if nk == len(odk) and (len(gdk) != len(odk) or ginfo["rank_baca"] != oinfo["rank_baca"]):
+        return f"iteration count differs: gpu {gdk} oracle {odk}"
+    return None

@@ -1,0 +1,71 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+symbol include/hbaca.h declares, and rejects invalid arguments before any
+HIP call."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1901_06101_amd", "libhbaca.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libhbaca.so not built")
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "hbaca.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hb\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    from paper_1901_06101_amd import _binding
+    lib = _binding.load(LIB)
+    names = _declared()
+    assert "hbaca_compress" in names and "hb_result_free" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert missing == []
+    assert set(names) == set(_binding.EXPORTED)
+
+
+def test_status_strings():
+    from paper_1901_06101_amd import _binding
+    lib = _binding.load(LIB)
+    for st in range(-6, 1):
+        assert lib.hb_status_string(st).decode()
+    assert lib.hb_status_string(-99).decode() == "unknown status"
+
+
+def _call(**over):
+    from paper_1901_06101_amd import _binding
+    lib = _binding.load(LIB)
+    p = _binding.HbParams()
+    p.dim, p.h, p.gauss_c, p.wavenumber = 3, 0.5, 1.0, 20.0
+    args = dict(entry=1, params=C.byref(p), X=C.c_void_p(16), Y=C.c_void_p(16), m=100, n=100,
+                tol=1e-6, d=8, leaf=50)
+    args.update(over)
+    out = C.c_void_p(1234)
+    st = lib.hbaca_compress(args["entry"], args["params"], args["X"], args["Y"], args["m"],
+                            args["n"], args["tol"], args["d"], args["leaf"], None, C.byref(out))
+    return st, out
+
+
+@pytest.mark.parametrize("over,expect", [
+    (dict(tol=0.0), -1), (dict(tol=1.0), -1), (dict(tol=float("nan")), -5),
+    (dict(d=0), -1), (dict(d=33), -6), (dict(leaf=0), -1), (dict(m=0), -1),
+    (dict(entry=9), -1), (dict(X=None), -1), (dict(params=None), -1),
+])
+def test_invalid_arguments_rejected_on_host(over, expect):
+    st, out = _call(**over)
+    assert st == expect
+    assert out.value is None
+
+
+def test_result_accessors_reject_null():
+    from paper_1901_06101_amd import _binding
+    lib = _binding.load(LIB)
+    assert lib.hb_result_rank(None, 0) == -1
+    assert lib.hb_result_nblocks(None) == -1
+    assert lib.hb_result_copy(None, 0, None, None, None, None) == -1
+    lib.hb_result_free(None)
