@@ -66,7 +66,7 @@ def main():
     Y = torch.tensor(wl["Y"], device=dev) if wl.get("Y") is not None else None
     p = hb.params(dim=(wl["X"].shape[1] if wl.get("X") is not None else 0), h=wl.get("h", 0.0),
                   gauss_c=wl.get("gauss_c", 1.0), wavenumber=wl.get("wavenumber", 0.0),
-                  seed=wl["seed"], record_tape=1)
+                  seed=wl["seed"])
     if wl["entry"] == hb.HB_K_LOWRANK_SPIKES:
         p["G1"] = torch.tensor(wl["G1"], device=dev)
         p["G2"] = torch.tensor(wl["G2"], device=dev)

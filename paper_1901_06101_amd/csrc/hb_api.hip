@@ -14,8 +14,10 @@
 #include <cstdint>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/hbaca.h"
@@ -43,18 +45,93 @@ struct HbError {
   } while (0)
 
 // --------------------------------------------------------- device memory ---
-static void keep_pool_memory() {
-  // keep freed stream-ordered allocations in the pool across calls
-  static bool done = false;
-  if (done) return;
-  int dev = 0;
-  hipMemPool_t pool;
-  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-    uint64_t thr = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+// Caching device allocator.  Blocks are rounded up to size classes (four per
+// octave, at least 256 bytes), obtained once with hipMalloc and never given
+// back to the driver: a freed block goes to a free list tagged with the stream
+// whose work last used it and is reused only by work on that same stream
+// (stream order makes the reuse safe), or by any stream once the device has
+// been synchronised (result memory).  This keeps allocation off the critical
+// path: a call allocates and frees a few hundred buffers.
+class BlockCache {
+ public:
+  static BlockCache& get() {
+    static BlockCache c;
+    return c;
   }
-  done = true;
-}
+  void* alloc(size_t bytes, hipStream_t st) {
+    const size_t cls = size_class(bytes);
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      int dev = 0;
+      (void)hipGetDevice(&dev);
+      auto& lst = free_[cls];
+      for (size_t i = lst.size(); i-- > 0;) {
+        const Entry& e = lst[i];
+        if (e.dev == dev && (e.st == st || e.idle)) {
+          void* p = e.ptr;
+          lst.erase(lst.begin() + (ptrdiff_t)i);
+          return p;
+        }
+      }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, cls) != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      trim();
+      if (hipMalloc(&p, cls) != hipSuccess || p == nullptr) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+    }
+    std::lock_guard<std::mutex> g(mu_);
+    size_[p] = cls;
+    return p;
+  }
+  // `idle`: the device has finished every use of the block
+  void release(void* p, hipStream_t st, bool idle) {
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = size_.find(p);
+    if (it == size_.end()) return;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    free_[it->second].push_back(Entry{p, it->second, st, idle, dev});
+  }
+
+ private:
+  struct Entry {
+    void* ptr;
+    size_t bytes;
+    hipStream_t st;
+    bool idle;
+    int dev;
+  };
+  static size_t size_class(size_t b) {
+    size_t c = 256;
+    while (c < b) {
+      // four classes per octave: c, 1.25c, 1.5c, 1.75c
+      const size_t q = c / 4;
+      if (c + q >= b) return c + q;
+      if (c + 2 * q >= b) return c + 2 * q;
+      if (c + 3 * q >= b) return c + 3 * q;
+      c *= 2;
+    }
+    return c;
+  }
+  // out of memory: give every idle cached block back and try again
+  void trim() {
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto& kv : free_)
+      for (auto& e : kv.second) {
+        (void)hipFree(e.ptr);
+        size_.erase(e.ptr);
+      }
+    free_.clear();
+  }
+  std::mutex mu_;
+  std::unordered_map<size_t, std::vector<Entry>> free_;  // by size class
+  std::unordered_map<void*, size_t> size_;
+};
 
 struct DevMem {
   std::vector<void*> ptrs;
@@ -62,8 +139,8 @@ struct DevMem {
   bool sync_free = false;  // results outlive the caller's stream
   void* alloc(size_t bytes) {
     if (bytes == 0) bytes = 16;
-    void* p = nullptr;
-    if (hipMallocAsync(&p, bytes, st) != hipSuccess || p == nullptr) throw HbError{HB_ENOMEM};
+    void* p = BlockCache::get().alloc(bytes, st);
+    if (p == nullptr) throw HbError{HB_ENOMEM};
     ptrs.push_back(p);
     return p;
   }
@@ -82,9 +159,9 @@ struct DevMem {
     return out;
   }
   void release() {
-    if (sync_free && !ptrs.empty()) (void)hipDeviceSynchronize();
-    for (void* p : ptrs) (void)hipFreeAsync(p, sync_free ? nullptr : st);
-    if (sync_free && !ptrs.empty()) (void)hipStreamSynchronize(nullptr);
+    if (ptrs.empty()) return;
+    if (sync_free) (void)hipDeviceSynchronize();
+    for (void* p : ptrs) BlockCache::get().release(p, st, sync_free);
     ptrs.clear();
   }
   ~DevMem() { release(); }
@@ -1303,7 +1380,6 @@ static hb_status run(const CallSpec& c, hb_result** out) {
   std::unique_ptr<hb_result> R(new (std::nothrow) hb_result());
   if (!R) return HB_ENOMEM;
   hipStream_t st = c.st;
-  keep_pool_memory();
   R->keep.st = st;
   R->keep.sync_free = true;
   DevMem tmp;

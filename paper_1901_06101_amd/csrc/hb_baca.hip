@@ -39,7 +39,7 @@ struct GramCfg {
 // X is column-major with leading dimension ld and `nrows` rows.  The result
 // lands in sG (GT x DMAX).  All threads of the block must call it.
 template <typename T, int DMAX>
-__device__ void gram_tile(const T* __restrict__ X, int64_t ld, int nrows, int t0, int tw, int k0,
+__device__ __forceinline__ void gram_tile(const T* __restrict__ X, int64_t ld, int nrows, int t0, int tw, int k0,
                           int dk, T* sXs, T* sKs, T* sG) {
   using C = GramCfg<T, DMAX>;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -94,7 +94,7 @@ __device__ void gram_tile(const T* __restrict__ X, int64_t ld, int nrows, int t0
 // Upper Cholesky factor in place (G = T^H T, T stored over G's upper part);
 // returns false on a pivot <= 0.  Single thread.
 template <typename T, int DMAX>
-__device__ bool chol_upper(T* G, int n) {
+__device__ __forceinline__ bool chol_upper(T* G, int n) {
   for (int j = 0; j < n; ++j) {
     double s = sc_re(G[j * DMAX + j]);
     for (int k = 0; k < j; ++k) s -= sc_abs2(G[k * DMAX + j]);
@@ -115,7 +115,7 @@ __device__ bool chol_upper(T* G, int n) {
 // tid + s * NT) with panel vectors x[s][0..nrow).  `excl[idx] != 0` removes a
 // candidate.  Writes the nsel chosen indices to out[].  Destroys x.
 template <typename T, int DMAX, int RPT>
-__device__ void qrcp_select(T (&x)[RPT][DMAX], int ncand_total, const unsigned char* excl,
+__device__ __forceinline__ void qrcp_select(T (&x)[RPT][DMAX], int ncand_total, const unsigned char* excl,
                             int nrow, int nsel, int* out, T* sPiv, double (*redv)[NW],
                             int (*redi)[NW]) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;

@@ -148,30 +148,69 @@ __device__ inline hb_cplx sc_shfl_xor(hb_cplx v, int m) {
   return hb_cplx{__shfl_xor(v.re, m, HB_WAVE), __shfl_xor(v.im, m, HB_WAVE)};
 }
 
-// Sum over groups of G adjacent lanes (G a power of two <= 64).
-template <int G> __device__ inline double group_sum(double v) {
-#pragma unroll
-  for (int m = G / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, HB_WAVE);
-  return v;
+// Butterfly partner exchange inside a wave.  Steps 1 and 2 swap lanes
+// inside a quad, step 4 mirrors each half-row of 8 lanes and step 8 mirrors
+// each row of 16 lanes: all four are DPP moves (no LDS round trip).  Applied
+// in ascending order, each step pairs a lane with one holding the partial sum
+// of the other half of its group, so a butterfly sum ends with the same
+// value in every lane.  Steps 16 and 32 cross rows and use a shuffle.
+template <int CTRL> __device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
+template <int CTRL> __device__ inline float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int M, typename R> __device__ inline R bfly(R v) {
+  if constexpr (M == 1) return dpp_move<0xB1>(v);        // quad_perm(1,0,3,2)
+  else if constexpr (M == 2) return dpp_move<0x4E>(v);   // quad_perm(2,3,0,1)
+  else if constexpr (M == 4) return dpp_move<0x141>(v);  // row_half_mirror
+  else if constexpr (M == 8) return dpp_move<0x140>(v);  // row_mirror
+  else return __shfl_xor(v, M, HB_WAVE);
+}
+template <int M> __device__ inline hb_cplx bfly_sc(hb_cplx v) {
+  return hb_cplx{bfly<M>(v.re), bfly<M>(v.im)};
+}
+template <int M> __device__ inline double bfly_sc(double v) { return bfly<M>(v); }
+template <int M> __device__ inline float bfly_sc(float v) { return bfly<M>(v); }
+
+template <int G, int M = 1> __device__ inline double group_sum_step(double v) {
+  if constexpr (M >= G) return v;
+  else return group_sum_step<G, 2 * M>(v + bfly<M>(v));
+}
+template <int G, typename T, int M = 1> __device__ inline T group_sum_sc_step(T v) {
+  if constexpr (M >= G) return v;
+  else return group_sum_sc_step<G, T, 2 * M>(sc_add(v, bfly_sc<M>(v)));
+}
+
+// Sum over groups of G adjacent lanes (G a power of two <= 64); all lanes of
+// a group must be active, and all receive the same value.
+template <int G> __device__ inline double group_sum(double v) { return group_sum_step<G>(v); }
 template <int G, typename T> __device__ inline T group_sum_sc(T v) {
-#pragma unroll
-  for (int m = G / 2; m >= 1; m >>= 1) v = sc_add(v, sc_shfl_xor(v, m));
-  return v;
+  return group_sum_sc_step<G, T>(v);
+}
+
+template <int M> __device__ inline void argmax_step(double& val, int& idx) {
+  const double ov = bfly<M>(val);
+  int oi;
+  if constexpr (M <= 8) oi = __builtin_amdgcn_mov_dpp(idx, M == 1 ? 0xB1 : M == 2 ? 0x4E : M == 4 ? 0x141 : 0x140, 0xF, 0xF, false);
+  else oi = __shfl_xor(idx, M, HB_WAVE);
+  if (ov > val || (ov == val && oi < idx)) {
+    val = ov;
+    idx = oi;
+  }
 }
 
 // Wave-wide argmax of (val, idx): larger value wins, equal values go to the
 // lower index.  Every lane gets the winner.
 __device__ inline void wave_argmax(double& val, int& idx) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    double ov = __shfl_xor(val, m, HB_WAVE);
-    int oi = __shfl_xor(idx, m, HB_WAVE);
-    if (ov > val || (ov == val && oi < idx)) {
-      val = ov;
-      idx = oi;
-    }
-  }
+  argmax_step<1>(val, idx);
+  argmax_step<2>(val, idx);
+  argmax_step<4>(val, idx);
+  argmax_step<8>(val, idx);
+  argmax_step<16>(val, idx);
+  argmax_step<32>(val, idx);
 }
 
 __device__ inline double wave_sum(double v) { return group_sum<64>(v); }

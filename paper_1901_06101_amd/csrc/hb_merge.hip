@@ -17,9 +17,13 @@
 namespace {
 
 constexpr int MC_ALL = 256;
+// reflector entries read from LDS per batch in the TSQR inner products (the
+// entries below the diagonal step are stored as zeros, so every lane runs the
+// same straight-line code)
+constexpr int TQ_CH = 8;
 
 template <typename T>
-__device__ inline T node_R(const T* store, const T* alpha, const QRNodeDev& N, int i, int j) {
+__device__ __forceinline__ T node_R(const T* store, const T* alpha, const QRNodeDev& N, int i, int j) {
   // R(i, j) of a factored node (i < steps, j < k)
   if (i < j) return store[N.store + (int64_t)j * MC_ALL + i];
   if (i == j) return alpha[N.ab + j];
@@ -27,7 +31,7 @@ __device__ inline T node_R(const T* store, const T* alpha, const QRNodeDev& N, i
 }
 
 template <typename T, int KMAX, int NQ, int SEG>
-__global__ __launch_bounds__(KMAX* NQ) void tsqr_factor_kernel(const QRNodeDev* __restrict__ nodes,
+__global__ __launch_bounds__(KMAX* NQ) __attribute__((amdgpu_waves_per_eu(1, 2))) void tsqr_factor_kernel(const QRNodeDev* __restrict__ nodes,
                                                               const QRNodeDev* __restrict__ below,
                                                               T* __restrict__ store,
                                                               T* __restrict__ alpha,
@@ -115,15 +119,23 @@ __global__ __launch_bounds__(KMAX* NQ) void tsqr_factor_kernel(const QRNodeDev* 
       if (be != 0.0) {
         T w = sc_zero<T>();
 #pragma unroll
-        for (int s = 0; s < SEG; ++s) {
-          const int rho = s * NQ + q;
-          if (rho >= st) sc_cfma(w, sV[buf][rho], x[s]);
+        for (int s0 = 0; s0 < SEG; s0 += TQ_CH) {
+          T vv[TQ_CH];
+#pragma unroll
+          for (int u = 0; u < TQ_CH; ++u) vv[u] = sV[buf][(s0 + u) * NQ + q];
+#pragma unroll
+          for (int u = 0; u < TQ_CH; ++u) sc_cfma(w, vv[u], x[s0 + u]);
+          __builtin_amdgcn_sched_barrier(0);
         }
         w = group_sum_sc<NQ>(w);
 #pragma unroll
-        for (int s = 0; s < SEG; ++s) {
-          const int rho = s * NQ + q;
-          if (rho >= st) sc_axpy_neg(x[s], be, sV[buf][rho], w);
+        for (int s0 = 0; s0 < SEG; s0 += TQ_CH) {
+          T vv[TQ_CH];
+#pragma unroll
+          for (int u = 0; u < TQ_CH; ++u) vv[u] = sV[buf][(s0 + u) * NQ + q];
+#pragma unroll
+          for (int u = 0; u < TQ_CH; ++u) sc_axpy_neg(x[s0 + u], be, vv[u], w);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
@@ -136,7 +148,7 @@ __global__ __launch_bounds__(KMAX* NQ) void tsqr_factor_kernel(const QRNodeDev* 
 }
 
 template <typename T, int KMAX, int NQ, int SEG>
-__global__ __launch_bounds__(KMAX* NQ) void tsqr_apply_kernel(const QRApplyDev* __restrict__ jobs,
+__global__ __launch_bounds__(KMAX* NQ) __attribute__((amdgpu_waves_per_eu(1, 2))) void tsqr_apply_kernel(const QRApplyDev* __restrict__ jobs,
                                                              const T* __restrict__ store,
                                                              const double* __restrict__ beta) {
   constexpr int MC = MC_ALL;
@@ -161,26 +173,44 @@ __global__ __launch_bounds__(KMAX* NQ) void tsqr_apply_kernel(const QRApplyDev* 
     }
     z[s] = v;
   }
+  // reflector st is read from HBM one step ahead of its use (one element
+  // per thread, MC <= NTH), so the load latency overlaps the previous step
+  static_assert(MC <= NTH, "one reflector element per thread");
+  auto vload = [&](int st) -> T {
+    return (st >= 0 && tid >= st && tid < rows) ? store[J.store + (int64_t)st * MC + tid]
+                                                : sc_zero<T>();
+  };
+  T vnext = vload(steps - 1);
+  double bnext = steps > 0 ? beta[J.ab + steps - 1] : 0.0;
   int buf = 0;
   for (int st = steps - 1; st >= 0; --st) {
-    for (int e = tid; e < MC; e += NTH)
-      sV[buf][e] = (e >= st && e < rows) ? store[J.store + (int64_t)st * MC + e] : sc_zero<T>();
-    if (tid == 0) sB[buf] = beta[J.ab + st];
+    if (tid < MC) sV[buf][tid] = vnext;
+    if (tid == 0) sB[buf] = bnext;
     __syncthreads();
+    vnext = vload(st - 1);
+    if (st > 0) bnext = beta[J.ab + st - 1];
     if (j < r) {
       const double be = sB[buf];
       if (be != 0.0) {
         T w = sc_zero<T>();
 #pragma unroll
-        for (int s = 0; s < SEG; ++s) {
-          const int rho = s * NQ + q;
-          if (rho >= st) sc_cfma(w, sV[buf][rho], z[s]);
+        for (int s0 = 0; s0 < SEG; s0 += TQ_CH) {
+          T vv[TQ_CH];
+#pragma unroll
+          for (int u = 0; u < TQ_CH; ++u) vv[u] = sV[buf][(s0 + u) * NQ + q];
+#pragma unroll
+          for (int u = 0; u < TQ_CH; ++u) sc_cfma(w, vv[u], z[s0 + u]);
+          __builtin_amdgcn_sched_barrier(0);
         }
         w = group_sum_sc<NQ>(w);
 #pragma unroll
-        for (int s = 0; s < SEG; ++s) {
-          const int rho = s * NQ + q;
-          if (rho >= st) sc_axpy_neg(z[s], be, sV[buf][rho], w);
+        for (int s0 = 0; s0 < SEG; s0 += TQ_CH) {
+          T vv[TQ_CH];
+#pragma unroll
+          for (int u = 0; u < TQ_CH; ++u) vv[u] = sV[buf][(s0 + u) * NQ + q];
+#pragma unroll
+          for (int u = 0; u < TQ_CH; ++u) sc_axpy_neg(z[s0 + u], be, vv[u], w);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
@@ -197,7 +227,7 @@ __global__ __launch_bounds__(KMAX* NQ) void tsqr_apply_kernel(const QRApplyDev* 
 
 
 template <typename T, int KMAX, int NQ, int SEG>
-__global__ __launch_bounds__(KMAX* NQ) void tsqr_applyh_kernel(const QRApplyHDev* __restrict__ jobs,
+__global__ __launch_bounds__(KMAX* NQ) __attribute__((amdgpu_waves_per_eu(1, 2))) void tsqr_applyh_kernel(const QRApplyHDev* __restrict__ jobs,
                                                               const T* __restrict__ store,
                                                               const double* __restrict__ beta) {
   constexpr int MC = MC_ALL;
@@ -215,26 +245,43 @@ __global__ __launch_bounds__(KMAX* NQ) void tsqr_applyh_kernel(const QRApplyHDev
     const int rho = s * NQ + q;
     z[s] = (j < r && rho < rows) ? Zin[(int64_t)j * J.ldin + rho] : sc_zero<T>();
   }
+  // reflector st is read from HBM one step ahead of its use
+  static_assert(MC <= NTH, "one reflector element per thread");
+  auto vload = [&](int st) -> T {
+    return (st < steps && tid >= st && tid < rows) ? store[J.store + (int64_t)st * MC + tid]
+                                                   : sc_zero<T>();
+  };
+  T vnext = vload(0);
+  double bnext = steps > 0 ? beta[J.ab] : 0.0;
   int buf = 0;
   for (int st = 0; st < steps; ++st) {
-    for (int e = tid; e < MC; e += NTH)
-      sV[buf][e] = (e >= st && e < rows) ? store[J.store + (int64_t)st * MC + e] : sc_zero<T>();
-    if (tid == 0) sB[buf] = beta[J.ab + st];
+    if (tid < MC) sV[buf][tid] = vnext;
+    if (tid == 0) sB[buf] = bnext;
     __syncthreads();
+    vnext = vload(st + 1);
+    if (st + 1 < steps) bnext = beta[J.ab + st + 1];
     if (j < r) {
       const double be = sB[buf];
       if (be != 0.0) {
         T w = sc_zero<T>();
 #pragma unroll
-        for (int s = 0; s < SEG; ++s) {
-          const int rho = s * NQ + q;
-          if (rho >= st) sc_cfma(w, sV[buf][rho], z[s]);
+        for (int s0 = 0; s0 < SEG; s0 += TQ_CH) {
+          T vv[TQ_CH];
+#pragma unroll
+          for (int u = 0; u < TQ_CH; ++u) vv[u] = sV[buf][(s0 + u) * NQ + q];
+#pragma unroll
+          for (int u = 0; u < TQ_CH; ++u) sc_cfma(w, vv[u], z[s0 + u]);
+          __builtin_amdgcn_sched_barrier(0);
         }
         w = group_sum_sc<NQ>(w);
 #pragma unroll
-        for (int s = 0; s < SEG; ++s) {
-          const int rho = s * NQ + q;
-          if (rho >= st) sc_axpy_neg(z[s], be, sV[buf][rho], w);
+        for (int s0 = 0; s0 < SEG; s0 += TQ_CH) {
+          T vv[TQ_CH];
+#pragma unroll
+          for (int u = 0; u < TQ_CH; ++u) vv[u] = sV[buf][(s0 + u) * NQ + q];
+#pragma unroll
+          for (int u = 0; u < TQ_CH; ++u) sc_axpy_neg(z[s0 + u], be, vv[u], w);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
@@ -310,8 +357,8 @@ __global__ void copy_list_kernel(const CopyDev* __restrict__ jobs) {
 // One-sided (Hestenes) Jacobi on the columns of R (p x k) with the classic
 // round-robin pairing: k/2 disjoint column pairs per round, each rotated by
 // a group of G lanes.  Column norms are recomputed at the start of every
-// sweep and the two norms of a rotated pair are accumulated while it is
-// rotated, so a pair costs one dot product.  Sweeps end when no pair has
+// sweep and updated in closed form after each rotation (recomputed when the
+// update would cancel).  Sweeps end when no pair has
 // |a_i^H a_j| > tol |a_i| |a_j|; a column whose norm is below the rounding
 // level of R (1e-16 sqrt(p) ||R||_F) takes no part.  The rotation tangent is
 // evaluated without overflow for large zeta.  R lives in LDS when it fits,
@@ -321,18 +368,30 @@ __global__ void copy_list_kernel(const CopyDev* __restrict__ jobs) {
 constexpr int SVD_NT = 512;
 
 template <typename T, int G>
-__device__ int jacobi_rounds(T* A, int lda, int p, int k, int K, double tol, double negl,
+__device__ __forceinline__ int jacobi_rounds(T* A, int lda, int p, int k, int K, double tol, double negl,
                              double* nrm, int* sRot) {
   const int tid = threadIdx.x;
   const int grp = tid / G, gl = tid % G;
   constexpr int ngrp = SVD_NT / G;
+  // elements per lane loaded together before use (LDS latency is paid once
+  // per chunk, not per element); indexes past p are clamped and masked
+  constexpr int CH = 8;
   const int npairs = K / 2;
+  const double tol2 = tol * tol;
   int sweep = 0;
   for (; sweep < 60; ++sweep) {
     // fresh column norms
     for (int j = grp; j < k; j += ngrp) {
+      const T* x = A + (int64_t)j * lda;
       double s2 = 0.0;
-      for (int i = gl; i < p; i += G) s2 += sc_abs2(A[(int64_t)j * lda + i]);
+      for (int i0 = gl; i0 < p; i0 += CH * G) {
+        T u[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) u[c] = x[min(i0 + c * G, p - 1)];
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+          if (i0 + c * G < p) s2 += sc_abs2(u[c]);
+      }
       s2 = group_sum<G>(s2);
       if (gl == 0) nrm[j] = s2;
     }
@@ -359,31 +418,62 @@ __device__ int jacobi_rounds(T* A, int lda, int p, int k, int K, double tol, dou
         T* xa = A + (int64_t)a * lda;
         T* xb = A + (int64_t)b * lda;
         T g = sc_zero<T>();
-        for (int i = gl; i < p; i += G) sc_cfma(g, xa[i], xb[i]);
+        for (int i0 = gl; i0 < p; i0 += CH * G) {
+          T u[CH], v[CH];
+#pragma unroll
+          for (int c = 0; c < CH; ++c) {
+            const int i = min(i0 + c * G, p - 1);
+            u[c] = xa[i];
+            v[c] = xb[i];
+          }
+#pragma unroll
+          for (int c = 0; c < CH; ++c)
+            if (i0 + c * G < p) sc_cfma(g, u[c], v[c]);
+        }
         g = group_sum_sc<G, T>(g);
-        const double ag = sqrt(sc_abs2(g));
-        if (ag > tol * sqrt(al) * sqrt(bt)) {
-          const T ph = sc_scale(g, 1.0 / ag);
-          const double zeta = (bt - al) / (2.0 * ag);
+        const double g2 = sc_abs2(g);
+        if (g2 > tol2 * al * bt) {
+          const double ag = sqrt(g2);
+          const double iag = 1.0 / ag;
+          const T ph = sc_scale(g, iag);
+          const double zeta = 0.5 * (bt - al) * iag;
           const double az = fabs(zeta);
           // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), without overflow
-          const double den = az > 1.0 ? az * (1.0 + sqrt(1.0 + (1.0 / az) * (1.0 / az)))
-                                      : az + sqrt(1.0 + az * az);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / den;
-          const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-          double na = 0.0, nb = 0.0;
-          for (int i = gl; i < p; i += G) {
-            const T u = xa[i];
-            const T v = sc_mulc(xb[i], ph);  // y * conj(phase)
-            const T u2 = sc_sub(sc_scale(u, c), sc_scale(v, s));
-            const T v2 = sc_add(sc_scale(u, s), sc_scale(v, c));
-            xa[i] = u2;
-            xb[i] = v2;
-            na += sc_abs2(u2);
-            nb += sc_abs2(v2);
+          double tt = az > 1.0e150 ? 0.5 / az : 1.0 / (az + sqrt(1.0 + az * az));
+          if (zeta < 0.0) tt = -tt;
+          const double c = rsqrt(1.0 + tt * tt), s = c * tt;
+          for (int i0 = gl; i0 < p; i0 += CH * G) {
+            T u[CH], v[CH];
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+              const int i = min(i0 + e * G, p - 1);
+              u[e] = xa[i];
+              v[e] = xb[i];
+            }
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+              const int i = i0 + e * G;
+              if (i < p) {
+                const T vv = sc_mulc(v[e], ph);  // y * conj(phase)
+                xa[i] = sc_sub(sc_scale(u[e], c), sc_scale(vv, s));
+                xb[i] = sc_add(sc_scale(u[e], s), sc_scale(vv, c));
+              }
+            }
           }
-          na = group_sum<G>(na);
-          nb = group_sum<G>(nb);
+          // squared norms after the rotation: |a'|^2 = |a|^2 - t |g|,
+          // |b'|^2 = |b|^2 + t |g|; a norm that shrinks below a quarter of its
+          // old value is recomputed, as the update then cancels
+          double na = al - tt * ag, nb = bt + tt * ag;
+          if (na < 0.25 * al || nb < 0.25 * bt) {
+            na = 0.0;
+            nb = 0.0;
+            for (int i = gl; i < p; i += G) {
+              na += sc_abs2(xa[i]);
+              nb += sc_abs2(xb[i]);
+            }
+            na = group_sum<G>(na);
+            nb = group_sum<G>(nb);
+          }
           if (gl == 0) {
             nrm[a] = na;
             nrm[b] = nb;
@@ -400,11 +490,10 @@ __device__ int jacobi_rounds(T* A, int lda, int p, int k, int K, double tol, dou
   return sweep + 1;
 }
 
-template <typename T>
+template <typename T, bool INLDS>
 __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict__ jobs,
                                                      const T* __restrict__ store,
-                                                     const T* __restrict__ alpha, double eps,
-                                                     int lds_mode) {
+                                                     const T* __restrict__ alpha, double eps) {
   const SVDJobDev Jb = jobs[blockIdx.x];
   const int p = Jb.p, k = Jb.k, tid = threadIdx.x;
   extern __shared__ unsigned char smem_raw[];
@@ -412,8 +501,9 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
   __shared__ double sS[512];
   __shared__ double sN[512];
   __shared__ double sRed[SVD_NT / 64];
-  // lds_mode: 1 = R in LDS, 0 = R in the HBM workspace
-  T* A = lds_mode == 1 ? (T*)smem_raw : (T*)Jb.A;
+  // R lives in LDS (INLDS) or in the HBM workspace; the choice is a template
+  // parameter so that LDS accesses compile to LDS instructions
+  T* A = INLDS ? (T*)smem_raw : (T*)Jb.A;
   QRNodeDev N;
   N.store = Jb.store;
   N.ab = Jb.ab;
@@ -436,19 +526,29 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
   int sweeps = 0;
   if (k >= 2) {
     const int npairs = K / 2;
-    if (npairs * 32 <= SVD_NT) sweeps = jacobi_rounds<T, 32>(A, p, p, k, K, tol, negl, sN, &sRot);
-    else if (npairs * 16 <= SVD_NT) sweeps = jacobi_rounds<T, 16>(A, p, p, k, K, tol, negl, sN, &sRot);
-    else if (npairs * 8 <= SVD_NT) sweeps = jacobi_rounds<T, 8>(A, p, p, k, K, tol, negl, sN, &sRot);
-    else if (npairs * 4 <= SVD_NT) sweeps = jacobi_rounds<T, 4>(A, p, p, k, K, tol, negl, sN, &sRot);
+    // lanes per pair: up to 8, fewer for short columns (at most two chunks
+    // of CH elements per lane) and for many pairs (all pairs of a round at once)
+    const int gp = p <= 16 ? 2 : (p <= 32 ? 4 : 8);
+    const int gk = npairs * 8 <= SVD_NT ? 8 : (npairs * 4 <= SVD_NT ? 4 : 2);
+    const int g = gp < gk ? gp : gk;
+    if (g == 8) sweeps = jacobi_rounds<T, 8>(A, p, p, k, K, tol, negl, sN, &sRot);
+    else if (g == 4) sweeps = jacobi_rounds<T, 4>(A, p, p, k, K, tol, negl, sN, &sRot);
     else sweeps = jacobi_rounds<T, 2>(A, p, p, k, K, tol, negl, sN, &sRot);
   }
-  // column norms, descending order (ties by index), eps-rank
-  for (int j = tid; j < k; j += SVD_NT) {
-    double s2 = 0.0;
-    for (int i = 0; i < p; ++i) s2 += sc_abs2(A[(int64_t)j * p + i]);
-    sS[j] = sqrt(s2);
+  // column norms (16 lanes per column), descending order (ties by index),
+  // eps-rank
+  {
+    constexpr int G = 16;
+    const int grp = tid / G, gl = tid % G;
+    for (int j = grp; j < k; j += SVD_NT / G) {
+      double s2 = 0.0;
+      for (int i = gl; i < p; i += G) s2 += sc_abs2(A[(int64_t)j * p + i]);
+      s2 = group_sum<G>(s2);
+      if (gl == 0) sS[j] = sqrt(s2);
+    }
   }
   __syncthreads();
+  __shared__ int sPerm[512];
   for (int j = tid; j < k; j += SVD_NT) {
     const double sj = sS[j];
     int pos = 0;
@@ -457,6 +557,7 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
       if (si > sj || (si == sj && i < j)) ++pos;
     }
     Jb.perm[pos] = j;
+    sPerm[pos] = j;
     Jb.S[pos] = sj;
     sN[pos] = sj;
   }
@@ -471,23 +572,34 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
     Jb.rank[0] = r;
     Jb.rank[1] = sweeps;
   }
+  // normalise the columns in place: A(:, j) becomes the left singular vector
+  for (int e = tid; e < p * k; e += SVD_NT) {
+    const double sj = sS[e / p];
+    A[e] = sj > 0.0 ? sc_scale(A[e], 1.0 / sj) : sc_zero<T>();
+  }
   __syncthreads();
   const int r = sR;
   T* Xr = (T*)Jb.Xr;
   T* Yr = (T*)Jb.Yr;
   for (int e = tid; e < p * k; e += SVD_NT) {
     const int i = e % p, pos = e / p;
-    const int j = Jb.perm[pos];
-    const double sj = sN[pos];
-    Xr[e] = sj > 0.0 ? sc_scale(A[(int64_t)j * p + i], 1.0 / sj) : sc_zero<T>();
+    Xr[e] = A[(int64_t)sPerm[pos] * p + i];
   }
-  __syncthreads();
-  // right singular vectors of the kept part: Y_r = R^H X_r diag(1 / S_r)
-  for (int e = tid; e < k * r; e += SVD_NT) {
-    const int i = e % k, pos = e / k;
-    T acc = sc_zero<T>();
-    for (int t = 0; t < p; ++t) sc_cfma(acc, Rat(t, i), Xr[(int64_t)pos * p + t]);
-    Yr[(int64_t)pos * k + i] = sc_scale(acc, 1.0 / sN[pos]);
+  // right singular vectors of the kept part: Y_r = R^H X_r diag(1 / S_r);
+  // 16 lanes per output element share the inner index, R upper triangular
+  {
+    constexpr int G = 16;
+    const int grp = tid / G, gl = tid % G;
+    for (int o = grp; o < k * r; o += SVD_NT / G) {
+      const int i = o % k, pos = o / k;
+      const T* x = A + (int64_t)sPerm[pos] * p;
+      // a TSQR node's R is upper trapezoidal; an explicit R is full
+      const int tmax = Jb.from_node ? (i < p - 1 ? i : p - 1) : p - 1;
+      T acc = sc_zero<T>();
+      for (int t = gl; t <= tmax; t += G) sc_cfma(acc, Rat(t, i), x[t]);
+      acc = group_sum_sc<G, T>(acc);
+      if (gl == 0) Yr[(int64_t)pos * k + i] = sc_scale(acc, 1.0 / sN[pos]);
+    }
   }
 }
 
@@ -730,17 +842,27 @@ int svd_launch(int scalar, const SVDJobDev* jobs, int n, int kmax_batch, int pma
   if (force_storage == 1) mode = 0;
   const size_t sh = mode == 1 ? a_bytes : 0;
   if (scalar == 0) {
-    if (sh > 64 * 1024)
-      (void)hipFuncSetAttribute((const void*)svd_kernel<double>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL((svd_kernel<double>), dim3(n), dim3(SVD_NT), sh, st, jobs,
-                       (const double*)store, (const double*)alpha, eps, mode);
+    if (mode == 1) {
+      if (sh > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)svd_kernel<double, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+      hipLaunchKernelGGL((svd_kernel<double, true>), dim3(n), dim3(SVD_NT), sh, st, jobs,
+                         (const double*)store, (const double*)alpha, eps);
+    } else {
+      hipLaunchKernelGGL((svd_kernel<double, false>), dim3(n), dim3(SVD_NT), 0, st, jobs,
+                         (const double*)store, (const double*)alpha, eps);
+    }
   } else {
-    if (sh > 64 * 1024)
-      (void)hipFuncSetAttribute((const void*)svd_kernel<hb_cplx>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL((svd_kernel<hb_cplx>), dim3(n), dim3(SVD_NT), sh, st, jobs,
-                       (const hb_cplx*)store, (const hb_cplx*)alpha, eps, mode);
+    if (mode == 1) {
+      if (sh > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)svd_kernel<hb_cplx, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+      hipLaunchKernelGGL((svd_kernel<hb_cplx, true>), dim3(n), dim3(SVD_NT), sh, st, jobs,
+                         (const hb_cplx*)store, (const hb_cplx*)alpha, eps);
+    } else {
+      hipLaunchKernelGGL((svd_kernel<hb_cplx, false>), dim3(n), dim3(SVD_NT), 0, st, jobs,
+                         (const hb_cplx*)store, (const hb_cplx*)alpha, eps);
+    }
   }
   return (int)hipGetLastError();
 }
