@@ -765,21 +765,23 @@ static void run_svds(Engine& E, std::vector<SVDJobDev>& jobs, const void* store,
     const size_t p = jobs[a].p, k = jobs[a].k;
     kmax = std::max(kmax, (int)k);
     pmax = std::max(pmax, (int)p);
-    sz.push_back(p * k * E.sb());   // HBM workspace (used when R exceeds LDS)
+    sz.push_back(p * k * E.sb());   // HBM workspace (R^H when it exceeds LDS)
     sz.push_back(k * 8);
     sz.push_back(k * 4);
     sz.push_back(p * k * E.sb());
     sz.push_back(k * k * E.sb());
+    sz.push_back(p * k * E.sb());   // HBM workspace (R2^H)
   }
   std::vector<char*> bufs = E.tmp.carve(sz);
   for (size_t a = 0; a < nj; ++a) {
     SVDJobDev& J = jobs[a];
-    J.A = bufs[5 * a + 0];
-    J.S = (double*)bufs[5 * a + 1];
-    J.perm = (int32_t*)bufs[5 * a + 2];
+    J.A = bufs[6 * a + 0];
+    J.S = (double*)bufs[6 * a + 1];
+    J.perm = (int32_t*)bufs[6 * a + 2];
     J.rank = dr + 2 * a;
-    J.Xr = bufs[5 * a + 3];
-    J.Yr = bufs[5 * a + 4];
+    J.Xr = bufs[6 * a + 3];
+    J.Yr = bufs[6 * a + 4];
+    J.W = bufs[6 * a + 5];
     outs[a] = SvdOut{J.Xr, J.Yr, J.S, J.rank, J.p, J.k};
   }
   SVDJobDev* dj = upload(E.tmp, jobs, E.st);

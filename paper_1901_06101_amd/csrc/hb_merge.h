@@ -80,7 +80,9 @@ struct SVDJobDev {
   int32_t ab;
   int32_t pad2;
   const void* R;   // explicit R, column-major ld p
-  void* A;         // workspace p x k (becomes X S) when it does not fit in LDS
+  void* A;         // HBM workspace, p x k elements (R^H and its QR when they
+                   // do not fit in LDS)
+  void* W;         // HBM workspace, p x k elements (R2^H)
   double* S;       // k singular values (sorted descending on return)
   int32_t* perm;   // k: sorted position -> column
   int32_t* rank;   // out: [0] eps-rank r, [1] Jacobi sweeps used

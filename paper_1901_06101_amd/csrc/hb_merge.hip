@@ -490,116 +490,290 @@ __device__ __forceinline__ int jacobi_rounds(T* A, int lda, int p, int k, int K,
   return sweep + 1;
 }
 
+// Small SVD of R (p x k), preconditioned as in the one-sided Jacobi SVD of
+// Drmac and Veselic (2008): a QR factorisation with column pivoting of R^H,
+//   R^H P = Q2 R2   (R2 upper trapezoidal, q = min(p, k) rows),
+// followed by one-sided Jacobi on the columns of W = R2^H (p x q).  The rows
+// of R2 are strongly graded, so the Jacobi sweeps converge in a few passes.
+// With W V = U Sigma, R = (P U) Sigma (Q2 V)^H: the left singular vectors of
+// R are the rows of U permuted by P (orthonormal to the sweep tolerance) and
+// the kept right vectors follow as Y_r = R^H X_r / S_r.
+//
+// QRCP picks, at every step, the candidate column with the largest trailing
+// norm (recomputed exactly during the previous step's update) and leaves the
+// columns in place: a logical-to-physical column map is permuted instead.
+// The transposition R2 -> R2^H goes through the HBM workspace W.
+constexpr int SVD_G = 8;  // lanes per column in the QRCP updates
+
+__host__ __device__ __forceinline__ int svd_odd(int n) { return n | 1; }
+
+template <typename T>
+struct SvdSmem {
+  T* mat;        // LDS matrix region (INLDS only)
+  double* nrm2;  // 2 x nm
+  int* cp;       // 2 x p
+  double* sN;    // k
+  int* sPerm;    // k
+};
+
+// bytes of dynamic LDS for a job: [matrix | aux]; the matrix part only when
+// the matrices are held in LDS
+__host__ __device__ inline size_t svd_mat_bytes(int p, int k, size_t sb) {
+  const int q = p < k ? p : k;
+  const size_t b1 = (size_t)svd_odd(k) * p, b2 = (size_t)svd_odd(p) * q;
+  return ((b1 > b2 ? b1 : b2) * sb + 15) & ~(size_t)15;
+}
+__host__ __device__ inline size_t svd_aux_bytes(int p, int k) {
+  const int nm = p > k ? p : k;
+  return (size_t)2 * nm * 8 + (size_t)k * 8 + (((size_t)2 * p * 4 + (size_t)k * 4 + 15) & ~(size_t)15);
+}
+
 template <typename T, bool INLDS>
 __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict__ jobs,
                                                      const T* __restrict__ store,
                                                      const T* __restrict__ alpha, double eps) {
   const SVDJobDev Jb = jobs[blockIdx.x];
   const int p = Jb.p, k = Jb.k, tid = threadIdx.x;
+  const int q = p < k ? p : k;
+  const int lane = tid & 63, wid = tid >> 6;
   extern __shared__ unsigned char smem_raw[];
   __shared__ int sRot;
-  __shared__ double sS[512];
-  __shared__ double sN[512];
-  __shared__ double sRed[SVD_NT / 64];
-  // R lives in LDS (INLDS) or in the HBM workspace; the choice is a template
-  // parameter so that LDS accesses compile to LDS instructions
-  T* A = INLDS ? (T*)smem_raw : (T*)Jb.A;
+  __shared__ int sR;
+  __shared__ double sWv[SVD_NT / 64];
+  __shared__ int sWi[SVD_NT / 64];
+  // dynamic LDS layout
+  unsigned char* sp = smem_raw;
+  T* Lmat = (T*)sp;
+  if (INLDS) sp += svd_mat_bytes(p, k, sizeof(T));
+  const int nm = p > k ? p : k;
+  double* nrm2 = (double*)sp;
+  double* sN = nrm2 + 2 * nm;
+  int* cp = (int*)(sN + k);
+  int* sPerm = cp + 2 * p;
+  // B = R^H (k x p, ld ldb), W = R2^H (p x q, ld ldw); in LDS both share the
+  // matrix region, in HBM they are the A and W workspaces
+  const int ldb = INLDS ? svd_odd(k) : k;
+  const int ldw = INLDS ? svd_odd(p) : p;
+  T* B = INLDS ? Lmat : (T*)Jb.A;
+  T* W = INLDS ? Lmat : (T*)Jb.W;
+  T* Wg = (T*)Jb.W;
   QRNodeDev N;
   N.store = Jb.store;
   N.ab = Jb.ab;
   auto Rat = [&](int i, int j) -> T {
     return Jb.from_node ? node_R<T>(store, alpha, N, i, j) : ((const T*)Jb.R)[(int64_t)j * p + i];
   };
-  for (int e = tid; e < p * k; e += SVD_NT) A[e] = Rat(e % p, e / p);
+  constexpr int G = SVD_G;
+  constexpr int NGRP = SVD_NT / G;
+  constexpr int CH = 8;
+  const int grp = tid / G, gl = tid % G;
+
+  // ---- load B = R^H and the initial column norms
+  for (int e = tid; e < p * k; e += SVD_NT) {
+    const int i = e % k, j = e / k;  // B(i, j) = conj(R(j, i))
+    B[(int64_t)j * ldb + i] = sc_conj(Rat(j, i));
+  }
+  if (tid < p) {
+    cp[tid] = tid;
+    cp[p + tid] = tid;
+  }
   __syncthreads();
-  const int K = k + (k & 1);
+  for (int j = grp; j < p; j += NGRP) {
+    const T* col = B + (int64_t)j * ldb;
+    double s2 = 0.0;
+    for (int i = gl; i < k; i += G) s2 += sc_abs2(col[i]);
+    s2 = group_sum<G>(s2);
+    if (gl == 0) nrm2[j] = s2;
+  }
+  __syncthreads();
+
+  // ---- QRCP of B: q steps, two barriers each
+  int cur = 0;
+  for (int s = 0; s < q; ++s) {
+    const int nxt = cur ^ 1;
+    double* n_cur = nrm2 + cur * nm;
+    double* n_nxt = nrm2 + nxt * nm;
+    int* c_cur = cp + cur * p;
+    int* c_nxt = cp + nxt * p;
+    {
+      double v = -1.0;
+      int idx = 0x7fffffff;
+      if (tid >= s && tid < p) {
+        v = n_cur[tid];
+        idx = tid;
+      }
+      wave_argmax(v, idx);
+      if (lane == 0) {
+        sWv[wid] = v;
+        sWi[wid] = idx;
+      }
+    }
+    __syncthreads();
+    double bv = sWv[0];
+    int piv = sWi[0];
+    for (int w = 1; w < SVD_NT / 64; ++w)
+      if (sWv[w] > bv || (sWv[w] == bv && sWi[w] < piv)) {
+        bv = sWv[w];
+        piv = sWi[w];
+      }
+    const int cs = c_cur[s], cpv = c_cur[piv];
+    if (tid < p) c_nxt[tid] = tid == s ? cpv : (tid == piv ? cs : c_cur[tid]);
+    const T* vcol = B + (int64_t)cpv * ldb;
+    const T x0 = vcol[s];
+    const double sig = sqrt(n_cur[piv]);
+    T al = sc_zero<T>();
+    double be = 0.0;
+    if (sig > 0.0) {
+      al = sc_scale(sc_phase(x0), -sig);
+      be = 1.0 / (sig * (sig + sqrt(sc_abs2(x0))));
+    }
+    const T v0 = sc_sub(x0, al);
+    for (int j = s + 1 + grp; j < p; j += NGRP) {
+      T* col = B + (int64_t)(j == piv ? cs : c_cur[j]) * ldb;
+      T w = sc_zero<T>();
+      for (int i0 = s + gl; i0 < k; i0 += CH * G) {
+        T u[CH], v[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int i = min(i0 + c * G, k - 1);
+          u[c] = vcol[i];
+          v[c] = col[i];
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int i = i0 + c * G;
+          if (i < k) sc_cfma(w, i == s ? v0 : u[c], v[c]);
+        }
+      }
+      w = group_sum_sc<G, T>(w);
+      double n2 = 0.0;
+      for (int i0 = s + gl; i0 < k; i0 += CH * G) {
+        T u[CH], v[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int i = min(i0 + c * G, k - 1);
+          u[c] = vcol[i];
+          v[c] = col[i];
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int i = i0 + c * G;
+          if (i < k) {
+            T x = v[c];
+            if (be != 0.0) sc_axpy_neg(x, be, i == s ? v0 : u[c], w);
+            col[i] = x;
+            if (i > s) n2 += sc_abs2(x);
+          }
+        }
+      }
+      n2 = group_sum<G>(n2);
+      if (gl == 0) n_nxt[j] = n2;
+    }
+    __syncthreads();
+    // the pivot column is not touched after its step: its entry s becomes
+    // the diagonal of R2 (every read of x0 happened before the barrier)
+    if (tid == 0) B[(int64_t)cpv * ldb + s] = al;
+    cur = nxt;
+  }
+  __syncthreads();
+  const int* cfin = cp + cur * p;  // logical -> physical (= row of R)
+
+  // ---- W = R2^H (p x q) through the HBM workspace
+  for (int e = tid; e < p * q; e += SVD_NT) {
+    const int i = e % p, a = e / p;
+    Wg[e] = i >= a ? sc_conj(B[(int64_t)cfin[i] * ldb + a]) : sc_zero<T>();
+  }
+  __syncthreads();
+  if (INLDS) {
+    for (int e = tid; e < p * q; e += SVD_NT) W[(int64_t)(e / p) * ldw + (e % p)] = Wg[e];
+    __syncthreads();
+  }
+
+  // ---- one-sided Jacobi on the columns of W
+  const int Q = q + (q & 1);
   const double tol = 4.0e-16 * (p > 4 ? (double)p : 4.0);
-  // squared Frobenius norm of R, for the negligible-column level
   double f2 = 0.0;
-  for (int e = tid; e < p * k; e += SVD_NT) f2 += sc_abs2(A[e]);
+  for (int e = tid; e < p * q; e += SVD_NT) f2 += sc_abs2(W[(int64_t)(e / p) * ldw + (e % p)]);
   f2 = wave_sum(f2);
-  if ((tid & 63) == 0) sRed[tid >> 6] = f2;
+  if (lane == 0) sWv[wid] = f2;
   __syncthreads();
   f2 = 0.0;
-  for (int w = 0; w < SVD_NT / 64; ++w) f2 += sRed[w];
+  for (int w = 0; w < SVD_NT / 64; ++w) f2 += sWv[w];
   const double negl = 1.0e-32 * (double)(p > 1 ? p : 1) * f2;
+  double* jn = nrm2;  // Jacobi column norms (q)
   int sweeps = 0;
-  if (k >= 2) {
-    const int npairs = K / 2;
-    // lanes per pair: up to 8, fewer for short columns (at most two chunks
-    // of CH elements per lane) and for many pairs (all pairs of a round at once)
+  if (q >= 2) {
+    const int npairs = Q / 2;
     const int gp = p <= 16 ? 2 : (p <= 32 ? 4 : 8);
     const int gk = npairs * 8 <= SVD_NT ? 8 : (npairs * 4 <= SVD_NT ? 4 : 2);
     const int g = gp < gk ? gp : gk;
-    if (g == 8) sweeps = jacobi_rounds<T, 8>(A, p, p, k, K, tol, negl, sN, &sRot);
-    else if (g == 4) sweeps = jacobi_rounds<T, 4>(A, p, p, k, K, tol, negl, sN, &sRot);
-    else sweeps = jacobi_rounds<T, 2>(A, p, p, k, K, tol, negl, sN, &sRot);
-  }
-  // column norms (16 lanes per column), descending order (ties by index),
-  // eps-rank
-  {
-    constexpr int G = 16;
-    const int grp = tid / G, gl = tid % G;
-    for (int j = grp; j < k; j += SVD_NT / G) {
-      double s2 = 0.0;
-      for (int i = gl; i < p; i += G) s2 += sc_abs2(A[(int64_t)j * p + i]);
-      s2 = group_sum<G>(s2);
-      if (gl == 0) sS[j] = sqrt(s2);
-    }
+    if (g == 8) sweeps = jacobi_rounds<T, 8>(W, ldw, p, q, Q, tol, negl, jn, &sRot);
+    else if (g == 4) sweeps = jacobi_rounds<T, 4>(W, ldw, p, q, Q, tol, negl, jn, &sRot);
+    else sweeps = jacobi_rounds<T, 2>(W, ldw, p, q, Q, tol, negl, jn, &sRot);
   }
   __syncthreads();
-  __shared__ int sPerm[512];
+  // ---- singular values: column norms, sorted descending (ties by index)
+  double* sS = nrm2 + nm;
+  for (int j = grp; j < q; j += NGRP) {
+    const T* x = W + (int64_t)j * ldw;
+    double s2 = 0.0;
+    for (int i = gl; i < p; i += G) s2 += sc_abs2(x[i]);
+    s2 = group_sum<G>(s2);
+    if (gl == 0) sS[j] = sqrt(s2);
+  }
+  __syncthreads();
   for (int j = tid; j < k; j += SVD_NT) {
-    const double sj = sS[j];
-    int pos = 0;
-    for (int i = 0; i < k; ++i) {
-      const double si = sS[i];
-      if (si > sj || (si == sj && i < j)) ++pos;
+    if (j < q) {
+      const double sj = sS[j];
+      int pos = 0;
+      for (int i = 0; i < q; ++i) {
+        const double si = sS[i];
+        if (si > sj || (si == sj && i < j)) ++pos;
+      }
+      sPerm[pos] = j;
+      sN[pos] = sj;
+    } else {
+      sPerm[j] = -1;
+      sN[j] = 0.0;
     }
-    Jb.perm[pos] = j;
-    sPerm[pos] = j;
-    Jb.S[pos] = sj;
-    sN[pos] = sj;
   }
   __syncthreads();
-  __shared__ int sR;
   if (tid == 0) {
-    const double s1 = k > 0 ? sN[0] : 0.0;
+    const double s1 = q > 0 ? sN[0] : 0.0;
     int r = 0;
     if (s1 > 0.0)
-      while (r < k && sN[r] >= eps * s1) ++r;
+      while (r < q && sN[r] >= eps * s1) ++r;
     sR = r;
     Jb.rank[0] = r;
     Jb.rank[1] = sweeps;
   }
-  // normalise the columns in place: A(:, j) becomes the left singular vector
-  for (int e = tid; e < p * k; e += SVD_NT) {
-    const double sj = sS[e / p];
-    A[e] = sj > 0.0 ? sc_scale(A[e], 1.0 / sj) : sc_zero<T>();
+  for (int j = tid; j < k; j += SVD_NT) {
+    Jb.S[j] = sN[j];
+    Jb.perm[j] = sPerm[j];
   }
   __syncthreads();
   const int r = sR;
+  // ---- X = P U: X(cfin[i], pos) = W(i, sPerm[pos]) / S(pos); zero columns
+  // beyond q
   T* Xr = (T*)Jb.Xr;
-  T* Yr = (T*)Jb.Yr;
   for (int e = tid; e < p * k; e += SVD_NT) {
     const int i = e % p, pos = e / p;
-    Xr[e] = A[(int64_t)sPerm[pos] * p + i];
+    T v = sc_zero<T>();
+    if (pos < q && sN[pos] > 0.0) v = sc_scale(W[(int64_t)sPerm[pos] * ldw + i], 1.0 / sN[pos]);
+    Xr[(int64_t)pos * p + cfin[i]] = v;
   }
-  // right singular vectors of the kept part: Y_r = R^H X_r diag(1 / S_r);
-  // 16 lanes per output element share the inner index, R upper triangular
-  {
-    constexpr int G = 16;
-    const int grp = tid / G, gl = tid % G;
-    for (int o = grp; o < k * r; o += SVD_NT / G) {
-      const int i = o % k, pos = o / k;
-      const T* x = A + (int64_t)sPerm[pos] * p;
-      // a TSQR node's R is upper trapezoidal; an explicit R is full
-      const int tmax = Jb.from_node ? (i < p - 1 ? i : p - 1) : p - 1;
-      T acc = sc_zero<T>();
-      for (int t = gl; t <= tmax; t += G) sc_cfma(acc, Rat(t, i), x[t]);
-      acc = group_sum_sc<G, T>(acc);
-      if (gl == 0) Yr[(int64_t)pos * k + i] = sc_scale(acc, 1.0 / sN[pos]);
-    }
+  __syncthreads();
+  // ---- Y_r = R^H X_r diag(1 / S_r); G lanes per output, R upper trapezoidal
+  // when it comes from a TSQR node
+  T* Yr = (T*)Jb.Yr;
+  for (int o = grp; o < k * r; o += NGRP) {
+    const int i = o % k, pos = o / k;
+    const T* x = Xr + (int64_t)pos * p;
+    const int tmax = Jb.from_node ? (i < p - 1 ? i : p - 1) : p - 1;
+    T acc = sc_zero<T>();
+    for (int t = gl; t <= tmax; t += G) sc_cfma(acc, Rat(t, i), x[t]);
+    acc = group_sum_sc<G, T>(acc);
+    if (gl == 0) Yr[(int64_t)pos * k + i] = sc_scale(acc, 1.0 / sN[pos]);
   }
 }
 
@@ -834,35 +1008,26 @@ int svd_launch(int scalar, const SVDJobDev* jobs, int n, int kmax_batch, int pma
                const void* store, const void* alpha, double eps, hipStream_t st,
                int force_storage) {
   if (n == 0) return 0;
-  if (kmax_batch > 512) return -1;
+  if (kmax_batch > 512 || pmax_batch > 512) return -1;
   const size_t sb = scalar == 0 ? 8 : 16;
-  const size_t lds_cap = 150 * 1024;
-  const size_t a_bytes = (size_t)pmax_batch * kmax_batch * sb;
-  int mode = a_bytes <= lds_cap ? 1 : 0;
-  if (force_storage == 1) mode = 0;
-  const size_t sh = mode == 1 ? a_bytes : 0;
+  const size_t lds_cap = 158 * 1024;
+  const size_t aux = svd_aux_bytes(pmax_batch, kmax_batch);
+  const size_t full = svd_mat_bytes(pmax_batch, kmax_batch, sb) + aux;
+  const bool in_lds = full <= lds_cap && force_storage != 1;
+  const size_t sh = in_lds ? full : aux;
+  auto go = [&](auto kern, auto tag) {
+    using TT = decltype(tag);
+    if (sh > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL(kern, dim3(n), dim3(SVD_NT), sh, st, jobs, (const TT*)store, (const TT*)alpha,
+                       eps);
+  };
   if (scalar == 0) {
-    if (mode == 1) {
-      if (sh > 64 * 1024)
-        (void)hipFuncSetAttribute((const void*)svd_kernel<double, true>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-      hipLaunchKernelGGL((svd_kernel<double, true>), dim3(n), dim3(SVD_NT), sh, st, jobs,
-                         (const double*)store, (const double*)alpha, eps);
-    } else {
-      hipLaunchKernelGGL((svd_kernel<double, false>), dim3(n), dim3(SVD_NT), 0, st, jobs,
-                         (const double*)store, (const double*)alpha, eps);
-    }
+    if (in_lds) go(svd_kernel<double, true>, 0.0);
+    else go(svd_kernel<double, false>, 0.0);
   } else {
-    if (mode == 1) {
-      if (sh > 64 * 1024)
-        (void)hipFuncSetAttribute((const void*)svd_kernel<hb_cplx, true>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-      hipLaunchKernelGGL((svd_kernel<hb_cplx, true>), dim3(n), dim3(SVD_NT), sh, st, jobs,
-                         (const hb_cplx*)store, (const hb_cplx*)alpha, eps);
-    } else {
-      hipLaunchKernelGGL((svd_kernel<hb_cplx, false>), dim3(n), dim3(SVD_NT), 0, st, jobs,
-                         (const hb_cplx*)store, (const hb_cplx*)alpha, eps);
-    }
+    if (in_lds) go(svd_kernel<hb_cplx, true>, hb_cplx{});
+    else go(svd_kernel<hb_cplx, false>, hb_cplx{});
   }
   return (int)hipGetLastError();
 }
