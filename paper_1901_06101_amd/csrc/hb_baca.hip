@@ -26,13 +26,16 @@ namespace {
 
 constexpr int NT = 512;
 constexpr int NW = NT / HB_WAVE;
+constexpr int LCH = 8;  // HBM loads issued together before their first use
 
 template <typename T, int DMAX>
 struct GramCfg {
   static constexpr int CB = DMAX / 2;       // column blocks of 2
   static constexpr int TB = HB_WAVE / CB;   // row blocks of 4
   static constexpr int GT = 4 * TB;         // t-tile width
-  static constexpr int GCH = 16;            // rows per staged chunk
+  // rows per staged chunk: the staging buffers hold at most 2048 + 1024
+  // elements, and every chunk costs two barriers and one HBM round trip
+  static constexpr int GCH = (2048 / GT < 1024 / DMAX) ? 2048 / GT : 1024 / DMAX;
 };
 
 // G[tt * DMAX + c] = sum_i conj(X(i, t0 + tt)) * X(i, k0 + c), tt < tw, c < dk.
@@ -42,6 +45,8 @@ template <typename T, int DMAX>
 __device__ __forceinline__ void gram_tile(const T* __restrict__ X, int64_t ld, int nrows, int t0, int tw, int k0,
                           int dk, T* sXs, T* sKs, T* sG) {
   using C = GramCfg<T, DMAX>;
+  constexpr int NX = (C::GCH * C::GT + NT - 1) / NT;   // staged elements per thread
+  constexpr int NK = (C::GCH * DMAX + NT - 1) / NT;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int tb = lane % C::TB, cb = lane / C::TB;
   T acc[4][2];
@@ -51,17 +56,36 @@ __device__ __forceinline__ void gram_tile(const T* __restrict__ X, int64_t ld, i
     for (int b = 0; b < 2; ++b) acc[a][b] = sc_zero<T>();
 #pragma unroll 1
   for (int i0 = 0; i0 < nrows; i0 += C::GCH) {
-    __syncthreads();
-    for (int e = tid; e < C::GCH * C::GT; e += NT) {
-      const int ii = e % C::GCH, tt = e / C::GCH, i = i0 + ii;
-      sXs[ii * C::GT + tt] = (i < nrows && tt < tw) ? X[(int64_t)(t0 + tt) * ld + i] : sc_zero<T>();
+    // all loads of the chunk are issued before any is used; indexes are
+    // clamped into the matrix and out-of-range values replaced by zero
+    T vx[NX], vk[NK];
+#pragma unroll
+    for (int u = 0; u < NX; ++u) {
+      const int e = tid + u * NT, ii = e % C::GCH, tt = e / C::GCH, i = i0 + ii;
+      const int ic = i < nrows ? i : nrows - 1, tc = tt < tw ? tt : tw - 1;
+      const T v = X[(int64_t)(t0 + tc) * ld + ic];
+      vx[u] = (i < nrows && tt < tw) ? v : sc_zero<T>();
     }
-    for (int e = tid; e < C::GCH * DMAX; e += NT) {
-      const int ii = e % C::GCH, c = e / C::GCH, i = i0 + ii;
-      sKs[ii * DMAX + c] = (i < nrows && c < dk) ? X[(int64_t)(k0 + c) * ld + i] : sc_zero<T>();
+#pragma unroll
+    for (int u = 0; u < NK; ++u) {
+      const int e = tid + u * NT, ii = e % C::GCH, c = e / C::GCH, i = i0 + ii;
+      const int ic = i < nrows ? i : nrows - 1, cc = c < dk ? c : dk - 1;
+      const T v = X[(int64_t)(k0 + cc) * ld + ic];
+      vk[u] = (i < nrows && c < dk) ? v : sc_zero<T>();
     }
     __syncthreads();
 #pragma unroll
+    for (int u = 0; u < NX; ++u) {
+      const int e = tid + u * NT;
+      if (e < C::GCH * C::GT) sXs[(e % C::GCH) * C::GT + e / C::GCH] = vx[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NK; ++u) {
+      const int e = tid + u * NT;
+      if (e < C::GCH * DMAX) sKs[(e % C::GCH) * DMAX + e / C::GCH] = vk[u];
+    }
+    __syncthreads();
+#pragma unroll 4
     for (int q = 0; q < C::GCH / NW; ++q) {
       const int ii = wid * (C::GCH / NW) + q;
       T xa[4], kb[2];
@@ -91,21 +115,27 @@ __device__ __forceinline__ void gram_tile(const T* __restrict__ X, int64_t ld, i
   __syncthreads();
 }
 
-// Upper Cholesky factor in place (G = T^H T, T stored over G's upper part);
-// returns false on a pivot <= 0.  Single thread.
+// Upper Cholesky factor in place (G = T^H T, T stored over G's upper part)
+// by one wave: the diagonal of row j from a wave sum, its off-diagonal
+// entries one per lane.  Returns false on a pivot <= 0 (same in every lane).
 template <typename T, int DMAX>
-__device__ __forceinline__ bool chol_upper(T* G, int n) {
+__device__ __forceinline__ bool chol_wave(T* G, int n, int lane) {
   for (int j = 0; j < n; ++j) {
-    double s = sc_re(G[j * DMAX + j]);
-    for (int k = 0; k < j; ++k) s -= sc_abs2(G[k * DMAX + j]);
-    if (!(s > 0.0)) return false;
-    const double d = sqrt(s);
-    G[j * DMAX + j] = sc_real<T>(d);
-    for (int c = j + 1; c < n; ++c) {
+    double part = 0.0;
+    for (int k = lane; k < j; k += HB_WAVE) part += sc_abs2(G[k * DMAX + j]);
+    part = wave_sum(part);
+    const double sj = sc_re(G[j * DMAX + j]) - part;
+    if (!(sj > 0.0)) return false;
+    const double d = sqrt(sj);
+    const double id = 1.0 / d;
+    for (int c = j + 1 + lane; c < n; c += HB_WAVE) {
       T v = G[j * DMAX + c];
       for (int k = 0; k < j; ++k) v = sc_sub(v, sc_cmul(G[k * DMAX + j], G[k * DMAX + c]));
-      G[j * DMAX + c] = sc_scale(v, 1.0 / d);
+      G[j * DMAX + c] = sc_scale(v, id);
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (lane == 0) G[j * DMAX + j] = sc_real<T>(d);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
   return true;
 }
@@ -114,9 +144,12 @@ __device__ __forceinline__ bool chol_upper(T* G, int n) {
 // lines selecting I_k and J_{k+1}).  Each thread owns RPT candidates (index
 // tid + s * NT) with panel vectors x[s][0..nrow).  `excl[idx] != 0` removes a
 // candidate.  Writes the nsel chosen indices to out[].  Destroys x.
+// One barrier per step: every wave publishes its best candidate's vector
+// with its (norm, index); after the barrier all threads take the overall
+// winner from LDS.  Buffers alternate between steps.
 template <typename T, int DMAX, int RPT>
 __device__ __forceinline__ void qrcp_select(T (&x)[RPT][DMAX], int ncand_total, const unsigned char* excl,
-                            int nrow, int nsel, int* out, T* sPiv, double (*redv)[NW],
+                            int nrow, int nsel, int* out, T (*sPivW)[NW][DMAX], double (*redv)[NW],
                             int (*redi)[NW]) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   bool picked[RPT];
@@ -124,6 +157,7 @@ __device__ __forceinline__ void qrcp_select(T (&x)[RPT][DMAX], int ncand_total, 
   for (int s = 0; s < RPT; ++s) picked[s] = false;
 #pragma unroll 1
   for (int st = 0; st < nsel; ++st) {
+    const int bb = st & 1;
     double bv = -1.0;
     int bi = 0x7fffffff;
 #pragma unroll
@@ -142,40 +176,43 @@ __device__ __forceinline__ void qrcp_select(T (&x)[RPT][DMAX], int ncand_total, 
     }
     wave_argmax(bv, bi);
     if (lane == 0) {
-      redv[st & 1][wid] = bv;
-      redi[st & 1][wid] = bi;
-    }
-    __syncthreads();
-    bv = redv[st & 1][0];
-    bi = redi[st & 1][0];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) {
-      const double ov = redv[st & 1][w];
-      const int oi = redi[st & 1][w];
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
+      redv[bb][wid] = bv;
+      redi[bb][wid] = bi;
     }
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
       if (tid + s * NT == bi) {
 #pragma unroll
-        for (int c = 0; c < DMAX; ++c)
-          if (c >= st && c < nrow) sPiv[c] = x[s][c];
-        picked[s] = true;
+        for (int c = 0; c < DMAX; ++c) sPivW[bb][wid][c] = x[s][c];
       }
     }
-    if (tid == 0) out[st] = bi;
     __syncthreads();
+    int ww = 0;
+    bv = redv[bb][0];
+    bi = redi[bb][0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      const double ov = redv[bb][w];
+      const int oi = redi[bb][w];
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+        ww = w;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < RPT; ++s)
+      if (tid + s * NT == bi) picked[s] = true;
+    if (tid == 0) out[st] = bi;
+    const T* piv = sPivW[bb][ww];
     // Householder reflector of the pivot's trailing part, applied to the rest
     double sig2 = 0.0;
 #pragma unroll
     for (int c = 0; c < DMAX; ++c)
-      if (c >= st && c < nrow) sig2 += sc_abs2(sPiv[c]);
+      if (c >= st && c < nrow) sig2 += sc_abs2(piv[c]);
     const double sigma = sqrt(sig2);
     if (sigma > 0.0 && st + 1 < nsel) {
-      const T x0 = sPiv[st];
+      const T x0 = piv[st];
       const double a0 = sqrt(sc_abs2(x0));
       const T alpha = sc_scale(sc_phase(x0), -sigma);
       const double beta = 1.0 / (sigma * (sigma + a0));
@@ -187,14 +224,18 @@ __device__ __forceinline__ void qrcp_select(T (&x)[RPT][DMAX], int ncand_total, 
           T w = sc_zero<T>();
 #pragma unroll
           for (int c = 0; c < DMAX; ++c)
-            if (c >= st && c < nrow) sc_cfma(w, c == st ? v0 : sPiv[c], x[s][c]);
+            if (c >= st && c < nrow) sc_cfma(w, c == st ? v0 : piv[c], x[s][c]);
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int c = 0; c < DMAX; ++c)
-            if (c >= st && c < nrow) sc_axpy_neg(x[s][c], beta, c == st ? v0 : sPiv[c], w);
+            if (c >= st && c < nrow) sc_axpy_neg(x[s][c], beta, c == st ? v0 : piv[c], w);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
   }
+  // the chosen indices are read after the call
+  __syncthreads();
 }
 
 template <typename T, int DMAX, int RPT>
@@ -218,10 +259,12 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
   __shared__ double redv[2][NW];
   __shared__ int redi[2][NW];
   __shared__ double redd[NW];
-  __shared__ T sPiv[DMAX];
+  __shared__ T sPivW[2][NW][DMAX];
+  __shared__ T sPcol[DMAX];
   __shared__ T sRefl[DMAX * DMAX];
   __shared__ double sBeta[DMAX];
   __shared__ T sTm[DMAX * DMAX];
+  __shared__ T sTinv[DMAX];
   __shared__ double sTabs[DMAX];
   __shared__ double sPts[DMAX * HB_MAXDIM];
   __shared__ T sTile[DMAX * TILE];
@@ -231,7 +274,8 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
   __shared__ T sGU[C::GT * DMAX];
   __shared__ T sGUd[DMAX * DMAX];
   __shared__ T sGVd[DMAX * DMAX];
-  __shared__ double sScal[2];
+  __shared__ double sScal[3];
+  __shared__ int sOk[2];
 
   for (int i = tid; i < NT * RPT; i += NT) {
     used_r[i] = 0;
@@ -288,13 +332,20 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
 #pragma unroll
       for (int s = 0; s < RPT; ++s) {
         const int i = tid + s * NT;
-        if (i < m0) {
-#pragma unroll 2
-          for (int tt = 0; tt < tw; ++tt) {
-            const T u = U[(int64_t)(t0 + tt) * m0 + i];
+        const int ic = i < m0 ? i : m0 - 1;
+        // TILE factor columns per pass, loaded LCH at a time before use;
+        // entries past tw have zero weights in sTile
+#pragma unroll 1
+        for (int tb0 = 0; tb0 < tw; tb0 += LCH) {
+          T uu[LCH];
+#pragma unroll
+          for (int u = 0; u < LCH; ++u) uu[u] = U[(int64_t)(t0 + min(tb0 + u, tw - 1)) * m0 + ic];
+#pragma unroll
+          for (int u = 0; u < LCH; ++u) {
 #pragma unroll
             for (int c = 0; c < DMAX; ++c)
-              if (c < nJ) sc_fma(x[s][c], u, sTile[c * TILE + tt]);
+              if (c < nJ) sc_fma(x[s][c], uu[u], sTile[c * TILE + tb0 + u]);
+            __builtin_amdgcn_sched_barrier(0);
           }
         }
       }
@@ -303,20 +354,27 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
       const int i = tid + s * NT;
-      if (i < m0) {
+      const int ic = i < m0 ? i : m0 - 1;
 #pragma unroll
-        for (int c = 0; c < DMAX; ++c) {
-          if (c < nJ) {
-            const T cv = sc_sub(Cg[(int64_t)c * m0 + i], x[s][c]);
-            Cg[(int64_t)c * m0 + i] = cv;
-            x[s][c] = sc_conj(cv);
+      for (int c0 = 0; c0 < DMAX; c0 += LCH) {
+        T cv[LCH];
+#pragma unroll
+        for (int u = 0; u < LCH; ++u) cv[u] = Cg[(int64_t)min(c0 + u, nJ - 1) * m0 + ic];
+#pragma unroll
+        for (int u = 0; u < LCH; ++u) {
+          const int c = c0 + u;
+          if (i < m0 && c < nJ) {
+            const T v = sc_sub(cv[u], x[s][c]);
+            Cg[(int64_t)c * m0 + i] = v;
+            x[s][c] = sc_conj(v);
           }
         }
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     // ------------------------------------------------ I_k = QR(C^H, d) (eq. (6))
     const int nI = min(nJ, m0 - r);
-    qrcp_select<T, DMAX, RPT>(x, m0, used_r, nJ, nI, sI, sPiv, redv, redi);
+    qrcp_select<T, DMAX, RPT>(x, m0, used_r, nJ, nI, sI, sPivW, redv, redi);
     // (the last select step ends with a barrier, so sI is visible)
 
     // ------------------------------------------------ R_k = A(I,:) - U(I,:) V
@@ -356,13 +414,19 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
 #pragma unroll
         for (int s = 0; s < RPT; ++s) {
           const int j = tid + s * NT;
-          if (j < n0) {
-#pragma unroll 2
-            for (int tt = 0; tt < tw; ++tt) {
-              const T vc = sc_conj(Vh[(int64_t)(t0 + tt) * n0 + j]);
+          const int jc = j < n0 ? j : n0 - 1;
+#pragma unroll 1
+          for (int tb0 = 0; tb0 < tw; tb0 += LCH) {
+            T vv[LCH];
+#pragma unroll
+            for (int u = 0; u < LCH; ++u)
+              vv[u] = sc_conj(Vh[(int64_t)(t0 + min(tb0 + u, tw - 1)) * n0 + jc]);
+#pragma unroll
+            for (int u = 0; u < LCH; ++u) {
 #pragma unroll
               for (int c = 0; c < DMAX; ++c)
-                if (c < nI) sc_fma(y[s][c], sTile[c * TILE + tt], vc);
+                if (c < nI) sc_fma(y[s][c], sTile[c * TILE + tb0 + u], vv[u]);
+              __builtin_amdgcn_sched_barrier(0);
             }
           }
         }
@@ -371,10 +435,18 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
 #pragma unroll
       for (int s = 0; s < RPT; ++s) {
         const int j = tid + s * NT;
-        if (j < n0) {
+        const int jc = j < n0 ? j : n0 - 1;
 #pragma unroll
-          for (int c = 0; c < DMAX; ++c)
-            if (c < nI) Rg[(int64_t)c * n0 + j] = sc_sub(Rg[(int64_t)c * n0 + j], y[s][c]);
+        for (int c0 = 0; c0 < DMAX; c0 += LCH) {
+          T rv[LCH];
+#pragma unroll
+          for (int u = 0; u < LCH; ++u) rv[u] = Rg[(int64_t)min(c0 + u, nI - 1) * n0 + jc];
+#pragma unroll
+          for (int u = 0; u < LCH; ++u) {
+            const int c = c0 + u;
+            if (j < n0 && c < nI) Rg[(int64_t)c * n0 + j] = sc_sub(rv[u], y[s][c]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
@@ -382,9 +454,14 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
     if (wid == 0) {
       T w[DMAX];
       bool rem = lane < nJ;
+      {
+        const int lc = lane < nJ ? lane : nJ - 1;
 #pragma unroll
-      for (int c = 0; c < DMAX; ++c)
-        w[c] = (lane < nJ && c < nI) ? Cg[(int64_t)lane * m0 + sI[c]] : sc_zero<T>();
+        for (int c = 0; c < DMAX; ++c) {
+          const T v = Cg[(int64_t)lc * m0 + sI[c < nI ? c : nI - 1]];
+          w[c] = (lane < nJ && c < nI) ? v : sc_zero<T>();
+        }
+      }
       const int q = min(nI, nJ);
 #pragma unroll 1
       for (int st = 0; st < q; ++st) {
@@ -398,20 +475,21 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
         int bi = rem ? lane : 0x7fffffff;
         wave_argmax(bv, bi);
         const int p = bi;
-        // the pivot column's entries are broadcast from lane p on use
+        // the pivot column goes through LDS to every lane of the wave
+        if (lane == p) {
+#pragma unroll
+          for (int c = 0; c < DMAX; ++c) sPcol[c] = w[c];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        T pc[DMAX];
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) pc[c] = sPcol[c];
         double sig2 = 0.0;
 #pragma unroll
-        for (int c = 0; c < DMAX; ++c) {
-          const T pc = sc_shfl(w[c], p);
-          if (c >= st && c < nI) sig2 += sc_abs2(pc);
-        }
+        for (int c = 0; c < DMAX; ++c)
+          if (c >= st && c < nI) sig2 += sc_abs2(pc[c]);
         const double sigma = sqrt(sig2);
-        T x0 = sc_zero<T>();
-#pragma unroll
-        for (int c = 0; c < DMAX; ++c) {
-          const T pc = sc_shfl(w[c], p);
-          if (c == st) x0 = pc;
-        }
+        const T x0 = sPcol[st];
         T alpha = sc_zero<T>();
         double beta = 0.0;
         if (sigma > 0.0) {
@@ -422,16 +500,13 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
         {
           T ww = sc_zero<T>();
 #pragma unroll
-          for (int c = 0; c < DMAX; ++c) {
-            const T pc = sc_shfl(w[c], p);
-            if (c >= st && c < nI) sc_cfma(ww, c == st ? v0 : pc, w[c]);
-          }
+          for (int c = 0; c < DMAX; ++c)
+            if (c >= st && c < nI) sc_cfma(ww, c == st ? v0 : pc[c], w[c]);
           const bool upd = rem && lane != p && beta != 0.0;
 #pragma unroll
           for (int c = 0; c < DMAX; ++c) {
-            const T pc = sc_shfl(w[c], p);
-            if (upd && c >= st && c < nI) sc_axpy_neg(w[c], beta, c == st ? v0 : pc, ww);
-            if (lane == 0 && c >= st && c < nI) sRefl[st * DMAX + c] = (c == st) ? v0 : pc;
+            if (upd && c >= st && c < nI) sc_axpy_neg(w[c], beta, c == st ? v0 : pc[c], ww);
+            if (lane == 0 && c >= st && c < nI) sRefl[st * DMAX + c] = (c == st) ? v0 : pc[c];
           }
         }
         if (lane == p) {
@@ -444,12 +519,14 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
 #pragma unroll
           for (int c = 0; c < DMAX; ++c)
             if (c <= st) sTm[c * DMAX + st] = w[c];
+          sTinv[st] = sigma > 0.0 ? sc_div(sc_real<T>(1.0), alpha) : sc_zero<T>();
         }
         if (lane == 0) {
           sBeta[st] = beta;
           sTabs[st] = sigma;
           sJbar[st] = p;
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       }
       if (lane == 0) {
         int dk = 0;
@@ -476,7 +553,10 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
       if (j < n0) {
         T z[DMAX];
 #pragma unroll
-        for (int c = 0; c < DMAX; ++c) z[c] = c < nI ? Rg[(int64_t)c * n0 + j] : sc_zero<T>();
+        for (int c = 0; c < DMAX; ++c) {
+          const T v = Rg[(int64_t)min(c, nI - 1) * n0 + j];
+          z[c] = c < nI ? v : sc_zero<T>();
+        }
 #pragma unroll 1
         for (int st = 0; st < dk; ++st) {
           T ww = sc_zero<T>();
@@ -488,15 +568,20 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
           for (int c = 0; c < DMAX; ++c)
             if (c >= st && c < nI) sc_axpy_neg(z[c], beta, sRefl[st * DMAX + c], ww);
         }
+        // back substitution: the row loop runs at run time, the register
+        // array is addressed with compile-time indexes only
+#pragma unroll 1
+        for (int cc = dk - 1; cc >= 0; --cc) {
+          T sum = sc_zero<T>();
 #pragma unroll
-        for (int cc = DMAX - 1; cc >= 0; --cc) {
-          if (cc < dk) {
-            T sum = z[cc];
-#pragma unroll
-            for (int e = cc + 1; e < DMAX; ++e)
-              if (e < dk) sum = sc_sub(sum, sc_mul(sTm[cc * DMAX + e], z[e]));
-            z[cc] = sc_div(sum, sTm[cc * DMAX + cc]);
+          for (int e = 0; e < DMAX; ++e) {
+            if (e == cc) sum = sc_add(sum, z[e]);
+            if (e > cc && e < dk) sum = sc_sub(sum, sc_mul(sTm[cc * DMAX + e], z[e]));
           }
+          sum = sc_mul(sum, sTinv[cc]);
+#pragma unroll
+          for (int e = 0; e < DMAX; ++e)
+            if (e == cc) z[e] = sum;
         }
 #pragma unroll
         for (int c = 0; c < DMAX; ++c)
@@ -545,30 +630,44 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
       }
       cross += block_sum<NT>(part, redd);
     }
-    if (tid == 0) {
-      // sGUd / sGVd hold U_k^H U_k and Vh_k^H Vh_k (dk x dk, Hermitian)
-      double fb = 0.0;  // tr(G_U G_V): the breakdown fallback
-      for (int a = 0; a < dk; ++a)
-        for (int b = 0; b < dk; ++b) fb += sc_re(sc_mulc(sGUd[a * DMAX + b], sGVd[a * DMAX + b]));
-      const bool ok1 = chol_upper<T, DMAX>(sGUd, dk);
-      const bool ok2 = ok1 && chol_upper<T, DMAX>(sGVd, dk);
-      double nu2;
-      if (ok1 && ok2) {
-        // ||T1 T2^H||_F^2 with T1, T2 upper triangular
-        nu2 = 0.0;
-        for (int a = 0; a < dk; ++a)
-          for (int b = 0; b < dk; ++b) {
-            T s = sc_zero<T>();
-            const int k0 = a > b ? a : b;
-            for (int k = k0; k < dk; ++k) sc_fma(s, sGUd[a * DMAX + k], sc_conj(sGVd[b * DMAX + k]));
-            nu2 += sc_abs2(s);
-          }
-      } else {
-        nu2 = fb > 0.0 ? fb : 0.0;
+    // sGUd / sGVd hold U_k^H U_k and Vh_k^H Vh_k (dk x dk, Hermitian): the
+    // breakdown fallback tr(G_U G_V) first, then both Cholesky factors at once
+    // (waves 0 and 1), then ||T1 T2^H||_F (eqs. (11)-(12)) and mu (eq. (13))
+    if (wid == 0) {
+      double fb = 0.0;
+      for (int e = lane; e < dk * dk; e += HB_WAVE) {
+        const int a = e / dk, b = e % dk;
+        fb += sc_re(sc_mulc(sGUd[a * DMAX + b], sGVd[a * DMAX + b]));
       }
-      sScal[0] = sqrt(nu2);
-      const double m2 = mu2 + nu2 + 2.0 * cross;
-      sScal[1] = m2 > 0.0 ? m2 : 0.0;
+      fb = wave_sum(fb);
+      if (lane == 0) sScal[2] = fb;
+    }
+    __syncthreads();
+    if (wid < 2) {
+      const bool ok = chol_wave<T, DMAX>(wid == 0 ? sGUd : sGVd, dk, lane);
+      if (lane == 0) sOk[wid] = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (wid == 0) {
+      double nu2;
+      if (sOk[0] && sOk[1]) {
+        double part = 0.0;
+        for (int e = lane; e < dk * dk; e += HB_WAVE) {
+          const int a = e / dk, b = e % dk;
+          T sv = sc_zero<T>();
+          const int k0 = a > b ? a : b;
+          for (int kk = k0; kk < dk; ++kk) sc_fma(sv, sGUd[a * DMAX + kk], sc_conj(sGVd[b * DMAX + kk]));
+          part += sc_abs2(sv);
+        }
+        nu2 = wave_sum(part);
+      } else {
+        nu2 = sScal[2] > 0.0 ? sScal[2] : 0.0;
+      }
+      if (lane == 0) {
+        sScal[0] = sqrt(nu2);
+        const double m2 = mu2 + nu2 + 2.0 * cross;
+        sScal[1] = m2 > 0.0 ? m2 : 0.0;
+      }
     }
     __syncthreads();
     const double nu = sScal[0];
@@ -601,7 +700,7 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
         for (int c = 0; c < DMAX; ++c)
           y[s][c] = (j < n0 && c < nI) ? Rg[(int64_t)c * n0 + j] : sc_zero<T>();
       }
-      qrcp_select<T, DMAX, RPT>(y, n0, used_c, nI, nsel, sJ, sPiv, redv, redi);
+      qrcp_select<T, DMAX, RPT>(y, n0, used_c, nI, nsel, sJ, sPivW, redv, redi);
     }
     for (int i = tid; i < NT * RPT; i += NT)
       if (used_c[i] == 2) used_c[i] = 0;
