@@ -56,7 +56,13 @@ typedef enum {
 } hb_entry_fn;
 
 typedef enum {
-  HB_PREC_FP64 = 0   /* every step in FP64 (complex: FP64 pairs) */
+  HB_PREC_FP64 = 0,  /* every step in FP64 (complex: FP64 pairs) */
+  HB_PREC_MIXED = 1  /* real kernels only: the leaf BACA evaluates entries and
+                        forms residual blocks and factors in FP32, accumulating
+                        products and Gram blocks in FP64; the norm estimates
+                        nu, mu (eqs. (11)-(13)), the leaf SVD re-compression
+                        and every merge stay FP64.  Complex kernels return
+                        HB_EUNSUPPORTED. */
 } hb_precision;
 
 typedef struct {

@@ -11,6 +11,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <memory>
@@ -32,16 +34,31 @@ namespace {
 struct HbError {
   hb_status st;
 };
-#define HB_HIP(call)                                   \
-  do {                                                 \
-    hipError_t e_ = (call);                            \
-    if (e_ != hipSuccess) throw HbError{HB_EDEVICE};   \
+// With HB_VERBOSE set in the environment, every failing HIP call or launch
+// and every unsupported size is reported on stderr with its source line.
+static void hb_report(const char* what, int code, const char* detail, int line) {
+  static const bool on = std::getenv("HB_VERBOSE") != nullptr;
+  if (on) std::fprintf(stderr, "[hbaca] %s failed (%d: %s) at hb_api.hip:%d\n", what, code, detail, line);
+}
+#define HB_HIP(call)                                                         \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      hb_report(#call, (int)e_, hipGetErrorString(e_), __LINE__);            \
+      throw HbError{HB_EDEVICE};                                             \
+    }                                                                        \
   } while (0)
-#define HB_LAUNCH(call)                                \
-  do {                                                 \
-    int e_ = (call);                                   \
-    if (e_ == -1) throw HbError{HB_EUNSUPPORTED};      \
-    if (e_ != 0) throw HbError{HB_EDEVICE};            \
+#define HB_LAUNCH(call)                                                      \
+  do {                                                                       \
+    int e_ = (call);                                                         \
+    if (e_ == -1) {                                                          \
+      hb_report(#call, e_, "size outside the built kernels", __LINE__);      \
+      throw HbError{HB_EUNSUPPORTED};                                        \
+    }                                                                        \
+    if (e_ != 0) {                                                           \
+      hb_report(#call, e_, hipGetErrorString((hipError_t)e_), __LINE__);     \
+      throw HbError{HB_EDEVICE};                                             \
+    }                                                                        \
   } while (0)
 
 // --------------------------------------------------------- device memory ---
@@ -226,6 +243,20 @@ __global__ void aos_to_soa_kernel(const double* __restrict__ src, double* __rest
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npts) return;
   for (int c = 0; c < dim; ++c) dst[(int64_t)c * npts + i] = src[i * dim + c];
+}
+
+// FP32 leaf factors of the mixed-precision path widened to FP64 for the
+// re-compression and the merges (one grid row per factor).
+struct CvtDev {
+  const float* src;
+  double* dst;
+  int64_t n;
+};
+__global__ void cvt_f2d_kernel(const CvtDev* __restrict__ jobs) {
+  const CvtDev J = jobs[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < J.n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    J.dst[i] = (double)J.src[i];
 }
 
 // M = R_U R_V^H for one leaf: R_U (pu x r), R_V (pv x r) from TSQR top nodes.
@@ -1205,7 +1236,66 @@ struct RecJob {
   Block* out;
 };
 
+static void run_recompress_narrow(Engine& E, std::vector<RecJob>& jobs, DevMem& out_mem);
+
+// Leaves whose BACA rank exceeds the register TSQR tile: V^H is first
+// orthonormalised by a merge of the single block with no truncation above
+// the rounding level (V^H = Q X S Y^H, so U V = (U Y) S (Q X)^H), then
+// (U Y) S (Q X)^H is truncated at eps by a second single-block merge, whose
+// wide QR runs column panel by column panel.
+static void run_recompress_wide(Engine& E, std::vector<RecJob>& jobs, DevMem& out_mem) {
+  if (jobs.empty()) return;
+  DevMem mid;
+  mid.st = E.st;
+  std::vector<Block> midb(jobs.size());
+  std::vector<MergeJob> j1, j2;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    const RecJob& R = jobs[i];
+    MergeJob J{};
+    J.rows = R.n0;
+    J.P1 = R.Vh; J.r1 = R.r; J.S1 = nullptr;
+    J.P2 = nullptr; J.r2 = 0; J.S2 = nullptr;
+    J.O1 = R.U; J.n1 = R.m0;
+    J.O2 = nullptr; J.n2 = 0;
+    J.p_is_u = false;
+    J.outP_owner = &midb[i];
+    j1.push_back(J);
+  }
+  const double eps = E.eps;
+  E.eps = 1e-14;
+  run_merges(E, j1, mid);
+  E.eps = eps;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    const Block& b = midb[i];
+    MergeJob J{};
+    J.rows = b.m;
+    J.P1 = b.U; J.r1 = b.r; J.S1 = b.S;
+    J.P2 = nullptr; J.r2 = 0; J.S2 = nullptr;
+    J.O1 = b.Vh; J.n1 = b.n;
+    J.O2 = nullptr; J.n2 = 0;
+    J.p_is_u = true;
+    J.outP_owner = jobs[i].out;
+    j2.push_back(J);
+  }
+  run_merges(E, j2, out_mem);
+  mid.release();
+}
+
 static void run_recompress(Engine& E, std::vector<RecJob>& jobs, DevMem& out_mem) {
+  std::vector<RecJob> narrow, wide;
+  for (auto& J : jobs) {
+    Block& B = *J.out;
+    B.m = J.m0;
+    B.n = J.n0;
+    B.r = 0;
+    if (J.r > 512) throw HbError{HB_EUNSUPPORTED};
+    (J.r > E.kcap() ? wide : narrow).push_back(J);
+  }
+  run_recompress_narrow(E, narrow, out_mem);
+  run_recompress_wide(E, wide, out_mem);
+}
+
+static void run_recompress_narrow(Engine& E, std::vector<RecJob>& jobs, DevMem& out_mem) {
   const size_t nj = jobs.size();
   std::vector<QRNodeDev> mats;
   std::vector<int64_t> rows;
@@ -1339,7 +1429,8 @@ static hb_status validate(const CallSpec& c) {
   if (!(c.tol > 0.0 && c.tol < 1.0)) return std::isfinite(c.tol) ? HB_EINVAL : HB_ENONFINITE;
   if (c.d < 1 || c.leaf < 1) return HB_EINVAL;
   if (c.d > 32) return HB_EUNSUPPORTED;
-  if (p->precision != HB_PREC_FP64) return HB_EUNSUPPORTED;
+  if (p->precision != HB_PREC_FP64 && p->precision != HB_PREC_MIXED) return HB_EINVAL;
+  if (p->precision == HB_PREC_MIXED && c.entry == HB_K_HELMHOLTZ3D) return HB_EUNSUPPORTED;
   if (p->stop_after < 0 || p->stop_after > 2 + 2 * 30 || p->rank_cap < 0) return HB_EINVAL;
   if (p->diag_panel < 0 || p->diag_panel > 128 || p->diag_svd_storage < 0 ||
       p->diag_svd_storage > 2)
@@ -1400,6 +1491,12 @@ static hb_status run(const CallSpec& c, hb_result** out) {
   R->scalar = scalar;
   R->entry = c.entry;
   const size_t sbytes = scalar_bytes(scalar);
+  // mixed precision: the leaf BACA runs on FP32 data (entries, residual
+  // blocks, factors) with FP64 accumulation and norms; everything after it
+  // is FP64
+  const bool mixed = P.precision == HB_PREC_MIXED;
+  const int bscalar = mixed ? 2 : scalar;
+  const size_t bbytes = mixed ? 4 : sbytes;
 
   // ---- entry description (SoA points owned by the result)
   EntryDev E{};
@@ -1468,7 +1565,7 @@ static hb_status run(const CallSpec& c, hb_result** out) {
   const int rpt = (maxdim + 511) / 512;
   int rpt_v = rpt <= 1 ? 1 : (rpt <= 2 ? 2 : 4);
   if (scalar == 1 && ((dmax == 16 && rpt_v > 2) || (dmax == 32 && rpt_v > 1))) return HB_EUNSUPPORTED;
-  if (scalar == 0 && dmax == 32 && rpt_v > 2) return HB_EUNSUPPORTED;
+  if (scalar == 0 && !mixed && dmax == 32 && rpt_v > 2) return HB_EUNSUPPORTED;
 
   // ---- leaf descriptors; largest leaves first
   std::vector<int> order(nleaves);
@@ -1519,10 +1616,10 @@ static hb_status run(const CallSpec& c, hb_result** out) {
   A.leaves = upload(tmp, ld, st);
   A.out = tmp.get<BacaOutDev>(nleaves);
   A.E = E;
-  A.U = baca_mem.alloc((size_t)std::max<int64_t>(uo, 1) * sbytes);
-  A.V = baca_mem.alloc((size_t)std::max<int64_t>(vo, 1) * sbytes);
-  A.C = tmp.alloc((size_t)std::max<int64_t>(co, 1) * sbytes);
-  A.R = tmp.alloc((size_t)std::max<int64_t>(ro, 1) * sbytes);
+  A.U = baca_mem.alloc((size_t)std::max<int64_t>(uo, 1) * bbytes);
+  A.V = baca_mem.alloc((size_t)std::max<int64_t>(vo, 1) * bbytes);
+  A.C = tmp.alloc((size_t)std::max<int64_t>(co, 1) * bbytes);
+  A.R = tmp.alloc((size_t)std::max<int64_t>(ro, 1) * bbytes);
   A.j1 = upload(tmp, j1, st);
   A.tape_rows = tmp.get<int32_t>(std::max(tapeo, 1));
   A.tape_cols = tmp.get<int32_t>(std::max(tapeo, 1));
@@ -1532,21 +1629,20 @@ static hb_status run(const CallSpec& c, hb_result** out) {
   A.eps = c.tol;
   A.nleaves = (int32_t)nleaves;
   HB_HIP(hipEventRecord(ev[1], st));
-  HB_LAUNCH(hbk::baca_launch(scalar, dmax, rpt_v, A, st));
+  HB_LAUNCH(hbk::baca_launch(bscalar, dmax, rpt_v, A, st));
   HB_HIP(hipEventRecord(ev[2], st));
   std::vector<BacaOutDev> bo(nleaves);
   HB_HIP(hipMemcpyAsync(bo.data(), A.out, nleaves * sizeof(BacaOutDev), hipMemcpyDeviceToHost, st));
-  std::vector<int32_t> h_rows, h_cols, h_dk;
+  std::vector<int32_t> h_rows, h_cols, h_dk(std::max(ito, 1));
   std::vector<double> h_nu, h_mu;
+  HB_HIP(hipMemcpyAsync(h_dk.data(), A.it_dk, ito * 4, hipMemcpyDeviceToHost, st));
   if (P.record_tape) {
     h_rows.resize(tapeo);
     h_cols.resize(tapeo);
-    h_dk.resize(ito);
     h_nu.resize(ito);
     h_mu.resize(ito);
     HB_HIP(hipMemcpyAsync(h_rows.data(), A.tape_rows, tapeo * 4, hipMemcpyDeviceToHost, st));
     HB_HIP(hipMemcpyAsync(h_cols.data(), A.tape_cols, tapeo * 4, hipMemcpyDeviceToHost, st));
-    HB_HIP(hipMemcpyAsync(h_dk.data(), A.it_dk, ito * 4, hipMemcpyDeviceToHost, st));
     HB_HIP(hipMemcpyAsync(h_nu.data(), A.it_nu, ito * 8, hipMemcpyDeviceToHost, st));
     HB_HIP(hipMemcpyAsync(h_mu.data(), A.it_mu, ito * 8, hipMemcpyDeviceToHost, st));
   }
@@ -1576,17 +1672,15 @@ static hb_status run(const CallSpec& c, hb_result** out) {
   // columns of U and V once and evaluates d (m0 + n0) entries)
   {
     const double phi = scalar ? 4.0 : 1.0;
-    if (P.record_tape) {
-      for (size_t s = 0; s < nleaves; ++s) {
-        const LeafHost& lf = R->leaves[order[s]];
-        int r = 0;
-        for (int k = 0; k < lf.iters; ++k) {
-          const double mn = (double)lf.m0 + lf.n0;
-          S.resid_bytes += (double)sbytes * r * mn;
-          S.resid_flops += 2.0 * phi * std::min(c.d, lf.n0) * r * mn;
-          S.entries_evaluated += (double)std::min(c.d, lf.n0) * mn;
-          r += lf.it_dk[k];
-        }
+    for (size_t s = 0; s < nleaves; ++s) {
+      const LeafHost& lf = R->leaves[order[s]];
+      int r = 0;
+      for (int k = 0; k < lf.iters; ++k) {
+        const double mn = (double)lf.m0 + lf.n0;
+        S.resid_bytes += (double)bbytes * r * mn;
+        S.resid_flops += 2.0 * phi * std::min(c.d, lf.n0) * r * mn;
+        S.entries_evaluated += (double)std::min(c.d, lf.n0) * mn;
+        r += h_dk[ld[s].it_off + k];
       }
     }
   }
@@ -1598,8 +1692,39 @@ static hb_status run(const CallSpec& c, hb_result** out) {
     b.m = ld[s].m0;
     b.n = ld[s].n0;
     b.r = bo[s].rank;
-    b.U = (char*)A.U + (size_t)ld[s].u_off * sbytes;
-    b.Vh = (char*)A.V + (size_t)ld[s].v_off * sbytes;
+    b.U = (char*)A.U + (size_t)ld[s].u_off * bbytes;
+    b.Vh = (char*)A.V + (size_t)ld[s].v_off * bbytes;
+  }
+  DevMem cvt_mem;
+  cvt_mem.st = st;
+  if (mixed) {
+    // widen the used factor columns to FP64
+    size_t tot = 0;
+    for (auto& b : leafblk) tot += (size_t)(b.m + b.n) * b.r;
+    double* wide = cvt_mem.get<double>(std::max<size_t>(tot, 1));
+    std::vector<CvtDev> cj;
+    size_t off = 0;
+    for (auto& b : leafblk) {
+      if (b.r == 0) {
+        b.U = wide;
+        b.Vh = wide;
+        continue;
+      }
+      cj.push_back(CvtDev{(const float*)b.U, wide + off, (int64_t)b.m * b.r});
+      b.U = wide + off;
+      off += (size_t)b.m * b.r;
+      cj.push_back(CvtDev{(const float*)b.Vh, wide + off, (int64_t)b.n * b.r});
+      b.Vh = wide + off;
+      off += (size_t)b.n * b.r;
+    }
+    if (!cj.empty()) {
+      CvtDev* dj = upload(tmp, cj, st);
+      for (size_t j0 = 0; j0 < cj.size(); j0 += 65535) {
+        const unsigned ny = (unsigned)std::min<size_t>(65535, cj.size() - j0);
+        hipLaunchKernelGGL(cvt_f2d_kernel, dim3(8, ny), dim3(256), 0, st, dj + j0);
+        HB_HIP(hipGetLastError());
+      }
+    }
   }
   Engine Eng(st, scalar, c.tol, tmp);
   Eng.panel = P.diag_panel;
@@ -1608,6 +1733,8 @@ static hb_status run(const CallSpec& c, hb_result** out) {
     // keep the BACA arena in the result; blocks are leaves with sigma = 1
     for (void* p : baca_mem.ptrs) R->keep.ptrs.push_back(p);
     baca_mem.ptrs.clear();
+    for (void* p : cvt_mem.ptrs) R->keep.ptrs.push_back(p);
+    cvt_mem.ptrs.clear();
     int maxr = 1;
     for (auto& b : leafblk) maxr = std::max(maxr, b.r);
     std::vector<double> ones(maxr, 1.0);
@@ -1627,6 +1754,7 @@ static hb_status run(const CallSpec& c, hb_result** out) {
       rj.push_back(RecJob{leafblk[i].U, leafblk[i].Vh, leafblk[i].m, leafblk[i].n, leafblk[i].r, &cur[i]});
     run_recompress(Eng, rj, lvl_mem);
     baca_mem.release();
+    cvt_mem.release();
     HB_HIP(hipEventRecord(ev[3], st));
     for (size_t i = 0; i < nleaves; ++i) {
       R->leaves[i].rank_leaf = cur[i].r;

@@ -43,17 +43,18 @@ struct GramCfg {
 // lands in sG (GT x DMAX).  All threads of the block must call it.
 template <typename T, int DMAX>
 __device__ __forceinline__ void gram_tile(const T* __restrict__ X, int64_t ld, int nrows, int t0, int tw, int k0,
-                          int dk, T* sXs, T* sKs, T* sG) {
+                          int dk, T* sXs, T* sKs, typename acc_type<T>::type* sG) {
   using C = GramCfg<T, DMAX>;
+  using TA = typename acc_type<T>::type;
   constexpr int NX = (C::GCH * C::GT + NT - 1) / NT;   // staged elements per thread
   constexpr int NK = (C::GCH * DMAX + NT - 1) / NT;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int tb = lane % C::TB, cb = lane / C::TB;
-  T acc[4][2];
+  TA acc[4][2];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = sc_zero<T>();
+    for (int b = 0; b < 2; ++b) acc[a][b] = sc_zero<TA>();
 #pragma unroll 1
   for (int i0 = 0; i0 < nrows; i0 += C::GCH) {
     // all loads of the chunk are issued before any is used; indexes are
@@ -96,7 +97,7 @@ __device__ __forceinline__ void gram_tile(const T* __restrict__ X, int64_t ld, i
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) sc_cfma(acc[a][b], xa[a], kb[b]);
+        for (int b = 0; b < 2; ++b) sc_cfma(acc[a][b], sc_to_acc(xa[a]), sc_to_acc(kb[b]));
     }
   }
   // deterministic cross-wave sum: wave 0 writes, waves 1..7 add in order
@@ -168,6 +169,8 @@ __device__ __forceinline__ void qrcp_select(T (&x)[RPT][DMAX], int ncand_total, 
 #pragma unroll
         for (int c = 0; c < DMAX; ++c)
           if (c >= st && c < nrow) nv += sc_abs2(x[s][c]);
+        // a NaN norm (non-finite data) must still leave a valid winner
+        if (!(nv == nv)) nv = 0.0;
         if (nv > bv || (nv == bv && i < bi)) {
           bv = nv;
           bi = i;
@@ -241,6 +244,7 @@ __device__ __forceinline__ void qrcp_select(T (&x)[RPT][DMAX], int ncand_total, 
 template <typename T, int DMAX, int RPT>
 __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
   using C = GramCfg<T, DMAX>;
+  using TA = typename acc_type<T>::type;  // FP32 data accumulate in FP64
   constexpr int TILE = 32;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const BacaLeafDev L = A.leaves[blockIdx.x];
@@ -270,10 +274,10 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
   __shared__ T sTile[DMAX * TILE];
   __shared__ T sXs[C::GCH * C::GT];
   __shared__ T sKs[C::GCH * DMAX];
-  __shared__ T sG[C::GT * DMAX];
-  __shared__ T sGU[C::GT * DMAX];
-  __shared__ T sGUd[DMAX * DMAX];
-  __shared__ T sGVd[DMAX * DMAX];
+  __shared__ TA sG[C::GT * DMAX];
+  __shared__ TA sGU[C::GT * DMAX];
+  __shared__ TA sGUd[DMAX * DMAX];
+  __shared__ TA sGVd[DMAX * DMAX];
   __shared__ double sScal[3];
   __shared__ int sOk[2];
 
@@ -315,11 +319,11 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
               eval_entry<T>(A.E, L.row0 + i, L.col0 + sJ[c], xi, &sPts[c * HB_MAXDIM]);
       }
     }
-    T x[RPT][DMAX];
+    TA xa[RPT][DMAX];
 #pragma unroll
     for (int s = 0; s < RPT; ++s)
 #pragma unroll
-      for (int c = 0; c < DMAX; ++c) x[s][c] = sc_zero<T>();
+      for (int c = 0; c < DMAX; ++c) xa[s][c] = sc_zero<TA>();
     for (int t0 = 0; t0 < r; t0 += TILE) {
       const int tw = min(TILE, r - t0);
       __syncthreads();
@@ -344,13 +348,14 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
           for (int u = 0; u < LCH; ++u) {
 #pragma unroll
             for (int c = 0; c < DMAX; ++c)
-              if (c < nJ) sc_fma(x[s][c], uu[u], sTile[c * TILE + tb0 + u]);
+              if (c < nJ) sc_fma(xa[s][c], sc_to_acc(uu[u]), sc_to_acc(sTile[c * TILE + tb0 + u]));
             __builtin_amdgcn_sched_barrier(0);
           }
         }
       }
     }
     // C_k = A(:, J_k) - U V(:, J_k); the panel is its conjugate transpose
+    T x[RPT][DMAX];
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
       const int i = tid + s * NT;
@@ -363,11 +368,9 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
 #pragma unroll
         for (int u = 0; u < LCH; ++u) {
           const int c = c0 + u;
-          if (i < m0 && c < nJ) {
-            const T v = sc_sub(cv[u], x[s][c]);
-            Cg[(int64_t)c * m0 + i] = v;
-            x[s][c] = sc_conj(v);
-          }
+          const T v = sc_from_acc<T>(sc_sub(sc_to_acc(cv[u]), xa[s][c]));
+          if (i < m0 && c < nJ) Cg[(int64_t)c * m0 + i] = v;
+          x[s][c] = (i < m0 && c < nJ) ? sc_conj(v) : sc_zero<T>();
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -398,11 +401,11 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
       }
     }
     {
-      T y[RPT][DMAX];
+      TA y[RPT][DMAX];
 #pragma unroll
       for (int s = 0; s < RPT; ++s)
 #pragma unroll
-        for (int c = 0; c < DMAX; ++c) y[s][c] = sc_zero<T>();
+        for (int c = 0; c < DMAX; ++c) y[s][c] = sc_zero<TA>();
       for (int t0 = 0; t0 < r; t0 += TILE) {
         const int tw = min(TILE, r - t0);
         __syncthreads();
@@ -425,7 +428,7 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
             for (int u = 0; u < LCH; ++u) {
 #pragma unroll
               for (int c = 0; c < DMAX; ++c)
-                if (c < nI) sc_fma(y[s][c], sTile[c * TILE + tb0 + u], vv[u]);
+                if (c < nI) sc_fma(y[s][c], sc_to_acc(sTile[c * TILE + tb0 + u]), sc_to_acc(vv[u]));
               __builtin_amdgcn_sched_barrier(0);
             }
           }
@@ -444,7 +447,8 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
 #pragma unroll
           for (int u = 0; u < LCH; ++u) {
             const int c = c0 + u;
-            if (j < n0 && c < nI) Rg[(int64_t)c * n0 + j] = sc_sub(rv[u], y[s][c]);
+            if (j < n0 && c < nI)
+              Rg[(int64_t)c * n0 + j] = sc_from_acc<T>(sc_sub(sc_to_acc(rv[u]), y[s][c]));
           }
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -471,6 +475,7 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
 #pragma unroll
           for (int c = 0; c < DMAX; ++c)
             if (c >= st && c < nI) bv += sc_abs2(w[c]);
+          if (!(bv == bv)) bv = 0.0;
         }
         int bi = rem ? lane : 0x7fffffff;
         wave_argmax(bv, bi);
@@ -644,7 +649,7 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
     }
     __syncthreads();
     if (wid < 2) {
-      const bool ok = chol_wave<T, DMAX>(wid == 0 ? sGUd : sGVd, dk, lane);
+      const bool ok = chol_wave<TA, DMAX>(wid == 0 ? sGUd : sGVd, dk, lane);
       if (lane == 0) sOk[wid] = ok ? 1 : 0;
     }
     __syncthreads();
@@ -654,7 +659,7 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
         double part = 0.0;
         for (int e = lane; e < dk * dk; e += HB_WAVE) {
           const int a = e / dk, b = e % dk;
-          T sv = sc_zero<T>();
+          TA sv = sc_zero<TA>();
           const int k0 = a > b ? a : b;
           for (int kk = k0; kk < dk; ++kk) sc_fma(sv, sGUd[a * DMAX + kk], sc_conj(sGVd[b * DMAX + kk]));
           part += sc_abs2(sv);
@@ -744,6 +749,9 @@ int baca_launch(int scalar, int dmax, int rpt, const BacaArgs& a, hipStream_t st
   HB_CASE(1, hb_cplx, 8, 1) HB_CASE(1, hb_cplx, 8, 2) HB_CASE(1, hb_cplx, 8, 4)
   HB_CASE(1, hb_cplx, 16, 1) HB_CASE(1, hb_cplx, 16, 2)
   HB_CASE(1, hb_cplx, 32, 1)
+  HB_CASE(2, float, 8, 1) HB_CASE(2, float, 8, 2) HB_CASE(2, float, 8, 4)
+  HB_CASE(2, float, 16, 1) HB_CASE(2, float, 16, 2) HB_CASE(2, float, 16, 4)
+  HB_CASE(2, float, 32, 1) HB_CASE(2, float, 32, 2) HB_CASE(2, float, 32, 4)
 #undef HB_CASE
   return -1;
 }

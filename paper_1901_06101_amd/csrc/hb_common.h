@@ -81,7 +81,7 @@ __device__ __host__ inline hb_cplx sc_cmul(hb_cplx a, hb_cplx b) {
   return hb_cplx{a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
 __device__ __host__ inline double sc_scale(double a, double s) { return a * s; }
-__device__ __host__ inline float sc_scale(float a, double s) { return a * (float)s; }
+__device__ __host__ inline float sc_scale(float a, double s) { return (float)((double)a * s); }
 __device__ __host__ inline hb_cplx sc_scale(hb_cplx a, double s) { return hb_cplx{a.re * s, a.im * s}; }
 __device__ __host__ inline double sc_div(double a, double b) { return a / b; }
 __device__ __host__ inline float sc_div(float a, float b) { return a / b; }
@@ -95,6 +95,17 @@ __device__ __host__ inline hb_cplx sc_div(hb_cplx a, hb_cplx b) {
     return hb_cplx{(a.re * r + a.im) / den, (a.im * r - a.re) / den};
   }
 }
+// Accumulation type of a storage scalar: FP32 data accumulate in FP64.
+template <typename T> struct acc_type { using type = T; };
+template <> struct acc_type<float> { using type = double; };
+__device__ __host__ inline double sc_to_acc(float a) { return (double)a; }
+__device__ __host__ inline double sc_to_acc(double a) { return a; }
+__device__ __host__ inline hb_cplx sc_to_acc(hb_cplx a) { return a; }
+template <typename T> __device__ __host__ inline T sc_from_acc(typename acc_type<T>::type a);
+template <> __device__ __host__ inline float sc_from_acc<float>(double a) { return (float)a; }
+template <> __device__ __host__ inline double sc_from_acc<double>(double a) { return a; }
+template <> __device__ __host__ inline hb_cplx sc_from_acc<hb_cplx>(hb_cplx a) { return a; }
+
 // acc += a * b ; acc += conj(a) * b ; acc += a * conj(b)
 __device__ inline void sc_fma(double& acc, double a, double b) { acc = fma(a, b, acc); }
 __device__ inline void sc_fma(float& acc, float a, float b) { acc = fmaf(a, b, acc); }
@@ -114,7 +125,11 @@ __device__ inline void sc_cfma(hb_cplx& acc, hb_cplx a, hb_cplx b) {
 }
 // acc -= s * v * w  (s real)
 __device__ inline void sc_axpy_neg(double& x, double s, double v, double w) { x = fma(-s * v, w, x); }
-__device__ inline void sc_axpy_neg(float& x, double s, float v, float w) { x = fmaf((float)(-s) * v, w, x); }
+// FP32 data: the product is formed in FP64 (a reflector's s can exceed the
+// FP32 range when v is tiny)
+__device__ inline void sc_axpy_neg(float& x, double s, float v, float w) {
+  x = (float)fma(-s * (double)v, (double)w, (double)x);
+}
 __device__ inline void sc_axpy_neg(hb_cplx& x, double s, hb_cplx v, hb_cplx w) {
   hb_cplx p = sc_mul(v, w);
   x.re = fma(-s, p.re, x.re);

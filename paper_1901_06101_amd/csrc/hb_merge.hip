@@ -600,6 +600,7 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
       int idx = 0x7fffffff;
       if (tid >= s && tid < p) {
         v = n_cur[tid];
+        if (!(v == v)) v = 0.0;  // non-finite data still yield a valid pivot
         idx = tid;
       }
       wave_argmax(v, idx);

@@ -37,11 +37,12 @@ def test_status_strings():
     assert lib.hb_status_string(-99).decode() == "unknown status"
 
 
-def _call(**over):
+def _call(precision=0, **over):
     from paper_1901_06101_amd import _binding
     lib = _binding.load(LIB)
     p = _binding.HbParams()
     p.dim, p.h, p.gauss_c, p.wavenumber = 3, 0.5, 1.0, 20.0
+    p.precision = precision
     args = dict(entry=1, params=C.byref(p), X=C.c_void_p(16), Y=C.c_void_p(16), m=100, n=100,
                 tol=1e-6, d=8, leaf=50)
     args.update(over)
@@ -58,6 +59,15 @@ def _call(**over):
 ])
 def test_invalid_arguments_rejected_on_host(over, expect):
     st, out = _call(**over)
+    assert st == expect
+    assert out.value is None
+
+
+@pytest.mark.parametrize("precision,entry,expect", [(2, 1, -1), (-1, 1, -1), (1, 3, -6)])
+def test_precision_modes_checked_on_host(precision, entry, expect):
+    """Only FP64 and mixed precision exist; mixed precision is for real
+    kernels only."""
+    st, out = _call(precision=precision, entry=entry)
     assert st == expect
     assert out.value is None
 

