@@ -34,8 +34,10 @@ Readings where the paper is silent or garbled:
   term of eq. (13) takes the real part.
 
 Instrumentation (no effect on the arithmetic): every iteration records its
-pivots, d_k, nu, mu and the trailing norms of the row picks (sel_I) and of
-the column picks that chose the next block (sel_J).
+pivots, d_k, nu, mu, the trailing norms of the row picks (sel_I) and of the
+column picks that chose the next block (sel_J), and the whole blocks I_k,
+J_k with the pivot order of QR(W_k, eps) (Iblock, Jblock, piv), which is
+what a replay with frozen pivots needs.
 """
 from __future__ import annotations
 
@@ -150,7 +152,8 @@ def baca_leaf(block, m0: int, n0: int, d: int, eps: float, J1: np.ndarray,
             if record:
                 iters.append(dict(I=np.zeros(0, np.int64), J=np.zeros(0, np.int64),
                                   dk=0, nu=0.0, mu=float(np.sqrt(mu2)), r=r,
-                                  sel_I=np.abs(selI.tdiag), sel_J=np.zeros(0)))
+                                  sel_I=np.abs(selI.tdiag), sel_J=np.zeros(0),
+                                  Iblock=I.copy(), Jblock=J.copy(), piv=full.piv.copy()))
             break
         jbar = full.piv[:dk]
         Uk = C[:, jbar]
@@ -171,7 +174,8 @@ def baca_leaf(block, m0: int, n0: int, d: int, eps: float, J1: np.ndarray,
         if record:
             iters.append(dict(I=I[:dk].copy(), J=J[jbar].copy(), dk=dk, nu=nu,
                               mu=mu, r=U.shape[1], sel_I=np.abs(selI.tdiag),
-                              sel_J=np.zeros(0)))
+                              sel_J=np.zeros(0), Iblock=I.copy(), Jblock=J.copy(),
+                              piv=full.piv.copy()))
         # (8) stopping test, then the next column block (eq. (7))
         if nu < eps * mu or Pc.size == 0 or U.shape[1] >= rmax:
             break
