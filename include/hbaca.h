@@ -96,8 +96,9 @@ typedef struct {
   int32_t diag_panel;  /* diagnostics: 0 default; > 0 merges wider than this
                           many columns use the column-panel QR with panels of
                           this width (1..128 real, 1..64 complex) */
-  int32_t diag_svd_storage; /* diagnostics: 0 default; 1 keep the small SVD's
-                          matrices in HBM; 2 R in LDS, V in HBM */
+  int32_t diag_svd_storage; /* diagnostics: 0 default (the small SVD's
+                          matrices in LDS when they fit); 1 keep them in HBM;
+                          2 behaves as 0 */
 } hb_params;
 
 typedef struct hb_result hb_result; /* opaque */

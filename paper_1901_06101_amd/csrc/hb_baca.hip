@@ -735,14 +735,8 @@ static int launch_one(const BacaArgs& a, hipStream_t st) {
 
 int baca_launch(int scalar, int dmax, int rpt, const BacaArgs& a, hipStream_t st) {
   if (a.nleaves == 0) return 0;
-#ifdef HB_ONLY_VARIANT
-#define HB_CASE(S, TY, D, R) \
-  if (HB_ONLY_VARIANT == S * 1000 + D * 10 + R && scalar == S && dmax == D && rpt == R) \
-    return launch_one<TY, D, R>(a, st);
-#else
 #define HB_CASE(S, TY, D, R) \
   if (scalar == S && dmax == D && rpt == R) return launch_one<TY, D, R>(a, st);
-#endif
   HB_CASE(0, double, 8, 1) HB_CASE(0, double, 8, 2) HB_CASE(0, double, 8, 4)
   HB_CASE(0, double, 16, 1) HB_CASE(0, double, 16, 2) HB_CASE(0, double, 16, 4)
   HB_CASE(0, double, 32, 1) HB_CASE(0, double, 32, 2)

@@ -114,47 +114,6 @@ struct BlockGemmDev {
   int64_t ldc;
 };
 
-// Partial products of a tall A^H B over a chunk of rows (the projection of a
-// merge whose second block is orthogonalised against the first).
-struct AhbJobDev {
-  const void* A;  // m x ka, ld m
-  const void* B;  // m x kb, ld m
-  int64_t m;
-  int32_t ka, kb;
-  void* part;     // nchunk x ka x kb partial sums (column-major ka x kb each)
-  void* out;      // ka x kb result (column-major)
-  int32_t nchunk;
-  int32_t pad;
-};
-
-// C = Cin + sgn * A * B with A tall (m x ka) and B small (ka x nc).
-struct TallGemmDev {
-  const void* Cin;  // m x nc, ld ldc (may equal C)
-  const void* A;    // m x ka, ld lda
-  const void* B;    // ka x nc, ld ldb
-  void* C;          // m x nc, ld ldc
-  int64_t m, lda, ldb, ldc;
-  int32_t ka, nc;
-  double sgn;
-};
-
-// R of a split merge.  The block "a" (orthonormal P_a, r_a columns) is kept
-// as a basis; block "b" is projected: P_b = P_a (M + M2) + Q_b R_b.  Rows of R
-// follow the basis [P_a, Q_b]; columns follow B = [P1 diag(S1), P2 diag(S2)].
-struct SplitRDev {
-  const double* S1;
-  const double* S2;
-  const void* M;   // r_a x r_b
-  const void* M2;  // r_a x r_b
-  int32_t r1, r2;
-  int32_t ra, rb, pb;
-  int32_t a_first;  // 1: block a is the first block
-  int64_t store;    // TSQR top node of the projected block (R_b), if pb > 0
-  int32_t ab;
-  int32_t pad2;
-  void* R;          // (ra + pb) x (r1 + r2), column-major
-};
-
 // Copy of a TSQR top node's R (p x k) into a column-major block (ld ld).
 struct RCopyDev {
   int64_t store;
@@ -180,12 +139,6 @@ int rcopy_launch(int scalar, const RCopyDev* jobs_dev, int njobs, const void* st
                  const void* alpha, hipStream_t st);
 int rcompact_launch(int scalar, const RCompactDev* jobs_dev, int njobs, hipStream_t st);
 int zero_fill_launch(void* ptr, size_t bytes, hipStream_t st);
-int ahb_launch(int scalar, const AhbJobDev* jobs_dev, int njobs, int max_chunks, int max_ka,
-               int max_kb, hipStream_t st);
-int tall_gemm_launch(int scalar, const TallGemmDev* jobs_dev, int njobs, int64_t max_m,
-                     int max_ka, hipStream_t st);
-int split_r_launch(int scalar, const SplitRDev* jobs_dev, int njobs, const void* store,
-                   const void* alpha, hipStream_t st);
 int tsqr_factor_launch(int scalar, int kmax, const QRNodeDev* nodes_dev, int nnodes,
                        const QRNodeDev* level_below_dev, void* store, void* alpha,
                        double* beta, hipStream_t st);

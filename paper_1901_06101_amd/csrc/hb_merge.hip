@@ -824,124 +824,6 @@ __global__ __launch_bounds__(BG_NT) void block_gemm_kernel(const BlockGemmDev* _
 }
 
 
-// ------------------------------------------- split merge (block CGS2) -----
-constexpr int AHB_RC = 32;   // rows per chunk
-constexpr int AHB_NT = 256;
-
-template <typename T>
-__global__ __launch_bounds__(AHB_NT) void ahb_partial_kernel(const AhbJobDev* __restrict__ jobs) {
-  const AhbJobDev J = jobs[blockIdx.y];
-  const int c = blockIdx.x;
-  if (c >= J.nchunk) return;
-  const int ka = J.ka, kb = J.kb;
-  const int64_t i0 = (int64_t)c * AHB_RC;
-  const int nr = (int)min<int64_t>(AHB_RC, J.m - i0);
-  extern __shared__ unsigned char smem_raw[];
-  T* sA = (T*)smem_raw;              // AHB_RC x ka (row-major)
-  T* sB = sA + (size_t)AHB_RC * ka;  // AHB_RC x kb
-  const T* A = (const T*)J.A;
-  const T* B = (const T*)J.B;
-  for (int e = threadIdx.x; e < AHB_RC * ka; e += AHB_NT) {
-    const int ii = e % AHB_RC, t = e / AHB_RC;
-    sA[ii * ka + t] = ii < nr ? A[(int64_t)t * J.m + i0 + ii] : sc_zero<T>();
-  }
-  for (int e = threadIdx.x; e < AHB_RC * kb; e += AHB_NT) {
-    const int ii = e % AHB_RC, t = e / AHB_RC;
-    sB[ii * kb + t] = ii < nr ? B[(int64_t)t * J.m + i0 + ii] : sc_zero<T>();
-  }
-  __syncthreads();
-  T* part = (T*)J.part + (size_t)c * ka * kb;
-  for (int o = threadIdx.x; o < ka * kb; o += AHB_NT) {
-    const int a = o % ka, b = o / ka;
-    T acc = sc_zero<T>();
-    for (int ii = 0; ii < AHB_RC; ++ii) sc_cfma(acc, sA[ii * ka + a], sB[ii * kb + b]);
-    part[o] = acc;
-  }
-}
-
-template <typename T>
-__global__ void ahb_reduce_kernel(const AhbJobDev* __restrict__ jobs) {
-  const AhbJobDev J = jobs[blockIdx.y];
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n = J.ka * J.kb;
-  if (o >= n) return;
-  const T* part = (const T*)J.part;
-  T acc = sc_zero<T>();
-  for (int c = 0; c < J.nchunk; ++c) acc = sc_add(acc, part[(size_t)c * n + o]);
-  ((T*)J.out)[o] = acc;
-}
-
-constexpr int TG_NT = 256;
-constexpr int TG_CT = 16;
-
-template <typename T>
-__global__ __launch_bounds__(TG_NT) void tall_gemm_kernel(const TallGemmDev* __restrict__ jobs) {
-  const TallGemmDev J = jobs[blockIdx.y];
-  const int64_t row = (int64_t)blockIdx.x * TG_NT + threadIdx.x;
-  if ((int64_t)blockIdx.x * TG_NT >= J.m) return;
-  extern __shared__ unsigned char smem_raw[];
-  T* sB = (T*)smem_raw;  // ka x TG_CT
-  const T* A = (const T*)J.A;
-  const T* Bm = (const T*)J.B;
-  const T* Cin = (const T*)J.Cin;
-  T* Cm = (T*)J.C;
-  for (int c0 = 0; c0 < J.nc; c0 += TG_CT) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < J.ka * TG_CT; e += TG_NT) {
-      const int t = e % J.ka, cc = e / J.ka;
-      sB[t * TG_CT + cc] = (c0 + cc < J.nc) ? Bm[(int64_t)(c0 + cc) * J.ldb + t] : sc_zero<T>();
-    }
-    __syncthreads();
-    if (row < J.m) {
-      T acc[TG_CT];
-#pragma unroll
-      for (int cc = 0; cc < TG_CT; ++cc) acc[cc] = sc_zero<T>();
-      for (int t = 0; t < J.ka; ++t) {
-        const T a = A[(int64_t)t * J.lda + row];
-#pragma unroll
-        for (int cc = 0; cc < TG_CT; ++cc) sc_fma(acc[cc], a, sB[t * TG_CT + cc]);
-      }
-#pragma unroll
-      for (int cc = 0; cc < TG_CT; ++cc) {
-        if (c0 + cc < J.nc) {
-          const int64_t idx = (int64_t)(c0 + cc) * J.ldc + row;
-          const T base = Cin ? Cin[idx] : sc_zero<T>();
-          Cm[idx] = sc_add(base, sc_scale(acc[cc], J.sgn));
-        }
-      }
-    }
-  }
-}
-
-template <typename T>
-__global__ void split_r_kernel(const SplitRDev* __restrict__ jobs, const T* __restrict__ store,
-                               const T* __restrict__ alpha) {
-  const SplitRDev J = jobs[blockIdx.x];
-  const int r1 = J.r1, ra = J.ra, rb = J.rb, p = J.ra + J.pb, k = J.r1 + J.r2;
-  T* R = (T*)J.R;
-  const T* M = (const T*)J.M;
-  const T* M2 = (const T*)J.M2;
-  QRNodeDev N;
-  N.store = J.store;
-  N.ab = J.ab;
-  for (int e = threadIdx.x; e < p * k; e += blockDim.x) {
-    const int i = e % p, j = e / p;
-    const bool first = j < r1;
-    const int jj = first ? j : j - r1;
-    const double sc = first ? J.S1[jj] : J.S2[jj];
-    const bool in_a = (first == (J.a_first != 0));
-    T v = sc_zero<T>();
-    if (in_a) {
-      if (i == jj) v = sc_real<T>(sc);
-    } else if (i < ra) {
-      v = sc_scale(sc_add(M[(int64_t)jj * ra + i], M2[(int64_t)jj * ra + i]), sc);
-    } else {
-      v = sc_scale(node_R<T>(store, alpha, N, i - ra, jj), sc);
-    }
-    (void)rb;
-    R[e] = v;
-  }
-}
 }  // namespace
 
 namespace hbk {
@@ -1045,64 +927,6 @@ int block_gemm_launch(int scalar, const BlockGemmDev* jobs, int n, int max_rows,
     hipLaunchKernelGGL((block_gemm_kernel<hb_cplx>), grid, dim3(BG_NT), sh, st, jobs, max_rin);
   return (int)hipGetLastError();
 }
-
-int ahb_launch(int scalar, const AhbJobDev* jobs, int n, int max_chunks, int max_ka, int max_kb,
-               hipStream_t st) {
-  if (n == 0) return 0;
-  const size_t sb = scalar == 0 ? 8 : 16;
-  const size_t sh = (size_t)AHB_RC * (max_ka + max_kb) * sb;
-  if (sh > 150 * 1024) return -1;
-  dim3 g1(max_chunks, n);
-  dim3 g2((max_ka * max_kb + 255) / 256, n);
-  if (scalar == 0) {
-    if (sh > 64 * 1024)
-      (void)hipFuncSetAttribute((const void*)ahb_partial_kernel<double>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL((ahb_partial_kernel<double>), g1, dim3(AHB_NT), sh, st, jobs);
-    hipLaunchKernelGGL((ahb_reduce_kernel<double>), g2, dim3(256), 0, st, jobs);
-  } else {
-    if (sh > 64 * 1024)
-      (void)hipFuncSetAttribute((const void*)ahb_partial_kernel<hb_cplx>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL((ahb_partial_kernel<hb_cplx>), g1, dim3(AHB_NT), sh, st, jobs);
-    hipLaunchKernelGGL((ahb_reduce_kernel<hb_cplx>), g2, dim3(256), 0, st, jobs);
-  }
-  return (int)hipGetLastError();
-}
-
-int tall_gemm_launch(int scalar, const TallGemmDev* jobs, int n, int64_t max_m, int max_ka,
-                     hipStream_t st) {
-  if (n == 0 || max_m == 0) return 0;
-  const size_t sb = scalar == 0 ? 8 : 16;
-  const size_t sh = (size_t)std::max(max_ka, 1) * TG_CT * sb;
-  if (sh > 150 * 1024) return -1;
-  dim3 g((unsigned)((max_m + TG_NT - 1) / TG_NT), n);
-  if (scalar == 0) {
-    if (sh > 64 * 1024)
-      (void)hipFuncSetAttribute((const void*)tall_gemm_kernel<double>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL((tall_gemm_kernel<double>), g, dim3(TG_NT), sh, st, jobs);
-  } else {
-    if (sh > 64 * 1024)
-      (void)hipFuncSetAttribute((const void*)tall_gemm_kernel<hb_cplx>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL((tall_gemm_kernel<hb_cplx>), g, dim3(TG_NT), sh, st, jobs);
-  }
-  return (int)hipGetLastError();
-}
-
-int split_r_launch(int scalar, const SplitRDev* jobs, int n, const void* store, const void* alpha,
-                   hipStream_t st) {
-  if (n == 0) return 0;
-  if (scalar == 0)
-    hipLaunchKernelGGL((split_r_kernel<double>), dim3(n), dim3(256), 0, st, jobs,
-                       (const double*)store, (const double*)alpha);
-  else
-    hipLaunchKernelGGL((split_r_kernel<hb_cplx>), dim3(n), dim3(256), 0, st, jobs,
-                       (const hb_cplx*)store, (const hb_cplx*)alpha);
-  return (int)hipGetLastError();
-}
-
 
 template <typename T, int KMAX, int NQ, int SEG>
 static int apph(const QRApplyHDev* jobs, int n, const void* store, const double* beta,
