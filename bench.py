@@ -2,8 +2,10 @@
 
 A step is one full H-BACA pass (leaf BACA, leaf SVD re-compression, every
 merge level) over the benchmark workload with its inputs already resident in
-HBM.  Prints one JSON line.  See the design doc for the roofline and the
-algorithmic byte counts.
+HBM.  Prints one JSON line.  The roofline object rates the leaf BACA kernel:
+its algorithmic bytes (U and V streamed once per iteration, counted by the
+library from the per-iteration block ranks) over its duration from HIP events
+on the call's stream, against the 8 TB/s HBM peak.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload helmholtz]
                   [--no-cpu-baseline]

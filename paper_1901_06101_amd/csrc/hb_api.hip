@@ -64,7 +64,7 @@ static void hb_report(const char* what, int code, const char* detail, int line) 
 // --------------------------------------------------------- device memory ---
 // Caching device allocator.  Blocks are rounded up to size classes (four per
 // octave, at least 256 bytes), obtained once with hipMalloc and never given
-// back to the driver: a freed block goes to a free list tagged with the stream
+// back to the HIP runtime: a freed block goes to a free list tagged with the stream
 // whose work last used it and is reused only by work on that same stream
 // (stream order makes the reuse safe), or by any stream once the device has
 // been synchronised (result memory).  This keeps allocation off the critical
@@ -1403,7 +1403,7 @@ static void run_recompress_narrow(Engine& E, std::vector<RecJob>& jobs, DevMem& 
   E.apply(F, zin, ldin, rr, zout, ldout);
 }
 
-// ------------------------------------------------------------ the driver ---
+// ---------------------------------------------------------- the pipeline ---
 struct CallSpec {
   int entry;
   const hb_params* prm;
