@@ -170,6 +170,19 @@ int32_t hb_result_is_complex(const hb_result* res);
 hb_status hb_result_copy(const hb_result* res, int64_t block, void* U, double* sigma, void* Vh,
                          void* stream);
 
+/*
+ * The compressed operator of block `block` applied to a DEVICE vector:
+ *   adjoint = 0:  out (rows)  = U diag(sigma) Vh^H in  (in: cols entries)
+ *   adjoint = 1:  out (cols)  = Vh diag(sigma) U^H in  (in: rows entries)
+ * Vectors hold the result's scalar type (FP64, or interleaved FP64 pairs for
+ * a complex result).  This is y = U (V^T w) of the differentiation workload
+ * and its adjoint, the gradient of <y, ybar> with respect to w.  Asynchronous
+ * on `stream`; `in` and `out` must not overlap.  Ranks above 4096 (8192 real)
+ * return HB_EUNSUPPORTED.
+ */
+hb_status hbaca_apply(const hb_result* res, int64_t block, const void* in, void* out,
+                      int32_t adjoint, void* stream);
+
 /* Statistics of the call (host struct). */
 hb_status hb_result_stats(const hb_result* res, hb_stats* out);
 

@@ -18,7 +18,7 @@ from ._binding import (HB_K_GAUSS, HB_K_HELMHOLTZ3D, HB_K_LAPLACE,  # noqa: F401
                        HB_K_LOWRANK_SPIKES, HB_PREC_FP64, HB_PREC_MIXED, HBACAError, HbParams,
                        HbStats, load)
 
-__all__ = ["compress", "compress_batched", "Result", "require_gpu", "params", "load",
+__all__ = ["compress", "compress_batched", "Result", "operator", "require_gpu", "params", "load",
            "HBACAError", "HB_K_GAUSS", "HB_K_LAPLACE", "HB_K_HELMHOLTZ3D",
            "HB_K_LOWRANK_SPIKES", "HB_PREC_FP64", "HB_PREC_MIXED"]
 
@@ -157,6 +157,20 @@ class Result:
             mu.ctypes.data_as(C.c_void_p)), "hb_result_leaf_tape")
         return dict(rows=rows[:n], cols=cols[:n], dk=dk[:it], nu=nu[:it], mu=mu[:it])
 
+    def apply(self, w, block=0, adjoint=False):
+        """U diag(S) Vh^H w (adjoint=False) or Vh diag(S) U^H w (adjoint=True)
+        for a device vector w; returns a new device vector."""
+        import torch
+        m, n = self.shape(block)
+        dt = torch.complex128 if self.is_complex else torch.float64
+        w = w.to(dtype=dt).contiguous()
+        if w.numel() != (m if adjoint else n):
+            raise ValueError(f"vector of length {w.numel()} for a {m} x {n} block")
+        out = torch.empty((n if adjoint else m,), dtype=dt, device=w.device)
+        B._check(self._lib.hbaca_apply(self._h, block, _ptr(w), _ptr(out), int(bool(adjoint)),
+                                       _stream()), "hbaca_apply")
+        return out
+
     def error(self, block=0, row_stride=1):
         """(sum |A - A~|^2, sum |A|^2) over rows 0, stride, ... (device FP64)."""
         e = C.c_double()
@@ -164,6 +178,26 @@ class Result:
         B._check(self._lib.hb_result_error(self._h, block, row_stride, C.byref(e), C.byref(a),
                                            _stream()), "hb_result_error")
         return e.value, a.value
+
+
+def operator(result: Result, block: int = 0):
+    """y = A~ w as a differentiable function of w: its backward applies the
+    adjoint Vh diag(S) U^H on the GPU (the gradient with respect to w; the
+    factors are constants)."""
+    import torch
+
+    class _Apply(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, w):
+            return result.apply(w, block, adjoint=False)
+
+        @staticmethod
+        def backward(ctx, ybar):
+            # torch's complex convention: the vector-Jacobian product of a
+            # linear map A is A^H ybar
+            return result.apply(ybar.contiguous(), block, adjoint=True)
+
+    return _Apply.apply
 
 
 def compress(entry: int, p: dict, X, Y, m: int, n: int, tol: float, d: int, leaf: int) -> Result:

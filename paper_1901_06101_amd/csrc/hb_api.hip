@@ -245,6 +245,46 @@ __global__ void aos_to_soa_kernel(const double* __restrict__ src, double* __rest
   for (int c = 0; c < dim; ++c) dst[(int64_t)c * npts + i] = src[i * dim + c];
 }
 
+// Compressed operator applied to a vector: y = U diag(S) Vh^H w, or its
+// adjoint w~ = Vh diag(S) U^H y.  First t_j = S_j sum_i conj(X(i, j)) v_i for
+// every column j of X (one workgroup per column, a deterministic tree sum),
+// then out_i = sum_j Z(i, j) t_j (one thread per row, t staged in LDS).
+constexpr int AP_NT = 256;
+template <typename T>
+__global__ __launch_bounds__(AP_NT) void apply_reduce_kernel(const T* __restrict__ X, int64_t len,
+                                                             int r, const double* __restrict__ S,
+                                                             const T* __restrict__ v,
+                                                             T* __restrict__ t) {
+  const int j = blockIdx.x;
+  if (j >= r) return;
+  const T* x = X + (int64_t)j * len;
+  T acc = sc_zero<T>();
+  for (int64_t i = threadIdx.x; i < len; i += AP_NT) sc_cfma(acc, x[i], v[i]);
+  acc = group_sum_sc<64, T>(acc);
+  __shared__ T part[AP_NT / 64];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T sum = part[0];
+    for (int w = 1; w < AP_NT / 64; ++w) sum = sc_add(sum, part[w]);
+    t[j] = sc_scale(sum, S[j]);
+  }
+}
+template <typename T>
+__global__ __launch_bounds__(AP_NT) void apply_expand_kernel(const T* __restrict__ Z, int64_t len,
+                                                             int r, const T* __restrict__ t,
+                                                             T* __restrict__ out) {
+  extern __shared__ unsigned char smem_ap[];
+  T* st = (T*)smem_ap;
+  for (int j = threadIdx.x; j < r; j += AP_NT) st[j] = t[j];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * AP_NT + threadIdx.x;
+  if (i >= len) return;
+  T acc = sc_zero<T>();
+  for (int j = 0; j < r; ++j) sc_fma(acc, Z[(int64_t)j * len + i], st[j]);
+  out[i] = acc;
+}
+
 // FP32 leaf factors of the mixed-precision path widened to FP64 for the
 // re-compression and the merges (one grid row per factor).
 struct CvtDev {
@@ -2015,6 +2055,41 @@ hb_status hb_result_copy(const hb_result* r, int64_t b, void* U, double* sigma, 
   if (sigma && hipMemcpyAsync(sigma, B.S, (size_t)B.r * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return HB_EDEVICE;
   return HB_OK;
+}
+
+hb_status hbaca_apply(const hb_result* r, int64_t b, const void* in, void* out, int32_t adjoint,
+                      void* stream) {
+  if (!r || b < 0 || b >= (int64_t)r->out_blocks.size() || !in || !out) return HB_EINVAL;
+  if (adjoint != 0 && adjoint != 1) return HB_EINVAL;
+  const Block& B = r->out_blocks[b];
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nin = adjoint ? B.m : B.n, nout = adjoint ? B.n : B.m;
+  const size_t sb = scalar_bytes(r->scalar);
+  if (B.r == 0) {
+    if (nout > 0 && hbk::zero_fill_launch(out, (size_t)nout * sb, st) != 0) return HB_EDEVICE;
+    return HB_OK;
+  }
+  if ((size_t)B.r * sb > 64 * 1024) return HB_EUNSUPPORTED;
+  void* t = BlockCache::get().alloc((size_t)B.r * sb, st);
+  if (!t) return HB_ENOMEM;
+  const void* X = adjoint ? B.U : B.Vh;  // reduced against the input
+  const void* Z = adjoint ? B.Vh : B.U;  // expanded into the output
+  const unsigned ng = (unsigned)((nout + AP_NT - 1) / AP_NT);
+  const size_t sh = (size_t)B.r * sb;
+  if (r->scalar == 0) {
+    hipLaunchKernelGGL(apply_reduce_kernel<double>, dim3(B.r), dim3(AP_NT), 0, st,
+                       (const double*)X, nin, B.r, B.S, (const double*)in, (double*)t);
+    hipLaunchKernelGGL(apply_expand_kernel<double>, dim3(ng), dim3(AP_NT), sh, st,
+                       (const double*)Z, nout, B.r, (const double*)t, (double*)out);
+  } else {
+    hipLaunchKernelGGL(apply_reduce_kernel<hb_cplx>, dim3(B.r), dim3(AP_NT), 0, st,
+                       (const hb_cplx*)X, nin, B.r, B.S, (const hb_cplx*)in, (hb_cplx*)t);
+    hipLaunchKernelGGL(apply_expand_kernel<hb_cplx>, dim3(ng), dim3(AP_NT), sh, st,
+                       (const hb_cplx*)Z, nout, B.r, (const hb_cplx*)t, (hb_cplx*)out);
+  }
+  const hipError_t e = hipGetLastError();
+  BlockCache::get().release(t, st, false);
+  return e == hipSuccess ? HB_OK : HB_EDEVICE;
 }
 
 hb_status hb_result_stats(const hb_result* r, hb_stats* out) {

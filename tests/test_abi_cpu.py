@@ -78,4 +78,5 @@ def test_result_accessors_reject_null():
     assert lib.hb_result_rank(None, 0) == -1
     assert lib.hb_result_nblocks(None) == -1
     assert lib.hb_result_copy(None, 0, None, None, None, None) == -1
+    assert lib.hbaca_apply(None, 0, None, None, 0, None) == -1
     lib.hb_result_free(None)
