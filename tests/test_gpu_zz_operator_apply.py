@@ -9,7 +9,7 @@ from workloads import generators as G
 from _hbtest import run_gpu, say
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skip(
-    reason="hbaca_apply was written after GPU access closed and has not run on a GPU yet")]
+    reason="hbaca_apply has not run on a GPU yet")]
 
 
 @pytest.mark.parametrize("name", ["gauss3d", "helmholtz"])
