@@ -2010,11 +2010,15 @@ hb_status hbaca_compress_batched(int entry_fn_id, const hb_params* params, int64
   c.Y = points_col;
   c.nx = 0;
   c.ny = 0;
+  try {
+    c.roff.assign(row_off, row_off + nblocks);
+    c.rcnt.assign(row_cnt, row_cnt + nblocks);
+    c.coff.assign(col_off, col_off + nblocks);
+    c.ccnt.assign(col_cnt, col_cnt + nblocks);
+  } catch (...) {
+    return HB_ENOMEM;
+  }
   for (int64_t b = 0; b < nblocks; ++b) {
-    c.roff.push_back(row_off[b]);
-    c.rcnt.push_back(row_cnt[b]);
-    c.coff.push_back(col_off[b]);
-    c.ccnt.push_back(col_cnt[b]);
     c.nx = std::max(c.nx, row_off[b] + row_cnt[b]);
     c.ny = std::max(c.ny, col_off[b] + col_cnt[b]);
   }
