@@ -720,7 +720,9 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
     double s2 = 0.0;
     for (int i = gl; i < p; i += G) s2 += sc_abs2(x[i]);
     s2 = group_sum<G>(s2);
-    if (gl == 0) sS[j] = sqrt(s2);
+    // a non-finite column (non-finite input) sorts as zero, so the sort
+    // below still yields a permutation
+    if (gl == 0) sS[j] = (s2 == s2 && s2 <= 1.0e300) ? sqrt(s2) : 0.0;
   }
   __syncthreads();
   for (int j = tid; j < k; j += SVD_NT) {
