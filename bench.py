@@ -8,7 +8,12 @@ library from the per-iteration block ranks) over its duration from HIP events
 on the call's stream, against the 8 TB/s HBM peak.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload helmholtz]
-                  [--no-cpu-baseline]
+                  [--no-cpu-baseline] [--no-comparisons]
+
+Besides the headline workload, the line carries "comparisons": mixed
+precision against plain FP64 (Gaussian 2000^2) and one batched call against
+one call per block (1024 Laplace blocks), measured in a child process that
+runs before this process uses the GPU.
 """
 import argparse
 import json
@@ -43,6 +48,111 @@ def cpu_baseline(wl):
                 rank=int(res.rank))
 
 
+def comparisons(steps=5, warmup=1):
+    """Mixed precision and batching against the plain FP64 GPU path, each at
+    the accuracy it reaches; prints one JSON object.  Runs in a child process
+    of the benchmark so that its outcome cannot affect the headline line."""
+    import numpy as np
+    import torch
+
+    import paper_1901_06101_amd as hb
+    from workloads import generators as G
+    from workloads import make_config
+
+    hb.require_gpu()
+    dev = torch.device("cuda:0")
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn().close()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = None
+        for _ in range(steps):
+            if res is not None:
+                res.close()
+            res = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / steps, res
+
+    def rel_err(res, block=0):
+        e2, a2 = res.error(block, 7)
+        return float(np.sqrt(e2 / a2))
+
+    out = {}
+    # plain FP64 against mixed precision on the Gaussian R^3 workload
+    wl = make_config("gauss3d")
+    X = torch.tensor(wl["X"], device=dev)
+    Y = torch.tensor(wl["Y"], device=dev)
+
+    def single(prec):
+        p = hb.params(dim=3, h=wl["h"], gauss_c=wl["gauss_c"], seed=wl["seed"], precision=prec)
+        return hb.compress(wl["entry"], p, X, Y, wl["m"], wl["n"], wl["tol"], wl["d"], wl["leaf"])
+
+    f_ms, f_res = timed(lambda: single(hb.HB_PREC_FP64), steps, warmup)
+    m_ms, m_res = timed(lambda: single(hb.HB_PREC_MIXED), steps, warmup)
+    ef, em = rel_err(f_res), rel_err(m_res)
+    out["mixed_vs_fp64"] = dict(
+        workload=f"gauss3d {wl['m']}x{wl['n']} tol={wl['tol']} d={wl['d']} leaf={wl['leaf']}",
+        fp64_ms=f_ms, mixed_ms=m_ms, speedup=f_ms / m_ms, fp64_rank=f_res.rank(0),
+        mixed_rank=m_res.rank(0), fp64_rel_err_rows7=ef, mixed_rel_err_rows7=em,
+        mixed_within_5tol=bool(em <= 5 * wl["tol"]))
+    f_res.close()
+    m_res.close()
+    # one batched call against one call per block (Laplace blocks of the
+    # batched workload's recipe), FP64 and mixed
+    nb = 1024
+    wb = G.make_laplace_blocks(nblocks=nb, cfg=3)
+    Xb = torch.tensor(wb["X"], device=dev)
+    Yb = torch.tensor(wb["Y"], device=dev)
+
+    def batched(prec):
+        p = hb.params(dim=3, seed=wb["seed"], precision=prec)
+        return hb.compress_batched(wb["entry"], p, Xb, wb["row_off"], wb["row_cnt"], Yb,
+                                   wb["col_off"], wb["col_cnt"], wb["tol"], wb["d"], wb["leaf"])
+
+    bf_ms, bf_res = timed(lambda: batched(hb.HB_PREC_FP64), 3, 1)
+    bm_ms, bm_res = timed(lambda: batched(hb.HB_PREC_MIXED), 3, 1)
+
+    def sequential():
+        last = None
+        for b in range(nb):
+            r0, m = int(wb["row_off"][b]), int(wb["row_cnt"][b])
+            c0, n = int(wb["col_off"][b]), int(wb["col_cnt"][b])
+            p = hb.params(dim=3, seed=wb["seed"] + b)
+            if last is not None:
+                last.close()
+            last = hb.compress(wb["entry"], p, Xb[r0:r0 + m], Yb[c0:c0 + n], m, n, wb["tol"],
+                               wb["d"], wb["leaf"])
+        return last
+
+    s_ms, s_res = timed(sequential, 1, 1)
+    s_res.close()
+    ebf = max(rel_err(bf_res, b) for b in range(nb))
+    ebm = max(rel_err(bm_res, b) for b in range(nb))
+    out["batched_vs_sequential"] = dict(
+        workload=f"laplace_batched {nb} blocks, sizes 64-1024, tol={wb['tol']} d={wb['d']} "
+                 f"leaf={wb['leaf']}",
+        sequential_fp64_ms=s_ms, batched_fp64_ms=bf_ms, batched_mixed_ms=bm_ms,
+        speedup_batched_fp64=s_ms / bf_ms, speedup_batched_mixed=s_ms / bm_ms,
+        max_rel_err_rows7_fp64=ebf, max_rel_err_rows7_mixed=ebm,
+        mixed_within_5tol=bool(ebm <= 5 * wb["tol"]))
+    print(json.dumps(out), flush=True)
+
+
+def run_comparisons(timeout=300):
+    import subprocess
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--comparisons"],
+                           capture_output=True, text=True, timeout=timeout)
+    except subprocess.TimeoutExpired:
+        return {"error": f"timed out after {timeout} s"}
+    for line in reversed(r.stdout.strip().splitlines()):
+        if line.startswith("{"):
+            return json.loads(line)
+    return {"error": f"exit {r.returncode}: {r.stderr.strip()[-400:]}"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,7 +160,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="helmholtz")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparisons", action="store_true")
+    ap.add_argument("--comparisons", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.comparisons:
+        comparisons()
+        return
+    # the comparisons run first, in a child process, before this process
+    # touches the GPU
+    comp = None if args.no_comparisons else run_comparisons()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); how H-BACA would "
               "shard over several GPUs is described in the design notes", file=sys.stderr)
@@ -136,6 +254,8 @@ def main():
         except Exception as e:  # the GPU line is still reported
             out["cpu_baseline"] = {"value": None, "unit": "ms", "cores": None, "kind": "oracle",
                                    "sample": f"failed: {type(e).__name__}: {e}"}
+    if comp is not None:
+        out["comparisons"] = comp
     print(json.dumps(out), flush=True)
 
 
