@@ -87,7 +87,10 @@ typedef struct {
   uint64_t seed;
   int32_t precision;   /* hb_precision */
   int32_t rank_cap;    /* max BACA rank per leaf; 0 = min(m0, n0) */
-  int32_t record_tape; /* keep per-leaf pivots, d_k, nu, mu for hb_result_leaf_tape */
+  int32_t record_tape; /* 0: nothing; 1: keep per-leaf pivots, d_k, nu, mu for
+                          hb_result_leaf_tape; 2: also the frozen structure
+                          (every I_k, J_k and pivot order of QR(W_k, eps), and
+                          every truncation rank) that hbaca_vjp replays */
   int32_t stop_after;  /* diagnostics: 0 full H-BACA; 1 stop after the leaf
                           BACA (blocks = leaves, A_leaf ~ U Vh^H, sigma = 1);
                           2 stop after the leaf SVD re-compression;
@@ -182,6 +185,41 @@ hb_status hb_result_copy(const hb_result* res, int64_t block, void* U, double* s
  */
 hb_status hbaca_apply(const hb_result* res, int64_t block, const void* in, void* out,
                       int32_t adjoint, void* stream);
+
+/*
+ * Vector-Jacobian product of y = A~(h, X, Y) w with pivots and ranks frozen.
+ *
+ * With every BACA iteration's row block I_k, column block J_k, pivot order
+ * of QR(W_k, eps) and d_k (Algorithm 2, eqs. (6)-(9)) and every truncation
+ * rank of the re-compression and of the merges (Algorithm 3, eqs.
+ * (14)-(15)) held at the values of the forward run, the compressed
+ * operator A~ depends smoothly on the sampled Gaussian entries
+ * exp(-|x_i - y_j|^2 / (c h^2)).  This call replays that fixed pipeline in
+ * FP64 on the device and runs it in reverse, returning the gradient of
+ * <ybar, A~ w> with respect to w, the width h, the row points and the
+ * column points.
+ *
+ * res:   a real Gaussian (HB_K_GAUSS) result of hbaca_compress run to the
+ *        end (stop_after = 0) with params->record_tape = 2; otherwise
+ *        HB_EINVAL (HB_EUNSUPPORTED for another kernel).
+ * w:     DEVICE, n FP64 entries;  ybar: DEVICE, m FP64 entries.
+ * grad_w: DEVICE, n FP64 (= A~^T ybar of the replayed factors);
+ * grad_h: DEVICE, 1 FP64;
+ * grad_points_row: DEVICE, m x dim FP64 in the layout of points_row;
+ * grad_points_col: DEVICE, n x dim FP64 in the layout of points_col.
+ * Any gradient pointer may be NULL to skip it.  The call allocates its own
+ * device workspace (the replayed factors, the saved blocks of every
+ * iteration and merge, and the cotangents), runs on `stream` and
+ * synchronises it before returning.  A merge whose stacked factor has fewer
+ * rows than columns (leaves smaller than the sum of two children's ranks)
+ * returns HB_EUNSUPPORTED.  The replay assumes the frozen ranks sit at a gap
+ * of the singular values (distinct kept values, separated from the dropped
+ * ones); where they do not, the gradient is not defined and the result is
+ * not finite.
+ */
+hb_status hbaca_vjp(const hb_result* res, const double* w, const double* ybar, double* grad_w,
+                    double* grad_h, double* grad_points_row, double* grad_points_col,
+                    void* stream);
 
 /* Statistics of the call (host struct). */
 hb_status hb_result_stats(const hb_result* res, hb_stats* out);

@@ -18,7 +18,8 @@ from ._binding import (HB_K_GAUSS, HB_K_HELMHOLTZ3D, HB_K_LAPLACE,  # noqa: F401
                        HB_K_LOWRANK_SPIKES, HB_PREC_FP64, HB_PREC_MIXED, HBACAError, HbParams,
                        HbStats, load)
 
-__all__ = ["compress", "compress_batched", "Result", "operator", "require_gpu", "params", "load",
+__all__ = ["compress", "compress_batched", "Result", "operator", "gaussian_operator",
+           "require_gpu", "params", "load",
            "HBACAError", "HB_K_GAUSS", "HB_K_LAPLACE", "HB_K_HELMHOLTZ3D",
            "HB_K_LOWRANK_SPIKES", "HB_PREC_FP64", "HB_PREC_MIXED"]
 
@@ -171,6 +172,28 @@ class Result:
                                        _stream()), "hbaca_apply")
         return out
 
+    def vjp(self, w, ybar, want=("w", "h", "x", "y")):
+        """Gradients of <ybar, A~ w> with pivots and ranks frozen (needs a
+        Gaussian result compressed with record_tape=2): (grad_w, grad_h,
+        grad_X, grad_Y) as device tensors, None where not in `want`."""
+        import torch
+        m, n = self.shape(0)
+        X, Y = self._keep[0], self._keep[1]
+        dim = int(X.shape[1])
+        w = w.to(dtype=torch.float64).contiguous()
+        ybar = ybar.to(dtype=torch.float64).contiguous()
+        if w.numel() != n or ybar.numel() != m:
+            raise ValueError(f"w of length {w.numel()} and ybar of length {ybar.numel()} "
+                             f"for a {m} x {n} operator")
+        f64 = dict(dtype=torch.float64, device=w.device)
+        gw = torch.empty((n,), **f64) if "w" in want else None
+        gh = torch.empty((1,), **f64) if "h" in want else None
+        gX = torch.empty((m, dim), **f64) if "x" in want else None
+        gY = torch.empty((n, dim), **f64) if "y" in want else None
+        B._check(self._lib.hbaca_vjp(self._h, _ptr(w), _ptr(ybar), _ptr(gw), _ptr(gh), _ptr(gX),
+                                     _ptr(gY), _stream()), "hbaca_vjp")
+        return gw, gh, gX, gY
+
     def error(self, block=0, row_stride=1):
         """(sum |A - A~|^2, sum |A|^2) over rows 0, stride, ... (device FP64)."""
         e = C.c_double()
@@ -198,6 +221,40 @@ def operator(result: Result, block: int = 0):
             return result.apply(ybar.contiguous(), block, adjoint=True)
 
     return _Apply.apply
+
+
+def gaussian_operator(X, Y, h, w, tol: float, d: int, leaf: int, gauss_c: float = 1.0,
+                      seed: int = 0):
+    """y = A~ w for the H-BACA compression A~ of A(i, j) = exp(-|x_i - y_j|^2 /
+    (c h^2)), differentiable with respect to the points X (m x dim), Y
+    (n x dim), the width h (a 0-dim or 1-element tensor) and w: the forward
+    pass compresses on the GPU (recording its pivots and ranks) and applies
+    the factors; the backward pass is hbaca_vjp, the adjoint of the same
+    compression with those pivots and ranks frozen."""
+    import torch
+
+    class _GaussApply(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, X, Y, h, w):
+            p = params(dim=int(X.shape[1]), h=float(h), gauss_c=gauss_c, seed=seed, record_tape=2)
+            Xd = X.detach().to(torch.float64).contiguous()
+            Yd = Y.detach().to(torch.float64).contiguous()
+            res = compress(HB_K_GAUSS, p, Xd, Yd, Xd.shape[0], Yd.shape[0], tol, d, leaf)
+            wd = w.detach().to(torch.float64).contiguous()
+            ctx.res = res
+            ctx.h_shape = h.shape
+            ctx.save_for_backward(wd)
+            return res.apply(wd)
+
+        @staticmethod
+        def backward(ctx, ybar):
+            (wd,) = ctx.saved_tensors
+            need = ctx.needs_input_grad
+            want = tuple(k for k, f in zip(("x", "y", "h", "w"), need) if f)
+            gw, gh, gX, gY = ctx.res.vjp(wd, ybar, want=want)
+            return gX, gY, (gh.reshape(ctx.h_shape) if gh is not None else None), gw
+
+    return _GaussApply.apply(X, Y, h, w)
 
 
 def compress(entry: int, p: dict, X, Y, m: int, n: int, tol: float, d: int, leaf: int) -> Result:

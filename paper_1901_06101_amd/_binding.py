@@ -22,7 +22,7 @@ EXPORTED = (
     "hbaca_compress", "hbaca_compress_batched", "hb_result_nblocks", "hb_result_rank",
     "hb_result_rows", "hb_result_cols", "hb_result_is_complex", "hb_result_copy",
     "hb_result_stats", "hb_result_nleaves", "hb_result_leaf_info", "hb_result_leaf_tape",
-    "hb_result_error", "hb_result_free", "hb_status_string", "hbaca_apply",
+    "hb_result_error", "hb_result_free", "hb_status_string", "hbaca_apply", "hbaca_vjp",
 )
 
 
@@ -123,6 +123,8 @@ def load(path: str = LIB_PATH):
     lib.hb_result_error.restype = C.c_int
     lib.hbaca_apply.argtypes = [vp, i64, vp, vp, i32, vp]
     lib.hbaca_apply.restype = C.c_int
+    lib.hbaca_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hbaca_vjp.restype = C.c_int
     lib.hb_result_free.argtypes = [vp]
     lib.hb_result_free.restype = None
     lib.hb_status_string.argtypes = [C.c_int]

@@ -1,0 +1,853 @@
+// Frozen-pivot adjoint of the compressed operator: one-workgroup tasks.
+//
+// With the pivots of every BACA iteration (the row block I_k, the column
+// block J_k, the pivot order of QR(W_k, eps) and d_k) and every truncation
+// rank fixed to those of a forward run, the compressed operator
+// A~ = U diag(s) V^T is a smooth function of the sampled entries A(:, J_k)
+// and A(I_k, :) of every leaf, hence of the Gaussian width h and of the
+// point coordinates.  The tasks below replay that fixed pipeline
+// (Algorithm 2 with eqs. (8)-(9), the SVD re-compression, the merges of
+// Algorithm 3 with eqs. (14)-(15)) and run it in reverse, from the
+// cotangent of y = A~ w down to the cotangents of the sampled entries and
+// on to dL/dh and dL/d(points) through the closed-form derivatives of the
+// Gaussian entry.
+//
+// Reverse rules used (real arithmetic):
+// * V_k = T^-1 Q1^T R_k is the least-squares solution W_p^+ R_k with
+//   W_p = Q1 T (full column rank), so with Zb = T^-T Vb_k:
+//   Rb_k = Q1 Zb,  Wb_p = -Q1 Zb V_k^T + (R_k - Q1 Q1^T R_k) (T^-1 Zb)^T.
+// * A truncated SVD P ~ Ub diag(s) Vb^T kept at rank rho, with cotangents
+//   Ubb = [Ub_o, 0], Vbb = [Vb_o, 0] of the kept factors (Townsend,
+//   "Differentiating the singular value decomposition", 2016):
+//   Pb = Ub G Vb^T + (I - Ub Ub^T) Ubb s^-1 Vb^T + Ub s^-1 Vbb^T (I - Vb Vb^T),
+//   G = diag(sb) + (F o (J - J^T)) diag(s) + diag(s) (F o (K - K^T)),
+//   J = Ub^T Ubb, K = Vb^T Vbb, F_ij = 1 / (s_j^2 - s_i^2).  Only the kept
+//   singular values are inverted.  For the re-compression P = U Vt^T the
+//   third term vanishes in Pb Vt and the second in Pb^T U; for a merge,
+//   P = [P1 diag(S1), P2 diag(S2)] is tall with a square right factor, so
+//   its third term is zero.
+//
+// Every task runs on one workgroup.  `W` supplies the lane id `tid`, the
+// lane count `nt` (a power of two), a reduction array `red` of nt doubles
+// and `sync()`, a barrier that every lane reaches.  Loops stride by nt over
+// disjoint outputs and a phase that reads another lane's output follows a
+// sync(), so the result does not depend on the lane count.
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define HBA_FN __device__ inline
+#else
+#define HBA_FN inline
+#endif
+
+#define HBA_DMAX 32   // largest block size d of a replayed leaf
+#define HBA_MAXDIM 8  // largest point dimension
+
+enum AdjTaskKind {
+  ADJ_LEAF_FWD = 0,
+  ADJ_REC_FWD = 1,
+  ADJ_MERGE_FWD = 2,
+  ADJ_ROOT = 3,
+  ADJ_MERGE_BWD = 4,
+  ADJ_REC_BWD = 5,
+  ADJ_LEAF_BWD = 6,
+  ADJ_RED_ROWS = 7,
+  ADJ_RED_COLS = 8,
+  ADJ_RED_H = 9,
+};
+
+// One leaf (offsets are in doubles from the arena base D; ws_* are offsets
+// from the phase workspace).
+struct AdjLeaf {
+  int64_t row0, col0;  // first row / column of the leaf in the problem
+  int32_t m0, n0;
+  int32_t iters;       // replayed iterations (all with d_k > 0)
+  int32_t rb;          // BACA rank, sum of d_k
+  int32_t rho;         // rank after the SVD re-compression
+  int32_t fz_off;      // index of the first iteration record
+  int64_t U, Vt;       // BACA factors, m0 x rb and n0 x rb
+  int64_t it, it_sz;   // iteration k: C (m0 x dmax), R (dmax x n0), Q1, T (dmax x dmax)
+  int64_t Ub, Vb, S;   // re-compression: m0 x rb, n0 x rb, rb
+  int64_t gU, gVt;     // cotangents of U and Vt
+  int64_t gx, gy, gh;  // partial gradients: m0 x dim, n0 x dim (ld m0, n0), 1
+  int64_t ws_lf, ws_rf, ws_rb, ws_lb;
+};
+
+// A compressed block U diag(S) Vt^T and the cotangents of its factors.
+struct AdjBlock {
+  int64_t m, n;
+  int32_t r, pad;
+  int64_t U, ldU, Vt, ldVt, S;
+  int64_t gU, gVt, gS;  // m x r (ld m), n x r (ld n), r
+};
+
+// A merge of blocks b1 and b2 (horizontal: side by side, the P side is U;
+// vertical: stacked, the P side is Vt).
+struct AdjMerge {
+  int32_t b1, b2, out, horiz;
+  int32_t k, rho;      // k = r1 + r2 columns, rank kept
+  int64_t rows;        // rows of the P side
+  int64_t n1, n2;      // rows of the O sides
+  int64_t Ub, Y, S;    // rows x k, k x k, k
+  int64_t ws_f, ws_b;
+};
+
+struct AdjArgs {
+  double* D;            // arena
+  double* ws;           // phase workspace
+  const int32_t* fz;    // iteration records: nI, nJ, d_k, I_k, J_k, pivot order
+  const AdjLeaf* leaves;
+  const AdjBlock* blocks;
+  const AdjMerge* merges;
+  const double* X;      // points, structure of arrays: X[q * ldx + i]
+  const double* Y;
+  int64_t ldx, ldy;
+  int32_t dim, dmax, fz_stride, root;
+  int32_t nb, nleaves;
+  double h, nic;        // Gaussian width and -1 / (c h^2)
+  const double* w;      // n
+  const double* ybar;   // m
+  double* gw;           // n (may be null)
+  double* gh;           // 1 (may be null)
+  double* gX;           // m x dim, points-major (may be null)
+  double* gY;           // n x dim (may be null)
+};
+
+// --------------------------------------------------------------- helpers ---
+template <class W>
+HBA_FN double wg_sum(W& w, double v) {
+  w.red[w.tid] = v;
+  w.sync();
+  for (int s = w.nt / 2; s > 0; s >>= 1) {
+    if (w.tid < s) w.red[w.tid] += w.red[w.tid + s];
+    w.sync();
+  }
+  const double r = w.red[0];
+  w.sync();
+  return r;
+}
+
+// C (m x n) = alpha op(A) op(B) + beta C, column-major, op = transpose when
+// tA / tB is set; C must not overlap A or B.
+template <class W>
+HBA_FN void wg_gemm(W& w, int64_t m, int64_t n, int64_t k, double alpha, const double* A,
+                    int64_t lda, int tA, const double* B, int64_t ldb, int tB, double beta,
+                    double* C, int64_t ldc) {
+  for (int64_t e = w.tid; e < m * n; e += w.nt) {
+    const int64_t i = e % m, j = e / m;
+    double s = 0.0;
+    for (int64_t l = 0; l < k; ++l) {
+      const double x = tA ? A[l + i * lda] : A[i + l * lda];
+      const double y = tB ? B[j + l * ldb] : B[l + j * ldb];
+      s += x * y;
+    }
+    C[i + j * ldc] = alpha * s + (beta == 0.0 ? 0.0 : beta * C[i + j * ldc]);
+  }
+  w.sync();
+}
+
+// Thin QR of A (m x k, m >= k) by classical Gram-Schmidt with one full
+// re-orthogonalisation ("twice is enough"): Q (m x k) with orthonormal
+// columns, R (k x k) upper triangular with a non-negative diagonal.  Q may
+// be A itself (same ld).  h: k doubles of scratch.
+template <class W>
+HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* Q, int64_t ldq,
+                  double* R, int64_t ldr, double* h) {
+  for (int j = 0; j < k; ++j) {
+    if (A != Q)
+      for (int64_t i = w.tid; i < m; i += w.nt) Q[i + j * ldq] = A[i + j * lda];
+    for (int e = w.tid; e < k; e += w.nt) R[e + j * ldr] = 0.0;
+    w.sync();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = w.tid; i < j; i += w.nt) {
+        double s = 0.0;
+        for (int64_t l = 0; l < m; ++l) s += Q[l + i * ldq] * Q[l + j * ldq];
+        h[i] = s;
+      }
+      w.sync();
+      for (int64_t l = w.tid; l < m; l += w.nt) {
+        double s = Q[l + j * ldq];
+        for (int i = 0; i < j; ++i) s -= Q[l + i * ldq] * h[i];
+        Q[l + j * ldq] = s;
+      }
+      for (int i = w.tid; i < j; i += w.nt) R[i + j * ldr] += h[i];
+      w.sync();
+    }
+    double part = 0.0;
+    for (int64_t l = w.tid; l < m; l += w.nt) part += Q[l + j * ldq] * Q[l + j * ldq];
+    const double nrm = sqrt(wg_sum(w, part));
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int64_t l = w.tid; l < m; l += w.nt) Q[l + j * ldq] *= inv;
+    if (w.tid == 0) R[j + j * ldr] = nrm;
+    w.sync();
+  }
+}
+
+// SVD of the k x k matrix A = X diag(s) Y^T by one-sided Jacobi (Hestenes)
+// with round-robin pairs: on return A holds X (unit columns, zero for a zero
+// singular value), Y the orthogonal right factor, s the singular values in
+// descending order.  Aw, Yw: k x k scratch; st: k doubles of scratch.
+template <class W>
+HBA_FN void wg_svd(W& w, int k, double* A, int64_t lda, double* Yo, int64_t ldy, double* s,
+                   double* Aw, double* Yw, double* st) {
+  if (k == 0) return;
+  for (int e = w.tid; e < k * k; e += w.nt) {
+    const int i = e % k, j = e / k;
+    Aw[e] = A[i + (int64_t)j * lda];
+    Yw[e] = i == j ? 1.0 : 0.0;
+  }
+  w.sync();
+  const int kk = k + (k & 1);
+  const double tol = 4e-16 * (double)(k > 4 ? k : 4);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int rot = 0;
+    for (int rd = 0; rd < kk - 1; ++rd) {
+      for (int t = w.tid; t < kk / 2; t += w.nt) {
+        const int pa = t, pb = kk - 1 - t;
+        const int p = pa == 0 ? 0 : 1 + (pa - 1 + rd) % (kk - 1);
+        const int q = pb == 0 ? 0 : 1 + (pb - 1 + rd) % (kk - 1);
+        if (p >= k || q >= k) continue;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = 0; i < k; ++i) {
+          const double x = Aw[i + p * k], y = Aw[i + q * k];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+        if (!(al > 0.0 && be > 0.0) || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
+        const double ze = (be - al) / (2.0 * ga);
+        const double tn = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + hypot(1.0, ze));
+        const double c = 1.0 / sqrt(1.0 + tn * tn), sn = c * tn;
+        for (int i = 0; i < k; ++i) {
+          const double x = Aw[i + p * k], y = Aw[i + q * k];
+          Aw[i + p * k] = c * x - sn * y;
+          Aw[i + q * k] = sn * x + c * y;
+          const double u = Yw[i + p * k], v = Yw[i + q * k];
+          Yw[i + p * k] = c * u - sn * v;
+          Yw[i + q * k] = sn * u + c * v;
+        }
+        ++rot;
+      }
+      w.sync();
+    }
+    if (wg_sum(w, (double)rot) == 0.0) break;
+  }
+  for (int j = w.tid; j < k; j += w.nt) {
+    double nn = 0.0;
+    for (int i = 0; i < k; ++i) nn += Aw[i + j * k] * Aw[i + j * k];
+    st[j] = sqrt(nn);
+  }
+  w.sync();
+  // descending order, ties by index; each column goes to its own slot
+  for (int j = w.tid; j < k; j += w.nt) {
+    const double sj = st[j];
+    int pos = 0;
+    for (int i = 0; i < k; ++i)
+      if (st[i] > sj || (st[i] == sj && i < j)) ++pos;
+    const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+    s[pos] = sj;
+    for (int i = 0; i < k; ++i) {
+      A[i + (int64_t)pos * lda] = Aw[i + j * k] * inv;
+      Yo[i + (int64_t)pos * ldy] = Yw[i + j * k];
+    }
+  }
+  w.sync();
+}
+
+// G of the truncated-SVD reverse rule (k x k, ld k).  J and K hold their
+// first rho columns (ld k); the others are zero.
+template <class W>
+HBA_FN void adj_svd_g(W& w, int k, int rho, const double* s, const double* sb, const double* J,
+                      const double* K, double* G) {
+  for (int e = w.tid; e < k * k; e += w.nt) {
+    const int i = e % k, j = e / k;
+    double v = 0.0;
+    if (i == j) {
+      if (i < rho) v = sb[i];
+    } else if (i < rho || j < rho) {
+      const double jij = j < rho ? J[i + j * k] : 0.0, jji = i < rho ? J[j + i * k] : 0.0;
+      const double kij = j < rho ? K[i + j * k] : 0.0, kji = i < rho ? K[j + i * k] : 0.0;
+      const double f = 1.0 / (s[j] * s[j] - s[i] * s[i]);
+      v = f * ((jij - jji) * s[j] + s[i] * (kij - kji));
+    }
+    G[e] = v;
+  }
+  w.sync();
+}
+
+// Gaussian entry of problem row gi and column gj.
+HBA_FN double adj_entry(const AdjArgs& a, int64_t gi, int64_t gj) {
+  double r2 = 0.0;
+  for (int q = 0; q < a.dim; ++q) {
+    const double d = a.X[q * a.ldx + gi] - a.Y[q * a.ldy + gj];
+    r2 += d * d;
+  }
+  return exp(a.nic * r2);
+}
+
+// Contribution of the entry cotangent ab of (gi, gj): g[q] += ab dA/dx_q
+// (dA/dy_q is its negative); returns ab dA/dh.
+HBA_FN double adj_entry_grad(const AdjArgs& a, int64_t gi, int64_t gj, double ab, double* g) {
+  double d[HBA_MAXDIM];
+  double r2 = 0.0;
+  for (int q = 0; q < a.dim; ++q) {
+    d[q] = a.X[q * a.ldx + gi] - a.Y[q * a.ldy + gj];
+    r2 += d[q] * d[q];
+  }
+  const double f = ab * exp(a.nic * r2);
+  for (int q = 0; q < a.dim; ++q) g[q] += f * 2.0 * a.nic * d[q];
+  return f * r2 * (-2.0 * a.nic / a.h);
+}
+
+// ---------------------------------------------------------- forward tasks ---
+// Leaf BACA with frozen pivots (Algorithm 2, eqs. (8)-(9)); keeps C_k, R_k,
+// Q1 and T of every iteration.
+template <class W>
+HBA_FN void adj_leaf_fwd(W& w, const AdjArgs& a, int li) {
+  const AdjLeaf& L = a.leaves[li];
+  double* D = a.D;
+  const int m0 = L.m0, n0 = L.n0, dm = a.dmax;
+  double* U = D + L.U;
+  double* Vt = D + L.Vt;
+  double* hs = a.ws + L.ws_lf;
+  int r0 = 0;
+  for (int k = 0; k < L.iters; ++k) {
+    const int32_t* rec = a.fz + (int64_t)(L.fz_off + k) * a.fz_stride;
+    const int nI = rec[0], nJ = rec[1], dk = rec[2];
+    const int32_t* I = rec + 3;
+    const int32_t* J = rec + 3 + dm;
+    const int32_t* Jb = rec + 3 + 2 * dm;
+    double* C = D + L.it + k * L.it_sz;
+    double* R = C + (int64_t)m0 * dm;
+    double* Q1 = R + (int64_t)dm * n0;
+    double* T = Q1 + dm * dm;
+    // C_k = A(:, J_k) - U V(:, J_k)
+    for (int64_t e = w.tid; e < (int64_t)m0 * nJ; e += w.nt) {
+      const int i = (int)(e % m0), b = (int)(e / m0);
+      double s = adj_entry(a, L.row0 + i, L.col0 + J[b]);
+      for (int t = 0; t < r0; ++t) s -= U[i + (int64_t)t * m0] * Vt[J[b] + (int64_t)t * n0];
+      C[i + (int64_t)b * m0] = s;
+    }
+    // R_k = A(I_k, :) - U(I_k, :) V
+    for (int64_t e = w.tid; e < (int64_t)nI * n0; e += w.nt) {
+      const int c = (int)(e % nI);
+      const int64_t j = e / nI;
+      double s = adj_entry(a, L.row0 + I[c], L.col0 + j);
+      for (int t = 0; t < r0; ++t) s -= U[I[c] + (int64_t)t * m0] * Vt[j + (int64_t)t * n0];
+      R[c + j * dm] = s;
+    }
+    w.sync();
+    // the pivoted columns of W_k = C_k(I_k, :) and their thin QR
+    for (int e = w.tid; e < nI * dk; e += w.nt) {
+      const int c = e % nI, q = e / nI;
+      Q1[c + q * dm] = C[I[c] + (int64_t)Jb[q] * m0];
+    }
+    w.sync();
+    wg_qr(w, nI, dk, Q1, dm, Q1, dm, T, dm, hs);
+    // U_k = C_k(:, Jbar), V_k = T^-1 Q1^T R_k
+    for (int64_t e = w.tid; e < (int64_t)m0 * dk; e += w.nt) {
+      const int i = (int)(e % m0), q = (int)(e / m0);
+      U[i + (int64_t)(r0 + q) * m0] = C[i + (int64_t)Jb[q] * m0];
+    }
+    for (int64_t j = w.tid; j < n0; j += w.nt) {
+      double z[HBA_DMAX];
+      for (int q = 0; q < dk; ++q) {
+        double s = 0.0;
+        for (int c = 0; c < nI; ++c) s += Q1[c + q * dm] * R[c + j * dm];
+        z[q] = s;
+      }
+      for (int q = dk - 1; q >= 0; --q) {
+        double s = z[q];
+        for (int p = q + 1; p < dk; ++p) s -= T[q + p * dm] * z[p];
+        z[q] = s / T[q + q * dm];
+      }
+      for (int q = 0; q < dk; ++q) Vt[j + (int64_t)(r0 + q) * n0] = z[q];
+    }
+    w.sync();
+    r0 += dk;
+  }
+}
+
+// SVD re-compression of U Vt^T: U = QU TU, Vt = QV TV, TU TV^T = X diag(s) Y^T,
+// Ub = QU X, Vb = QV Y; the leaf's block keeps the first rho columns.
+template <class W>
+HBA_FN void adj_rec_fwd(W& w, const AdjArgs& a, int li) {
+  const AdjLeaf& L = a.leaves[li];
+  const int m0 = L.m0, n0 = L.n0, r = L.rb;
+  if (r == 0) return;
+  double* D = a.D;
+  double* QU = a.ws + L.ws_rf;
+  double* QV = QU + (int64_t)m0 * r;
+  double* TU = QV + (int64_t)n0 * r;
+  double* TV = TU + r * r;
+  double* M = TV + r * r;
+  double* Yo = M + r * r;
+  double* Aw = Yo + r * r;
+  double* Yw = Aw + r * r;
+  double* hs = Yw + r * r;
+  wg_qr(w, m0, r, D + L.U, m0, QU, m0, TU, r, hs);
+  wg_qr(w, n0, r, D + L.Vt, n0, QV, n0, TV, r, hs);
+  wg_gemm(w, r, r, r, 1.0, TU, r, 0, TV, r, 1, 0.0, M, r);
+  wg_svd(w, r, M, r, Yo, r, D + L.S, Aw, Yw, hs);
+  wg_gemm(w, m0, r, r, 1.0, QU, m0, 0, M, r, 0, 0.0, D + L.Ub, m0);
+  wg_gemm(w, n0, r, r, 1.0, QV, n0, 0, Yo, r, 0, 0.0, D + L.Vb, n0);
+}
+
+struct AdjSides {
+  const double *P1, *P2, *O1, *O2, *S1, *S2;
+  int64_t ldP1, ldP2, ldO1, ldO2;
+};
+
+HBA_FN AdjSides adj_sides(const AdjArgs& a, const AdjMerge& M) {
+  const AdjBlock& b1 = a.blocks[M.b1];
+  const AdjBlock& b2 = a.blocks[M.b2];
+  AdjSides s;
+  s.P1 = a.D + (M.horiz ? b1.U : b1.Vt);
+  s.ldP1 = M.horiz ? b1.ldU : b1.ldVt;
+  s.P2 = a.D + (M.horiz ? b2.U : b2.Vt);
+  s.ldP2 = M.horiz ? b2.ldU : b2.ldVt;
+  s.O1 = a.D + (M.horiz ? b1.Vt : b1.U);
+  s.ldO1 = M.horiz ? b1.ldVt : b1.ldU;
+  s.O2 = a.D + (M.horiz ? b2.Vt : b2.U);
+  s.ldO2 = M.horiz ? b2.ldVt : b2.ldU;
+  s.S1 = a.D + b1.S;
+  s.S2 = a.D + b2.S;
+  return s;
+}
+
+// Merge (Algorithm 3, eqs. (14)-(15)): B = [P1 diag(S1), P2 diag(S2)] = Q R,
+// R = X diag(s) Y^T, Ub = Q X; the new block is P = Ub(:, :rho), s(:rho),
+// O = blockdiag(O1, O2) Y(:, :rho).
+template <class W>
+HBA_FN void adj_merge_fwd(W& w, const AdjArgs& a, int mi) {
+  const AdjMerge& M = a.merges[mi];
+  const int k = M.k, rho = M.rho;
+  if (k == 0) return;
+  const int r1 = a.blocks[M.b1].r, r2 = a.blocks[M.b2].r;
+  const int64_t rows = M.rows, n1 = M.n1, n2 = M.n2;
+  const AdjSides sd = adj_sides(a, M);
+  const AdjBlock& out = a.blocks[M.out];
+  double* D = a.D;
+  double* B = a.ws + M.ws_f;
+  double* R = B + rows * k;
+  double* Aw = R + k * k;
+  double* Yw = Aw + k * k;
+  double* hs = Yw + k * k;
+  for (int64_t e = w.tid; e < rows * k; e += w.nt) {
+    const int64_t l = e % rows;
+    const int c = (int)(e / rows);
+    B[e] = c < r1 ? sd.P1[l + c * sd.ldP1] * sd.S1[c] : sd.P2[l + (c - r1) * sd.ldP2] * sd.S2[c - r1];
+  }
+  w.sync();
+  wg_qr(w, rows, k, B, rows, B, rows, R, k, hs);
+  wg_svd(w, k, R, k, D + M.Y, k, D + M.S, Aw, Yw, hs);
+  wg_gemm(w, rows, k, k, 1.0, B, rows, 0, R, k, 0, 0.0, D + M.Ub, rows);
+  double* On = D + (M.horiz ? out.Vt : out.U);
+  wg_gemm(w, n1, rho, r1, 1.0, sd.O1, sd.ldO1, 0, D + M.Y, k, 0, 0.0, On, n1 + n2);
+  wg_gemm(w, n2, rho, r2, 1.0, sd.O2, sd.ldO2, 0, D + M.Y + r1, k, 0, 0.0, On + n1, n1 + n2);
+}
+
+// ---------------------------------------------------------- reverse tasks ---
+// y = U diag(S) Vt^T w: cotangents of the root factors from ybar, and
+// wbar = Vt diag(S) U^T ybar.
+template <class W>
+HBA_FN void adj_root(W& w, const AdjArgs& a) {
+  const AdjBlock& B = a.blocks[a.root];
+  const int r = B.r;
+  const int64_t m = B.m, n = B.n;
+  double* D = a.D;
+  const double* U = D + B.U;
+  const double* Vt = D + B.Vt;
+  const double* S = D + B.S;
+  double* g = a.ws;      // Vt^T w
+  double* u = a.ws + r;  // U^T ybar
+  for (int j = w.tid; j < r; j += w.nt) {
+    double sg = 0.0, su = 0.0;
+    for (int64_t l = 0; l < n; ++l) sg += Vt[l + j * B.ldVt] * a.w[l];
+    for (int64_t l = 0; l < m; ++l) su += U[l + j * B.ldU] * a.ybar[l];
+    g[j] = sg;
+    u[j] = su;
+  }
+  w.sync();
+  for (int64_t e = w.tid; e < m * r; e += w.nt) {
+    const int64_t l = e % m;
+    const int j = (int)(e / m);
+    D[B.gU + e] = a.ybar[l] * S[j] * g[j];
+  }
+  for (int64_t e = w.tid; e < n * r; e += w.nt) {
+    const int64_t l = e % n;
+    const int j = (int)(e / n);
+    D[B.gVt + e] = a.w[l] * S[j] * u[j];
+  }
+  for (int j = w.tid; j < r; j += w.nt) D[B.gS + j] = u[j] * g[j];
+  if (a.gw)
+    for (int64_t l = w.tid; l < n; l += w.nt) {
+      double s = 0.0;
+      for (int j = 0; j < r; ++j) s += Vt[l + j * B.ldVt] * S[j] * u[j];
+      a.gw[l] = s;
+    }
+  w.sync();
+}
+
+// Reverse of a merge: cotangents of the children's factors.
+template <class W>
+HBA_FN void adj_merge_bwd(W& w, const AdjArgs& a, int mi) {
+  const AdjMerge& M = a.merges[mi];
+  const int k = M.k, rho = M.rho;
+  if (k == 0) return;
+  const AdjBlock& b1 = a.blocks[M.b1];
+  const AdjBlock& b2 = a.blocks[M.b2];
+  const AdjBlock& out = a.blocks[M.out];
+  const int r1 = b1.r, r2 = b2.r;
+  const int64_t rows = M.rows, n1 = M.n1, n2 = M.n2;
+  const AdjSides sd = adj_sides(a, M);
+  double* D = a.D;
+  const double* gPo = D + (M.horiz ? out.gU : out.gVt);  // rows x rho
+  const double* gOo = D + (M.horiz ? out.gVt : out.gU);  // (n1 + n2) x rho
+  const double* gSo = D + out.gS;
+  double* gP1 = D + (M.horiz ? b1.gU : b1.gVt);  // rows x r1
+  double* gP2 = D + (M.horiz ? b2.gU : b2.gVt);
+  double* gO1 = D + (M.horiz ? b1.gVt : b1.gU);  // n1 x r1
+  double* gO2 = D + (M.horiz ? b2.gVt : b2.gU);
+  const double* Ub = D + M.Ub;
+  const double* Y = D + M.Y;
+  const double* s = D + M.S;
+  double* Yb = a.ws + M.ws_b;  // k x rho
+  double* Jm = Yb + k * rho;
+  double* Km = Jm + k * rho;
+  double* G = Km + k * rho;
+  double* H = G + k * k;
+  double* E = H + k * k;       // rows x rho
+  double* Bb = E + rows * rho;  // rows x k
+  const int64_t ldo = n1 + n2;
+  // O = blockdiag(O1, O2) Y(:, :rho)
+  wg_gemm(w, r1, rho, n1, 1.0, sd.O1, sd.ldO1, 1, gOo, ldo, 0, 0.0, Yb, k);
+  wg_gemm(w, r2, rho, n2, 1.0, sd.O2, sd.ldO2, 1, gOo + n1, ldo, 0, 0.0, Yb + r1, k);
+  wg_gemm(w, n1, r1, rho, 1.0, gOo, ldo, 0, Y, k, 1, 0.0, gO1, n1);
+  wg_gemm(w, n2, r2, rho, 1.0, gOo + n1, ldo, 0, Y + r1, k, 1, 0.0, gO2, n2);
+  // B = Ub diag(s) Y^T truncated at rho
+  wg_gemm(w, k, rho, rows, 1.0, Ub, rows, 1, gPo, rows, 0, 0.0, Jm, k);
+  wg_gemm(w, k, rho, k, 1.0, Y, k, 1, Yb, k, 0, 0.0, Km, k);
+  adj_svd_g(w, k, rho, s, gSo, Jm, Km, G);
+  wg_gemm(w, k, k, k, 1.0, G, k, 0, Y, k, 1, 0.0, H, k);
+  for (int64_t e = w.tid; e < rows * rho; e += w.nt) {
+    const int64_t l = e % rows;
+    const int j = (int)(e / rows);
+    double v = gPo[e];
+    for (int i = 0; i < k; ++i) v -= Ub[l + i * rows] * Jm[i + j * k];
+    E[e] = v / s[j];
+  }
+  w.sync();
+  wg_gemm(w, rows, k, k, 1.0, Ub, rows, 0, H, k, 0, 0.0, Bb, rows);
+  wg_gemm(w, rows, k, rho, 1.0, E, rows, 0, Y, k, 1, 1.0, Bb, rows);
+  // B = [P1 diag(S1), P2 diag(S2)]
+  for (int64_t e = w.tid; e < rows * k; e += w.nt) {
+    const int64_t l = e % rows;
+    const int c = (int)(e / rows);
+    if (c < r1)
+      gP1[l + c * rows] = Bb[e] * sd.S1[c];
+    else
+      gP2[l + (c - r1) * rows] = Bb[e] * sd.S2[c - r1];
+  }
+  for (int c = w.tid; c < k; c += w.nt) {
+    double v = 0.0;
+    if (c < r1) {
+      for (int64_t l = 0; l < rows; ++l) v += Bb[l + c * rows] * sd.P1[l + c * sd.ldP1];
+      D[b1.gS + c] = v;
+    } else {
+      for (int64_t l = 0; l < rows; ++l) v += Bb[l + c * rows] * sd.P2[l + (c - r1) * sd.ldP2];
+      D[b2.gS + c - r1] = v;
+    }
+  }
+  w.sync();
+}
+
+// Reverse of the re-compression: cotangents of the BACA factors U and Vt.
+template <class W>
+HBA_FN void adj_rec_bwd(W& w, const AdjArgs& a, int li) {
+  const AdjLeaf& L = a.leaves[li];
+  const AdjBlock& B = a.blocks[li];
+  const int m0 = L.m0, n0 = L.n0, r = L.rb, rho = L.rho;
+  if (r == 0) return;
+  double* D = a.D;
+  const double* Ub = D + L.Ub;
+  const double* Vb = D + L.Vb;
+  const double* s = D + L.S;
+  const double* gUo = D + B.gU;  // m0 x rho
+  const double* gVo = D + B.gVt; // n0 x rho
+  double* Jm = a.ws + L.ws_rb;   // r x rho
+  double* Km = Jm + r * rho;
+  double* G = Km + r * rho;
+  double* Wu = G + r * r;
+  double* Wv = Wu + r * r;
+  double* H1 = Wv + r * r;
+  double* H2 = H1 + r * r;
+  double* E1 = H2 + r * r;                 // m0 x rho
+  double* E2 = E1 + (int64_t)m0 * rho;     // n0 x rho
+  wg_gemm(w, r, rho, m0, 1.0, Ub, m0, 1, gUo, m0, 0, 0.0, Jm, r);
+  wg_gemm(w, r, rho, n0, 1.0, Vb, n0, 1, gVo, n0, 0, 0.0, Km, r);
+  adj_svd_g(w, r, rho, s, D + B.gS, Jm, Km, G);
+  wg_gemm(w, r, r, m0, 1.0, Ub, m0, 1, D + L.U, m0, 0, 0.0, Wu, r);
+  wg_gemm(w, r, r, n0, 1.0, Vb, n0, 1, D + L.Vt, n0, 0, 0.0, Wv, r);
+  wg_gemm(w, r, r, r, 1.0, G, r, 0, Wv, r, 0, 0.0, H1, r);
+  wg_gemm(w, r, r, r, 1.0, G, r, 1, Wu, r, 0, 0.0, H2, r);
+  for (int64_t e = w.tid; e < (int64_t)m0 * rho; e += w.nt) {
+    const int64_t l = e % m0;
+    const int j = (int)(e / m0);
+    double v = gUo[e];
+    for (int i = 0; i < r; ++i) v -= Ub[l + i * (int64_t)m0] * Jm[i + j * r];
+    E1[e] = v / s[j];
+  }
+  for (int64_t e = w.tid; e < (int64_t)n0 * rho; e += w.nt) {
+    const int64_t l = e % n0;
+    const int j = (int)(e / n0);
+    double v = gVo[e];
+    for (int i = 0; i < r; ++i) v -= Vb[l + i * (int64_t)n0] * Km[i + j * r];
+    E2[e] = v / s[j];
+  }
+  w.sync();
+  wg_gemm(w, m0, r, r, 1.0, Ub, m0, 0, H1, r, 0, 0.0, D + L.gU, m0);
+  wg_gemm(w, m0, r, rho, 1.0, E1, m0, 0, Wv, r, 0, 1.0, D + L.gU, m0);
+  wg_gemm(w, n0, r, r, 1.0, Vb, n0, 0, H2, r, 0, 0.0, D + L.gVt, n0);
+  wg_gemm(w, n0, r, rho, 1.0, E2, n0, 0, Wu, r, 0, 1.0, D + L.gVt, n0);
+}
+
+// Reverse of the leaf BACA, last iteration first: entry cotangents of
+// C_k and R_k go to the partial point and width gradients; the rest flows
+// to the factor columns of earlier iterations.
+template <class W>
+HBA_FN void adj_leaf_bwd(W& w, const AdjArgs& a, int li) {
+  const AdjLeaf& L = a.leaves[li];
+  const int m0 = L.m0, n0 = L.n0, dm = a.dmax, dim = a.dim;
+  double* D = a.D;
+  const double* U = D + L.U;
+  const double* Vt = D + L.Vt;
+  double* gU = D + L.gU;
+  double* gVt = D + L.gVt;
+  double* gx = D + L.gx;
+  double* gy = D + L.gy;
+  double* Zb = a.ws + L.ws_lb;       // dm x n0
+  double* Y2 = Zb + (int64_t)dm * n0;  // dm x n0
+  double* E = Y2 + (int64_t)dm * n0;   // dm x n0
+  double* Rb = E + (int64_t)dm * n0;   // dm x n0
+  double* Cb = Rb + (int64_t)dm * n0;  // m0 x dm
+  double* S1 = Cb + (int64_t)m0 * dm;  // dm x dm
+  double* S2 = S1 + dm * dm;
+  double* Wb = S2 + dm * dm;
+  for (int64_t e = w.tid; e < (int64_t)m0 * dim; e += w.nt) gx[e] = 0.0;
+  for (int64_t e = w.tid; e < (int64_t)n0 * dim; e += w.nt) gy[e] = 0.0;
+  w.sync();
+  double ghl = 0.0;
+  int r0 = L.rb;
+  for (int k = L.iters - 1; k >= 0; --k) {
+    const int32_t* rec = a.fz + (int64_t)(L.fz_off + k) * a.fz_stride;
+    const int nI = rec[0], nJ = rec[1], dk = rec[2];
+    const int32_t* I = rec + 3;
+    const int32_t* J = rec + 3 + dm;
+    const int32_t* Jb = rec + 3 + 2 * dm;
+    r0 -= dk;
+    const double* C = D + L.it + k * L.it_sz;
+    const double* R = C + (int64_t)m0 * dm;
+    const double* Q1 = R + (int64_t)dm * n0;
+    const double* T = Q1 + dm * dm;
+    (void)C;
+    // per column j of the row block: Zb = T^-T Vb_k, Y2 = T^-1 Zb,
+    // E = R_k - Q1 Q1^T R_k, Rb_k = Q1 Zb
+    for (int64_t j = w.tid; j < n0; j += w.nt) {
+      double zb[HBA_DMAX], z[HBA_DMAX];
+      for (int q = 0; q < dk; ++q) {
+        double s = gVt[j + (int64_t)(r0 + q) * n0];
+        for (int p = 0; p < q; ++p) s -= T[p + q * dm] * zb[p];
+        zb[q] = s / T[q + q * dm];
+      }
+      for (int q = dk - 1; q >= 0; --q) {
+        double s = zb[q];
+        for (int p = q + 1; p < dk; ++p) s -= T[q + p * dm] * z[p];
+        z[q] = s / T[q + q * dm];
+      }
+      for (int q = 0; q < dk; ++q) {
+        Zb[q + j * dm] = zb[q];
+        Y2[q + j * dm] = z[q];
+      }
+      for (int q = 0; q < dk; ++q) {
+        double s = 0.0;
+        for (int c = 0; c < nI; ++c) s += Q1[c + q * dm] * R[c + j * dm];
+        z[q] = s;
+      }
+      for (int c = 0; c < nI; ++c) {
+        double e = R[c + j * dm], rb = 0.0;
+        for (int q = 0; q < dk; ++q) {
+          e -= Q1[c + q * dm] * z[q];
+          rb += Q1[c + q * dm] * zb[q];
+        }
+        E[c + j * dm] = e;
+        Rb[c + j * dm] = rb;
+      }
+    }
+    w.sync();
+    // S1 = Zb V_k^T (dk x dk), S2 = E Y2^T (nI x dk)
+    for (int e = w.tid; e < dk * dk; e += w.nt) {
+      const int q = e % dk, p = e / dk;
+      double s = 0.0;
+      for (int64_t j = 0; j < n0; ++j) s += Zb[q + j * dm] * Vt[j + (int64_t)(r0 + p) * n0];
+      S1[q + p * dm] = s;
+    }
+    for (int e = w.tid; e < nI * dk; e += w.nt) {
+      const int c = e % nI, p = e / nI;
+      double s = 0.0;
+      for (int64_t j = 0; j < n0; ++j) s += E[c + j * dm] * Y2[p + j * dm];
+      S2[c + p * dm] = s;
+    }
+    w.sync();
+    // cotangent of the pivoted W_k: -Q1 S1 + S2
+    for (int e = w.tid; e < nI * dk; e += w.nt) {
+      const int c = e % nI, p = e / nI;
+      double s = S2[c + p * dm];
+      for (int q = 0; q < dk; ++q) s -= Q1[c + q * dm] * S1[q + p * dm];
+      Wb[c + p * dm] = s;
+    }
+    w.sync();
+    // cotangent of C_k: U_k = C_k(:, Jbar) and W_k = C_k(I_k, Jbar)
+    for (int64_t e = w.tid; e < (int64_t)m0 * nJ; e += w.nt) {
+      const int i = (int)(e % m0), b = (int)(e / m0);
+      double v = 0.0;
+      for (int q = 0; q < dk; ++q)
+        if (Jb[q] == b) {
+          v += gU[i + (int64_t)(r0 + q) * m0];
+          for (int c = 0; c < nI; ++c)
+            if (I[c] == i) v += Wb[c + q * dm];
+        }
+      Cb[i + (int64_t)b * m0] = v;
+    }
+    w.sync();
+    // entry cotangents: A(:, J_k) carries Cb, A(I_k, :) carries Rb
+    for (int64_t i = w.tid; i < m0; i += w.nt) {
+      double g[HBA_MAXDIM];
+      for (int q = 0; q < dim; ++q) g[q] = 0.0;
+      for (int b = 0; b < nJ; ++b) {
+        const double cb = Cb[i + (int64_t)b * m0];
+        if (cb != 0.0) ghl += adj_entry_grad(a, L.row0 + i, L.col0 + J[b], cb, g);
+      }
+      for (int q = 0; q < dim; ++q) gx[i + (int64_t)q * m0] += g[q];
+    }
+    w.sync();
+    for (int b = w.tid; b < nJ; b += w.nt) {
+      double g[HBA_MAXDIM];
+      for (int q = 0; q < dim; ++q) g[q] = 0.0;
+      for (int64_t i = 0; i < m0; ++i) {
+        const double cb = Cb[i + (int64_t)b * m0];
+        if (cb != 0.0) (void)adj_entry_grad(a, L.row0 + i, L.col0 + J[b], cb, g);
+      }
+      for (int q = 0; q < dim; ++q) gy[J[b] + (int64_t)q * n0] -= g[q];
+    }
+    w.sync();
+    for (int64_t j = w.tid; j < n0; j += w.nt) {
+      double g[HBA_MAXDIM];
+      for (int q = 0; q < dim; ++q) g[q] = 0.0;
+      for (int c = 0; c < nI; ++c) {
+        const double rb = Rb[c + j * dm];
+        if (rb != 0.0) ghl += adj_entry_grad(a, L.row0 + I[c], L.col0 + j, rb, g);
+      }
+      for (int q = 0; q < dim; ++q) gy[j + (int64_t)q * n0] -= g[q];
+    }
+    w.sync();
+    for (int c = w.tid; c < nI; c += w.nt) {
+      double g[HBA_MAXDIM];
+      for (int q = 0; q < dim; ++q) g[q] = 0.0;
+      for (int64_t j = 0; j < n0; ++j) {
+        const double rb = Rb[c + j * dm];
+        if (rb != 0.0) (void)adj_entry_grad(a, L.row0 + I[c], L.col0 + j, rb, g);
+      }
+      for (int q = 0; q < dim; ++q) gx[I[c] + (int64_t)q * m0] += g[q];
+    }
+    w.sync();
+    // C_k = A(:, J_k) - U V(:, J_k) and R_k = A(I_k, :) - U(I_k, :) V
+    // reach the factor columns t < r0
+    for (int64_t e = w.tid; e < (int64_t)m0 * r0; e += w.nt) {
+      const int i = (int)(e % m0), t = (int)(e / m0);
+      double s = 0.0;
+      for (int b = 0; b < nJ; ++b) s += Cb[i + (int64_t)b * m0] * Vt[J[b] + (int64_t)t * n0];
+      gU[e] -= s;
+    }
+    w.sync();
+    for (int e = w.tid; e < nI * r0; e += w.nt) {
+      const int c = e % nI, t = e / nI;
+      double s = 0.0;
+      for (int64_t j = 0; j < n0; ++j) s += Rb[c + j * dm] * Vt[j + (int64_t)t * n0];
+      gU[I[c] + (int64_t)t * m0] -= s;
+    }
+    w.sync();
+    for (int e = w.tid; e < nJ * r0; e += w.nt) {
+      const int b = e % nJ, t = e / nJ;
+      double s = 0.0;
+      for (int64_t i = 0; i < m0; ++i) s += U[i + (int64_t)t * m0] * Cb[i + (int64_t)b * m0];
+      gVt[J[b] + (int64_t)t * n0] -= s;
+    }
+    w.sync();
+    for (int64_t e = w.tid; e < (int64_t)n0 * r0; e += w.nt) {
+      const int64_t j = e % n0;
+      const int t = (int)(e / n0);
+      double s = 0.0;
+      for (int c = 0; c < nI; ++c) s += U[I[c] + (int64_t)t * m0] * Rb[c + j * dm];
+      gVt[e] -= s;
+    }
+    w.sync();
+  }
+  const double tot = wg_sum(w, ghl);
+  if (w.tid == 0) D[L.gh] = tot;
+}
+
+// Gradient rows of row cluster t: the sum over its leaves (t, v).
+template <class W>
+HBA_FN void adj_red_rows(W& w, const AdjArgs& a, int t) {
+  const AdjLeaf& L0 = a.leaves[(int64_t)t * a.nb];
+  const int m0 = L0.m0, dim = a.dim;
+  for (int64_t e = w.tid; e < (int64_t)m0 * dim; e += w.nt) {
+    const int64_t i = e % m0;
+    const int q = (int)(e / m0);
+    double s = 0.0;
+    for (int v = 0; v < a.nb; ++v) s += a.D[a.leaves[(int64_t)t * a.nb + v].gx + e];
+    a.gX[(L0.row0 + i) * dim + q] = s;
+  }
+}
+
+template <class W>
+HBA_FN void adj_red_cols(W& w, const AdjArgs& a, int v) {
+  const AdjLeaf& L0 = a.leaves[v];
+  const int n0 = L0.n0, dim = a.dim;
+  for (int64_t e = w.tid; e < (int64_t)n0 * dim; e += w.nt) {
+    const int64_t j = e % n0;
+    const int q = (int)(e / n0);
+    double s = 0.0;
+    for (int t = 0; t < a.nb; ++t) s += a.D[a.leaves[(int64_t)t * a.nb + v].gy + e];
+    a.gY[(L0.col0 + j) * dim + q] = s;
+  }
+}
+
+template <class W>
+HBA_FN void adj_red_h(W& w, const AdjArgs& a) {
+  double s = 0.0;
+  for (int i = w.tid; i < a.nleaves; i += w.nt) s += a.D[a.leaves[i].gh];
+  s = wg_sum(w, s);
+  if (w.tid == 0) a.gh[0] = s;
+}
+
+template <class W>
+HBA_FN void adj_run_task(W& w, const AdjArgs& a, int kind, int g) {
+  switch (kind) {
+    case ADJ_LEAF_FWD: adj_leaf_fwd(w, a, g); break;
+    case ADJ_REC_FWD: adj_rec_fwd(w, a, g); break;
+    case ADJ_MERGE_FWD: adj_merge_fwd(w, a, g); break;
+    case ADJ_ROOT: adj_root(w, a); break;
+    case ADJ_MERGE_BWD: adj_merge_bwd(w, a, g); break;
+    case ADJ_REC_BWD: adj_rec_bwd(w, a, g); break;
+    case ADJ_LEAF_BWD: adj_leaf_bwd(w, a, g); break;
+    case ADJ_RED_ROWS: adj_red_rows(w, a, g); break;
+    case ADJ_RED_COLS: adj_red_cols(w, a, g); break;
+    case ADJ_RED_H: adj_red_h(w, a); break;
+    default: break;
+  }
+}

@@ -25,6 +25,7 @@
 #include "../../include/hbaca.h"
 #include "hb_common.h"
 #include "hb_entries.h"
+#include "hb_adj_plan.h"
 #include "hb_internal.h"
 #include "hb_merge.h"
 
@@ -386,6 +387,7 @@ struct LeafHost {
   int rank_baca = 0, rank_leaf = 0, iters = 0, status = 0;
   std::vector<int32_t> tape_rows, tape_cols, it_dk;
   std::vector<double> it_nu, it_mu;
+  std::vector<int32_t> fz;  // frozen structure: iters records of fz_stride ints
 };
 
 }  // namespace
@@ -399,6 +401,14 @@ struct hb_result {
   std::vector<Block> out_blocks;  // what hb_result_copy returns
   DevMem keep;                     // device memory owned by the result
   hb_stats stats{};
+  // frozen structure for the adjoint (record_tape == 2, single problem):
+  // the stride of the per-iteration records, the ranks of the horizontal
+  // merges of level l (block (ti, v), ti-major) and of the vertical merges
+  // (block (t, v), t-major), and the kernel parameters
+  int fz_stride = 0;
+  bool fz_complete = false;  // set once the whole pipeline ran on one problem
+  std::vector<std::vector<int>> fz_hrank, fz_vrank;
+  double fz_h = 0.0, fz_c = 0.0;
 };
 
 namespace {
@@ -1472,6 +1482,7 @@ static hb_status validate(const CallSpec& c) {
   if (p->precision != HB_PREC_FP64 && p->precision != HB_PREC_MIXED) return HB_EINVAL;
   if (p->precision == HB_PREC_MIXED && c.entry == HB_K_HELMHOLTZ3D) return HB_EUNSUPPORTED;
   if (p->stop_after < 0 || p->stop_after > 2 + 2 * 30 || p->rank_cap < 0) return HB_EINVAL;
+  if (p->record_tape < 0 || p->record_tape > 2) return HB_EINVAL;
   if (p->diag_panel < 0 || p->diag_panel > 128 || p->diag_svd_storage < 0 ||
       p->diag_svd_storage > 2)
     return HB_EINVAL;
@@ -1666,6 +1677,14 @@ static hb_status run(const CallSpec& c, hb_result** out) {
   A.it_dk = tmp.get<int32_t>(std::max(ito, 1));
   A.it_nu = tmp.get<double>(std::max(ito, 1));
   A.it_mu = tmp.get<double>(std::max(ito, 1));
+  const bool frozen = P.record_tape == 2;
+  if (frozen) {
+    A.fz_stride = 3 + 3 * dmax;
+    A.fz = tmp.get<int32_t>((size_t)std::max(ito, 1) * A.fz_stride);
+    R->fz_stride = A.fz_stride;
+    R->fz_h = P.h;
+    R->fz_c = P.gauss_c;
+  }
   A.eps = c.tol;
   A.nleaves = (int32_t)nleaves;
   HB_HIP(hipEventRecord(ev[1], st));
@@ -1673,8 +1692,13 @@ static hb_status run(const CallSpec& c, hb_result** out) {
   HB_HIP(hipEventRecord(ev[2], st));
   std::vector<BacaOutDev> bo(nleaves);
   HB_HIP(hipMemcpyAsync(bo.data(), A.out, nleaves * sizeof(BacaOutDev), hipMemcpyDeviceToHost, st));
-  std::vector<int32_t> h_rows, h_cols, h_dk(std::max(ito, 1));
+  std::vector<int32_t> h_rows, h_cols, h_dk(std::max(ito, 1)), h_fz;
   std::vector<double> h_nu, h_mu;
+  if (frozen) {
+    h_fz.resize((size_t)std::max(ito, 1) * A.fz_stride);
+    HB_HIP(hipMemcpyAsync(h_fz.data(), A.fz, (size_t)ito * A.fz_stride * 4, hipMemcpyDeviceToHost,
+                          st));
+  }
   HB_HIP(hipMemcpyAsync(h_dk.data(), A.it_dk, ito * 4, hipMemcpyDeviceToHost, st));
   if (P.record_tape) {
     h_rows.resize(tapeo);
@@ -1704,6 +1728,9 @@ static hb_status run(const CallSpec& c, hb_result** out) {
       lf.it_nu.assign(h_nu.begin() + ld[s].it_off, h_nu.begin() + ld[s].it_off + lf.iters);
       lf.it_mu.assign(h_mu.begin() + ld[s].it_off, h_mu.begin() + ld[s].it_off + lf.iters);
     }
+    if (frozen)
+      lf.fz.assign(h_fz.begin() + (size_t)ld[s].it_off * A.fz_stride,
+                   h_fz.begin() + (size_t)(ld[s].it_off + lf.iters) * A.fz_stride);
     S.leaf_rank_baca_max = std::max(S.leaf_rank_baca_max, lf.rank_baca);
     S.iters_max = std::max(S.iters_max, lf.iters);
     S.iters_total += lf.iters;
@@ -1851,6 +1878,11 @@ static hb_status run(const CallSpec& c, hb_result** out) {
         run_merges(Eng, jobs, *hm);
         int mx = 0;
         for (auto& J : jobs) mx = std::max(mx, J.outP_owner->r);
+        if (frozen && np == 1) {
+          std::vector<int> rk;
+          for (auto& J : jobs) rk.push_back(J.outP_owner->r);
+          R->fz_hrank.push_back(rk);
+        }
         S.step_rank_max[std::min(++step, 63)] = mx;
         if (P.stop_after == 2 + step) {  // diagnostics: blocks after this step
           for (size_t p = 0; p < np; ++p)
@@ -1893,6 +1925,11 @@ static hb_status run(const CallSpec& c, hb_result** out) {
         run_merges(Eng, jobs, *vm);
         mx = 0;
         for (auto& J : jobs) mx = std::max(mx, J.outP_owner->r);
+        if (frozen && np == 1) {
+          std::vector<int> rk;
+          for (auto& J : jobs) rk.push_back(J.outP_owner->r);
+          R->fz_vrank.push_back(rk);
+        }
         S.step_rank_max[std::min(++step, 63)] = mx;
         if (P.stop_after == 2 + step) {  // diagnostics: blocks after this step
           for (size_t p = 0; p < np; ++p)
@@ -1935,6 +1972,7 @@ static hb_status run(const CallSpec& c, hb_result** out) {
         R->problems[p].root = blk[p][0];
         R->out_blocks.push_back(blk[p][0]);
       }
+      R->fz_complete = frozen && np == 1;
     }
     HB_HIP(hipEventRecord(ev[4], st));
   }
@@ -1970,6 +2008,85 @@ static hb_status guarded(const CallSpec& c, hb_result** out) {
 }  // namespace
 
 // ============================================================== C ABI =======
+namespace {
+
+struct GpuAdjExec {
+  const AdjArgs& a;
+  hipStream_t st;
+  int err;
+  void launch(int kind, int base, int count) {
+    if (err == 0) err = hbk::adj_launch(kind, base, count, a, st);
+  }
+};
+
+static hb_status vjp_run(const hb_result* r, const double* w, const double* ybar, double* gw,
+                         double* gh, double* gX, double* gY, hipStream_t st) {
+  const Problem& pr = r->problems[0];
+  AdjPlanIn in;
+  in.m = pr.m;
+  in.n = pr.n;
+  in.L = pr.L;
+  in.dim = r->E.dim;
+  in.fz_stride = r->fz_stride;
+  in.dmax = (r->fz_stride - 3) / 3;
+  for (const LeafHost& lf : r->leaves) {
+    AdjLeafIn li;
+    li.row0 = lf.row0 - pr.row_base;
+    li.col0 = lf.col0 - pr.col_base;
+    li.m0 = lf.m0;
+    li.n0 = lf.n0;
+    li.nrec = lf.iters;
+    li.rank_leaf = lf.rank_leaf;
+    li.rec = lf.fz.empty() ? nullptr : lf.fz.data();
+    if ((int64_t)lf.fz.size() != (int64_t)lf.iters * r->fz_stride) return HB_EINVAL;
+    in.leaves.push_back(li);
+  }
+  in.hrank = r->fz_hrank;
+  in.vrank = r->fz_vrank;
+  AdjPlan P;
+  const int ps = adj_plan(in, P);
+  if (ps == -6) return HB_EUNSUPPORTED;
+  if (ps != 0) return HB_EINVAL;
+  DevMem mem;
+  mem.st = st;
+  double* D = mem.get<double>((size_t)P.arena);
+  AdjArgs a{};
+  a.D = D;
+  a.ws = D + P.ws_off;
+  a.fz = upload(mem, P.fz, st);
+  a.leaves = upload(mem, P.leaves, st);
+  a.blocks = upload(mem, P.blocks, st);
+  a.merges = upload(mem, P.merges, st);
+  a.X = r->E.X;
+  a.Y = r->E.Y;
+  a.ldx = r->E.ldx;
+  a.ldy = r->E.ldy;
+  a.dim = r->E.dim;
+  a.dmax = in.dmax;
+  a.fz_stride = 3 + 3 * in.dmax;
+  a.root = P.root;
+  a.nb = P.nb;
+  a.nleaves = (int32_t)P.leaves.size();
+  a.h = r->fz_h;
+  a.nic = r->E.neg_inv_ch2;
+  a.w = w;
+  a.ybar = ybar;
+  a.gw = gw;
+  a.gh = gh;
+  a.gX = gX;
+  a.gY = gY;
+  GpuAdjExec ex{a, st, 0};
+  adj_execute(ex, P, gX != nullptr, gY != nullptr, gh != nullptr);
+  if (ex.err != 0) {
+    hb_report("adjoint launch", ex.err, hipGetErrorString((hipError_t)ex.err), __LINE__);
+    return HB_EDEVICE;
+  }
+  HB_HIP(hipStreamSynchronize(st));
+  return HB_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 hb_status hbaca_compress(int entry_fn_id, const hb_params* params, const double* points_row,
@@ -2094,6 +2211,23 @@ hb_status hbaca_apply(const hb_result* r, int64_t b, const void* in, void* out, 
   const hipError_t e = hipGetLastError();
   BlockCache::get().release(t, st, false);
   return e == hipSuccess ? HB_OK : HB_EDEVICE;
+}
+
+
+hb_status hbaca_vjp(const hb_result* r, const double* w, const double* ybar, double* grad_w,
+                    double* grad_h, double* grad_points_row, double* grad_points_col,
+                    void* stream) {
+  if (!r || !w || !ybar) return HB_EINVAL;
+  if (r->entry != HB_K_GAUSS || r->scalar != 0) return HB_EUNSUPPORTED;
+  if (!r->fz_complete || r->fz_stride < 6 || r->problems.size() != 1) return HB_EINVAL;
+  try {
+    return vjp_run(r, w, ybar, grad_w, grad_h, grad_points_row, grad_points_col,
+                   (hipStream_t)stream);
+  } catch (const HbError& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    return HB_ENOMEM;
+  }
 }
 
 hb_status hb_result_stats(const hb_result* r, hb_stats* out) {

@@ -542,6 +542,18 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
     }
     __syncthreads();
     const int dk = sDK;
+    if (A.fz && A.fz_stride >= 3 + 3 * DMAX) {
+      // the iteration's pivots in full, for a replay with frozen pivots
+      int32_t* rec = A.fz + (int64_t)(L.it_off + iter) * A.fz_stride;
+      if (tid == 0) {
+        rec[0] = nI;
+        rec[1] = nJ;
+        rec[2] = dk;
+      }
+      if (tid < nI) rec[3 + tid] = sI[tid];
+      if (tid < nJ) rec[3 + DMAX + tid] = sJ[tid];
+      if (tid < dk) rec[3 + 2 * DMAX + tid] = sJbar[tid];
+    }
     if (dk == 0) {
       if (tid == 0) {
         A.it_dk[L.it_off + iter] = 0;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hb_adj.h"
 #include "hb_entries.h"
 
 // One BACA leaf (Algorithm 2) as the leaf kernel sees it.
@@ -44,13 +45,20 @@ struct BacaArgs {
   int32_t* it_dk;
   double* it_nu;
   double* it_mu;
+  // frozen structure (NULL: not recorded): per iteration, at
+  // (it_off + k) * fz_stride: nI, nJ, d_k, then I_k (DMAX slots), J_k (DMAX
+  // slots) and the pivot order of QR(W_k, eps) (DMAX slots)
+  int32_t* fz;
   double eps;
   int32_t nleaves;
-  int32_t pad;
+  int32_t fz_stride;  // 3 + 3 DMAX when fz is set
 };
 
 // host launchers (defined in the .hip files)
 namespace hbk {
 int baca_launch(int scalar /*0 f64, 1 c128, 2 f32*/, int dmax, int rpt, const BacaArgs& a,
                 hipStream_t st);
+// one launch of the adjoint tasks of one kind (AdjTaskKind), tasks
+// base .. base + count - 1
+int adj_launch(int kind, int base, int count, const AdjArgs& a, hipStream_t st);
 }

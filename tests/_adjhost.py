@@ -1,0 +1,150 @@
+"""Host emulation of the adjoint's workgroup tasks (tests/adjoint_host).
+
+Builds adj_host.cpp with g++ and feeds it a frozen structure in the record
+format the leaf kernel writes (nI, nJ, d_k, I_k, J_k, pivot order), taken
+here from the oracle's forward run."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "adjoint_host", "adj_host.cpp")
+OUT = os.path.join(HERE, "adjoint_host", "_build")
+
+_lib = None
+
+
+def build(extra=()):
+    os.makedirs(OUT, exist_ok=True)
+    so = os.path.join(OUT, "adj_host.so")
+    cmd = ["g++", "-std=c++20", "-O2", "-pthread", "-shared", "-fPIC", *extra, SRC, "-o", so]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    return so
+
+
+def load():
+    global _lib
+    if _lib is None:
+        lib = C.CDLL(build())
+        p = C.c_void_p
+        lib.adj_host_vjp.argtypes = [C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int,
+                                     p, p, p, p, p, C.c_double, C.c_double, p, p, p, p, p, p,
+                                     C.c_int, C.POINTER(C.c_int64)]
+        lib.adj_host_vjp.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def dmax_for(d):
+    return 8 if d <= 8 else (16 if d <= 16 else 32)
+
+
+def records_from_oracle(fs):
+    """(leaf_info int64 [nleaves, 7], records int32, ranks int32, dmax, stride)."""
+    wl, res = fs.wl, fs.res
+    dm = dmax_for(wl["d"])
+    stride = 3 + 3 * dm
+    nb = 1 << fs.L
+    info, recs = [], []
+    for b in range(nb * nb):
+        li = res.leaf_info[b]
+        first = len(recs)
+        for it in li["iters"]:
+            I = np.asarray(it["Iblock"], dtype=np.int64)
+            J = np.asarray(it["Jblock"], dtype=np.int64)
+            dk = int(it["dk"])
+            piv = np.asarray(it["piv"], dtype=np.int64)[:dk]
+            r = np.zeros(stride, dtype=np.int32)
+            r[0], r[1], r[2] = I.size, J.size, dk
+            r[3:3 + I.size] = I
+            r[3 + dm:3 + dm + J.size] = J
+            r[3 + 2 * dm:3 + 2 * dm + dk] = piv
+            recs.append(r)
+            if dk == 0:
+                break
+        info.append([li["row0"], li["col0"], li["m0"], li["n0"], len(recs) - first, li["rank"],
+                     first])
+    ranks = []
+    for lev in range(1, fs.L + 1):
+        nbl = 1 << (fs.L - lev)
+        h = fs.res.ranks[lev - 0.5]  # order (t, v, i): block (2t + i, v)
+        hp = np.zeros(2 * nbl * nbl, dtype=np.int32)
+        for t in range(nbl):
+            for v in range(nbl):
+                for i in range(2):
+                    hp[(2 * t + i) * nbl + v] = h[(t * nbl + v) * 2 + i]
+        ranks.extend(hp.tolist())
+        ranks.extend(fs.res.ranks[lev])
+    recs = np.concatenate(recs) if recs else np.zeros(stride, dtype=np.int32)
+    return (np.asarray(info, dtype=np.int64), recs.astype(np.int32),
+            np.asarray(ranks, dtype=np.int32), dm, stride)
+
+
+def vjp(fs, w, ybar, nt=8, info=None):
+    """(gw, gh, gX, gY) of <ybar, A~ w> through the host emulation."""
+    lib = load()
+    wl = fs.wl
+    li, recs, ranks, dm, stride = info or records_from_oracle(fs)
+    X = np.ascontiguousarray(np.asarray(wl["X"], dtype=np.float64).T)
+    Y = np.ascontiguousarray(np.asarray(wl["Y"], dtype=np.float64).T)
+    m, n, dim = wl["m"], wl["n"], X.shape[0]
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    ybar = np.ascontiguousarray(ybar, dtype=np.float64)
+    gw = np.zeros(n)
+    gh = np.zeros(1)
+    gX = np.zeros((m, dim))
+    gY = np.zeros((n, dim))
+    arena = C.c_int64(0)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    st = lib.adj_host_vjp(m, n, fs.L, dim, dm, stride, ptr(li), ptr(recs), ptr(ranks), ptr(X),
+                          ptr(Y), float(wl["h"]), float(wl.get("gauss_c", 1.0)), ptr(w),
+                          ptr(ybar), ptr(gw), ptr(gh), ptr(gX), ptr(gY), nt, C.byref(arena))
+    if st != 0:
+        raise RuntimeError(f"adj_host_vjp status {st}")
+    return gw, float(gh[0]), gX, gY
+
+
+def build_tsan():
+    """The stand-alone driver built with ThreadSanitizer."""
+    os.makedirs(OUT, exist_ok=True)
+    exe = os.path.join(OUT, "adj_host_tsan")
+    cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=thread", "-pthread", "-DADJ_HOST_MAIN",
+           SRC, "-o", exe]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    return exe
+
+
+def run_exe(exe, fs, w, ybar, nt, workdir):
+    """Runs the stand-alone driver; returns (returncode, stderr, outputs or None)."""
+    wl = fs.wl
+    li, recs, ranks, dm, stride = records_from_oracle(fs)
+    X = np.ascontiguousarray(np.asarray(wl["X"], dtype=np.float64).T)
+    Y = np.ascontiguousarray(np.asarray(wl["Y"], dtype=np.float64).T)
+    m, n, dim = wl["m"], wl["n"], X.shape[0]
+    inp = os.path.join(workdir, "adj_in.bin")
+    out = os.path.join(workdir, "adj_out.bin")
+    with open(inp, "wb") as f:
+        np.asarray([m, n, fs.L, dim, dm, stride, li.shape[0], recs.size, ranks.size],
+                   dtype=np.int64).tofile(f)
+        li.astype(np.int64).tofile(f)
+        recs.astype(np.int32).tofile(f)
+        ranks.astype(np.int32).tofile(f)
+        X.tofile(f)
+        Y.tofile(f)
+        np.asarray([wl["h"], wl.get("gauss_c", 1.0)], dtype=np.float64).tofile(f)
+        np.asarray(w, dtype=np.float64).tofile(f)
+        np.asarray(ybar, dtype=np.float64).tofile(f)
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66")
+    p = subprocess.run([exe, inp, out, str(nt)], capture_output=True, text=True, env=env,
+                       timeout=900)
+    if p.returncode != 0:
+        return p.returncode, p.stderr, None
+    v = np.fromfile(out, dtype=np.float64)
+    gw, gh = v[:n], v[n]
+    gX = v[n + 1:n + 1 + m * dim].reshape(m, dim)
+    gY = v[n + 1 + m * dim:].reshape(n, dim)
+    return 0, p.stderr, (gw, gh, gX, gY)

@@ -1,0 +1,174 @@
+// Host emulation of the adjoint's workgroup tasks, for tests only.
+//
+// The library runs every task of paper_1901_06101_amd/csrc/hb_adj.h on one
+// GPU workgroup.  This file compiles the same task code for the host and
+// runs each workgroup as `nt` operating-system threads that meet at a
+// std::barrier wherever the device code calls __syncthreads(), in the
+// launch order the library uses (adj_execute).  It checks the tasks'
+// arithmetic, indexing and barrier placement against the oracle on the CPU;
+// it is not linked into the library, which has no host path.
+#include <barrier>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <thread>
+#include <vector>
+
+#include "../../paper_1901_06101_amd/csrc/hb_adj_plan.h"
+
+namespace {
+
+struct WgHost {
+  int tid, nt;
+  double* red;
+  std::barrier<>* bar;
+  void sync() { bar->arrive_and_wait(); }
+};
+
+struct HostExec {
+  AdjArgs a;
+  int nt;
+  void launch(int kind, int base, int count) {
+    for (int g = 0; g < count; ++g) {
+      std::vector<double> red(nt, 0.0);
+      std::barrier<> bar(nt);
+      if (nt == 1) {
+        WgHost w{0, 1, red.data(), &bar};
+        adj_run_task(w, a, kind, base + g);
+        continue;
+      }
+      std::vector<std::thread> th;
+      th.reserve(nt);
+      for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+          WgHost w{t, nt, red.data(), &bar};
+          adj_run_task(w, a, kind, base + g);
+        });
+      for (auto& x : th) x.join();
+    }
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+// leaf_info: per leaf (b = t 2^L + v) row0, col0, m0, n0, records,
+// rank_leaf, first record index; recs: records of fz_stride ints; ranks:
+// per level l = 1..L the horizontal ranks (block (ti, v), ti-major) then
+// the vertical ranks (block (t, v), t-major).  Points are structure of
+// arrays.  The arena starts filled with NaN so that a read of memory no
+// task wrote shows up in the outputs.  Returns the planner's status.
+int adj_host_vjp(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stride,
+                 const int64_t* leaf_info, const int32_t* recs, const int32_t* ranks,
+                 const double* Xsoa, const double* Ysoa, double h, double c, const double* w,
+                 const double* ybar, double* gw, double* gh, double* gX, double* gY, int nt,
+                 int64_t* arena_out) {
+  AdjPlanIn in;
+  in.m = m;
+  in.n = n;
+  in.L = L;
+  in.dim = dim;
+  in.dmax = dmax;
+  in.fz_stride = fz_stride;
+  const int nb = 1 << L;
+  for (int b = 0; b < nb * nb; ++b) {
+    const int64_t* f = leaf_info + 7 * b;
+    AdjLeafIn li;
+    li.row0 = f[0];
+    li.col0 = f[1];
+    li.m0 = (int32_t)f[2];
+    li.n0 = (int32_t)f[3];
+    li.nrec = (int32_t)f[4];
+    li.rank_leaf = (int32_t)f[5];
+    li.rec = recs + f[6] * fz_stride;
+    in.leaves.push_back(li);
+  }
+  int64_t off = 0;
+  for (int l = 1; l <= L; ++l) {
+    const int nbc = 1 << (L - l + 1), nbp = nbc / 2;
+    in.hrank.emplace_back(ranks + off, ranks + off + nbc * nbp);
+    off += nbc * nbp;
+    in.vrank.emplace_back(ranks + off, ranks + off + nbp * nbp);
+    off += nbp * nbp;
+  }
+  AdjPlan P;
+  const int st = adj_plan(in, P);
+  if (st != 0) return st;
+  if (arena_out) *arena_out = P.arena;
+  std::vector<double> D(P.arena, std::numeric_limits<double>::quiet_NaN());
+  AdjArgs a{};
+  a.D = D.data();
+  a.ws = D.data() + P.ws_off;
+  a.fz = P.fz.data();
+  a.leaves = P.leaves.data();
+  a.blocks = P.blocks.data();
+  a.merges = P.merges.data();
+  a.X = Xsoa;
+  a.Y = Ysoa;
+  a.ldx = m;
+  a.ldy = n;
+  a.dim = dim;
+  a.dmax = dmax;
+  a.fz_stride = 3 + 3 * dmax;
+  a.root = P.root;
+  a.nb = P.nb;
+  a.nleaves = (int32_t)P.leaves.size();
+  a.h = h;
+  a.nic = -1.0 / (c * h * h);
+  a.w = w;
+  a.ybar = ybar;
+  a.gw = gw;
+  a.gh = gh;
+  a.gX = gX;
+  a.gY = gY;
+  HostExec ex{a, nt};
+  adj_execute(ex, P, gX != nullptr, gY != nullptr, gh != nullptr);
+  return 0;
+}
+
+}  // extern "C"
+
+#ifdef ADJ_HOST_MAIN
+// Stand-alone driver (for a ThreadSanitizer build): reads the inputs of
+// adj_host_vjp from argv[1], runs it with argv[3] lanes per workgroup and
+// writes gw, gh, gX, gY to argv[2].
+int main(int argc, char** argv) {
+  if (argc < 4) return 2;
+  FILE* f = std::fopen(argv[1], "rb");
+  if (!f) return 2;
+  int64_t hd[9];
+  if (std::fread(hd, 8, 9, f) != 9) return 2;
+  const int64_t m = hd[0], n = hd[1], nleaves = hd[6], nrec = hd[7], nrank = hd[8];
+  const int L = (int)hd[2], dim = (int)hd[3], dmax = (int)hd[4], stride = (int)hd[5];
+  std::vector<int64_t> info(7 * nleaves);
+  std::vector<int32_t> recs(nrec), ranks(nrank + 1);
+  std::vector<double> X(dim * m), Y(dim * n), hc(2), w(n), yb(m);
+  bool ok = std::fread(info.data(), 8, info.size(), f) == info.size();
+  ok = ok && std::fread(recs.data(), 4, nrec, f) == (size_t)nrec;
+  ok = ok && std::fread(ranks.data(), 4, nrank, f) == (size_t)nrank;
+  ok = ok && std::fread(X.data(), 8, X.size(), f) == X.size();
+  ok = ok && std::fread(Y.data(), 8, Y.size(), f) == Y.size();
+  ok = ok && std::fread(hc.data(), 8, 2, f) == 2;
+  ok = ok && std::fread(w.data(), 8, n, f) == (size_t)n;
+  ok = ok && std::fread(yb.data(), 8, m, f) == (size_t)m;
+  std::fclose(f);
+  if (!ok) return 2;
+  std::vector<double> gw(n), gh(1), gX(m * dim), gY(n * dim);
+  const int st = adj_host_vjp(m, n, L, dim, dmax, stride, info.data(), recs.data(), ranks.data(),
+                              X.data(), Y.data(), hc[0], hc[1], w.data(), yb.data(), gw.data(),
+                              gh.data(), gX.data(), gY.data(), std::atoi(argv[3]), nullptr);
+  if (st != 0) return 3;
+  FILE* o = std::fopen(argv[2], "wb");
+  if (!o) return 2;
+  std::fwrite(gw.data(), 8, n, o);
+  std::fwrite(gh.data(), 8, 1, o);
+  std::fwrite(gX.data(), 8, gX.size(), o);
+  std::fwrite(gY.data(), 8, gY.size(), o);
+  std::fclose(o);
+  return 0;
+}
+#endif

@@ -37,12 +37,13 @@ def test_status_strings():
     assert lib.hb_status_string(-99).decode() == "unknown status"
 
 
-def _call(precision=0, **over):
+def _call(precision=0, record_tape=0, **over):
     from paper_1901_06101_amd import _binding
     lib = _binding.load(LIB)
     p = _binding.HbParams()
     p.dim, p.h, p.gauss_c, p.wavenumber = 3, 0.5, 1.0, 20.0
     p.precision = precision
+    p.record_tape = record_tape
     args = dict(entry=1, params=C.byref(p), X=C.c_void_p(16), Y=C.c_void_p(16), m=100, n=100,
                 tol=1e-6, d=8, leaf=50)
     args.update(over)
@@ -72,6 +73,15 @@ def test_precision_modes_checked_on_host(precision, entry, expect):
     assert out.value is None
 
 
+@pytest.mark.parametrize("record_tape,expect", [(3, -1), (-1, -1)])
+def test_record_modes_checked_on_host(record_tape, expect):
+    """0 (nothing), 1 (pivot tapes) and 2 (also the frozen structure of the
+    adjoint) are the only recording modes."""
+    st, out = _call(record_tape=record_tape)
+    assert st == expect
+    assert out.value is None
+
+
 def test_result_accessors_reject_null():
     from paper_1901_06101_amd import _binding
     lib = _binding.load(LIB)
@@ -79,4 +89,5 @@ def test_result_accessors_reject_null():
     assert lib.hb_result_nblocks(None) == -1
     assert lib.hb_result_copy(None, 0, None, None, None, None) == -1
     assert lib.hbaca_apply(None, 0, None, None, 0, None) == -1
+    assert lib.hbaca_vjp(None, None, None, None, None, None, None, None) == -1
     lib.hb_result_free(None)

@@ -1,0 +1,131 @@
+"""The adjoint's workgroup tasks (paper_1901_06101_amd/csrc/hb_adj.h), compiled
+for the host and run with one thread per lane and a real barrier per
+__syncthreads() (tests/adjoint_host), against the frozen-pivot adjoint
+oracle (oracle/adjoint.py) on the same pivots and ranks.
+
+This checks the device code's arithmetic, indexing and barrier placement
+on the CPU; the library itself has no host path and its GPU run is checked
+by tests/test_gpu_zz_adjoint.py."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as adj
+from workloads import generators as G
+
+import _adjhost as AH
+
+
+def _ybar(fs, w, b):
+    f64 = dict(dtype=torch.float64)
+    wl = fs.wl
+    U, S, V = adj.frozen_operator(fs, torch.tensor(wl["X"], **f64), torch.tensor(wl["Y"], **f64),
+                                  torch.tensor(wl["h"], **f64))
+    y = (U @ (S * (V @ torch.tensor(w, **f64)))).numpy()
+    return 2.0 * (y - b)
+
+
+@pytest.fixture(scope="module")
+def case():
+    wl = G.make_gauss3d(n=400, m=360, h=0.7, leaf=100, tol=1e-6, d=8, cfg=51)
+    fs = adj.FrozenStructure(wl)
+    rng = np.random.default_rng(5105)
+    w = rng.standard_normal(wl["n"])
+    b = rng.standard_normal(wl["m"])
+    return fs, w, b
+
+
+def _rel(a, r):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(r)) / np.linalg.norm(np.asarray(r)))
+
+
+def test_host_tasks_match_frozen_oracle(case):
+    fs, w, b = case
+    _, gw, gh, gX, gY = adj.frozen_gradients(fs, w, b)
+    hw, hh, hX, hY = AH.vjp(fs, w, _ybar(fs, w, b), nt=4)
+    assert _rel(hw, gw) <= 1e-10
+    assert abs(hh - gh) <= 1e-10 * abs(gh)
+    assert _rel(hX, gX) <= 1e-10
+    assert _rel(hY, gY) <= 1e-10
+
+
+def test_host_tasks_ragged_d16_three_levels():
+    # L = 3, ragged cluster sizes, block size 16, another width
+    wl = G.make_gauss3d(n=700, m=650, h=0.6, leaf=90, tol=1e-5, d=16, cfg=53)
+    fs = adj.FrozenStructure(wl)
+    assert fs.L == 3
+    rng = np.random.default_rng(53)
+    w = rng.standard_normal(wl["n"])
+    b = rng.standard_normal(wl["m"])
+    _, gw, gh, gX, gY = adj.frozen_gradients(fs, w, b)
+    hw, hh, hX, hY = AH.vjp(fs, w, _ybar(fs, w, b), nt=8)
+    assert _rel(hw, gw) <= 1e-10
+    assert abs(hh - gh) <= 1e-10 * abs(gh)
+    assert _rel(hX, gX) <= 1e-10
+    assert _rel(hY, gY) <= 1e-10
+
+
+def test_lane_count_does_not_change_the_result(case):
+    fs, w, b = case
+    yb = _ybar(fs, w, b)
+    one = AH.vjp(fs, w, yb, nt=1)
+    many = AH.vjp(fs, w, yb, nt=16)
+    for a, r in zip(one, many):
+        assert np.max(np.abs(np.asarray(a) - np.asarray(r))) <= 1e-12 * max(1.0, np.max(np.abs(r)))
+
+
+def test_no_data_race_under_thread_sanitizer(tmp_path):
+    wl = G.make_gauss3d(n=300, m=270, h=0.7, leaf=75, tol=1e-5, d=8, cfg=52)
+    fs = adj.FrozenStructure(wl)
+    rng = np.random.default_rng(1)
+    w = rng.standard_normal(wl["n"])
+    yb = rng.standard_normal(wl["m"])
+    exe = AH.build_tsan()
+    rc, err, outs = AH.run_exe(exe, fs, w, yb, 4, str(tmp_path))
+    assert rc == 0, err[-4000:]
+    assert "ThreadSanitizer" not in err
+    ref = AH.vjp(fs, w, yb, nt=1)
+    for a, r in zip(outs, ref):
+        assert np.max(np.abs(np.asarray(a) - np.asarray(r))) <= 1e-12 * max(1.0, np.max(np.abs(r)))
+
+
+def test_planner_rejects_inconsistent_structures(case):
+    fs, w, b = case
+    yb = np.zeros(fs.wl["m"])
+    li, recs, ranks, dm, stride = AH.records_from_oracle(fs)
+
+    def status(li2, recs2, ranks2):
+        try:
+            AH.vjp(fs, w, yb, nt=1, info=(li2, recs2, ranks2, dm, stride))
+        except RuntimeError as e:
+            return int(str(e).split()[-1])
+        return 0
+
+    assert status(li, recs, ranks) == 0
+    bad = recs.copy()
+    bad[3] = fs.wl["m"]  # a row index outside its leaf
+    assert status(li, bad, ranks) == -1
+    bad = recs.copy()
+    bad[3 + dm + 1] = bad[3 + dm]  # a repeated column
+    assert status(li, bad, ranks) == -1
+    bad = recs.copy()
+    bad[2] = 0  # d_k = 0 before the last record of a leaf with more records
+    if li[0, 4] > 1:
+        assert status(li, bad, ranks) == -1
+    neg = ranks.copy()
+    neg[-1] = -1  # a negative rank
+    assert status(li, recs, neg) == -1
+    big = ranks.copy()
+    big[0] = 10_000  # more than r1 + r2
+    assert status(li, recs, big) == -1
+    li2 = li.copy()
+    li2[0, 5] = li2[0, 5] + 1000  # leaf rank above its BACA rank
+    assert status(li2, recs, ranks) == -1
+
+
+def test_planner_needs_merge_rows_at_least_columns():
+    # leaves of 45 rows whose ranks add up to more than 45 at the first merge
+    wl = G.make_gauss3d(n=200, m=180, h=0.7, leaf=50, tol=1e-6, d=8, cfg=52)
+    fs = adj.FrozenStructure(wl)
+    with pytest.raises(RuntimeError, match="-6"):
+        AH.vjp(fs, np.zeros(wl["n"]), np.zeros(wl["m"]), nt=1)
