@@ -90,7 +90,9 @@ def comparisons(steps=5, warmup=1):
         return hb.compress(wl["entry"], p, X, Y, wl["m"], wl["n"], wl["tol"], wl["d"], wl["leaf"])
 
     f_ms, f_res = timed(lambda: single(hb.HB_PREC_FP64), steps, warmup)
+    _note(f"comparisons: gauss3d FP64 {f_ms:.1f} ms")
     m_ms, m_res = timed(lambda: single(hb.HB_PREC_MIXED), steps, warmup)
+    _note(f"comparisons: gauss3d mixed {m_ms:.1f} ms")
     ef, em = rel_err(f_res), rel_err(m_res)
     out["mixed_vs_fp64"] = dict(
         workload=f"gauss3d {wl['m']}x{wl['n']} tol={wl['tol']} d={wl['d']} leaf={wl['leaf']}",
@@ -112,7 +114,9 @@ def comparisons(steps=5, warmup=1):
                                    wb["col_off"], wb["col_cnt"], wb["tol"], wb["d"], wb["leaf"])
 
     bf_ms, bf_res = timed(lambda: batched(hb.HB_PREC_FP64), 3, 1)
+    _note(f"comparisons: {nb} Laplace blocks batched FP64 {bf_ms:.1f} ms")
     bm_ms, bm_res = timed(lambda: batched(hb.HB_PREC_MIXED), 3, 1)
+    _note(f"comparisons: {nb} Laplace blocks batched mixed {bm_ms:.1f} ms")
 
     def sequential():
         last = None
@@ -128,6 +132,7 @@ def comparisons(steps=5, warmup=1):
 
     s_ms, s_res = timed(sequential, 1, 1)
     s_res.close()
+    _note(f"comparisons: {nb} Laplace blocks one call each {s_ms:.1f} ms")
     ebf = max(rel_err(bf_res, b) for b in range(nb))
     ebm = max(rel_err(bm_res, b) for b in range(nb))
     out["batched_vs_sequential"] = dict(
@@ -140,17 +145,23 @@ def comparisons(steps=5, warmup=1):
     print(json.dumps(out), flush=True)
 
 
+def _note(msg):
+    """Progress of the run on stderr (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def run_comparisons(timeout=300):
     import subprocess
+    _note("comparisons start in a child process")
     try:
         r = subprocess.run([sys.executable, os.path.abspath(__file__), "--comparisons"],
-                           capture_output=True, text=True, timeout=timeout)
+                           stdout=subprocess.PIPE, text=True, timeout=timeout)
     except subprocess.TimeoutExpired:
         return {"error": f"timed out after {timeout} s"}
     for line in reversed(r.stdout.strip().splitlines()):
         if line.startswith("{"):
             return json.loads(line)
-    return {"error": f"exit {r.returncode}: {r.stderr.strip()[-400:]}"}
+    return {"error": f"exit {r.returncode} (its messages are on stderr)"}
 
 
 def main():
@@ -166,13 +177,13 @@ def main():
     if args.comparisons:
         comparisons()
         return
-    # the comparisons run first, in a child process, before this process
-    # touches the GPU
-    comp = None if args.no_comparisons else run_comparisons()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); how H-BACA would "
               "shard over several GPUs is described in the design notes", file=sys.stderr)
         sys.exit(2)
+    # the comparisons run first, in a child process, before this process
+    # touches the GPU
+    comp = None if args.no_comparisons else run_comparisons()
 
     import numpy as np
     import torch
@@ -198,9 +209,11 @@ def main():
         return hb.compress(wl["entry"], p, X, Y, wl["m"], wl["n"], wl["tol"], wl["d"],
                            wl["leaf"])
 
+    _note(f"{wl['name']} {wl['m']}x{wl['n']}: warm-up")
     for _ in range(args.warmup):
         step().close()
     torch.cuda.synchronize()
+    _note(f"{wl['name']}: {args.steps} timed steps")
     stats = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -248,7 +261,9 @@ def main():
         "roofline": roofline,
     }
     last.close()
+    _note(f"{wl['name']}: {ms:.2f} ms per compress")
     if not args.no_cpu_baseline:
+        _note("CPU baseline (the oracle on the same workload)")
         try:
             out["cpu_baseline"] = cpu_baseline(wl)
         except Exception as e:  # the GPU line is still reported
