@@ -221,6 +221,27 @@ hb_status hbaca_vjp(const hb_result* res, const double* w, const double* ybar, d
                     double* grad_h, double* grad_points_row, double* grad_points_col,
                     void* stream);
 
+/*
+ * The frozen operator at new parameters: the pipeline recorded in `tape`
+ * (same requirements as hbaca_vjp) replayed in FP64 with the same pivots
+ * and ranks, at new points and a new Gaussian width, without any new
+ * pivot or rank decision.  This is the map whose derivative hbaca_vjp
+ * returns, so central differences of it check that gradient.
+ *
+ * params: only dim (must equal the tape's), h and gauss_c are read.
+ * points_row, points_col: DEVICE, m x dim and n x dim FP64 (the tape's
+ *        m and n), copied into the new result.
+ * *out:  a new single-block result (rank = the tape's root rank) owned by
+ *        the caller (hb_result_free); it carries the tape's frozen
+ *        structure, so hbaca_vjp and hbaca_recompute_frozen accept it too.
+ *        NULL on error.
+ * Runs on `stream` and synchronises it before returning.  Errors as for
+ * hbaca_vjp; HB_ENONFINITE for a non-finite h or gauss_c.
+ */
+hb_status hbaca_recompute_frozen(const hb_result* tape, const hb_params* params,
+                                 const double* points_row, const double* points_col,
+                                 void* stream, hb_result** out);
+
 /* Statistics of the call (host struct). */
 hb_status hb_result_stats(const hb_result* res, hb_stats* out);
 

@@ -194,6 +194,21 @@ class Result:
                                      _ptr(gY), _stream()), "hbaca_vjp")
         return gw, gh, gX, gY
 
+    def recompute_frozen(self, X, Y, h, gauss_c=1.0):
+        """The frozen operator (same pivots and ranks as this result, which
+        needs record_tape=2) at new points X, Y and width h, as a new
+        Result."""
+        import torch
+        X = X.detach().to(torch.float64).contiguous()
+        Y = Y.detach().to(torch.float64).contiguous()
+        keep = [X, Y]
+        hp = _hb_params(params(dim=int(X.shape[1]), h=float(h), gauss_c=float(gauss_c)), keep)
+        out = C.c_void_p()
+        B._check(self._lib.hbaca_recompute_frozen(self._h, C.byref(hp), _ptr(X), _ptr(Y),
+                                                  _stream(), C.byref(out)),
+                 "hbaca_recompute_frozen")
+        return Result(out, keep)
+
     def error(self, block=0, row_stride=1):
         """(sum |A - A~|^2, sum |A|^2) over rows 0, stride, ... (device FP64)."""
         e = C.c_double()

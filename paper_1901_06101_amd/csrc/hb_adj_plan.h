@@ -276,12 +276,20 @@ inline int adj_plan(const AdjPlanIn& in, AdjPlan& P) {
 // The launch sequence, shared by the GPU and by the host emulation used in
 // tests: ex.launch(kind, first task, task count) runs the tasks of one
 // launch, each on its own workgroup, after every earlier launch finished.
+// The forward part alone evaluates the frozen operator (root block
+// P.blocks[P.root]).
 template <class Ex>
-inline void adj_execute(Ex& ex, const AdjPlan& P, bool want_x, bool want_y, bool want_h) {
+inline void adj_execute_forward(Ex& ex, const AdjPlan& P) {
   const int nl = (int)P.leaves.size();
   ex.launch(ADJ_LEAF_FWD, 0, nl);
   ex.launch(ADJ_REC_FWD, 0, nl);
   for (const AdjPhase& ph : P.merge_phases) ex.launch(ADJ_MERGE_FWD, ph.base, ph.count);
+}
+
+template <class Ex>
+inline void adj_execute(Ex& ex, const AdjPlan& P, bool want_x, bool want_y, bool want_h) {
+  const int nl = (int)P.leaves.size();
+  adj_execute_forward(ex, P);
   ex.launch(ADJ_ROOT, 0, 1);
   for (auto it = P.merge_phases.rbegin(); it != P.merge_phases.rend(); ++it)
     ex.launch(ADJ_MERGE_BWD, it->base, it->count);

@@ -2019,8 +2019,8 @@ struct GpuAdjExec {
   }
 };
 
-static hb_status vjp_run(const hb_result* r, const double* w, const double* ybar, double* gw,
-                         double* gh, double* gX, double* gY, hipStream_t st) {
+// The plan of the frozen pipeline recorded in a result (record_tape = 2).
+static hb_status frozen_plan(const hb_result* r, AdjPlan& P) {
   const Problem& pr = r->problems[0];
   AdjPlanIn in;
   in.m = pr.m;
@@ -2043,12 +2043,13 @@ static hb_status vjp_run(const hb_result* r, const double* w, const double* ybar
   }
   in.hrank = r->fz_hrank;
   in.vrank = r->fz_vrank;
-  AdjPlan P;
   const int ps = adj_plan(in, P);
   if (ps == -6) return HB_EUNSUPPORTED;
-  if (ps != 0) return HB_EINVAL;
-  DevMem mem;
-  mem.st = st;
+  return ps == 0 ? HB_OK : HB_EINVAL;
+}
+
+// Arena and descriptors on the device; the points and width of `r`.
+static AdjArgs frozen_args(const hb_result* r, const AdjPlan& P, DevMem& mem, hipStream_t st) {
   double* D = mem.get<double>((size_t)P.arena);
   AdjArgs a{};
   a.D = D;
@@ -2062,13 +2063,24 @@ static hb_status vjp_run(const hb_result* r, const double* w, const double* ybar
   a.ldx = r->E.ldx;
   a.ldy = r->E.ldy;
   a.dim = r->E.dim;
-  a.dmax = in.dmax;
-  a.fz_stride = 3 + 3 * in.dmax;
+  a.dmax = (r->fz_stride - 3) / 3;
+  a.fz_stride = 3 + 3 * a.dmax;
   a.root = P.root;
   a.nb = P.nb;
   a.nleaves = (int32_t)P.leaves.size();
   a.h = r->fz_h;
   a.nic = r->E.neg_inv_ch2;
+  return a;
+}
+
+static hb_status vjp_run(const hb_result* r, const double* w, const double* ybar, double* gw,
+                         double* gh, double* gX, double* gY, hipStream_t st) {
+  AdjPlan P;
+  const hb_status ps = frozen_plan(r, P);
+  if (ps != HB_OK) return ps;
+  DevMem mem;
+  mem.st = st;
+  AdjArgs a = frozen_args(r, P, mem, st);
   a.w = w;
   a.ybar = ybar;
   a.gw = gw;
@@ -2082,6 +2094,83 @@ static hb_status vjp_run(const hb_result* r, const double* w, const double* ybar
     return HB_EDEVICE;
   }
   HB_HIP(hipStreamSynchronize(st));
+  return HB_OK;
+}
+
+// The frozen operator of `t` at new points and width: a result of its own
+// that carries the same frozen structure.
+static hb_status recompute_run(const hb_result* t, const hb_params* p, const double* X,
+                               const double* Y, hipStream_t st, hb_result** out) {
+  const Problem& pr = t->problems[0];
+  AdjPlan P;
+  const hb_status ps = frozen_plan(t, P);
+  if (ps != HB_OK) return ps;
+  std::unique_ptr<hb_result> R(new (std::nothrow) hb_result());
+  if (!R) return HB_ENOMEM;
+  R->keep.st = st;
+  R->keep.sync_free = true;
+  R->scalar = 0;
+  R->entry = HB_K_GAUSS;
+  EntryDev E = t->E;
+  double* Xs = R->keep.get<double>((size_t)pr.m * p->dim);
+  double* Ys = R->keep.get<double>((size_t)pr.n * p->dim);
+  hipLaunchKernelGGL(aos_to_soa_kernel, dim3((unsigned)((pr.m + 255) / 256)), dim3(256), 0, st, X,
+                     Xs, pr.m, p->dim);
+  hipLaunchKernelGGL(aos_to_soa_kernel, dim3((unsigned)((pr.n + 255) / 256)), dim3(256), 0, st, Y,
+                     Ys, pr.n, p->dim);
+  HB_HIP(hipGetLastError());
+  E.X = Xs;
+  E.Y = Ys;
+  E.ldx = pr.m;
+  E.ldy = pr.n;
+  E.neg_inv_ch2 = -1.0 / (p->gauss_c * p->h * p->h);
+  R->E = E;
+  R->problems.push_back(pr);
+  R->problems[0].root = Block{};
+  R->problems[0].row_base = 0;
+  R->problems[0].col_base = 0;
+  R->leaves = t->leaves;
+  for (LeafHost& lf : R->leaves) {
+    lf.row0 -= pr.row_base;
+    lf.col0 -= pr.col_base;
+  }
+  R->fz_stride = t->fz_stride;
+  R->fz_complete = true;
+  R->fz_hrank = t->fz_hrank;
+  R->fz_vrank = t->fz_vrank;
+  R->fz_h = p->h;
+  R->fz_c = p->gauss_c;
+  DevMem mem;
+  mem.st = st;
+  const AdjArgs a = frozen_args(R.get(), P, mem, st);
+  GpuAdjExec ex{a, st, 0};
+  adj_execute_forward(ex, P);
+  if (ex.err != 0) {
+    hb_report("frozen replay launch", ex.err, hipGetErrorString((hipError_t)ex.err), __LINE__);
+    return HB_EDEVICE;
+  }
+  const AdjBlock& B = P.blocks[P.root];
+  Block root;
+  root.m = pr.m;
+  root.n = pr.n;
+  root.r = B.r;
+  root.U = R->keep.alloc((size_t)pr.m * std::max(B.r, 1) * 8);
+  root.Vh = R->keep.alloc((size_t)pr.n * std::max(B.r, 1) * 8);
+  root.S = R->keep.get<double>((size_t)std::max(B.r, 1));
+  if (B.r > 0) {
+    HB_HIP(hipMemcpy2DAsync(root.U, (size_t)pr.m * 8, a.D + B.U, (size_t)B.ldU * 8,
+                            (size_t)pr.m * 8, (size_t)B.r, hipMemcpyDeviceToDevice, st));
+    HB_HIP(hipMemcpy2DAsync(root.Vh, (size_t)pr.n * 8, a.D + B.Vt, (size_t)B.ldVt * 8,
+                            (size_t)pr.n * 8, (size_t)B.r, hipMemcpyDeviceToDevice, st));
+    HB_HIP(hipMemcpyAsync(root.S, a.D + B.S, (size_t)B.r * 8, hipMemcpyDeviceToDevice, st));
+  }
+  R->problems[0].root = root;
+  R->out_blocks.push_back(root);
+  R->stats.n_blocks = 1;
+  R->stats.n_leaves = (int32_t)R->leaves.size();
+  R->stats.levels_max = pr.L;
+  HB_HIP(hipStreamSynchronize(st));
+  *out = R.release();
   return HB_OK;
 }
 
@@ -2213,6 +2302,26 @@ hb_status hbaca_apply(const hb_result* r, int64_t b, const void* in, void* out, 
   return e == hipSuccess ? HB_OK : HB_EDEVICE;
 }
 
+
+hb_status hbaca_recompute_frozen(const hb_result* tape, const hb_params* params,
+                                 const double* points_row, const double* points_col, void* stream,
+                                 hb_result** out) {
+  if (!out) return HB_EINVAL;
+  *out = nullptr;
+  if (!tape || !params || !points_row || !points_col) return HB_EINVAL;
+  if (tape->entry != HB_K_GAUSS || tape->scalar != 0) return HB_EUNSUPPORTED;
+  if (!tape->fz_complete || tape->fz_stride < 6 || tape->problems.size() != 1) return HB_EINVAL;
+  if (!std::isfinite(params->h) || !std::isfinite(params->gauss_c)) return HB_ENONFINITE;
+  if (!(params->h > 0.0) || !(params->gauss_c > 0.0) || params->dim != tape->E.dim)
+    return HB_EINVAL;
+  try {
+    return recompute_run(tape, params, points_row, points_col, (hipStream_t)stream, out);
+  } catch (const HbError& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    return HB_ENOMEM;
+  }
+}
 
 hb_status hbaca_vjp(const hb_result* r, const double* w, const double* ybar, double* grad_w,
                     double* grad_h, double* grad_points_row, double* grad_points_col,

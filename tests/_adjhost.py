@@ -35,6 +35,10 @@ def load():
                                      p, p, p, p, p, C.c_double, C.c_double, p, p, p, p, p, p,
                                      C.c_int, C.POINTER(C.c_int64)]
         lib.adj_host_vjp.restype = C.c_int
+        lib.adj_host_forward.argtypes = [C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int,
+                                         p, p, p, p, p, C.c_double, C.c_double, C.c_int, C.c_int,
+                                         p, p, p, C.POINTER(C.c_int32)]
+        lib.adj_host_forward.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -106,6 +110,31 @@ def vjp(fs, w, ybar, nt=8, info=None):
     if st != 0:
         raise RuntimeError(f"adj_host_vjp status {st}")
     return gw, float(gh[0]), gX, gY
+
+
+def forward(fs, X=None, Y=None, h=None, nt=1):
+    """(U, S, Vt) of the frozen operator at points X, Y (point-major) and
+    width h; the recorded ones by default."""
+    lib = load()
+    wl = fs.wl
+    li, recs, ranks, dm, stride = records_from_oracle(fs)
+    X = np.ascontiguousarray(np.asarray(wl["X"] if X is None else X, dtype=np.float64).T)
+    Y = np.ascontiguousarray(np.asarray(wl["Y"] if Y is None else Y, dtype=np.float64).T)
+    h = float(wl["h"] if h is None else h)
+    m, n = wl["m"], wl["n"]
+    cap = int(max(1, min(m, n)))
+    U = np.zeros((cap, m))
+    Vt = np.zeros((cap, n))
+    S = np.zeros(cap)
+    rk = C.c_int32(0)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    st = lib.adj_host_forward(m, n, fs.L, X.shape[0], dm, stride, ptr(li), ptr(recs), ptr(ranks),
+                              ptr(X), ptr(Y), h, float(wl.get("gauss_c", 1.0)), nt, cap, ptr(U),
+                              ptr(S), ptr(Vt), C.byref(rk))
+    if st != 0:
+        raise RuntimeError(f"adj_host_forward status {st}")
+    r = rk.value
+    return U[:r].T.copy(), S[:r].copy(), Vt[:r].T.copy()
 
 
 def build_tsan():

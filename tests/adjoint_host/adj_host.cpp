@@ -54,19 +54,9 @@ struct HostExec {
 
 }  // namespace
 
-extern "C" {
-
-// leaf_info: per leaf (b = t 2^L + v) row0, col0, m0, n0, records,
-// rank_leaf, first record index; recs: records of fz_stride ints; ranks:
-// per level l = 1..L the horizontal ranks (block (ti, v), ti-major) then
-// the vertical ranks (block (t, v), t-major).  Points are structure of
-// arrays.  The arena starts filled with NaN so that a read of memory no
-// task wrote shows up in the outputs.  Returns the planner's status.
-int adj_host_vjp(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stride,
-                 const int64_t* leaf_info, const int32_t* recs, const int32_t* ranks,
-                 const double* Xsoa, const double* Ysoa, double h, double c, const double* w,
-                 const double* ybar, double* gw, double* gh, double* gX, double* gY, int nt,
-                 int64_t* arena_out) {
+static int make_plan(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stride,
+                     const int64_t* leaf_info, const int32_t* recs, const int32_t* ranks,
+                     AdjPlan& P) {
   AdjPlanIn in;
   in.m = m;
   in.n = n;
@@ -95,11 +85,11 @@ int adj_host_vjp(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stride,
     in.vrank.emplace_back(ranks + off, ranks + off + nbp * nbp);
     off += nbp * nbp;
   }
-  AdjPlan P;
-  const int st = adj_plan(in, P);
-  if (st != 0) return st;
-  if (arena_out) *arena_out = P.arena;
-  std::vector<double> D(P.arena, std::numeric_limits<double>::quiet_NaN());
+  return adj_plan(in, P);
+}
+
+static AdjArgs make_args(const AdjPlan& P, std::vector<double>& D, int64_t m, int64_t n, int dim,
+                         int dmax, const double* Xsoa, const double* Ysoa, double h, double c) {
   AdjArgs a{};
   a.D = D.data();
   a.ws = D.data() + P.ws_off;
@@ -119,6 +109,28 @@ int adj_host_vjp(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stride,
   a.nleaves = (int32_t)P.leaves.size();
   a.h = h;
   a.nic = -1.0 / (c * h * h);
+  return a;
+}
+
+extern "C" {
+
+// leaf_info: per leaf (b = t 2^L + v) row0, col0, m0, n0, records,
+// rank_leaf, first record index; recs: records of fz_stride ints; ranks:
+// per level l = 1..L the horizontal ranks (block (ti, v), ti-major) then
+// the vertical ranks (block (t, v), t-major).  Points are structure of
+// arrays.  The arena starts filled with NaN so that a read of memory no
+// task wrote shows up in the outputs.  Returns the planner's status.
+int adj_host_vjp(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stride,
+                 const int64_t* leaf_info, const int32_t* recs, const int32_t* ranks,
+                 const double* Xsoa, const double* Ysoa, double h, double c, const double* w,
+                 const double* ybar, double* gw, double* gh, double* gX, double* gY, int nt,
+                 int64_t* arena_out) {
+  AdjPlan P;
+  const int st = make_plan(m, n, L, dim, dmax, fz_stride, leaf_info, recs, ranks, P);
+  if (st != 0) return st;
+  if (arena_out) *arena_out = P.arena;
+  std::vector<double> D(P.arena, std::numeric_limits<double>::quiet_NaN());
+  AdjArgs a = make_args(P, D, m, n, dim, dmax, Xsoa, Ysoa, h, c);
   a.w = w;
   a.ybar = ybar;
   a.gw = gw;
@@ -127,6 +139,30 @@ int adj_host_vjp(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stride,
   a.gY = gY;
   HostExec ex{a, nt};
   adj_execute(ex, P, gX != nullptr, gY != nullptr, gh != nullptr);
+  return 0;
+}
+
+// The frozen operator alone (the forward tasks): its root rank in *rank,
+// and, when the buffers hold cap columns, U (m x rank), S and Vt (n x rank).
+int adj_host_forward(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stride,
+                     const int64_t* leaf_info, const int32_t* recs, const int32_t* ranks,
+                     const double* Xsoa, const double* Ysoa, double h, double c, int nt, int cap,
+                     double* U, double* S, double* Vt, int32_t* rank) {
+  AdjPlan P;
+  const int st = make_plan(m, n, L, dim, dmax, fz_stride, leaf_info, recs, ranks, P);
+  if (st != 0) return st;
+  std::vector<double> D(P.arena, std::numeric_limits<double>::quiet_NaN());
+  AdjArgs a = make_args(P, D, m, n, dim, dmax, Xsoa, Ysoa, h, c);
+  HostExec ex{a, nt};
+  adj_execute_forward(ex, P);
+  const AdjBlock& B = P.blocks[P.root];
+  *rank = B.r;
+  if (B.r > cap) return 1;
+  for (int j = 0; j < B.r; ++j) {
+    for (int64_t i = 0; i < m; ++i) U[i + j * m] = D[B.U + i + j * B.ldU];
+    for (int64_t i = 0; i < n; ++i) Vt[i + j * n] = D[B.Vt + i + j * B.ldVt];
+    S[j] = D[B.S + j];
+  }
   return 0;
 }
 

@@ -65,6 +65,46 @@ def test_host_tasks_ragged_d16_three_levels():
     assert _rel(hY, gY) <= 1e-10
 
 
+def test_host_forward_reproduces_oracle_operator(case):
+    fs, _, _ = case
+    U, S, Vt = AH.forward(fs)
+    assert S.size == fs.res.rank
+    A = fs.res.dense()
+    assert np.linalg.norm((U * S) @ Vt.T - A) <= 1e-11 * np.linalg.norm(A)
+
+
+def test_host_vjp_matches_central_differences_of_host_forward(case):
+    """The task code's own frozen map, differenced: h, a random direction
+    over all points, and the w-gradient (exactly linear)."""
+    fs, _, _ = case
+    wl = fs.wl
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal(wl["n"])
+    yb = rng.standard_normal(wl["m"])
+
+    def f(X=None, Y=None, h=None):
+        U, S, Vt = AH.forward(fs, X, Y, h)
+        return float(yb @ (U @ (S * (Vt.T @ w))))
+
+    gw, gh, gX, gY = AH.vjp(fs, w, yb)
+    h, dh = wl["h"], 1e-4
+    c1 = (f(h=h + dh) - f(h=h - dh)) / (2 * dh)
+    c2 = (f(h=h + 2 * dh) - f(h=h - 2 * dh)) / (4 * dh)
+    assert abs((4 * c1 - c2) / 3 - gh) <= 1e-8 * abs(gh)
+    X, Y = wl["X"], wl["Y"]
+    PX = rng.standard_normal(X.shape)
+    PY = rng.standard_normal(Y.shape)
+    an = float(np.sum(gX * PX) + np.sum(gY * PY))
+
+    def cp(dp):
+        return (f(X + dp * PX, Y + dp * PY) - f(X - dp * PX, Y - dp * PY)) / (2 * dp)
+
+    fd = (4 * cp(1e-4) - cp(2e-4)) / 3
+    assert abs(fd - an) <= 1e-8 * abs(an)
+    U, S, Vt = AH.forward(fs)
+    assert np.linalg.norm(gw - Vt @ (S * (U.T @ yb))) <= 1e-12 * np.linalg.norm(gw)
+
+
 def test_lane_count_does_not_change_the_result(case):
     fs, w, b = case
     yb = _ybar(fs, w, b)

@@ -77,6 +77,47 @@ def test_autograd_function_matches_frozen_oracle(lib):
     assert _rel(Y.grad.cpu().numpy(), gY) <= 1e-8
 
 
+def test_recompute_frozen_and_central_differences(lib):
+    """hbaca_recompute_frozen at the recorded parameters reproduces the
+    forward result; its central differences in h and along a random point
+    direction match hbaca_vjp."""
+    import torch
+    wl = CASES["gauss3d_400x360"]()
+    res = run_gpu(lib, wl, record_tape=2)
+    X = torch.tensor(wl["X"], device="cuda")
+    Y = torch.tensor(wl["Y"], device="cuda")
+    h = float(wl["h"])
+    c = wl.get("gauss_c", 1.0)
+    same = res.recompute_frozen(X, Y, h, c)
+    assert same.rank() == res.rank()
+    U0, S0, V0 = res.factors(0)
+    U1, S1, V1 = same.factors(0)
+    ref = torch.linalg.norm((U0 * S0) @ V0.T)
+    assert torch.linalg.norm((U1 * S1) @ V1.T - (U0 * S0) @ V0.T) <= 1e-11 * ref
+    g = torch.Generator(device="cuda").manual_seed(3)
+    w = torch.randn(wl["n"], dtype=torch.float64, device="cuda", generator=g)
+    yb = torch.randn(wl["m"], dtype=torch.float64, device="cuda", generator=g)
+    _, gh, gX, gY = res.vjp(w, yb)
+
+    def f(Xp, Yp, hp):
+        r = res.recompute_frozen(Xp, Yp, hp, c)
+        return torch.dot(yb, r.apply(w)).item()
+
+    dh = 1e-4
+    c1 = (f(X, Y, h + dh) - f(X, Y, h - dh)) / (2 * dh)
+    c2 = (f(X, Y, h + 2 * dh) - f(X, Y, h - 2 * dh)) / (4 * dh)
+    assert abs((4 * c1 - c2) / 3 - gh.item()) <= 1e-8 * abs(gh.item())
+    PX = torch.randn(X.shape, dtype=torch.float64, device="cuda", generator=g)
+    PY = torch.randn(Y.shape, dtype=torch.float64, device="cuda", generator=g)
+    an = (torch.sum(gX * PX) + torch.sum(gY * PY)).item()
+
+    def cp(dp):
+        return (f(X + dp * PX, Y + dp * PY, h) - f(X - dp * PX, Y - dp * PY, h)) / (2 * dp)
+
+    fd = (4 * cp(1e-4) - cp(2e-4)) / 3
+    assert abs(fd - an) <= 1e-8 * abs(an)
+
+
 def test_vjp_rejects_results_without_frozen_structure(lib):
     import torch
     wl = CASES["gauss3d_400x360"]()
