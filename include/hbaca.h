@@ -210,9 +210,7 @@ hb_status hbaca_apply(const hb_result* res, int64_t block, const void* in, void*
  * Any gradient pointer may be NULL to skip it.  The call allocates its own
  * device workspace (the replayed factors, the saved blocks of every
  * iteration and merge, and the cotangents), runs on `stream` and
- * synchronises it before returning.  A merge whose stacked factor has fewer
- * rows than columns (leaves smaller than the sum of two children's ranks)
- * returns HB_EUNSUPPORTED.  The replay assumes the frozen ranks sit at a gap
+ * synchronises it before returning.  The replay assumes the frozen ranks sit at a gap
  * of the singular values (distinct kept values, separated from the dropped
  * ones); where they do not, the gradient is not defined and the result is
  * not finite.

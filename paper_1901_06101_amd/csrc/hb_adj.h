@@ -24,8 +24,9 @@
 //   J = Ub^T Ubb, K = Vb^T Vbb, F_ij = 1 / (s_j^2 - s_i^2).  Only the kept
 //   singular values are inverted.  For the re-compression P = U Vt^T the
 //   third term vanishes in Pb Vt and the second in Pb^T U; for a merge,
-//   P = [P1 diag(S1), P2 diag(S2)] is tall with a square right factor, so
-//   its third term is zero.
+//   P = [P1 diag(S1), P2 diag(S2)] keeps both (one is zero up to rounding
+//   when P has at least as many rows as columns, the other when it has
+//   fewer).
 //
 // Every task runs on one workgroup.  `W` supplies the lane id `tid`, the
 // lane count `nt` (a power of two), a reduction array `red` of nt doubles
@@ -89,9 +90,10 @@ struct AdjBlock {
 struct AdjMerge {
   int32_t b1, b2, out, horiz;
   int32_t k, rho;      // k = r1 + r2 columns, rank kept
+  int32_t p, pad;      // p = min(rows, k) singular values
   int64_t rows;        // rows of the P side
   int64_t n1, n2;      // rows of the O sides
-  int64_t Ub, Y, S;    // rows x k, k x k, k
+  int64_t Ub, Y, S;    // rows x p, k x p, p
   int64_t ws_f, ws_b;
 };
 
@@ -418,33 +420,52 @@ HBA_FN AdjSides adj_sides(const AdjArgs& a, const AdjMerge& M) {
   return s;
 }
 
-// Merge (Algorithm 3, eqs. (14)-(15)): B = [P1 diag(S1), P2 diag(S2)] = Q R,
-// R = X diag(s) Y^T, Ub = Q X; the new block is P = Ub(:, :rho), s(:rho),
-// O = blockdiag(O1, O2) Y(:, :rho).
+// Merge (Algorithm 3, eqs. (14)-(15)): the thin SVD B = Ub diag(s) Y^T of
+// B = [P1 diag(S1), P2 diag(S2)] (rows x k, p = min(rows, k) singular
+// values), through B = Q R, R = X diag(s) Y^T, Ub = Q X when rows >= k, and
+// through B^T = Q R, R^T = X diag(s) Z^T, Ub = X, Y = Q Z otherwise; the new
+// block is P = Ub(:, :rho), s(:rho), O = blockdiag(O1, O2) Y(:, :rho).
 template <class W>
 HBA_FN void adj_merge_fwd(W& w, const AdjArgs& a, int mi) {
   const AdjMerge& M = a.merges[mi];
-  const int k = M.k, rho = M.rho;
+  const int k = M.k, rho = M.rho, p = M.p;
   if (k == 0) return;
   const int r1 = a.blocks[M.b1].r, r2 = a.blocks[M.b2].r;
   const int64_t rows = M.rows, n1 = M.n1, n2 = M.n2;
   const AdjSides sd = adj_sides(a, M);
   const AdjBlock& out = a.blocks[M.out];
   double* D = a.D;
-  double* B = a.ws + M.ws_f;
-  double* R = B + rows * k;
-  double* Aw = R + k * k;
-  double* Yw = Aw + k * k;
-  double* hs = Yw + k * k;
+  double* B = a.ws + M.ws_f;  // rows x k (or its transpose)
+  double* R = B + rows * k;   // p x p
+  double* X = R + p * p;
+  double* Aw = X + p * p;
+  double* Yw = Aw + p * p;
+  double* Z = Yw + p * p;
+  double* hs = Z + p * p;     // rows + k
+  const bool tall = rows >= k;
   for (int64_t e = w.tid; e < rows * k; e += w.nt) {
     const int64_t l = e % rows;
     const int c = (int)(e / rows);
-    B[e] = c < r1 ? sd.P1[l + c * sd.ldP1] * sd.S1[c] : sd.P2[l + (c - r1) * sd.ldP2] * sd.S2[c - r1];
+    const double v =
+        c < r1 ? sd.P1[l + c * sd.ldP1] * sd.S1[c] : sd.P2[l + (c - r1) * sd.ldP2] * sd.S2[c - r1];
+    if (tall)
+      B[e] = v;
+    else
+      B[c + l * k] = v;
   }
   w.sync();
-  wg_qr(w, rows, k, B, rows, B, rows, R, k, hs);
-  wg_svd(w, k, R, k, D + M.Y, k, D + M.S, Aw, Yw, hs);
-  wg_gemm(w, rows, k, k, 1.0, B, rows, 0, R, k, 0, 0.0, D + M.Ub, rows);
+  if (tall) {
+    wg_qr(w, rows, k, B, rows, B, rows, R, k, hs);
+    wg_svd(w, k, R, k, D + M.Y, k, D + M.S, Aw, Yw, hs);
+    wg_gemm(w, rows, k, k, 1.0, B, rows, 0, R, k, 0, 0.0, D + M.Ub, rows);
+  } else {
+    wg_qr(w, k, (int)rows, B, k, B, k, R, p, hs);
+    for (int e = w.tid; e < p * p; e += w.nt) X[e] = R[(e / p) + (e % p) * p];
+    w.sync();
+    wg_svd(w, p, X, p, Z, p, D + M.S, Aw, Yw, hs);
+    for (int64_t e = w.tid; e < rows * p; e += w.nt) D[M.Ub + e] = X[e];
+    wg_gemm(w, k, p, p, 1.0, B, k, 0, Z, p, 0, 0.0, D + M.Y, k);
+  }
   double* On = D + (M.horiz ? out.Vt : out.U);
   wg_gemm(w, n1, rho, r1, 1.0, sd.O1, sd.ldO1, 0, D + M.Y, k, 0, 0.0, On, n1 + n2);
   wg_gemm(w, n2, rho, r2, 1.0, sd.O2, sd.ldO2, 0, D + M.Y + r1, k, 0, 0.0, On + n1, n1 + n2);
@@ -492,11 +513,14 @@ HBA_FN void adj_root(W& w, const AdjArgs& a) {
   w.sync();
 }
 
-// Reverse of a merge: cotangents of the children's factors.
+// Reverse of a merge: cotangents of the children's factors.  B = Ub
+// diag(s) Y^T is a thin SVD with p = min(rows, k) columns: both projector
+// terms of the truncated-SVD rule are kept (one of them vanishes, up to
+// rounding, when Ub or Y is square).
 template <class W>
 HBA_FN void adj_merge_bwd(W& w, const AdjArgs& a, int mi) {
   const AdjMerge& M = a.merges[mi];
-  const int k = M.k, rho = M.rho;
+  const int k = M.k, rho = M.rho, p = M.p;
   if (k == 0) return;
   const AdjBlock& b1 = a.blocks[M.b1];
   const AdjBlock& b2 = a.blocks[M.b2];
@@ -512,15 +536,16 @@ HBA_FN void adj_merge_bwd(W& w, const AdjArgs& a, int mi) {
   double* gP2 = D + (M.horiz ? b2.gU : b2.gVt);
   double* gO1 = D + (M.horiz ? b1.gVt : b1.gU);  // n1 x r1
   double* gO2 = D + (M.horiz ? b2.gVt : b2.gU);
-  const double* Ub = D + M.Ub;
-  const double* Y = D + M.Y;
+  const double* Ub = D + M.Ub;  // rows x p
+  const double* Y = D + M.Y;    // k x p
   const double* s = D + M.S;
-  double* Yb = a.ws + M.ws_b;  // k x rho
-  double* Jm = Yb + k * rho;
-  double* Km = Jm + k * rho;
-  double* G = Km + k * rho;
-  double* H = G + k * k;
-  double* E = H + k * k;       // rows x rho
+  double* Yb = a.ws + M.ws_b;   // k x rho
+  double* Jm = Yb + k * rho;    // p x rho
+  double* Km = Jm + p * rho;    // p x rho
+  double* G = Km + p * rho;     // p x p
+  double* H = G + p * p;        // p x k
+  double* E2 = H + p * k;       // k x rho
+  double* E = E2 + k * rho;     // rows x rho
   double* Bb = E + rows * rho;  // rows x k
   const int64_t ldo = n1 + n2;
   // O = blockdiag(O1, O2) Y(:, :rho)
@@ -529,20 +554,27 @@ HBA_FN void adj_merge_bwd(W& w, const AdjArgs& a, int mi) {
   wg_gemm(w, n1, r1, rho, 1.0, gOo, ldo, 0, Y, k, 1, 0.0, gO1, n1);
   wg_gemm(w, n2, r2, rho, 1.0, gOo + n1, ldo, 0, Y + r1, k, 1, 0.0, gO2, n2);
   // B = Ub diag(s) Y^T truncated at rho
-  wg_gemm(w, k, rho, rows, 1.0, Ub, rows, 1, gPo, rows, 0, 0.0, Jm, k);
-  wg_gemm(w, k, rho, k, 1.0, Y, k, 1, Yb, k, 0, 0.0, Km, k);
-  adj_svd_g(w, k, rho, s, gSo, Jm, Km, G);
-  wg_gemm(w, k, k, k, 1.0, G, k, 0, Y, k, 1, 0.0, H, k);
+  wg_gemm(w, p, rho, rows, 1.0, Ub, rows, 1, gPo, rows, 0, 0.0, Jm, p);
+  wg_gemm(w, p, rho, k, 1.0, Y, k, 1, Yb, k, 0, 0.0, Km, p);
+  adj_svd_g(w, p, rho, s, gSo, Jm, Km, G);
+  wg_gemm(w, p, k, p, 1.0, G, p, 0, Y, k, 1, 0.0, H, p);
   for (int64_t e = w.tid; e < rows * rho; e += w.nt) {
     const int64_t l = e % rows;
     const int j = (int)(e / rows);
     double v = gPo[e];
-    for (int i = 0; i < k; ++i) v -= Ub[l + i * rows] * Jm[i + j * k];
+    for (int i = 0; i < p; ++i) v -= Ub[l + i * rows] * Jm[i + j * p];
     E[e] = v / s[j];
   }
+  for (int e = w.tid; e < k * rho; e += w.nt) {
+    const int c = e % k, j = e / k;
+    double v = Yb[e];
+    for (int i = 0; i < p; ++i) v -= Y[c + i * k] * Km[i + j * p];
+    E2[e] = v / s[j];
+  }
   w.sync();
-  wg_gemm(w, rows, k, k, 1.0, Ub, rows, 0, H, k, 0, 0.0, Bb, rows);
+  wg_gemm(w, rows, k, p, 1.0, Ub, rows, 0, H, p, 0, 0.0, Bb, rows);
   wg_gemm(w, rows, k, rho, 1.0, E, rows, 0, Y, k, 1, 1.0, Bb, rows);
+  wg_gemm(w, rows, k, rho, 1.0, Ub, rows, 0, E2, k, 1, 1.0, Bb, rows);
   // B = [P1 diag(S1), P2 diag(S2)]
   for (int64_t e = w.tid; e < rows * k; e += w.nt) {
     const int64_t l = e % rows;

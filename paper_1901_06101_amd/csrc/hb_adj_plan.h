@@ -44,8 +44,7 @@ struct AdjPlan {
 };
 
 // 0 on success; -1 for a record or rank list that does not describe a
-// forward run of this shape; -6 for a merge whose P side has fewer rows than
-// columns (the replay's thin QR needs rows >= r1 + r2).
+// forward run of this shape.
 inline int adj_plan(const AdjPlanIn& in, AdjPlan& P) {
   P = AdjPlan();
   if (in.L < 0 || in.L > 20 || in.dim < 1 || in.dim > HBA_MAXDIM) return -1;
@@ -186,12 +185,12 @@ inline int adj_plan(const AdjPlanIn& in, AdjPlan& P) {
           M.n1 = horiz ? b1.n : b1.m;
           M.n2 = horiz ? b2.n : b2.m;
           M.k = b1.r + b2.r;
+          M.p = (int32_t)std::min<int64_t>(M.rows, M.k);
           M.rho = horiz ? hr[ti * nbp + v] : vr[ti * nbp + v];
-          if (M.rho < 0 || M.rho > M.k) return -1;
-          if (M.rows < M.k) return -6;
-          M.Ub = take(M.rows * M.k);
-          M.Y = take((int64_t)M.k * M.k);
-          M.S = take(M.k);
+          if (M.rho < 0 || M.rho > M.p) return -1;
+          M.Ub = take(M.rows * M.p);
+          M.Y = take((int64_t)M.k * M.p);
+          M.S = take(M.p);
           const int64_t on = take((M.n1 + M.n2) * M.rho);
           AdjBlock O{};
           O.r = M.rho;
@@ -246,14 +245,14 @@ inline int adj_plan(const AdjPlanIn& in, AdjPlan& P) {
   for (auto& ph : P.merge_phases) {
     for (int i = ph.base; i < ph.base + ph.count; ++i) {
       AdjMerge& M = P.merges[i];
-      const int64_t k = M.k;
-      M.ws_f = piece(M.rows * k + 3 * k * k + k);
+      const int64_t k = M.k, p = M.p;
+      M.ws_f = piece(M.rows * k + 5 * p * p + M.rows + k);
     }
     close();
     for (int i = ph.base; i < ph.base + ph.count; ++i) {
       AdjMerge& M = P.merges[i];
-      const int64_t k = M.k, rho = M.rho;
-      M.ws_b = piece(3 * k * rho + 2 * k * k + M.rows * (rho + k));
+      const int64_t k = M.k, rho = M.rho, p = M.p;
+      M.ws_b = piece(k * rho + 2 * p * rho + p * p + p * k + k * rho + M.rows * (rho + k));
     }
     close();
   }

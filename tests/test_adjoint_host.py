@@ -115,7 +115,8 @@ def test_lane_count_does_not_change_the_result(case):
 
 
 def test_no_data_race_under_thread_sanitizer(tmp_path):
-    wl = G.make_gauss3d(n=300, m=270, h=0.7, leaf=75, tol=1e-5, d=8, cfg=52)
+    # both merge shapes: wide first-level merges (45 rows), tall ones above
+    wl = G.make_gauss3d(n=200, m=180, h=0.7, leaf=50, tol=1e-6, d=8, cfg=52)
     fs = adj.FrozenStructure(wl)
     rng = np.random.default_rng(1)
     w = rng.standard_normal(wl["n"])
@@ -163,9 +164,24 @@ def test_planner_rejects_inconsistent_structures(case):
     assert status(li2, recs, ranks) == -1
 
 
-def test_planner_needs_merge_rows_at_least_columns():
-    # leaves of 45 rows whose ranks add up to more than 45 at the first merge
+def test_merges_wider_than_tall():
+    # leaves of 45 rows whose ranks add up to more than 45 at the first
+    # merge: the stacked factor is wide and its thin SVD has rows columns
     wl = G.make_gauss3d(n=200, m=180, h=0.7, leaf=50, tol=1e-6, d=8, cfg=52)
     fs = adj.FrozenStructure(wl)
-    with pytest.raises(RuntimeError, match="-6"):
-        AH.vjp(fs, np.zeros(wl["n"]), np.zeros(wl["m"]), nt=1)
+    nb = 1 << fs.L
+    r = [fs.res.leaf_info[b]["rank"] for b in range(nb * nb)]
+    m0 = fs.res.leaf_info[0]["m0"]
+    assert max(r[2 * v] + r[2 * v + 1] for v in range(nb // 2)) > m0
+    U, S, Vt = AH.forward(fs)
+    A = fs.res.dense()
+    assert np.linalg.norm((U * S) @ Vt.T - A) <= 1e-11 * np.linalg.norm(A)
+    rng = np.random.default_rng(52)
+    w = rng.standard_normal(wl["n"])
+    b = rng.standard_normal(wl["m"])
+    _, gw, gh, gX, gY = adj.frozen_gradients(fs, w, b)
+    hw, hh, hX, hY = AH.vjp(fs, w, _ybar(fs, w, b), nt=4)
+    assert _rel(hw, gw) <= 1e-10
+    assert abs(hh - gh) <= 1e-10 * abs(gh)
+    assert _rel(hX, gX) <= 1e-10
+    assert _rel(hY, gY) <= 1e-10
