@@ -34,24 +34,30 @@ def sampled_error(src, res, stride=7):
     return float(np.sqrt(e2 / a2))
 
 
+def record(name):
+    """The stored values of one workload, computed by the oracle."""
+    wl = make_config(name)
+    src = oracle.EntrySource(wl)
+    t = time.perf_counter()
+    res = oracle.hbaca(src, wl["m"], wl["n"], wl["tol"], wl["d"], wl["leaf"], wl["seed"])
+    el = time.perf_counter() - t
+    steps = [max(res.ranks[k]) for k in sorted(res.ranks)]
+    return dict(workload=name, m=wl["m"], n=wl["n"], tol=wl["tol"], d=wl["d"],
+                leaf=wl["leaf"], seed=wl["seed"], rank=int(res.rank),
+                step_rank_max=[int(x) for x in steps],
+                sigma=[float(x) for x in res.S],
+                rel_err_rows7=sampled_error(src, res),
+                oracle_seconds=el,
+                source="oracle.hbaca on workloads.make_config(%r)" % name)
+
+
 def main(names):
     for name in names:
-        wl = make_config(name)
-        src = oracle.EntrySource(wl)
-        t = time.perf_counter()
-        res = oracle.hbaca(src, wl["m"], wl["n"], wl["tol"], wl["d"], wl["leaf"], wl["seed"])
-        el = time.perf_counter() - t
-        steps = [max(res.ranks[k]) for k in sorted(res.ranks)]
-        out = dict(workload=name, m=wl["m"], n=wl["n"], tol=wl["tol"], d=wl["d"],
-                   leaf=wl["leaf"], seed=wl["seed"], rank=int(res.rank),
-                   step_rank_max=[int(x) for x in steps],
-                   sigma=[float(x) for x in res.S],
-                   rel_err_rows7=sampled_error(src, res),
-                   oracle_seconds=el,
-                   source="oracle.hbaca on workloads.make_config(%r)" % name)
+        out = record(name)
+        el = out["oracle_seconds"]
         with open(os.path.join(HERE, WORKLOADS[name]), "w") as f:
             json.dump(out, f, indent=1)
-        print(name, "rank", res.rank, "err", out["rel_err_rows7"], "time %.1fs" % el)
+        print(name, "rank", out["rank"], "err", out["rel_err_rows7"], "time %.1fs" % el)
 
 
 if __name__ == "__main__":
