@@ -240,6 +240,22 @@ hb_status hbaca_recompute_frozen(const hb_result* tape, const hb_params* params,
                                  const double* points_row, const double* points_col,
                                  void* stream, hb_result** out);
 
+/*
+ * The partition hbaca_compress uses (host only, no device work): the number
+ * of levels L (the smallest L with leaf 2^L >= max(m, n), lowered until
+ * 2^L <= min(m, n)) and, when the arrays are given, for every leaf
+ * b = t 2^L + v of the cluster trees (a node of size s splits into
+ * ceil(s/2) then floor(s/2), Algorithm 3):
+ *   leaves[4b .. 4b+3] = first row, rows, first column, columns;
+ *   j1[b d .. b d + d - 1] = its first column block J_1 (Algorithm 2), the
+ *   first min(d, n0) leaf-local columns of a partial Fisher-Yates shuffle
+ *   driven by SplitMix64 from seed + b * 0x632BE59BD9B4E019, then -1.
+ * Host arrays of 4^L * 4 and 4^L * d entries; either may be NULL (both
+ * NULL: only *L_out).  HB_EINVAL for m, n, leaf or d below 1.
+ */
+hb_status hb_partition(int64_t m, int64_t n, int32_t leaf, int32_t d, uint64_t seed,
+                       int32_t* L_out, int64_t* leaves, int32_t* j1);
+
 /* Statistics of the call (host struct). */
 hb_status hb_result_stats(const hb_result* res, hb_stats* out);
 

@@ -19,9 +19,26 @@ from ._binding import (HB_K_GAUSS, HB_K_HELMHOLTZ3D, HB_K_LAPLACE,  # noqa: F401
                        HbStats, load)
 
 __all__ = ["compress", "compress_batched", "Result", "operator", "gaussian_operator",
-           "require_gpu", "params", "load",
+           "partition", "require_gpu", "params", "load",
            "HBACAError", "HB_K_GAUSS", "HB_K_LAPLACE", "HB_K_HELMHOLTZ3D",
            "HB_K_LOWRANK_SPIKES", "HB_PREC_FP64", "HB_PREC_MIXED"]
+
+
+def partition(m: int, n: int, leaf: int, d: int, seed: int):
+    """The partition hbaca_compress uses (host only): (L, leaves, j1) with
+    leaves[b] = (first row, rows, first column, columns) and j1[b] the first
+    column block of leaf b = t 2^L + v (-1 past min(d, n0))."""
+    lib = load()
+    L = C.c_int32(0)
+    B._check(lib.hb_partition(int(m), int(n), int(leaf), int(d),
+                              int(seed) & ((1 << 64) - 1), C.byref(L), None, None), "hb_partition")
+    nl = 4 ** L.value
+    leaves = np.zeros((nl, 4), dtype=np.int64)
+    j1 = np.zeros((nl, int(d)), dtype=np.int32)
+    B._check(lib.hb_partition(int(m), int(n), int(leaf), int(d), int(seed) & ((1 << 64) - 1),
+                              C.byref(L), leaves.ctypes.data_as(C.c_void_p),
+                              j1.ctypes.data_as(C.c_void_p)), "hb_partition")
+    return L.value, leaves, j1
 
 
 def require_gpu():

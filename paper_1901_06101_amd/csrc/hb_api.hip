@@ -2303,6 +2303,40 @@ hb_status hbaca_apply(const hb_result* r, int64_t b, const void* in, void* out, 
 }
 
 
+hb_status hb_partition(int64_t m, int64_t n, int32_t leaf, int32_t d, uint64_t seed,
+                       int32_t* L_out, int64_t* leaves, int32_t* j1) {
+  if (m < 1 || n < 1 || leaf < 1 || d < 1 || !L_out) return HB_EINVAL;
+  const int L = tree_levels(m, n, leaf);
+  *L_out = L;
+  if (!leaves && !j1) return HB_OK;
+  try {
+    const auto rt = cluster_tree(m, L);
+    const auto ct = cluster_tree(n, L);
+    const int64_t nb = (int64_t)1 << L;
+    for (int64_t t = 0; t < nb; ++t)
+      for (int64_t v = 0; v < nb; ++v) {
+        const int64_t b = t * nb + v;
+        const Node& rn = rt[L][t];
+        const Node& cn = ct[L][v];
+        if (leaves) {
+          leaves[4 * b] = rn.off;
+          leaves[4 * b + 1] = rn.size;
+          leaves[4 * b + 2] = cn.off;
+          leaves[4 * b + 3] = cn.size;
+        }
+        if (j1) {
+          const int n0 = (int)cn.size;
+          const int q = std::min<int>(d, n0);
+          first_column_block(seed, (uint64_t)b, n0, d, j1 + b * d);
+          for (int k = q; k < d; ++k) j1[b * d + k] = -1;
+        }
+      }
+  } catch (const std::bad_alloc&) {
+    return HB_ENOMEM;
+  }
+  return HB_OK;
+}
+
 hb_status hbaca_recompute_frozen(const hb_result* tape, const hb_params* params,
                                  const double* points_row, const double* points_col, void* stream,
                                  hb_result** out) {
