@@ -139,10 +139,22 @@ def forward(fs, X=None, Y=None, h=None, nt=1):
 
 def build_tsan():
     """The stand-alone driver built with ThreadSanitizer."""
+    return _build_exe("adj_host_tsan", ["-fsanitize=thread"])
+
+
+def build_asan():
+    """The stand-alone driver built with AddressSanitizer and
+    UndefinedBehaviorSanitizer (host code only)."""
+    return _build_exe("adj_host_asan", ["-fsanitize=address,undefined",
+                                        "-fno-sanitize-recover=undefined",
+                                        "-fno-omit-frame-pointer"])
+
+
+def _build_exe(name, flags):
     os.makedirs(OUT, exist_ok=True)
-    exe = os.path.join(OUT, "adj_host_tsan")
-    cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=thread", "-pthread", "-DADJ_HOST_MAIN",
-           SRC, "-o", exe]
+    exe = os.path.join(OUT, name)
+    cmd = ["g++", "-std=c++20", "-O1", "-g", *flags, "-pthread", "-DADJ_HOST_MAIN", SRC, "-o",
+           exe]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     return exe
 
@@ -167,7 +179,8 @@ def run_exe(exe, fs, w, ybar, nt, workdir):
         np.asarray([wl["h"], wl.get("gauss_c", 1.0)], dtype=np.float64).tofile(f)
         np.asarray(w, dtype=np.float64).tofile(f)
         np.asarray(ybar, dtype=np.float64).tofile(f)
-    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66")
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66",
+               ASAN_OPTIONS="detect_leaks=1 exitcode=67")
     p = subprocess.run([exe, inp, out, str(nt)], capture_output=True, text=True, env=env,
                        timeout=900)
     if p.returncode != 0:

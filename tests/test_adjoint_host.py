@@ -130,6 +130,21 @@ def test_no_data_race_under_thread_sanitizer(tmp_path):
         assert np.max(np.abs(np.asarray(a) - np.asarray(r))) <= 1e-12 * max(1.0, np.max(np.abs(r)))
 
 
+def test_no_memory_error_under_address_sanitizer(tmp_path):
+    wl = G.make_gauss3d(n=200, m=180, h=0.7, leaf=50, tol=1e-6, d=8, cfg=52)
+    fs = adj.FrozenStructure(wl)
+    rng = np.random.default_rng(2)
+    w = rng.standard_normal(wl["n"])
+    yb = rng.standard_normal(wl["m"])
+    exe = AH.build_asan()
+    rc, err, outs = AH.run_exe(exe, fs, w, yb, 2, str(tmp_path))
+    assert rc == 0, err[-4000:]
+    assert "Sanitizer" not in err and "runtime error" not in err
+    ref = AH.vjp(fs, w, yb, nt=2)
+    for a, r in zip(outs, ref):
+        assert np.max(np.abs(np.asarray(a) - np.asarray(r))) <= 1e-12 * max(1.0, np.max(np.abs(r)))
+
+
 def test_planner_rejects_inconsistent_structures(case):
     fs, w, b = case
     yb = np.zeros(fs.wl["m"])
