@@ -200,3 +200,56 @@ def test_merges_wider_than_tall():
     assert abs(hh - gh) <= 1e-10 * abs(gh)
     assert _rel(hX, gX) <= 1e-10
     assert _rel(hY, gY) <= 1e-10
+
+
+def test_adjoint_reference_size_checks():
+    """The differentiation workload's reference size (its geometry at n =
+    2000, leaf 250, L = 3): the host-built adjoint against the frozen
+    oracle, against central differences (step 1e-4, FP64) of the host-built
+    frozen map in h, along a random direction over all points and in six
+    random coordinates, and the gap to the exact dense gradient."""
+    wl = G.make_gauss3d(n=2000, h=0.7, leaf=250, tol=1e-6, d=8, cfg=5)
+    fs = adj.FrozenStructure(wl)
+    assert fs.L == 3
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal(wl["n"])
+    b = rng.standard_normal(wl["m"])
+    _, gw, gh, gX, gY = adj.frozen_gradients(fs, w, b)
+    yb = _ybar(fs, w, b)
+    hw, hh, hX, hY = AH.vjp(fs, w, yb, nt=1)
+    assert _rel(hw, gw) <= 1e-10
+    assert abs(hh - gh) <= 1e-10 * abs(gh)
+    assert _rel(hX, gX) <= 1e-10
+    assert _rel(hY, gY) <= 1e-10
+
+    def f(X=None, Y=None, h=None):
+        U, S, Vt = AH.forward(fs, X, Y, h)
+        return float(yb @ (U @ (S * (Vt.T @ w))))
+
+    step = 1e-4
+    h = wl["h"]
+    fd = (f(h=h + step) - f(h=h - step)) / (2 * step)
+    assert abs(fd - hh) <= 1e-5 * abs(hh)
+    X, Y = wl["X"], wl["Y"]
+    PX = rng.standard_normal(X.shape)
+    PY = rng.standard_normal(Y.shape)
+    fd = (f(X + step * PX, Y + step * PY) - f(X - step * PX, Y - step * PY)) / (2 * step)
+    an = float(np.sum(hX * PX) + np.sum(hY * PY))
+    assert abs(fd - an) <= 1e-5 * abs(an)
+    scale = max(np.max(np.abs(hX)), np.max(np.abs(hY)))
+    for _ in range(3):
+        for side, G_, P_ in ((0, hX, X), (1, hY, Y)):
+            i = int(rng.integers(P_.shape[0]))
+            q = int(rng.integers(P_.shape[1]))
+            E = np.zeros(P_.shape)
+            E[i, q] = step
+            if side == 0:
+                fd = (f(X + E, Y) - f(X - E, Y)) / (2 * step)
+            else:
+                fd = (f(X, Y + E) - f(X, Y - E)) / (2 * step)
+            assert abs(fd - G_[i, q]) <= 1e-5 * max(abs(G_[i, q]), 1e-3 * scale)
+    # the frozen map against the exact dense loss: the truncation level
+    _, dw, dh, dX, dY = adj.dense_gradients(wl, w, b)
+    assert abs(hh - dh) <= 1e-3 * abs(dh)
+    for a, r in ((hw, dw), (hX, dX), (hY, dY)):
+        assert _rel(a, r) <= 1e-3

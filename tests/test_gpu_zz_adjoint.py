@@ -118,6 +118,66 @@ def test_recompute_frozen_and_central_differences(lib):
     assert abs(fd - an) <= 1e-8 * abs(an)
 
 
+def test_reference_size_checks(lib):
+    """n = 2000, leaf 250 (the differentiation workload's reference size):
+    against the frozen oracle (1e-8), central differences of
+    hbaca_recompute_frozen with step 1e-4 in FP64 (1e-5) on h, one random
+    direction over all points and 20 random coordinates, and the exact
+    dense gradient (1e-3)."""
+    import torch
+    wl = G.make_gauss3d(n=2000, h=0.7, leaf=250, tol=1e-6, d=8, cfg=5)
+    say("[vjp reference] 2000 x 2000, leaf 250")
+    fs = adj.FrozenStructure(wl)
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal(wl["n"])
+    b = rng.standard_normal(wl["m"])
+    _, gw, gh, gX, gY = adj.frozen_gradients(fs, w, b)
+    res = run_gpu(lib, wl, record_tape=2)
+    wd = torch.tensor(w, device="cuda")
+    yb = 2.0 * (res.apply(wd) - torch.tensor(b, device="cuda"))
+    hw, hh, hX, hY = res.vjp(wd, yb)
+    assert _rel(hw.cpu().numpy(), gw) <= 1e-8
+    assert abs(hh.item() - gh) <= 1e-8 * abs(gh)
+    assert _rel(hX.cpu().numpy(), gX) <= 1e-8
+    assert _rel(hY.cpu().numpy(), gY) <= 1e-8
+    X = torch.tensor(wl["X"], device="cuda")
+    Y = torch.tensor(wl["Y"], device="cuda")
+    c = wl.get("gauss_c", 1.0)
+
+    def f(Xp, Yp, hp):
+        r = res.recompute_frozen(Xp, Yp, hp, c)
+        return torch.dot(yb, r.apply(wd)).item()
+
+    step = 1e-4
+    h = float(wl["h"])
+    fd = (f(X, Y, h + step) - f(X, Y, h - step)) / (2 * step)
+    assert abs(fd - hh.item()) <= 1e-5 * abs(hh.item())
+    PX = torch.tensor(rng.standard_normal(wl["X"].shape), device="cuda")
+    PY = torch.tensor(rng.standard_normal(wl["Y"].shape), device="cuda")
+    fd = (f(X + step * PX, Y + step * PY, h) - f(X - step * PX, Y - step * PY, h)) / (2 * step)
+    an = (torch.sum(hX * PX) + torch.sum(hY * PY)).item()
+    assert abs(fd - an) <= 1e-5 * abs(an)
+    scale = max(hX.abs().max().item(), hY.abs().max().item())
+    for _ in range(10):
+        for side, G_, P_ in ((0, hX, X), (1, hY, Y)):
+            i = int(rng.integers(P_.shape[0]))
+            q = int(rng.integers(P_.shape[1]))
+            E = torch.zeros_like(P_)
+            E[i, q] = step
+            if side == 0:
+                fd = (f(X + E, Y, h) - f(X - E, Y, h)) / (2 * step)
+            else:
+                fd = (f(X, Y + E, h) - f(X, Y - E, h)) / (2 * step)
+            g = G_[i, q].item()
+            assert abs(fd - g) <= 1e-5 * max(abs(g), 1e-3 * scale)
+    _, dw, dh, dX, dY = adj.dense_gradients(wl, w, b)
+    say(f"  gap to the dense gradient: h {abs(hh.item() - dh) / abs(dh):.1e}, "
+        f"X {_rel(hX.cpu().numpy(), dX):.1e}, Y {_rel(hY.cpu().numpy(), dY):.1e}")
+    assert abs(hh.item() - dh) <= 1e-3 * abs(dh)
+    assert _rel(hX.cpu().numpy(), dX) <= 1e-3
+    assert _rel(hY.cpu().numpy(), dY) <= 1e-3
+
+
 def test_vjp_rejects_results_without_frozen_structure(lib):
     import torch
     wl = CASES["gauss3d_400x360"]()
