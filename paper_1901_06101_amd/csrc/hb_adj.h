@@ -38,6 +38,9 @@
 #include <math.h>
 #include <stdint.h>
 
+// hipcc compiles these tasks for the GPU (hb_adjoint.hip).  The tests also
+// compile them for the host, one thread per lane, to check them against
+// the oracle; the library itself has no host path.
 #if defined(__HIPCC__)
 #define HBA_FN __device__ inline
 #else
