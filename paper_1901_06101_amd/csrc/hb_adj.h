@@ -166,11 +166,29 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
       for (int64_t i = w.tid; i < m; i += w.nt) Q[i + j * ldq] = A[i + j * lda];
     for (int e = w.tid; e < k; e += w.nt) R[e + j * ldr] = 0.0;
     w.sync();
+    // g lanes share each of the j dot products (rows interleaved) when
+    // j <= nt / 2; their partial sums meet in red
+    const int g = j > 0 && w.nt / j >= 2 ? w.nt / j : 1;
     for (int pass = 0; pass < 2; ++pass) {
-      for (int i = w.tid; i < j; i += w.nt) {
-        double s = 0.0;
-        for (int64_t l = 0; l < m; ++l) s += Q[l + i * ldq] * Q[l + j * ldq];
-        h[i] = s;
+      if (g == 1) {
+        for (int i = w.tid; i < j; i += w.nt) {
+          double s = 0.0;
+          for (int64_t l = 0; l < m; ++l) s += Q[l + i * ldq] * Q[l + j * ldq];
+          h[i] = s;
+        }
+      } else {
+        if (w.tid < j * g) {
+          const int i = w.tid % j, c = w.tid / j;
+          double s = 0.0;
+          for (int64_t l = c; l < m; l += g) s += Q[l + i * ldq] * Q[l + j * ldq];
+          w.red[w.tid] = s;
+        }
+        w.sync();
+        for (int i = w.tid; i < j; i += w.nt) {
+          double s = 0.0;
+          for (int c = 0; c < g; ++c) s += w.red[i + c * j];
+          h[i] = s;
+        }
       }
       w.sync();
       for (int64_t l = w.tid; l < m; l += w.nt) {
