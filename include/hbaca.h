@@ -279,6 +279,24 @@ hb_status hb_result_leaf_tape(const hb_result* res, int64_t leaf, int32_t* rows,
                               int32_t* dk, double* nu, double* mu);
 
 /*
+ * Frozen structure of a result compressed with record_tape = 2 (host):
+ * *stride = ints per iteration record; records (host, iterations x stride
+ * int32, may be NULL) receives, per iteration of the leaf, nI, nJ, d_k,
+ * then I_k (DMAX slots), J_k (DMAX slots) and the pivot order of
+ * QR(W_k, eps) (DMAX slots), DMAX = (stride - 3) / 3.  HB_EINVAL if the
+ * result holds no frozen structure.
+ */
+hb_status hb_result_leaf_frozen(const hb_result* res, int64_t leaf, int32_t* stride,
+                                int32_t* records);
+/*
+ * Every merge rank of a whole-pipeline result with a frozen structure
+ * (host): for l = 1..L the horizontal merges of the level (block (ti, v)
+ * of the 2^(L-l+1) x 2^(L-l) grid, ti-major), then its vertical merges
+ * (block (t, v), t-major).  *count receives the number; ranks may be NULL.
+ */
+hb_status hb_result_merge_ranks(const hb_result* res, int32_t* ranks, int64_t* count);
+
+/*
  * Untimed check: sum over rows i = 0, stride, 2 stride, ... of
  * |A(i,j) - (U diag(sigma) Vh^H)(i,j)|^2 and of |A(i,j)|^2, every column j,
  * with A re-evaluated on the device in FP64 (host outputs).  The problem's

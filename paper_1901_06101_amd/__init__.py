@@ -175,6 +175,29 @@ class Result:
             mu.ctypes.data_as(C.c_void_p)), "hb_result_leaf_tape")
         return dict(rows=rows[:n], cols=cols[:n], dk=dk[:it], nu=nu[:it], mu=mu[:it])
 
+    def leaf_frozen(self, leaf):
+        """Iteration records of one leaf (record_tape=2): int32 array of
+        shape (iterations, stride), see hb_result_leaf_frozen."""
+        stride = C.c_int32(0)
+        B._check(self._lib.hb_result_leaf_frozen(self._h, leaf, C.byref(stride), None),
+                 "hb_result_leaf_frozen")
+        it = self.leaf_info(leaf)["iters"]
+        rec = np.zeros((max(it, 1), stride.value), dtype=np.int32)
+        B._check(self._lib.hb_result_leaf_frozen(self._h, leaf, C.byref(stride),
+                                                 rec.ctypes.data_as(C.c_void_p)),
+                 "hb_result_leaf_frozen")
+        return rec[:it]
+
+    def merge_ranks(self):
+        """Every merge rank (record_tape=2), in hb_result_merge_ranks order."""
+        n = C.c_int64(0)
+        B._check(self._lib.hb_result_merge_ranks(self._h, None, C.byref(n)),
+                 "hb_result_merge_ranks")
+        out = np.zeros(max(n.value, 1), dtype=np.int32)
+        B._check(self._lib.hb_result_merge_ranks(self._h, out.ctypes.data_as(C.c_void_p),
+                                                 C.byref(n)), "hb_result_merge_ranks")
+        return out[:n.value]
+
     def apply(self, w, block=0, adjoint=False):
         """U diag(S) Vh^H w (adjoint=False) or Vh diag(S) U^H w (adjoint=True)
         for a device vector w; returns a new device vector."""

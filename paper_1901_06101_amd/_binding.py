@@ -23,7 +23,7 @@ EXPORTED = (
     "hb_result_rows", "hb_result_cols", "hb_result_is_complex", "hb_result_copy",
     "hb_result_stats", "hb_result_nleaves", "hb_result_leaf_info", "hb_result_leaf_tape",
     "hb_result_error", "hb_result_free", "hb_status_string", "hbaca_apply", "hbaca_vjp",
-    "hbaca_recompute_frozen", "hb_partition",
+    "hbaca_recompute_frozen", "hb_partition", "hb_result_leaf_frozen", "hb_result_merge_ranks",
 )
 
 
@@ -130,6 +130,10 @@ def load(path: str = LIB_PATH):
     lib.hbaca_recompute_frozen.restype = C.c_int
     lib.hb_partition.argtypes = [i64, i64, i32, i32, C.c_uint64, C.POINTER(i32), vp, vp]
     lib.hb_partition.restype = C.c_int
+    lib.hb_result_leaf_frozen.argtypes = [vp, i64, C.POINTER(i32), vp]
+    lib.hb_result_leaf_frozen.restype = C.c_int
+    lib.hb_result_merge_ranks.argtypes = [vp, vp, C.POINTER(i64)]
+    lib.hb_result_merge_ranks.restype = C.c_int
     lib.hb_result_free.argtypes = [vp]
     lib.hb_result_free.restype = None
     lib.hb_status_string.argtypes = [C.c_int]

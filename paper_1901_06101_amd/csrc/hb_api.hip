@@ -2413,6 +2413,34 @@ hb_status hb_result_leaf_tape(const hb_result* r, int64_t leaf, int32_t* rows, i
   return HB_OK;
 }
 
+hb_status hb_result_leaf_frozen(const hb_result* r, int64_t leaf, int32_t* stride,
+                                int32_t* records) {
+  if (!r || !stride || leaf < 0 || leaf >= (int64_t)r->leaves.size()) return HB_EINVAL;
+  const LeafHost& L = r->leaves[leaf];
+  if (r->fz_stride == 0 || L.fz.size() != (size_t)L.iters * (size_t)r->fz_stride)
+    return HB_EINVAL;
+  *stride = r->fz_stride;
+  if (records && !L.fz.empty()) std::memcpy(records, L.fz.data(), L.fz.size() * 4);
+  return HB_OK;
+}
+
+hb_status hb_result_merge_ranks(const hb_result* r, int32_t* ranks, int64_t* count) {
+  if (!r || !count || !r->fz_complete) return HB_EINVAL;
+  int64_t n = 0;
+  for (size_t l = 0; l < r->fz_hrank.size(); ++l) {
+    for (int v : r->fz_hrank[l]) {
+      if (ranks) ranks[n] = v;
+      ++n;
+    }
+    for (int v : r->fz_vrank[l]) {
+      if (ranks) ranks[n] = v;
+      ++n;
+    }
+  }
+  *count = n;
+  return HB_OK;
+}
+
 hb_status hb_result_error(const hb_result* r, int64_t b, int64_t stride, double* err2, double* ref2,
                           void* stream) {
   if (!r || !err2 || !ref2 || stride < 1 || b < 0 || b >= (int64_t)r->out_blocks.size())

@@ -118,3 +118,28 @@ def compare_tape(gtape, ginfo, oinfo):
     if nk == len(odk) and (len(gdk) != len(odk) or ginfo["rank_baca"] != oinfo["rank_baca"]):
         return f"iteration count differs: gpu {gdk} oracle {odk}"
     return None
+
+
+def check_mixed(lib, case, wl):
+    """Mixed precision against the FP64 oracle on the same inputs: operator
+    difference and error against A within 5 tol, ranks close."""
+    tol = wl["tol"]
+    say(f"[mixed] {case}: m={wl['m']} n={wl['n']} d={wl['d']} leaf={wl['leaf']} tol={tol}")
+    res = run_gpu(lib, wl, precision=lib.HB_PREC_MIXED)
+    src, ores = run_oracle(wl)
+    U, S, Vh = factors_np(res)
+    assert U.dtype == np.float64 and Vh.dtype == np.float64
+    ref = recon_norm(ores.U * ores.S, ores.V.conj().T)
+    diff = lowrank_diff(U * S, Vh, ores.U * ores.S, ores.V.conj().T)
+    A = src.dense()
+    nA = np.linalg.norm(A)
+    eg = np.linalg.norm(A - (U * S) @ Vh.T) / nA
+    eo = np.linalg.norm(A - ores.dense()) / nA
+    say(f"  rank mixed {S.size} oracle {ores.rank}; operator difference {diff / ref:.2e}; "
+        f"error mixed {eg:.2e} oracle {eo:.2e}")
+    assert diff <= 5 * tol * ref
+    assert eg <= eo + 5 * tol
+    assert abs(S.size - ores.rank) <= max(3, ores.rank // 10)
+    # the device error check sees the same error
+    e2, a2 = res.error(0, 1)
+    assert abs(np.sqrt(e2 / a2) - eg) <= 1e-6 * eg + 1e-12

@@ -142,6 +142,18 @@ int adj_host_vjp(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stride,
   return 0;
 }
 
+// The plan alone: the arena size in doubles (workspace included).
+int adj_host_plan_size(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stride,
+                       const int64_t* leaf_info, const int32_t* recs, const int32_t* ranks,
+                       int64_t* arena, int64_t* ws) {
+  AdjPlan P;
+  const int st = make_plan(m, n, L, dim, dmax, fz_stride, leaf_info, recs, ranks, P);
+  if (st != 0) return st;
+  *arena = P.arena;
+  *ws = P.ws_size;
+  return 0;
+}
+
 // The frozen operator alone (the forward tasks): its root rank in *rank,
 // and, when the buffers hold cap columns, U (m x rank), S and Vt (n x rank).
 int adj_host_forward(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stride,

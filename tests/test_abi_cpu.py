@@ -92,5 +92,9 @@ def test_result_accessors_reject_null():
     assert lib.hbaca_vjp(None, None, None, None, None, None, None, None) == -1
     out = C.c_void_p(1234)
     assert lib.hbaca_recompute_frozen(None, None, None, None, None, C.byref(out)) == -1
+    stride = C.c_int32(0)
+    count = C.c_int64(0)
+    assert lib.hb_result_leaf_frozen(None, 0, C.byref(stride), None) == -1
+    assert lib.hb_result_merge_ranks(None, None, C.byref(count)) == -1
     assert out.value is None
     lib.hb_result_free(None)

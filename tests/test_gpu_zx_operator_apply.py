@@ -8,8 +8,7 @@ from workloads import generators as G
 
 from _hbtest import run_gpu, say
 
-pytestmark = [pytest.mark.gpu, pytest.mark.skip(
-    reason="hbaca_apply has not run on a GPU yet")]
+pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("name", ["gauss3d", "helmholtz"])

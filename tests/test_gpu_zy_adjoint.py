@@ -1,19 +1,39 @@
 """Frozen-pivot adjoint on the GPU (hbaca_vjp and gaussian_operator) against
-the adjoint oracle (oracle/adjoint.py): the GPU forward run's pivots and
-ranks are the oracle's (the parity tests compare the pivot tapes), so the
-gradients of <ybar, A~ w> with respect to w, h and the points must agree to
-FP64 rounding of the two replays."""
+the adjoint oracle (oracle/adjoint.py).  The GPU forward run's frozen
+structure (every I_k, J_k, pivot order, d_k and merge rank) is first checked
+equal to the oracle's; with the same structure the gradients of
+<ybar, A~ w> with respect to w, h and the points agree to FP64 rounding of
+the two replays.  The task code itself is checked on the CPU by
+tests/test_adjoint_host.py."""
 import numpy as np
 import pytest
 
 from oracle import adjoint as adj
 from workloads import generators as G
 
+from _adjhost import records_from_oracle
 from _hbtest import run_gpu, say
 
-pytestmark = [pytest.mark.gpu, pytest.mark.skip(
-    reason="hbaca_vjp has not run on a GPU yet; its tasks are checked on the CPU by "
-           "tests/test_adjoint_host.py")]
+pytestmark = pytest.mark.gpu
+
+
+def _same_structure(res, fs):
+    """The GPU run recorded the oracle's pivots, d_k and ranks."""
+    li, recs, ranks, dm, stride = records_from_oracle(fs)
+    for b in range(li.shape[0]):
+        g = res.leaf_frozen(b)
+        o = recs.reshape(-1, stride)[li[b, 6]:li[b, 6] + li[b, 4]]
+        assert g.shape[0] == o.shape[0], (b, g.shape, o.shape)
+        assert g.shape[1] == stride
+        for k in range(o.shape[0]):
+            nI, nJ, dk = (int(x) for x in o[k, :3])
+            assert tuple(g[k, :3]) == (nI, nJ, dk), (b, k)
+            assert np.array_equal(g[k, 3:3 + nI], o[k, 3:3 + nI]), (b, k)
+            assert np.array_equal(g[k, 3 + dm:3 + dm + nJ], o[k, 3 + dm:3 + dm + nJ]), (b, k)
+            assert np.array_equal(g[k, 3 + 2 * dm:3 + 2 * dm + dk],
+                                  o[k, 3 + 2 * dm:3 + 2 * dm + dk]), (b, k)
+        assert res.leaf_info(b)["rank_leaf"] == li[b, 5], b
+    assert np.array_equal(res.merge_ranks(), ranks)
 
 
 def _rel(a, r):
@@ -40,6 +60,7 @@ def test_vjp_matches_frozen_oracle(lib, name):
     _, gw, gh, gX, gY = adj.frozen_gradients(fs, w, b)
     res = run_gpu(lib, wl, record_tape=2)
     assert res.rank() == fs.res.rank
+    _same_structure(res, fs)
     wd = torch.tensor(w, device="cuda")
     yb = 2.0 * (res.apply(wd) - torch.tensor(b, device="cuda"))
     hw, hh, hX, hY = res.vjp(wd, yb)
@@ -133,6 +154,7 @@ def test_reference_size_checks(lib):
     b = rng.standard_normal(wl["m"])
     _, gw, gh, gX, gY = adj.frozen_gradients(fs, w, b)
     res = run_gpu(lib, wl, record_tape=2)
+    _same_structure(res, fs)
     wd = torch.tensor(w, device="cuda")
     yb = 2.0 * (res.apply(wd) - torch.tensor(b, device="cuda"))
     hw, hh, hX, hY = res.vjp(wd, yb)
