@@ -309,6 +309,8 @@ def gaussian_operator(X, Y, h, w, tol: float, d: int, leaf: int, gauss_c: float 
             gw, gh, gX, gY = ctx.res.vjp(wd, ybar, want=want)
             return gX, gY, (gh.reshape(ctx.h_shape) if gh is not None else None), gw
 
+    if not isinstance(h, torch.Tensor):
+        h = torch.as_tensor(float(h), dtype=torch.float64, device=X.device)
     return _GaussApply.apply(X, Y, h, w)
 
 
