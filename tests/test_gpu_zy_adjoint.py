@@ -269,7 +269,13 @@ def test_vjp_full_size_adjoint_geometry(lib):
     g = torch.Generator(device="cuda").manual_seed(5)
     wd = torch.randn(wl["n"], dtype=torch.float64, device="cuda", generator=g)
     yb = torch.randn(wl["m"], dtype=torch.float64, device="cuda", generator=g)
+    import time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     hw, hh, hX, hY = res.vjp(wd, yb)
+    torch.cuda.synchronize()
+    say(f"  rank {res.rank()}, forward {res.stats()['ms_total']:.1f} ms, "
+        f"hbaca_vjp {1e3 * (time.perf_counter() - t0):.1f} ms")
     ref = res.apply(yb, adjoint=True)
     sig1 = res.factors(0)[1][0].item()
     assert torch.linalg.norm(hw - ref).item() <= 1e-10 * sig1 * torch.linalg.norm(yb).item()
