@@ -24,10 +24,10 @@ def test_apply_and_adjoint_match_factor_products(lib, name):
     z = torch.randn(wl["m"], dtype=torch.float64, device="cuda", generator=g).to(dt)
     y = res.apply(w)
     y_ref = U @ (S.to(dt) * (Vh.conj().T @ w))
-    assert torch.allclose(y, y_ref, rtol=0, atol=1e-12 * y_ref.abs().max().item())
+    assert torch.allclose(y, y_ref, rtol=0, atol=1e-11 * y_ref.abs().max().item())
     wt = res.apply(z, adjoint=True)
     wt_ref = Vh @ (S.to(dt) * (U.conj().T @ z))
-    assert torch.allclose(wt, wt_ref, rtol=0, atol=1e-12 * wt_ref.abs().max().item())
+    assert torch.allclose(wt, wt_ref, rtol=0, atol=1e-11 * wt_ref.abs().max().item())
     # <A w, z> = <w, A^H z>, to rounding relative to the norms involved
     lhs = torch.vdot(z, y).item()
     rhs = torch.vdot(wt, w).item()
