@@ -105,6 +105,22 @@ def test_host_vjp_matches_central_differences_of_host_forward(case):
     assert np.linalg.norm(gw - Vt @ (S * (U.T @ yb))) <= 1e-12 * np.linalg.norm(gw)
 
 
+def test_host_tasks_single_leaf():
+    # L = 0: the root is the re-compressed leaf, no merge
+    wl = G.make_gauss3d(n=120, m=100, h=0.7, leaf=250, tol=1e-6, d=8, cfg=55)
+    fs = adj.FrozenStructure(wl)
+    assert fs.L == 0
+    rng = np.random.default_rng(55)
+    w = rng.standard_normal(wl["n"])
+    b = rng.standard_normal(wl["m"])
+    _, gw, gh, gX, gY = adj.frozen_gradients(fs, w, b)
+    hw, hh, hX, hY = AH.vjp(fs, w, _ybar(fs, w, b), nt=4)
+    assert _rel(hw, gw) <= 1e-10
+    assert abs(hh - gh) <= 1e-10 * abs(gh)
+    assert _rel(hX, gX) <= 1e-10
+    assert _rel(hY, gY) <= 1e-10
+
+
 def test_host_tasks_block_size_32():
     # the largest block size (32 rows and columns per iteration), tol 1e-7
     wl = G.make_gauss3d(n=600, m=520, h=0.8, leaf=150, tol=1e-7, d=32, cfg=54)
