@@ -94,10 +94,21 @@ def comparisons(steps=5, warmup=1):
     m_ms, m_res = timed(lambda: single(hb.HB_PREC_MIXED), steps, warmup)
     _note(f"comparisons: gauss3d mixed {m_ms:.1f} ms")
     ef, em = rel_err(f_res), rel_err(m_res)
+
+    def operator_rel_diff(a, b):
+        # ||Ua Sa Va^T - Ub Sb Vb^T||_F / ||Ua Sa Va^T||_F from the factors
+        Ua, Sa, Va = a.factors(0)
+        Ub, Sb, Vb = b.factors(0)
+        Qu, Ru = torch.linalg.qr(torch.cat([Ua, Ub], dim=1))
+        Qv, Rv = torch.linalg.qr(torch.cat([Va, Vb], dim=1))
+        M = Ru @ torch.diag(torch.cat([Sa, -Sb])) @ Rv.T
+        return float(torch.linalg.norm(M) / torch.linalg.norm(Sa))
+
     out["mixed_vs_fp64"] = dict(
         workload=f"gauss3d {wl['m']}x{wl['n']} tol={wl['tol']} d={wl['d']} leaf={wl['leaf']}",
         fp64_ms=f_ms, mixed_ms=m_ms, speedup=f_ms / m_ms, fp64_rank=f_res.rank(0),
         mixed_rank=m_res.rank(0), fp64_rel_err_rows7=ef, mixed_rel_err_rows7=em,
+        mixed_vs_fp64_operator_rel_diff=operator_rel_diff(f_res, m_res),
         mixed_within_5tol=bool(em <= 5 * wl["tol"]))
     f_res.close()
     m_res.close()
