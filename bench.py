@@ -156,6 +156,27 @@ def comparisons(steps=5, warmup=1):
     print(json.dumps(out), flush=True)
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate in GB/s (bytes read plus bytes written),
+    the measured counterpart of the HBM peak."""
+    try:
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b) / reps
+        del src, dst
+        return 2.0 * nbytes / (ms * 1e-3) / 1e9
+    except Exception:
+        return None
+
+
 def _note(msg):
     """Progress of the run on stderr (stdout carries only the JSON line)."""
     print(f"bench: {msg}", file=sys.stderr, flush=True)
@@ -247,6 +268,9 @@ def main():
                     traffic=None,
                     algorithmic_bytes_per_launch=st["resid_bytes"],
                     launch_ms=ms_baca)
+    copy = copy_bandwidth(torch)
+    roofline["copy_GBps_measured"] = copy
+    roofline["frac_of_copy"] = achieved / copy if copy else None
     phases = {k: float(np.mean([s[k] for s in stats])) for k in
               ("ms_setup", "ms_baca", "ms_recompress", "ms_merge", "ms_total")}
     out = {
