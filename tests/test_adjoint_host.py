@@ -5,7 +5,7 @@ oracle (oracle/adjoint.py) on the same pivots and ranks.
 
 This checks the device code's arithmetic, indexing and barrier placement
 on the CPU; the library itself has no host path and its GPU run is checked
-by tests/test_gpu_zz_adjoint.py."""
+by tests/test_gpu_zy_adjoint.py."""
 import numpy as np
 import pytest
 import torch
