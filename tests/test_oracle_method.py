@@ -107,7 +107,7 @@ def test_interpolation_on_selected_columns(kind):
 
 
 # ---------------------------------------------------------------- P2, P3 ---
-@pytest.mark.parametrize("r0", [1, 7, 30])
+@pytest.mark.parametrize("r0", [1, 7, 30, 64])
 @pytest.mark.parametrize("leaf", [200, 60])
 def test_exact_recovery_of_low_rank_products(r0, leaf):
     m = n = 200
