@@ -121,6 +121,22 @@ def test_host_tasks_single_leaf():
     assert _rel(hY, gY) <= 1e-10
 
 
+def test_host_tasks_eight_dimensional_points():
+    # the 8-D mixture: the largest point dimension and c = 2 in the Gaussian
+    wl = G.make_gauss_mixture(n=600, leaf=150, tol=1e-5, d=16, cfg=72)
+    fs = adj.FrozenStructure(wl)
+    assert wl["X"].shape[1] == 8 and wl["gauss_c"] == 2.0
+    rng = np.random.default_rng(9)
+    w = rng.standard_normal(wl["n"])
+    b = rng.standard_normal(wl["m"])
+    _, gw, gh, gX, gY = adj.frozen_gradients(fs, w, b)
+    hw, hh, hX, hY = AH.vjp(fs, w, _ybar(fs, w, b), nt=4)
+    assert _rel(hw, gw) <= 1e-10
+    assert abs(hh - gh) <= 1e-10 * abs(gh)
+    assert _rel(hX, gX) <= 1e-10
+    assert _rel(hY, gY) <= 1e-10
+
+
 def test_host_tasks_block_size_32():
     # the largest block size (32 rows and columns per iteration), tol 1e-7
     wl = G.make_gauss3d(n=600, m=520, h=0.8, leaf=150, tol=1e-7, d=32, cfg=54)
