@@ -273,6 +273,17 @@ def main():
     roofline["frac_of_copy"] = achieved / copy if copy else None
     phases = {k: float(np.mean([s[k] for s in stats])) for k in
               ("ms_setup", "ms_baca", "ms_recompress", "ms_merge", "ms_total")}
+    # the other kernel classes against the FP64 peak: algorithmic flops of
+    # the leaf residual passes, the re-compression and the merges (the
+    # library's counters) over each phase's device time
+    phase_rates = {}
+    for name, flops, ms in (("leaf_residuals", st["resid_flops"], phases["ms_baca"]),
+                            ("recompression", st["recompress_flops"], phases["ms_recompress"]),
+                            ("merges", st["merge_flops"], phases["ms_merge"])):
+        tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else None
+        phase_rates[name] = dict(flops=flops, ms=ms, achieved_TFLOPs=tf,
+                                 peak_TFLOPs=FP64_PEAK_TFLOPS,
+                                 frac=(tf / FP64_PEAK_TFLOPS) if tf is not None else None)
     out = {
         "metric": METRIC,
         "value": ms,
@@ -294,6 +305,7 @@ def main():
         "rel_err_rows7": rel_err,
         "phases_ms": phases,
         "roofline": roofline,
+        "phase_rates": phase_rates,
     }
     last.close()
     _note(f"{wl['name']}: {ms:.2f} ms per compress")

@@ -124,6 +124,13 @@ typedef struct {
   double resid_flops;        /* 2 phi d r (m0 + n0) summed over iterations */
   int32_t svd_sweeps_max;    /* most Jacobi sweeps taken by one small SVD */
   int32_t pad;
+  /* algorithmic flops (real arithmetic; complex counts 4 per product) of
+     the re-compression and of the merges: thin QR of an m x k factor
+     2 phi m k^2, applying its Q to k x r singular vectors 2 phi m k r, the
+     block product of the other side 2 phi r (r1 n1 + r2 n2); the small SVDs
+     are not counted */
+  double recompress_flops;
+  double merge_flops;
 } hb_stats;
 
 /*

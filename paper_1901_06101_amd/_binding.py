@@ -70,6 +70,8 @@ class HbStats(C.Structure):
         ("resid_flops", C.c_double),
         ("svd_sweeps_max", C.c_int32),
         ("pad", C.c_int32),
+        ("recompress_flops", C.c_double),
+        ("merge_flops", C.c_double),
     ]
 
     def as_dict(self):

@@ -1264,6 +1264,18 @@ static void run_merges_caqr(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_
   }
 }
 
+// Algorithmic flops of a batch of merges (see hb_stats::merge_flops).
+static double merge_job_flops(const std::vector<MergeJob>& jobs, int scalar) {
+  const double phi = scalar ? 4.0 : 1.0;
+  double f = 0.0;
+  for (const MergeJob& J : jobs) {
+    const double k = (double)J.r1 + J.r2, r = J.outP_owner ? J.outP_owner->r : 0;
+    f += 2.0 * phi * (double)J.rows * k * k + 2.0 * phi * (double)J.rows * k * r +
+         2.0 * phi * r * ((double)J.r1 * J.n1 + (double)J.r2 * J.n2);
+  }
+  return f;
+}
+
 static void run_merges(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_mem) {
   const int kcap = E.kcap();
   std::vector<MergeJob> direct, split;
@@ -1820,6 +1832,14 @@ static hb_status run(const CallSpec& c, hb_result** out) {
     for (size_t i = 0; i < nleaves; ++i)
       rj.push_back(RecJob{leafblk[i].U, leafblk[i].Vh, leafblk[i].m, leafblk[i].n, leafblk[i].r, &cur[i]});
     run_recompress(Eng, rj, lvl_mem);
+    {
+      const double phi = scalar ? 4.0 : 1.0;
+      for (size_t i = 0; i < nleaves; ++i) {
+        const double rb = leafblk[i].r, rho = cur[i].r;
+        const double mn = (double)leafblk[i].m + (double)leafblk[i].n;
+        S.recompress_flops += 2.0 * phi * mn * rb * rb + 2.0 * phi * mn * rb * rho;
+      }
+    }
     baca_mem.release();
     cvt_mem.release();
     HB_HIP(hipEventRecord(ev[3], st));
@@ -1876,6 +1896,7 @@ static hb_status run(const CallSpec& c, hb_result** out) {
             }
         }
         run_merges(Eng, jobs, *hm);
+        S.merge_flops += merge_job_flops(jobs, scalar);
         int mx = 0;
         for (auto& J : jobs) mx = std::max(mx, J.outP_owner->r);
         if (frozen && np == 1) {
@@ -1923,6 +1944,7 @@ static hb_status run(const CallSpec& c, hb_result** out) {
             }
         }
         run_merges(Eng, jobs, *vm);
+        S.merge_flops += merge_job_flops(jobs, scalar);
         mx = 0;
         for (auto& J : jobs) mx = std::max(mx, J.outP_owner->r);
         if (frozen && np == 1) {

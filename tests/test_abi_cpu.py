@@ -98,3 +98,31 @@ def test_result_accessors_reject_null():
     assert lib.hb_result_merge_ranks(None, None, C.byref(count)) == -1
     assert out.value is None
     lib.hb_result_free(None)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures have the header's sizes and field
+    offsets (compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    from paper_1901_06101_amd import _binding
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "hbaca.h"', "int main(void) {"]
+    for cname, cls in (("hb_params", _binding.HbParams), ("hb_stats", _binding.HbStats)):
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True,
+                   capture_output=True, text=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(line.split()[:2]): int(line.split()[2]) for line in out if line.strip()}
+    for cname, cls in (("hb_params", _binding.HbParams), ("hb_stats", _binding.HbStats)):
+        assert got[(cname, "size")] == C.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
