@@ -97,7 +97,7 @@ __device__ inline float eval_entry<float>(const EntryDev& P, int64_t i, int64_t 
 }
 
 template <>
-__device__ inline hb_cplx eval_entry<hb_cplx>(const EntryDev& P, int64_t i, int64_t j,
+__device__ inline hb_cplx eval_entry<hb_cplx>(const EntryDev& P, int64_t /*i*/, int64_t /*j*/,
                                               const double* x, const double* y) {
   // Helmholtz free-space Green's function
   double r = sqrt(kernel_r2(x, y, P.dim));

@@ -786,7 +786,7 @@ constexpr int BG_CT = 16;
 
 template <typename T>
 __global__ __launch_bounds__(BG_NT) void block_gemm_kernel(const BlockGemmDev* __restrict__ jobs,
-                                                           int ymax) {
+                                                           int /*ymax*/) {
   const BlockGemmDev Jb = jobs[blockIdx.y];
   const int row = blockIdx.x * BG_NT + threadIdx.x;
   const int nrows = Jb.n1 + Jb.n2;
