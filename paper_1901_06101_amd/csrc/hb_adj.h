@@ -61,6 +61,15 @@ enum AdjTaskKind {
   ADJ_RED_ROWS = 7,
   ADJ_RED_COLS = 8,
   ADJ_RED_H = 9,
+  // merges tall enough to be split over row chunks (one task per chunk or
+  // per merge, in this order within a merge step)
+  ADJ_MCH_FWD1 = 10,  // chunk: its rows of B and their thin QR
+  ADJ_MCH_FWD2 = 11,  // merge: QR of the stacked chunk R's, SVD
+  ADJ_MCH_FWD3 = 12,  // chunk: its rows of Ub and of the new O side
+  ADJ_MCH_BWD1 = 13,  // chunk: partial sums over its rows, O-side cotangents
+  ADJ_MCH_BWD2 = 14,  // merge: the small matrices of the reverse rule
+  ADJ_MCH_BWD3 = 15,  // chunk: its rows of the P-side cotangents
+  ADJ_MCH_BWD4 = 16,  // merge: the children's sigma cotangents
 };
 
 // One leaf (offsets are in doubles from the arena base D; ws_* are offsets
@@ -93,11 +102,24 @@ struct AdjBlock {
 struct AdjMerge {
   int32_t b1, b2, out, horiz;
   int32_t k, rho;      // k = r1 + r2 columns, rank kept
-  int32_t p, pad;      // p = min(rows, k) singular values
+  int32_t p, G;        // p = min(rows, k) singular values; G row chunks (1: one task)
   int64_t rows;        // rows of the P side
   int64_t n1, n2;      // rows of the O sides
   int64_t Ub, Y, S;    // rows x p, k x p, p
-  int64_t ws_f, ws_b;
+  int64_t ws_f, ws_b;  // G == 1
+  // G > 1: B and then each chunk's Q (rows x k), the chunks' R stacked and
+  // then their Q' (G k x k), Q' X (G k x k), per-chunk partial sums
+  // (G x (2 k rho + k)), and the reverse rule's J (k x rho), G Y^T (k x k)
+  // and E2 (k x rho)
+  int64_t Bq, Rs, QX, part, Jm, H, E2;
+  int64_t ws_f2, ws_b2;
+};
+
+// One row chunk of a split merge: P-side rows [p0, p1), O-side rows [o0, o1).
+struct AdjChunk {
+  int32_t merge, c;
+  int64_t p0, p1, o0, o1;
+  int64_t ws_f1, ws_b3;
 };
 
 struct AdjArgs {
@@ -107,6 +129,8 @@ struct AdjArgs {
   const AdjLeaf* leaves;
   const AdjBlock* blocks;
   const AdjMerge* merges;
+  const AdjChunk* chunks;
+  const int32_t* tasks;  // merge or chunk ids of the merge-step launches
   const double* X;      // points, structure of arrays: X[q * ldx + i]
   const double* Y;
   int64_t ldx, ldy;
@@ -154,10 +178,13 @@ HBA_FN void wg_gemm(W& w, int64_t m, int64_t n, int64_t k, double alpha, const d
   w.sync();
 }
 
-// Thin QR of A (m x k, m >= k) by classical Gram-Schmidt with one full
-// re-orthogonalisation ("twice is enough"): Q (m x k) with orthonormal
-// columns, R (k x k) upper triangular with a non-negative diagonal.  Q may
-// be A itself (same ld).  h: k doubles of scratch.
+// Thin QR of A (m x k, m >= k) by classical Gram-Schmidt with at least one
+// full re-orthogonalisation, and more (up to four passes) while a pass still
+// removes more than half of the column's norm, as happens for a column
+// nearly in the span of the earlier ones (Kahan and Parlett's criterion):
+// Q (m x k) with orthonormal columns, R (k x k) upper triangular with a
+// non-negative diagonal, A = Q R to working precision.  Q may be A itself
+// (same ld).  h: k doubles of scratch.
 template <class W>
 HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* Q, int64_t ldq,
                   double* R, int64_t ldr, double* h) {
@@ -169,7 +196,13 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
     // g lanes share each of the j dot products (rows interleaved) when
     // j <= nt / 2; their partial sums meet in red
     const int g = j > 0 && w.nt / j >= 2 ? w.nt / j : 1;
-    for (int pass = 0; pass < 2; ++pass) {
+    double nprev = 0.0;
+    if (j > 0) {
+      double part0 = 0.0;
+      for (int64_t l = w.tid; l < m; l += w.nt) part0 += Q[l + j * ldq] * Q[l + j * ldq];
+      nprev = sqrt(wg_sum(w, part0));
+    }
+    for (int pass = 0; j > 0 && pass < 4; ++pass) {
       if (g == 1) {
         for (int i = w.tid; i < j; i += w.nt) {
           double s = 0.0;
@@ -198,6 +231,11 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
       }
       for (int i = w.tid; i < j; i += w.nt) R[i + j * ldr] += h[i];
       w.sync();
+      double pn = 0.0;
+      for (int64_t l = w.tid; l < m; l += w.nt) pn += Q[l + j * ldq] * Q[l + j * ldq];
+      const double nnow = sqrt(wg_sum(w, pn));
+      if (pass >= 1 && !(nnow < 0.5 * nprev)) break;
+      nprev = nnow;
     }
     double part = 0.0;
     for (int64_t l = w.tid; l < m; l += w.nt) part += Q[l + j * ldq] * Q[l + j * ldq];
@@ -853,6 +891,222 @@ HBA_FN void adj_leaf_bwd(W& w, const AdjArgs& a, int li) {
   if (w.tid == 0) D[L.gh] = tot;
 }
 
+// ------------------------------------------------- merges split over rows ---
+// A tall merge (rows >= G max(k, chunk size)) runs as G row chunks: each
+// chunk takes the thin QR of its rows of B, B_c = Q_c R_c; the stacked
+// R_c = Q' R give B = blockdiag(Q_c) Q' R (a two-level tall-skinny QR);
+// R = X diag(s) Y^T, so Ub = blockdiag(Q_c) (Q' X).  The reverse rule is the
+// one of adj_merge_bwd, its sums over rows split into per-chunk partials.
+
+template <class W>
+HBA_FN void adj_mch_fwd1(W& w, const AdjArgs& a, int ci) {
+  const AdjChunk& Ch = a.chunks[ci];
+  const AdjMerge& M = a.merges[Ch.merge];
+  const int k = M.k;
+  const int r1 = a.blocks[M.b1].r;
+  const int64_t rows = M.rows, len = Ch.p1 - Ch.p0;
+  const AdjSides sd = adj_sides(a, M);
+  double* B = a.D + M.Bq + Ch.p0;  // ld rows
+  for (int64_t e = w.tid; e < len * k; e += w.nt) {
+    const int64_t l = Ch.p0 + e % len;
+    const int c = (int)(e / len);
+    B[(l - Ch.p0) + c * rows] = c < r1 ? sd.P1[l + c * sd.ldP1] * sd.S1[c]
+                                       : sd.P2[l + (c - r1) * sd.ldP2] * sd.S2[c - r1];
+  }
+  w.sync();
+  wg_qr(w, len, k, B, rows, B, rows, a.D + M.Rs + (int64_t)Ch.c * k, (int64_t)M.G * k,
+        a.ws + Ch.ws_f1);
+}
+
+template <class W>
+HBA_FN void adj_mch_fwd2(W& w, const AdjArgs& a, int mi) {
+  const AdjMerge& M = a.merges[mi];
+  const int k = M.k;
+  const int64_t gk = (int64_t)M.G * k;
+  double* D = a.D;
+  double* R = a.ws + M.ws_f2;  // k x k
+  double* Aw = R + k * k;
+  double* Yw = Aw + k * k;
+  double* hs = Yw + k * k;     // gk + k
+  wg_qr(w, gk, k, D + M.Rs, gk, D + M.Rs, gk, R, k, hs);
+  wg_svd(w, k, R, k, D + M.Y, k, D + M.S, Aw, Yw, hs);
+  wg_gemm(w, gk, k, k, 1.0, D + M.Rs, gk, 0, R, k, 0, 0.0, D + M.QX, gk);
+}
+
+template <class W>
+HBA_FN void adj_mch_fwd3(W& w, const AdjArgs& a, int ci) {
+  const AdjChunk& Ch = a.chunks[ci];
+  const AdjMerge& M = a.merges[Ch.merge];
+  const int k = M.k, rho = M.rho;
+  const int r1 = a.blocks[M.b1].r, r2 = a.blocks[M.b2].r;
+  const int64_t rows = M.rows, n1 = M.n1, n2 = M.n2, len = Ch.p1 - Ch.p0;
+  const int64_t gk = (int64_t)M.G * k;
+  const AdjSides sd = adj_sides(a, M);
+  double* D = a.D;
+  wg_gemm(w, len, k, k, 1.0, D + M.Bq + Ch.p0, rows, 0, D + M.QX + (int64_t)Ch.c * k, gk, 0,
+          0.0, D + M.Ub + Ch.p0, rows);
+  const AdjBlock& out = a.blocks[M.out];
+  double* On = D + (M.horiz ? out.Vt : out.U);
+  const int64_t a0 = Ch.o0, a1 = Ch.o1 < n1 ? Ch.o1 : n1;
+  const int64_t b0 = Ch.o0 > n1 ? Ch.o0 : n1, b1 = Ch.o1;
+  if (a1 > a0)
+    wg_gemm(w, a1 - a0, rho, r1, 1.0, sd.O1 + a0, sd.ldO1, 0, D + M.Y, k, 0, 0.0, On + a0,
+            n1 + n2);
+  if (b1 > b0)
+    wg_gemm(w, b1 - b0, rho, r2, 1.0, sd.O2 + (b0 - n1), sd.ldO2, 0, D + M.Y + r1, k, 0, 0.0,
+            On + b0, n1 + n2);
+}
+
+template <class W>
+HBA_FN void adj_mch_bwd1(W& w, const AdjArgs& a, int ci) {
+  const AdjChunk& Ch = a.chunks[ci];
+  const AdjMerge& M = a.merges[Ch.merge];
+  const int k = M.k, rho = M.rho;
+  const AdjBlock& b1 = a.blocks[M.b1];
+  const AdjBlock& b2 = a.blocks[M.b2];
+  const AdjBlock& out = a.blocks[M.out];
+  const int r1 = b1.r, r2 = b2.r;
+  const int64_t rows = M.rows, n1 = M.n1, n2 = M.n2, len = Ch.p1 - Ch.p0;
+  const AdjSides sd = adj_sides(a, M);
+  double* D = a.D;
+  const double* gPo = D + (M.horiz ? out.gU : out.gVt);
+  const double* gOo = D + (M.horiz ? out.gVt : out.gU);
+  double* gO1 = D + (M.horiz ? b1.gVt : b1.gU);
+  double* gO2 = D + (M.horiz ? b2.gVt : b2.gU);
+  const double* Y = D + M.Y;
+  const int64_t ldo = n1 + n2;
+  double* Ybp = D + M.part + (int64_t)Ch.c * (2 * k * rho + k);  // k x rho
+  double* Jmp = Ybp + k * rho;                                    // k x rho
+  const int64_t a0 = Ch.o0, a1 = Ch.o1 < n1 ? Ch.o1 : n1;
+  const int64_t o0 = Ch.o0 > n1 ? Ch.o0 : n1, o1 = Ch.o1;
+  // partial blockdiag(O1, O2)^T gOo over this chunk's O rows
+  for (int e = w.tid; e < k * rho; e += w.nt) {
+    const int c = e % k, j = e / k;
+    double s = 0.0;
+    if (c < r1) {
+      for (int64_t l = a0; l < a1; ++l) s += sd.O1[l + c * sd.ldO1] * gOo[l + j * ldo];
+    } else {
+      for (int64_t l = o0; l < o1; ++l)
+        s += sd.O2[(l - n1) + (c - r1) * sd.ldO2] * gOo[l + j * ldo];
+    }
+    Ybp[e] = s;
+  }
+  // this chunk's rows of the children's O-side cotangents
+  if (a1 > a0)
+    wg_gemm(w, a1 - a0, r1, rho, 1.0, gOo + a0, ldo, 0, Y, k, 1, 0.0, gO1 + a0, n1);
+  if (o1 > o0)
+    wg_gemm(w, o1 - o0, r2, rho, 1.0, gOo + o0, ldo, 0, Y + r1, k, 1, 0.0, gO2 + (o0 - n1), n2);
+  // partial Ub^T gPo over this chunk's P rows
+  wg_gemm(w, k, rho, len, 1.0, D + M.Ub + Ch.p0, rows, 1, gPo + Ch.p0, rows, 0, 0.0, Jmp, k);
+}
+
+template <class W>
+HBA_FN void adj_mch_bwd2(W& w, const AdjArgs& a, int mi) {
+  const AdjMerge& M = a.merges[mi];
+  const int k = M.k, rho = M.rho;
+  const AdjBlock& out = a.blocks[M.out];
+  double* D = a.D;
+  const double* Y = D + M.Y;
+  const double* s = D + M.S;
+  double* Jm = D + M.Jm;
+  double* Yb = a.ws + M.ws_b2;  // k x rho
+  double* Km = Yb + k * rho;    // k x rho
+  double* G = Km + k * rho;     // k x k
+  const int64_t stride = 2 * (int64_t)k * rho + k;
+  for (int e = w.tid; e < k * rho; e += w.nt) {
+    double sy = 0.0, sj = 0.0;
+    for (int c = 0; c < M.G; ++c) {
+      sy += D[M.part + c * stride + e];
+      sj += D[M.part + c * stride + k * rho + e];
+    }
+    Yb[e] = sy;
+    Jm[e] = sj;
+  }
+  w.sync();
+  wg_gemm(w, k, rho, k, 1.0, Y, k, 1, Yb, k, 0, 0.0, Km, k);
+  adj_svd_g(w, k, rho, s, D + out.gS, Jm, Km, G);
+  wg_gemm(w, k, k, k, 1.0, G, k, 0, Y, k, 1, 0.0, D + M.H, k);
+  for (int e = w.tid; e < k * rho; e += w.nt) {
+    const int c = e % k, j = e / k;
+    double v = Yb[e];
+    for (int i = 0; i < k; ++i) v -= Y[c + i * k] * Km[i + j * k];
+    D[M.E2 + e] = v / s[j];
+  }
+  w.sync();
+}
+
+template <class W>
+HBA_FN void adj_mch_bwd3(W& w, const AdjArgs& a, int ci) {
+  const AdjChunk& Ch = a.chunks[ci];
+  const AdjMerge& M = a.merges[Ch.merge];
+  const int k = M.k, rho = M.rho;
+  const AdjBlock& b1 = a.blocks[M.b1];
+  const AdjBlock& b2 = a.blocks[M.b2];
+  const AdjBlock& out = a.blocks[M.out];
+  const int r1 = b1.r;
+  const int64_t rows = M.rows, len = Ch.p1 - Ch.p0;
+  const AdjSides sd = adj_sides(a, M);
+  double* D = a.D;
+  const double* gPo = D + (M.horiz ? out.gU : out.gVt) + Ch.p0;  // ld rows
+  double* gP1 = D + (M.horiz ? b1.gU : b1.gVt);
+  double* gP2 = D + (M.horiz ? b2.gU : b2.gVt);
+  const double* Ub = D + M.Ub + Ch.p0;  // ld rows
+  const double* Jm = D + M.Jm;
+  const double* Y = D + M.Y;
+  const double* s = D + M.S;
+  double* gSp = D + M.part + (int64_t)Ch.c * (2 * k * rho + k) + 2 * k * rho;  // k
+  double* E = a.ws + Ch.ws_b3;  // len x rho
+  double* Bb = E + len * rho;   // len x k
+  for (int64_t e = w.tid; e < len * rho; e += w.nt) {
+    const int64_t l = e % len;
+    const int j = (int)(e / len);
+    double v = gPo[l + j * rows];
+    for (int i = 0; i < k; ++i) v -= Ub[l + i * rows] * Jm[i + j * k];
+    E[e] = v / s[j];
+  }
+  w.sync();
+  wg_gemm(w, len, k, k, 1.0, Ub, rows, 0, D + M.H, k, 0, 0.0, Bb, len);
+  wg_gemm(w, len, k, rho, 1.0, E, len, 0, Y, k, 1, 1.0, Bb, len);
+  wg_gemm(w, len, k, rho, 1.0, Ub, rows, 0, D + M.E2, k, 1, 1.0, Bb, len);
+  for (int64_t e = w.tid; e < len * k; e += w.nt) {
+    const int64_t l = Ch.p0 + e % len;
+    const int c = (int)(e / len);
+    if (c < r1)
+      gP1[l + c * rows] = Bb[e] * sd.S1[c];
+    else
+      gP2[l + (c - r1) * rows] = Bb[e] * sd.S2[c - r1];
+  }
+  for (int c = w.tid; c < k; c += w.nt) {
+    double v = 0.0;
+    if (c < r1) {
+      for (int64_t l = 0; l < len; ++l) v += Bb[l + c * len] * sd.P1[Ch.p0 + l + c * sd.ldP1];
+    } else {
+      for (int64_t l = 0; l < len; ++l)
+        v += Bb[l + c * len] * sd.P2[Ch.p0 + l + (c - r1) * sd.ldP2];
+    }
+    gSp[c] = v;
+  }
+  w.sync();
+}
+
+template <class W>
+HBA_FN void adj_mch_bwd4(W& w, const AdjArgs& a, int mi) {
+  const AdjMerge& M = a.merges[mi];
+  const int k = M.k, rho = M.rho;
+  const AdjBlock& b1 = a.blocks[M.b1];
+  const AdjBlock& b2 = a.blocks[M.b2];
+  const int64_t stride = 2 * (int64_t)k * rho + k;
+  for (int c = w.tid; c < k; c += w.nt) {
+    double v = 0.0;
+    for (int g = 0; g < M.G; ++g) v += a.D[M.part + g * stride + 2 * k * rho + c];
+    if (c < b1.r)
+      a.D[b1.gS + c] = v;
+    else
+      a.D[b2.gS + c - b1.r] = v;
+  }
+  w.sync();
+}
+
 // Gradient rows of row cluster t: the sum over its leaves (t, v).
 template <class W>
 HBA_FN void adj_red_rows(W& w, const AdjArgs& a, int t) {
@@ -893,9 +1147,16 @@ HBA_FN void adj_run_task(W& w, const AdjArgs& a, int kind, int g) {
   switch (kind) {
     case ADJ_LEAF_FWD: adj_leaf_fwd(w, a, g); break;
     case ADJ_REC_FWD: adj_rec_fwd(w, a, g); break;
-    case ADJ_MERGE_FWD: adj_merge_fwd(w, a, g); break;
+    case ADJ_MERGE_FWD: adj_merge_fwd(w, a, a.tasks[g]); break;
     case ADJ_ROOT: adj_root(w, a); break;
-    case ADJ_MERGE_BWD: adj_merge_bwd(w, a, g); break;
+    case ADJ_MERGE_BWD: adj_merge_bwd(w, a, a.tasks[g]); break;
+    case ADJ_MCH_FWD1: adj_mch_fwd1(w, a, a.tasks[g]); break;
+    case ADJ_MCH_FWD2: adj_mch_fwd2(w, a, a.tasks[g]); break;
+    case ADJ_MCH_FWD3: adj_mch_fwd3(w, a, a.tasks[g]); break;
+    case ADJ_MCH_BWD1: adj_mch_bwd1(w, a, a.tasks[g]); break;
+    case ADJ_MCH_BWD2: adj_mch_bwd2(w, a, a.tasks[g]); break;
+    case ADJ_MCH_BWD3: adj_mch_bwd3(w, a, a.tasks[g]); break;
+    case ADJ_MCH_BWD4: adj_mch_bwd4(w, a, a.tasks[g]); break;
     case ADJ_REC_BWD: adj_rec_bwd(w, a, g); break;
     case ADJ_LEAF_BWD: adj_leaf_bwd(w, a, g); break;
     case ADJ_RED_ROWS: adj_red_rows(w, a, g); break;

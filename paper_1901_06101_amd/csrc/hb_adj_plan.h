@@ -25,6 +25,10 @@ struct AdjPlanIn {
   int dim = 0, dmax = 0, fz_stride = 0;
   std::vector<AdjLeafIn> leaves;              // 4^L leaves, b = t 2^L + v
   std::vector<std::vector<int>> hrank, vrank;  // per level 1..L, as the forward run merged
+  // a merge whose P side holds at least 2 max(chunk_rows, k) rows runs as
+  // G = min(max_chunks, rows / max(chunk_rows, k)) row chunks
+  int64_t chunk_rows = 512;
+  int max_chunks = 32;
 };
 
 struct AdjPhase {
@@ -35,8 +39,11 @@ struct AdjPlan {
   std::vector<AdjLeaf> leaves;
   std::vector<AdjBlock> blocks;
   std::vector<AdjMerge> merges;
+  std::vector<AdjChunk> chunks;
   std::vector<int32_t> fz;
-  std::vector<AdjPhase> merge_phases;  // forward order
+  std::vector<int32_t> tasks;          // merge / chunk ids of the merge launches
+  std::vector<AdjPhase> fwd_phases;    // merge launches, forward order
+  std::vector<AdjPhase> bwd_phases;    // merge launches, reverse order
   int root = 0, nb = 1;
   int64_t arena = 0;     // doubles, workspace included
   int64_t ws_off = 0;    // start of the phase workspace in the arena
@@ -49,6 +56,7 @@ inline int adj_plan(const AdjPlanIn& in, AdjPlan& P) {
   P = AdjPlan();
   if (in.L < 0 || in.L > 20 || in.dim < 1 || in.dim > HBA_MAXDIM) return -1;
   if (in.dmax < 1 || in.dmax > HBA_DMAX || in.fz_stride < 3 + 3 * in.dmax) return -1;
+  if (in.chunk_rows < 1 || in.max_chunks < 1) return -1;
   const int nb = 1 << in.L;
   const int dm = in.dmax;
   P.nb = nb;
@@ -155,6 +163,12 @@ inline int adj_plan(const AdjPlanIn& in, AdjPlan& P) {
     if (rows != in.m || cols != in.n) return -1;
   }
   // ---- merges, level by level (horizontal, then vertical)
+  auto phase = [&](int kind, const std::vector<int>& ids) {
+    AdjPhase ph{kind, (int)P.tasks.size(), (int)ids.size()};
+    P.tasks.insert(P.tasks.end(), ids.begin(), ids.end());
+    return ph;
+  };
+  std::vector<std::vector<AdjPhase>> bwd_by_step;
   std::vector<int> cur(nb * nb);
   for (int i = 0; i < nb * nb; ++i) cur[i] = i;
   for (int l = 1; l <= in.L; ++l) {
@@ -218,12 +232,51 @@ inline int adj_plan(const AdjPlanIn& in, AdjPlan& P) {
           nxt.push_back(M.out);
           P.merges.push_back(M);
         }
-      P.merge_phases.push_back(AdjPhase{ADJ_MERGE_FWD, base,
-                                        (int)P.merges.size() - base});
+      // split the tall merges over row chunks
+      std::vector<int> whole, split, parts;
+      for (int i = base; i < (int)P.merges.size(); ++i) {
+        AdjMerge& M = P.merges[i];
+        const int64_t unit = std::max<int64_t>(in.chunk_rows, M.k);
+        const int64_t g = M.k >= 1 ? std::min<int64_t>(M.rows / unit, in.max_chunks) : 1;
+        M.G = g >= 2 ? (int32_t)g : 1;
+        if (M.G == 1) {
+          whole.push_back(i);
+          continue;
+        }
+        split.push_back(i);
+        const int64_t k = M.k, rho = M.rho, gk = (int64_t)M.G * k;
+        M.Bq = take(M.rows * k);
+        M.Rs = take(gk * k);
+        M.QX = take(gk * k);
+        M.part = take(M.G * (2 * k * rho + k));
+        M.Jm = take(k * rho);
+        M.H = take(k * k);
+        M.E2 = take(k * rho);
+        for (int c = 0; c < M.G; ++c) {
+          AdjChunk C{};
+          C.merge = i;
+          C.c = c;
+          C.p0 = M.rows * c / M.G;
+          C.p1 = M.rows * (c + 1) / M.G;
+          C.o0 = (M.n1 + M.n2) * c / M.G;
+          C.o1 = (M.n1 + M.n2) * (c + 1) / M.G;
+          parts.push_back((int)P.chunks.size());
+          P.chunks.push_back(C);
+        }
+      }
+      P.fwd_phases.push_back(phase(ADJ_MERGE_FWD, whole));
+      P.fwd_phases.push_back(phase(ADJ_MCH_FWD1, parts));
+      P.fwd_phases.push_back(phase(ADJ_MCH_FWD2, split));
+      P.fwd_phases.push_back(phase(ADJ_MCH_FWD3, parts));
+      bwd_by_step.push_back({phase(ADJ_MCH_BWD1, parts), phase(ADJ_MCH_BWD2, split),
+                             phase(ADJ_MCH_BWD3, parts), phase(ADJ_MCH_BWD4, split),
+                             phase(ADJ_MERGE_BWD, whole)});
       cur = nxt;
     }
   }
   P.root = cur[0];
+  for (auto it = bwd_by_step.rbegin(); it != bwd_by_step.rend(); ++it)
+    P.bwd_phases.insert(P.bwd_phases.end(), it->begin(), it->end());
   // ---- phase workspaces (tasks of one launch get disjoint pieces)
   int64_t ws = 0, acc = 0;
   auto piece = [&](int64_t n) {
@@ -242,17 +295,30 @@ inline int adj_plan(const AdjPlanIn& in, AdjPlan& P) {
     L.ws_rf = piece(((int64_t)L.m0 + L.n0) * r + 6 * r * r + r);
   }
   close();
-  for (auto& ph : P.merge_phases) {
-    for (int i = ph.base; i < ph.base + ph.count; ++i) {
-      AdjMerge& M = P.merges[i];
-      const int64_t k = M.k, p = M.p;
-      M.ws_f = piece(M.rows * k + 5 * p * p + M.rows + k);
-    }
-    close();
-    for (int i = ph.base; i < ph.base + ph.count; ++i) {
-      AdjMerge& M = P.merges[i];
+  std::vector<AdjPhase> all = P.fwd_phases;
+  all.insert(all.end(), P.bwd_phases.begin(), P.bwd_phases.end());
+  for (const AdjPhase& ph : all) {
+    for (int t = ph.base; t < ph.base + ph.count; ++t) {
+      const int id = P.tasks[t];
+      if (ph.kind == ADJ_MCH_FWD1 || ph.kind == ADJ_MCH_BWD3) {
+        AdjChunk& C = P.chunks[id];
+        const AdjMerge& M = P.merges[C.merge];
+        if (ph.kind == ADJ_MCH_FWD1)
+          C.ws_f1 = piece(M.k);
+        else
+          C.ws_b3 = piece((C.p1 - C.p0) * (M.rho + M.k));
+        continue;
+      }
+      AdjMerge& M = P.merges[id];
       const int64_t k = M.k, rho = M.rho, p = M.p;
-      M.ws_b = piece(k * rho + 2 * p * rho + p * p + p * k + k * rho + M.rows * (rho + k));
+      if (ph.kind == ADJ_MERGE_FWD)
+        M.ws_f = piece(M.rows * k + 5 * p * p + M.rows + k);
+      else if (ph.kind == ADJ_MERGE_BWD)
+        M.ws_b = piece(k * rho + 2 * p * rho + p * p + p * k + k * rho + M.rows * (rho + k));
+      else if (ph.kind == ADJ_MCH_FWD2)
+        M.ws_f2 = piece(3 * k * k + (int64_t)M.G * k + k);
+      else if (ph.kind == ADJ_MCH_BWD2)
+        M.ws_b2 = piece(2 * k * rho + k * k);
     }
     close();
   }
@@ -275,6 +341,8 @@ inline int adj_plan(const AdjPlanIn& in, AdjPlan& P) {
 // The launch sequence, shared by the GPU and by the host emulation used in
 // tests: ex.launch(kind, first task, task count) runs the tasks of one
 // launch, each on its own workgroup, after every earlier launch finished.
+// Task g of a leaf or reduction launch is leaf (or cluster) g; task g of a
+// merge-step launch is merge or chunk P.tasks[g].
 // The forward part alone evaluates the frozen operator (root block
 // P.blocks[P.root]).
 template <class Ex>
@@ -282,7 +350,7 @@ inline void adj_execute_forward(Ex& ex, const AdjPlan& P) {
   const int nl = (int)P.leaves.size();
   ex.launch(ADJ_LEAF_FWD, 0, nl);
   ex.launch(ADJ_REC_FWD, 0, nl);
-  for (const AdjPhase& ph : P.merge_phases) ex.launch(ADJ_MERGE_FWD, ph.base, ph.count);
+  for (const AdjPhase& ph : P.fwd_phases) ex.launch(ph.kind, ph.base, ph.count);
 }
 
 template <class Ex>
@@ -290,8 +358,7 @@ inline void adj_execute(Ex& ex, const AdjPlan& P, bool want_x, bool want_y, bool
   const int nl = (int)P.leaves.size();
   adj_execute_forward(ex, P);
   ex.launch(ADJ_ROOT, 0, 1);
-  for (auto it = P.merge_phases.rbegin(); it != P.merge_phases.rend(); ++it)
-    ex.launch(ADJ_MERGE_BWD, it->base, it->count);
+  for (const AdjPhase& ph : P.bwd_phases) ex.launch(ph.kind, ph.base, ph.count);
   ex.launch(ADJ_REC_BWD, 0, nl);
   ex.launch(ADJ_LEAF_BWD, 0, nl);
   if (want_x) ex.launch(ADJ_RED_ROWS, 0, P.nb);

@@ -44,6 +44,13 @@ int adj_launch(int kind, int base, int count, const AdjArgs& a, hipStream_t st) 
     case ADJ_RED_ROWS: launch_kind<ADJ_RED_ROWS>(base, count, a, st); break;
     case ADJ_RED_COLS: launch_kind<ADJ_RED_COLS>(base, count, a, st); break;
     case ADJ_RED_H: launch_kind<ADJ_RED_H>(base, count, a, st); break;
+    case ADJ_MCH_FWD1: launch_kind<ADJ_MCH_FWD1>(base, count, a, st); break;
+    case ADJ_MCH_FWD2: launch_kind<ADJ_MCH_FWD2>(base, count, a, st); break;
+    case ADJ_MCH_FWD3: launch_kind<ADJ_MCH_FWD3>(base, count, a, st); break;
+    case ADJ_MCH_BWD1: launch_kind<ADJ_MCH_BWD1>(base, count, a, st); break;
+    case ADJ_MCH_BWD2: launch_kind<ADJ_MCH_BWD2>(base, count, a, st); break;
+    case ADJ_MCH_BWD3: launch_kind<ADJ_MCH_BWD3>(base, count, a, st); break;
+    case ADJ_MCH_BWD4: launch_kind<ADJ_MCH_BWD4>(base, count, a, st); break;
     default: return -1;
   }
   return (int)hipGetLastError();

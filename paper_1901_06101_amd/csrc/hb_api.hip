@@ -2080,6 +2080,8 @@ static AdjArgs frozen_args(const hb_result* r, const AdjPlan& P, DevMem& mem, hi
   a.leaves = upload(mem, P.leaves, st);
   a.blocks = upload(mem, P.blocks, st);
   a.merges = upload(mem, P.merges, st);
+  a.chunks = upload(mem, P.chunks, st);
+  a.tasks = upload(mem, P.tasks, st);
   a.X = r->E.X;
   a.Y = r->E.Y;
   a.ldx = r->E.ldx;

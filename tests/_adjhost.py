@@ -39,8 +39,25 @@ def load():
                                          p, p, p, p, p, C.c_double, C.c_double, C.c_int, C.c_int,
                                          p, p, p, C.POINTER(C.c_int32)]
         lib.adj_host_forward.restype = C.c_int
+        lib.adj_host_set_chunking.argtypes = [C.c_int64, C.c_int]
+        lib.adj_host_set_chunking.restype = None
+        lib.adj_host_last_split.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        lib.adj_host_last_split.restype = None
         _lib = lib
     return _lib
+
+
+def set_chunking(chunk_rows=512, max_chunks=32):
+    """Row chunking of tall merges for later calls (512 and 32 are the
+    library's defaults)."""
+    load().adj_host_set_chunking(int(chunk_rows), int(max_chunks))
+
+
+def last_split():
+    """(merges split over row chunks, chunks) in the last plan."""
+    a, b = C.c_int(0), C.c_int(0)
+    load().adj_host_last_split(C.byref(a), C.byref(b))
+    return a.value, b.value
 
 
 def dmax_for(d):
@@ -159,7 +176,7 @@ def _build_exe(name, flags):
     return exe
 
 
-def run_exe(exe, fs, w, ybar, nt, workdir):
+def run_exe(exe, fs, w, ybar, nt, workdir, chunking=None):
     """Runs the stand-alone driver; returns (returncode, stderr, outputs or None)."""
     wl = fs.wl
     li, recs, ranks, dm, stride = records_from_oracle(fs)
@@ -181,8 +198,9 @@ def run_exe(exe, fs, w, ybar, nt, workdir):
         np.asarray(ybar, dtype=np.float64).tofile(f)
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66",
                ASAN_OPTIONS="detect_leaks=1 exitcode=67")
-    p = subprocess.run([exe, inp, out, str(nt)], capture_output=True, text=True, env=env,
-                       timeout=900)
+    extra = [str(chunking[0]), str(chunking[1])] if chunking else []
+    p = subprocess.run([exe, inp, out, str(nt), *extra], capture_output=True, text=True,
+                       env=env, timeout=900)
     if p.returncode != 0:
         return p.returncode, p.stderr, None
     v = np.fromfile(out, dtype=np.float64)

@@ -54,6 +54,11 @@ struct HostExec {
 
 }  // namespace
 
+// row chunking of tall merges (the library's defaults unless a test sets them)
+static int64_t g_chunk_rows = AdjPlanIn().chunk_rows;
+static int g_max_chunks = AdjPlanIn().max_chunks;
+static int g_split = 0, g_nchunks = 0;
+
 static int make_plan(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stride,
                      const int64_t* leaf_info, const int32_t* recs, const int32_t* ranks,
                      AdjPlan& P) {
@@ -64,6 +69,8 @@ static int make_plan(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stri
   in.dim = dim;
   in.dmax = dmax;
   in.fz_stride = fz_stride;
+  in.chunk_rows = g_chunk_rows;
+  in.max_chunks = g_max_chunks;
   const int nb = 1 << L;
   for (int b = 0; b < nb * nb; ++b) {
     const int64_t* f = leaf_info + 7 * b;
@@ -85,7 +92,11 @@ static int make_plan(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stri
     in.vrank.emplace_back(ranks + off, ranks + off + nbp * nbp);
     off += nbp * nbp;
   }
-  return adj_plan(in, P);
+  const int st = adj_plan(in, P);
+  g_split = 0;
+  for (const AdjMerge& M : P.merges) g_split += M.G > 1;
+  g_nchunks = (int)P.chunks.size();
+  return st;
 }
 
 static AdjArgs make_args(const AdjPlan& P, std::vector<double>& D, int64_t m, int64_t n, int dim,
@@ -97,6 +108,8 @@ static AdjArgs make_args(const AdjPlan& P, std::vector<double>& D, int64_t m, in
   a.leaves = P.leaves.data();
   a.blocks = P.blocks.data();
   a.merges = P.merges.data();
+  a.chunks = P.chunks.data();
+  a.tasks = P.tasks.data();
   a.X = Xsoa;
   a.Y = Ysoa;
   a.ldx = m;
@@ -113,6 +126,19 @@ static AdjArgs make_args(const AdjPlan& P, std::vector<double>& D, int64_t m, in
 }
 
 extern "C" {
+
+// Row chunking of tall merges for the following calls (tests force small
+// chunks to run the split path at small sizes).
+void adj_host_set_chunking(int64_t chunk_rows, int max_chunks) {
+  g_chunk_rows = chunk_rows;
+  g_max_chunks = max_chunks;
+}
+
+// Number of merges the last plan split, and their chunks.
+void adj_host_last_split(int* merges, int* chunks) {
+  *merges = g_split;
+  *chunks = g_nchunks;
+}
 
 // leaf_info: per leaf (b = t 2^L + v) row0, col0, m0, n0, records,
 // rank_leaf, first record index; recs: records of fz_stride ints; ranks:
@@ -181,11 +207,13 @@ int adj_host_forward(int64_t m, int64_t n, int L, int dim, int dmax, int fz_stri
 }  // extern "C"
 
 #ifdef ADJ_HOST_MAIN
-// Stand-alone driver (for a ThreadSanitizer build): reads the inputs of
-// adj_host_vjp from argv[1], runs it with argv[3] lanes per workgroup and
-// writes gw, gh, gX, gY to argv[2].
+// Stand-alone driver (for the sanitizer builds): reads the inputs of
+// adj_host_vjp from argv[1], runs it with argv[3] lanes per workgroup (and,
+// if given, row chunks of at least argv[4] rows, at most argv[5] per merge)
+// and writes gw, gh, gX, gY to argv[2].
 int main(int argc, char** argv) {
   if (argc < 4) return 2;
+  if (argc >= 6) adj_host_set_chunking(std::atoll(argv[4]), std::atoi(argv[5]));
   FILE* f = std::fopen(argv[1], "rb");
   if (!f) return 2;
   int64_t hd[9];

@@ -161,15 +161,17 @@ def test_lane_count_does_not_change_the_result(case):
         assert np.max(np.abs(np.asarray(a) - np.asarray(r))) <= 1e-12 * max(1.0, np.max(np.abs(r)))
 
 
-def test_no_data_race_under_thread_sanitizer(tmp_path):
-    # both merge shapes: wide first-level merges (45 rows), tall ones above
+@pytest.mark.parametrize("chunking", [None, (16, 32)])
+def test_no_data_race_under_thread_sanitizer(tmp_path, chunking):
+    # both merge shapes: wide first-level merges (45 rows), tall ones above;
+    # with small row chunks the tall ones run split
     wl = G.make_gauss3d(n=200, m=180, h=0.7, leaf=50, tol=1e-6, d=8, cfg=52)
     fs = adj.FrozenStructure(wl)
     rng = np.random.default_rng(1)
     w = rng.standard_normal(wl["n"])
     yb = rng.standard_normal(wl["m"])
     exe = AH.build_tsan()
-    rc, err, outs = AH.run_exe(exe, fs, w, yb, 4, str(tmp_path))
+    rc, err, outs = AH.run_exe(exe, fs, w, yb, 4, str(tmp_path), chunking)
     assert rc == 0, err[-4000:]
     assert "ThreadSanitizer" not in err
     ref = AH.vjp(fs, w, yb, nt=1)
@@ -177,19 +179,48 @@ def test_no_data_race_under_thread_sanitizer(tmp_path):
         assert np.max(np.abs(np.asarray(a) - np.asarray(r))) <= 1e-12 * max(1.0, np.max(np.abs(r)))
 
 
-def test_no_memory_error_under_address_sanitizer(tmp_path):
+@pytest.mark.parametrize("chunking", [None, (16, 32)])
+def test_no_memory_error_under_address_sanitizer(tmp_path, chunking):
     wl = G.make_gauss3d(n=200, m=180, h=0.7, leaf=50, tol=1e-6, d=8, cfg=52)
     fs = adj.FrozenStructure(wl)
     rng = np.random.default_rng(2)
     w = rng.standard_normal(wl["n"])
     yb = rng.standard_normal(wl["m"])
     exe = AH.build_asan()
-    rc, err, outs = AH.run_exe(exe, fs, w, yb, 2, str(tmp_path))
+    rc, err, outs = AH.run_exe(exe, fs, w, yb, 2, str(tmp_path), chunking)
     assert rc == 0, err[-4000:]
     assert "Sanitizer" not in err and "runtime error" not in err
     ref = AH.vjp(fs, w, yb, nt=2)
     for a, r in zip(outs, ref):
         assert np.max(np.abs(np.asarray(a) - np.asarray(r))) <= 1e-12 * max(1.0, np.max(np.abs(r)))
+
+
+@pytest.mark.parametrize("name,chunk", [("n400", 16), ("n700", 8)])
+def test_merges_split_over_row_chunks(name, chunk):
+    """Tall merges run as row chunks (a two-level thin QR, per-chunk partial
+    sums): forced small chunks make every merge above the first level split."""
+    wl = {"n400": lambda: G.make_gauss3d(n=400, m=360, h=0.7, leaf=100, tol=1e-6, d=8, cfg=51),
+          "n700": lambda: G.make_gauss3d(n=700, m=650, h=0.6, leaf=90, tol=1e-5, d=16,
+                                         cfg=53)}[name]()
+    fs = adj.FrozenStructure(wl)
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal(wl["n"])
+    b = rng.standard_normal(wl["m"])
+    _, gw, gh, gX, gY = adj.frozen_gradients(fs, w, b)
+    yb = _ybar(fs, w, b)
+    AH.set_chunking(chunk, 32)
+    try:
+        U, S, Vt = AH.forward(fs)
+        assert AH.last_split()[0] > 0
+        hw, hh, hX, hY = AH.vjp(fs, w, yb, nt=4)
+    finally:
+        AH.set_chunking()
+    A = fs.res.dense()
+    assert np.linalg.norm((U * S) @ Vt.T - A) <= 1e-11 * np.linalg.norm(A)
+    assert _rel(hw, gw) <= 1e-10
+    assert abs(hh - gh) <= 1e-10 * abs(gh)
+    assert _rel(hX, gX) <= 1e-10
+    assert _rel(hY, gY) <= 1e-10
 
 
 def test_planner_rejects_inconsistent_structures(case):
