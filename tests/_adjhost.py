@@ -43,8 +43,18 @@ def load():
         lib.adj_host_set_chunking.restype = None
         lib.adj_host_last_split.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int)]
         lib.adj_host_last_split.restype = None
+        lib.adj_host_set_fibers.argtypes = [C.c_int, C.POINTER(C.c_int64)]
+        lib.adj_host_set_fibers.restype = C.c_int
         _lib = lib
     return _lib
+
+
+def set_fibers(on):
+    """Lanes as fibers on one thread (on) or as threads; returns (diverged,
+    barriers) for the calls since the last switch."""
+    b = C.c_int64(0)
+    e = load().adj_host_set_fibers(1 if on else 0, C.byref(b))
+    return bool(e), b.value
 
 
 def set_chunking(chunk_rows=512, max_chunks=32):

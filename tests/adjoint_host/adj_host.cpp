@@ -7,6 +7,14 @@
 // launch order the library uses (adj_execute).  It checks the tasks'
 // arithmetic, indexing and barrier placement against the oracle on the CPU;
 // it is not linked into the library, which has no host path.
+//
+// A second mode runs the nt lanes as fibers (ucontext) on one thread, which
+// makes the GPU's 256 lanes affordable: each lane runs until its next
+// barrier, and a barrier that some lanes reach while others have finished
+// the task (a barrier inside lane-dependent control flow, which would hang
+// a GPU workgroup) is reported instead of deadlocking.
+#include <ucontext.h>
+
 #include <barrier>
 #include <cmath>
 #include <cstdint>
@@ -21,12 +29,97 @@
 
 namespace {
 
+struct Fibers;
+
 struct WgHost {
   int tid, nt;
   double* red;
   std::barrier<>* bar;
-  void sync() { bar->arrive_and_wait(); }
+  Fibers* fib;
+  void sync();
 };
+
+// One workgroup's lanes as fibers: the scheduler resumes every lane in
+// turn; a lane runs until it reaches a barrier or ends the task.
+struct Fibers {
+  static constexpr size_t kStack = 256 * 1024;
+  ucontext_t sched;
+  std::vector<ucontext_t> ctx;
+  std::vector<std::vector<char>> stack;
+  std::vector<int> state;  // 0 running, 1 at a barrier, 2 done
+  const AdjArgs* a = nullptr;
+  double* red = nullptr;
+  int nt = 0, kind = 0, task = 0, cur = 0;
+  int64_t barriers = 0;
+  bool diverged = false;
+
+  static thread_local Fibers* self;
+
+  static void entry() {
+    Fibers* f = self;
+    const int t = f->cur;
+    WgHost w{t, f->nt, f->red, nullptr, f};
+    adj_run_task(w, *f->a, f->kind, f->task);
+    f->state[t] = 2;  // uc_link returns to the scheduler
+  }
+
+  void yield(int t) {
+    state[t] = 1;
+    swapcontext(&ctx[t], &sched);
+  }
+
+  // Runs one task to its end; false if its lanes did not all meet at the
+  // same barriers.
+  bool run(const AdjArgs& args, int k, int tk, double* r, int lanes) {
+    a = &args;
+    kind = k;
+    task = tk;
+    red = r;
+    nt = lanes;
+    ctx.assign(nt, ucontext_t{});
+    if ((int)stack.size() < nt) stack.resize(nt);
+    state.assign(nt, 0);
+    self = this;
+    for (int t = 0; t < nt; ++t) {
+      stack[t].resize(kStack);
+      getcontext(&ctx[t]);
+      ctx[t].uc_stack.ss_sp = stack[t].data();
+      ctx[t].uc_stack.ss_size = kStack;
+      ctx[t].uc_link = &sched;
+      cur = t;
+      makecontext(&ctx[t], (void (*)())entry, 0);
+    }
+    for (;;) {
+      for (int t = 0; t < nt; ++t) {
+        if (state[t] == 2) continue;
+        state[t] = 0;
+        cur = t;
+        swapcontext(&sched, &ctx[t]);
+      }
+      int done = 0;
+      for (int t = 0; t < nt; ++t) done += state[t] == 2;
+      if (done == nt) return true;
+      if (done != 0) {
+        diverged = true;
+        return false;  // lanes left at a barrier are abandoned with their stacks
+      }
+      ++barriers;
+    }
+  }
+};
+
+thread_local Fibers* Fibers::self = nullptr;
+
+void WgHost::sync() {
+  if (fib)
+    fib->yield(tid);
+  else
+    bar->arrive_and_wait();
+}
+
+static bool g_fibers = false;
+static int g_fiber_error = 0;
+static int64_t g_fiber_barriers = 0;
 
 struct HostExec {
   AdjArgs a;
@@ -34,9 +127,20 @@ struct HostExec {
   void launch(int kind, int base, int count) {
     for (int g = 0; g < count; ++g) {
       std::vector<double> red(nt, 0.0);
+      if (g_fibers && nt > 1) {
+        Fibers f;
+        if (!f.run(a, kind, base + g, red.data(), nt)) {
+          g_fiber_error = 1;
+          std::fprintf(stderr, "adj_host: lanes diverged at a barrier (kind %d, task %d)\n",
+                       kind, base + g);
+          return;
+        }
+        g_fiber_barriers += f.barriers;
+        continue;
+      }
       std::barrier<> bar(nt);
       if (nt == 1) {
-        WgHost w{0, 1, red.data(), &bar};
+        WgHost w{0, 1, red.data(), &bar, nullptr};
         adj_run_task(w, a, kind, base + g);
         continue;
       }
@@ -44,7 +148,7 @@ struct HostExec {
       th.reserve(nt);
       for (int t = 0; t < nt; ++t)
         th.emplace_back([&, t] {
-          WgHost w{t, nt, red.data(), &bar};
+          WgHost w{t, nt, red.data(), &bar, nullptr};
           adj_run_task(w, a, kind, base + g);
         });
       for (auto& x : th) x.join();
@@ -132,6 +236,18 @@ extern "C" {
 void adj_host_set_chunking(int64_t chunk_rows, int max_chunks) {
   g_chunk_rows = chunk_rows;
   g_max_chunks = max_chunks;
+}
+
+// Lanes as fibers on the calling thread (on != 0) or as threads.  Returns,
+// and clears, whether a task's lanes diverged at a barrier since the last
+// call; *barriers gets the barrier count.
+int adj_host_set_fibers(int on, int64_t* barriers) {
+  g_fibers = on != 0;
+  const int e = g_fiber_error;
+  g_fiber_error = 0;
+  if (barriers) *barriers = g_fiber_barriers;
+  g_fiber_barriers = 0;
+  return e;
 }
 
 // Number of merges the last plan split, and their chunks.

@@ -161,6 +161,32 @@ def test_lane_count_does_not_change_the_result(case):
         assert np.max(np.abs(np.asarray(a) - np.asarray(r))) <= 1e-12 * max(1.0, np.max(np.abs(r)))
 
 
+def test_workgroup_of_256_lanes_as_fibers():
+    """The GPU's 256 lanes per workgroup, run as fibers: lane-count dependent
+    paths (dot products shared by 256/j lanes, reductions over 256 partial
+    sums) and every barrier reached by all lanes, with and without row
+    chunks."""
+    wl = G.make_gauss3d(n=200, m=180, h=0.7, leaf=50, tol=1e-6, d=8, cfg=52)
+    fs = adj.FrozenStructure(wl)
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal(wl["n"])
+    yb = rng.standard_normal(wl["m"])
+    ref = AH.vjp(fs, w, yb, nt=1)
+    AH.set_chunking(16, 32)
+    AH.set_fibers(True)
+    try:
+        got = AH.vjp(fs, w, yb, nt=256)
+        split = AH.last_split()[0]
+    finally:
+        diverged, barriers = AH.set_fibers(False)
+        AH.set_chunking()
+    assert not diverged
+    assert split > 0 and barriers > 0
+    for a, r in zip(got, ref):
+        a, r = np.asarray(a), np.asarray(r)
+        assert np.max(np.abs(a - r)) <= 1e-11 * max(1.0, np.max(np.abs(r)))
+
+
 @pytest.mark.parametrize("chunking", [None, (16, 32)])
 def test_no_data_race_under_thread_sanitizer(tmp_path, chunking):
     # both merge shapes: wide first-level merges (45 rows), tall ones above;
