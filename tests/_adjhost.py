@@ -45,8 +45,21 @@ def load():
         lib.adj_host_last_split.restype = None
         lib.adj_host_set_fibers.argtypes = [C.c_int, C.POINTER(C.c_int64)]
         lib.adj_host_set_fibers.restype = C.c_int
+        lib.adj_host_fiber_profile.argtypes = [p, p, p]
+        lib.adj_host_fiber_profile.restype = None
         _lib = lib
     return _lib
+
+
+def fiber_profile():
+    """{task kind: (critical path ns, barriers on it, launches)} of the fiber
+    runs since the last call."""
+    ns = np.zeros(32)
+    bar = np.zeros(32, dtype=np.int64)
+    nl = np.zeros(32, dtype=np.int64)
+    load().adj_host_fiber_profile(ns.ctypes.data_as(C.c_void_p), bar.ctypes.data_as(C.c_void_p),
+                                  nl.ctypes.data_as(C.c_void_p))
+    return {k: (float(ns[k]), int(bar[k]), int(nl[k])) for k in range(32) if nl[k]}
 
 
 def set_fibers(on):

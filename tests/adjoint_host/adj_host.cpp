@@ -16,6 +16,7 @@
 #include <ucontext.h>
 
 #include <barrier>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -51,6 +52,7 @@ struct Fibers {
   double* red = nullptr;
   int nt = 0, kind = 0, task = 0, cur = 0;
   int64_t barriers = 0;
+  double crit_ns = 0.0;  // sum over barrier intervals of the slowest lane's segment
   bool diverged = false;
 
   static thread_local Fibers* self;
@@ -89,13 +91,19 @@ struct Fibers {
       cur = t;
       makecontext(&ctx[t], (void (*)())entry, 0);
     }
+    using clk = std::chrono::steady_clock;
     for (;;) {
+      double seg_max = 0.0;
       for (int t = 0; t < nt; ++t) {
         if (state[t] == 2) continue;
         state[t] = 0;
         cur = t;
+        const auto t0 = clk::now();
         swapcontext(&sched, &ctx[t]);
+        const double ns = std::chrono::duration<double, std::nano>(clk::now() - t0).count();
+        seg_max = ns > seg_max ? ns : seg_max;
       }
+      crit_ns += seg_max;
       int done = 0;
       for (int t = 0; t < nt; ++t) done += state[t] == 2;
       if (done == nt) return true;
@@ -120,11 +128,17 @@ void WgHost::sync() {
 static bool g_fibers = false;
 static int g_fiber_error = 0;
 static int64_t g_fiber_barriers = 0;
+// per task kind: sum over launches of the slowest task's critical path (ns)
+// and of its barrier count, and the launches
+static double g_crit_ns[32];
+static int64_t g_crit_bar[32], g_crit_launches[32];
 
 struct HostExec {
   AdjArgs a;
   int nt;
   void launch(int kind, int base, int count) {
+    double crit = 0.0;
+    int64_t crit_bar = 0;
     for (int g = 0; g < count; ++g) {
       std::vector<double> red(nt, 0.0);
       if (g_fibers && nt > 1) {
@@ -136,6 +150,15 @@ struct HostExec {
           return;
         }
         g_fiber_barriers += f.barriers;
+        if (f.crit_ns > crit) {
+          crit = f.crit_ns;
+          crit_bar = f.barriers;
+        }
+        if (g + 1 == count && kind >= 0 && kind < 32) {
+          g_crit_ns[kind] += crit;
+          g_crit_bar[kind] += crit_bar;
+          ++g_crit_launches[kind];
+        }
         continue;
       }
       std::barrier<> bar(nt);
@@ -248,6 +271,21 @@ int adj_host_set_fibers(int on, int64_t* barriers) {
   if (barriers) *barriers = g_fiber_barriers;
   g_fiber_barriers = 0;
   return e;
+}
+
+// Fiber mode's critical-path profile per task kind (32 entries each): the
+// sum over launches of the slowest task's time summed over its barrier
+// intervals (each interval costing its slowest lane), its barriers, and
+// the launches; cleared after the call.
+void adj_host_fiber_profile(double* crit_ns, int64_t* barriers, int64_t* launches) {
+  for (int k = 0; k < 32; ++k) {
+    crit_ns[k] = g_crit_ns[k];
+    barriers[k] = g_crit_bar[k];
+    launches[k] = g_crit_launches[k];
+    g_crit_ns[k] = 0.0;
+    g_crit_bar[k] = 0;
+    g_crit_launches[k] = 0;
+  }
 }
 
 // Number of merges the last plan split, and their chunks.
