@@ -128,8 +128,9 @@ def records_from_oracle(fs):
             np.asarray(ranks, dtype=np.int32), dm, stride)
 
 
-def vjp(fs, w, ybar, nt=8, info=None):
-    """(gw, gh, gX, gY) of <ybar, A~ w> through the host emulation."""
+def vjp(fs, w, ybar, nt=8, info=None, want=("w", "h", "x", "y")):
+    """(gw, gh, gX, gY) of <ybar, A~ w> through the host emulation; None
+    (a null output pointer) for what is not in `want`."""
     lib = load()
     wl = fs.wl
     li, recs, ranks, dm, stride = info or records_from_oracle(fs)
@@ -143,13 +144,17 @@ def vjp(fs, w, ybar, nt=8, info=None):
     gX = np.zeros((m, dim))
     gY = np.zeros((n, dim))
     arena = C.c_int64(0)
-    ptr = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    gw = gw if "w" in want else None
+    gh = gh if "h" in want else None
+    gX = gX if "x" in want else None
+    gY = gY if "y" in want else None
     st = lib.adj_host_vjp(m, n, fs.L, dim, dm, stride, ptr(li), ptr(recs), ptr(ranks), ptr(X),
                           ptr(Y), float(wl["h"]), float(wl.get("gauss_c", 1.0)), ptr(w),
                           ptr(ybar), ptr(gw), ptr(gh), ptr(gX), ptr(gY), nt, C.byref(arena))
     if st != 0:
         raise RuntimeError(f"adj_host_vjp status {st}")
-    return gw, float(gh[0]), gX, gY
+    return gw, (None if gh is None else float(gh[0])), gX, gY
 
 
 def forward(fs, X=None, Y=None, h=None, nt=1):

@@ -161,6 +161,25 @@ def test_lane_count_does_not_change_the_result(case):
         assert np.max(np.abs(np.asarray(a) - np.asarray(r))) <= 1e-12 * max(1.0, np.max(np.abs(r)))
 
 
+def test_outputs_left_out_are_not_written():
+    """Null output pointers: only the wanted gradients are formed, and they
+    equal those of the full call (the reductions of the others are not
+    launched, and the root writes no w-gradient)."""
+    wl = G.make_gauss3d(n=400, m=360, h=0.7, leaf=100, tol=1e-6, d=8, cfg=51)
+    fs = adj.FrozenStructure(wl)
+    rng = np.random.default_rng(8)
+    w = rng.standard_normal(wl["n"])
+    yb = rng.standard_normal(wl["m"])
+    full = AH.vjp(fs, w, yb, nt=4)
+    for want in (("h",), ("w",), ("x", "y"), ("y",)):
+        got = AH.vjp(fs, w, yb, nt=4, want=want)
+        for key, g, r in zip(("w", "h", "x", "y"), got, full):
+            if key in want:
+                assert np.array_equal(np.asarray(g), np.asarray(r)), (want, key)
+            else:
+                assert g is None
+
+
 def test_workgroup_of_256_lanes_as_fibers():
     """The GPU's 256 lanes per workgroup, run as fibers: lane-count dependent
     paths (dot products shared by 256/j lanes, reductions over 256 partial
