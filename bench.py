@@ -8,12 +8,16 @@ library from the per-iteration block ranks) over its duration from HIP events
 on the call's stream, against the 8 TB/s HBM peak.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload helmholtz]
-                  [--no-cpu-baseline] [--no-comparisons]
+                  [--no-cpu-baseline] [--no-comparisons] [--no-adjoint]
 
 Besides the headline workload, the line carries "comparisons": mixed
 precision against plain FP64 (Gaussian 2000^2) and one batched call against
-one call per block (1024 Laplace blocks), measured in a child process that
-runs before this process uses the GPU.
+one call per block (1024 Laplace blocks); and "adjoint": the frozen-pivot
+adjoint on the differentiation workload (Gaussian 50000^2 in R^3, h = 0.7),
+that is the compression that records its pivots and ranks, the apply
+y = A~w and the gradients of <ybar, A~w> with respect to w, h and every
+point.  Each of the two runs in a child process of its own with a time
+limit, after the headline measurement, so that neither can change it.
 """
 import argparse
 import json
@@ -156,6 +160,65 @@ def comparisons(steps=5, warmup=1):
     print(json.dumps(out), flush=True)
 
 
+def adjoint(steps=3, warmup=1):
+    """The differentiation workload: compression with pivots and ranks
+    recorded, y = A~w, and hbaca_vjp (gradients with respect to w, h and the
+    points of both sides); prints one JSON object."""
+    import numpy as np
+    import torch
+
+    import paper_1901_06101_amd as hb
+    from workloads import make_config
+
+    hb.require_gpu()
+    dev = torch.device("cuda:0")
+    wl = make_config("gauss3d_adjoint")
+    X = torch.tensor(wl["X"], device=dev)
+    Y = torch.tensor(wl["Y"], device=dev)
+    p = hb.params(dim=3, h=wl["h"], gauss_c=wl["gauss_c"], seed=wl["seed"], record_tape=2)
+
+    def compress():
+        return hb.compress(wl["entry"], p, X, Y, wl["m"], wl["n"], wl["tol"], wl["d"],
+                           wl["leaf"])
+
+    def clock(fn, k):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(k):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / k, out
+
+    _note(f"adjoint: {wl['m']}x{wl['n']} compression with pivots recorded")
+    res = compress()
+    for _ in range(warmup):
+        compress().close()
+    c_ms, r2 = clock(compress, steps)
+    r2.close()
+    rng = np.random.default_rng(wl["seed"])
+    w = torch.tensor(rng.standard_normal(wl["n"]), device=dev)
+    b = torch.tensor(rng.standard_normal(wl["m"]), device=dev)
+    a_ms, y = clock(lambda: res.apply(w), steps)
+    yb = 2.0 * (y - b)
+    _note("adjoint: hbaca_vjp")
+    for _ in range(warmup):
+        res.vjp(w, yb)
+    v_ms, (gw, gh, gX, gY) = clock(lambda: res.vjp(w, yb), steps)
+    # w enters linearly: its gradient is the adjoint apply A~^T ybar
+    ref = res.apply(yb, adjoint=True)
+    check = float(torch.linalg.norm(gw - ref) / torch.linalg.norm(ref))
+    finite = bool(torch.isfinite(gh).all() and torch.isfinite(gX).all()
+                  and torch.isfinite(gY).all())
+    out = dict(workload=f"gauss3d_adjoint {wl['m']}x{wl['n']} h={wl['h']} tol={wl['tol']} "
+                        f"d={wl['d']} leaf={wl['leaf']}",
+               steps=steps, warmup=warmup, rank=res.rank(0), compress_recording_ms=c_ms,
+               apply_ms=a_ms, vjp_ms=v_ms, loss_and_gradient_ms=a_ms + v_ms,
+               w_grad_vs_adjoint_apply_rel=check, gradients_finite=finite)
+    _note(f"adjoint: vjp {v_ms:.1f} ms")
+    res.close()
+    print(json.dumps(out), flush=True)
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
     """Device-to-device copy rate in GB/s (bytes read plus bytes written),
     the measured counterpart of the HBM peak."""
@@ -182,11 +245,13 @@ def _note(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def run_comparisons(timeout=300):
+def run_child(flag, timeout=300):
+    """Runs this script with `flag` in a child process; its last JSON line,
+    or an error object."""
     import subprocess
-    _note("comparisons start in a child process")
+    _note(f"{flag[2:]} start in a child process")
     try:
-        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--comparisons"],
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), flag],
                            stdout=subprocess.PIPE, text=True, timeout=timeout)
     except subprocess.TimeoutExpired:
         return {"error": f"timed out after {timeout} s"}
@@ -204,19 +269,20 @@ def main():
     ap.add_argument("--workload", default="helmholtz")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparisons", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--comparisons", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--adjoint", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.comparisons:
         comparisons()
+        return
+    if args.adjoint:
+        adjoint()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); how H-BACA would "
               "shard over several GPUs is described in the design notes", file=sys.stderr)
         sys.exit(2)
-    # the comparisons run first, in a child process, before this process
-    # touches the GPU
-    comp = None if args.no_comparisons else run_comparisons()
-
     import numpy as np
     import torch
 
@@ -316,8 +382,11 @@ def main():
         except Exception as e:  # the GPU line is still reported
             out["cpu_baseline"] = {"value": None, "unit": "ms", "cores": None, "kind": "oracle",
                                    "sample": f"failed: {type(e).__name__}: {e}"}
-    if comp is not None:
-        out["comparisons"] = comp
+    # the legs beside the headline, each in a child process with a time limit
+    if not args.no_comparisons:
+        out["comparisons"] = run_child("--comparisons")
+    if not args.no_adjoint:
+        out["adjoint"] = run_child("--adjoint")
     print(json.dumps(out), flush=True)
 
 
