@@ -29,10 +29,11 @@
 //   fewer).
 //
 // Every task runs on one workgroup.  `W` supplies the lane id `tid`, the
-// lane count `nt` (a power of two), a reduction array `red` of nt doubles
+// lane count `nt`, a reduction array `red` of 3 nt + ADJ_RED_EXTRA doubles
 // and `sync()`, a barrier that every lane reaches.  Loops stride by nt over
 // disjoint outputs and a phase that reads another lane's output follows a
-// sync(), so the result does not depend on the lane count.
+// sync(), so the result does not depend on the lane count beyond the order
+// of rounding in sums.
 #pragma once
 
 #include <math.h>
@@ -49,6 +50,17 @@
 
 #define HBA_DMAX 32   // largest block size d of a replayed leaf
 #define HBA_MAXDIM 8  // largest point dimension
+
+// wg_svd shares each Jacobi pair over several lanes from this many columns
+// on (the host checks also build with 2, to run that path at small sizes)
+#ifndef ADJ_JACOBI_SPLIT_K
+#define ADJ_JACOBI_SPLIT_K 64
+#endif
+
+// `red` holds three doubles per lane (the pair sums of wg_svd) and
+// ADJ_RED_EXTRA more (the partial sums of wg_sum, at red[3 nt ..], which
+// nothing else touches)
+constexpr int ADJ_RED_EXTRA = 16;
 
 enum AdjTaskKind {
   ADJ_LEAF_FWD = 0,
@@ -148,14 +160,24 @@ struct AdjArgs {
 // --------------------------------------------------------------- helpers ---
 template <class W>
 HBA_FN double wg_sum(W& w, double v) {
+  // two barriers: ADJ_RED_EXTRA lanes each add a strided share of the nt
+  // values into the partial-sum slots red[3 nt ..], then every lane adds
+  // those.  Only the partial-sum slots are read after the second barrier,
+  // and no other code writes them (the next call does so past its first
+  // barrier), so red[0 .. 3 nt) is free again on return.
+  constexpr int P = ADJ_RED_EXTRA;
+  const int np = w.nt < P ? w.nt : P;
+  double* part = w.red + 3 * w.nt;
   w.red[w.tid] = v;
   w.sync();
-  for (int s = w.nt / 2; s > 0; s >>= 1) {
-    if (w.tid < s) w.red[w.tid] += w.red[w.tid + s];
-    w.sync();
+  if (w.tid < np) {
+    double s = 0.0;
+    for (int i = w.tid; i < w.nt; i += np) s += w.red[i];
+    part[w.tid] = s;
   }
-  const double r = w.red[0];
   w.sync();
+  double r = 0.0;
+  for (int c = 0; c < np; ++c) r += part[c];
   return r;
 }
 
@@ -196,12 +218,10 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
     // g lanes share each of the j dot products (rows interleaved) when
     // j <= nt / 2; their partial sums meet in red
     const int g = j > 0 && w.nt / j >= 2 ? w.nt / j : 1;
-    double nprev = 0.0;
-    if (j > 0) {
-      double part0 = 0.0;
-      for (int64_t l = w.tid; l < m; l += w.nt) part0 += Q[l + j * ldq] * Q[l + j * ldq];
-      nprev = sqrt(wg_sum(w, part0));
-    }
+    // nq: the norm of column j as it stands
+    double part0 = 0.0;
+    for (int64_t l = w.tid; l < m; l += w.nt) part0 += Q[l + j * ldq] * Q[l + j * ldq];
+    double nq = sqrt(wg_sum(w, part0));
     for (int pass = 0; j > 0 && pass < 4; ++pass) {
       if (g == 1) {
         for (int i = w.tid; i < j; i += w.nt) {
@@ -234,12 +254,11 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
       double pn = 0.0;
       for (int64_t l = w.tid; l < m; l += w.nt) pn += Q[l + j * ldq] * Q[l + j * ldq];
       const double nnow = sqrt(wg_sum(w, pn));
-      if (pass >= 1 && !(nnow < 0.5 * nprev)) break;
-      nprev = nnow;
+      const bool again = pass == 0 || nnow < 0.5 * nq;
+      nq = nnow;
+      if (!again) break;
     }
-    double part = 0.0;
-    for (int64_t l = w.tid; l < m; l += w.nt) part += Q[l + j * ldq] * Q[l + j * ldq];
-    const double nrm = sqrt(wg_sum(w, part));
+    const double nrm = nq;
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
     for (int64_t l = w.tid; l < m; l += w.nt) Q[l + j * ldq] *= inv;
     if (w.tid == 0) R[j + j * ldr] = nrm;
@@ -262,11 +281,67 @@ HBA_FN void wg_svd(W& w, int k, double* A, int64_t lda, double* Yo, int64_t ldy,
   }
   w.sync();
   const int kk = k + (k & 1);
+  const int npair = kk / 2;
+  // g lanes per pair (rows interleaved) when the pairs leave lanes idle and
+  // the columns are long enough for the split to outweigh the extra barrier
+  // per round; their partial sums meet in red[0 .. 3 npair g)
+  const int g = k >= ADJ_JACOBI_SPLIT_K && npair <= w.nt ? w.nt / npair : 1;
   const double tol = 4e-16 * (double)(k > 4 ? k : 4);
   for (int sweep = 0; sweep < 60; ++sweep) {
     int rot = 0;
     for (int rd = 0; rd < kk - 1; ++rd) {
-      for (int t = w.tid; t < kk / 2; t += w.nt) {
+      if (g > 1) {
+        if (w.tid < npair * g) {
+          const int t = w.tid / g, c0 = w.tid % g;
+          const int pa = t, pb = kk - 1 - t;
+          const int p = pa == 0 ? 0 : 1 + (pa - 1 + rd) % (kk - 1);
+          const int q = pb == 0 ? 0 : 1 + (pb - 1 + rd) % (kk - 1);
+          double al = 0.0, be = 0.0, ga = 0.0;
+          if (p < k && q < k)
+            for (int i = c0; i < k; i += g) {
+              const double x = Aw[i + p * k], y = Aw[i + q * k];
+              al += x * x;
+              be += y * y;
+              ga += x * y;
+            }
+          w.red[3 * w.tid] = al;
+          w.red[3 * w.tid + 1] = be;
+          w.red[3 * w.tid + 2] = ga;
+        }
+        w.sync();
+        if (w.tid < npair * g) {
+          const int t = w.tid / g, c0 = w.tid % g;
+          const int pa = t, pb = kk - 1 - t;
+          const int p = pa == 0 ? 0 : 1 + (pa - 1 + rd) % (kk - 1);
+          const int q = pb == 0 ? 0 : 1 + (pb - 1 + rd) % (kk - 1);
+          // every lane of the pair adds the partials in the same order, so
+          // all of them take the same rotation
+          double al = 0.0, be = 0.0, ga = 0.0;
+          for (int c = 0; c < g; ++c) {
+            al += w.red[3 * (t * g + c)];
+            be += w.red[3 * (t * g + c) + 1];
+            ga += w.red[3 * (t * g + c) + 2];
+          }
+          if (p < k && q < k && al > 0.0 && be > 0.0 &&
+              fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+            const double ze = (be - al) / (2.0 * ga);
+            const double tn = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + hypot(1.0, ze));
+            const double cs = 1.0 / sqrt(1.0 + tn * tn), sn = cs * tn;
+            for (int i = c0; i < k; i += g) {
+              const double x = Aw[i + p * k], y = Aw[i + q * k];
+              Aw[i + p * k] = cs * x - sn * y;
+              Aw[i + q * k] = sn * x + cs * y;
+              const double u = Yw[i + p * k], v = Yw[i + q * k];
+              Yw[i + p * k] = cs * u - sn * v;
+              Yw[i + q * k] = sn * u + cs * v;
+            }
+            if (c0 == 0) ++rot;
+          }
+        }
+        w.sync();
+        continue;
+      }
+      for (int t = w.tid; t < npair; t += w.nt) {
         const int pa = t, pb = kk - 1 - t;
         const int p = pa == 0 ? 0 : 1 + (pa - 1 + rd) % (kk - 1);
         const int q = pb == 0 ? 0 : 1 + (pb - 1 + rd) % (kk - 1);

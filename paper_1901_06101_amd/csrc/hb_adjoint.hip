@@ -17,7 +17,7 @@ struct WgDev {
 
 template <int KIND>
 __global__ __launch_bounds__(ADJ_NT) void adj_kernel(AdjArgs a, int base) {
-  __shared__ double red[ADJ_NT];
+  __shared__ double red[3 * ADJ_NT + ADJ_RED_EXTRA];
   WgDev w{(int)threadIdx.x, ADJ_NT, red};
   adj_run_task(w, a, KIND, base + (int)blockIdx.x);
 }

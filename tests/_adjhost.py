@@ -15,21 +15,27 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "adjoint_host", "adj_host.cpp")
 OUT = os.path.join(HERE, "adjoint_host", "_build")
 
-_lib = None
+_libs = {}
+
+# the build in which every Jacobi SVD shares its pairs over several lanes
+# (the library does so from 64 columns on)
+SPLIT_ALL = ("-DADJ_JACOBI_SPLIT_K=2",)
 
 
-def build(extra=()):
+def build(extra=(), name="adj_host"):
     os.makedirs(OUT, exist_ok=True)
-    so = os.path.join(OUT, "adj_host.so")
+    so = os.path.join(OUT, name + ".so")
     cmd = ["g++", "-std=c++20", "-O2", "-pthread", "-shared", "-fPIC", *extra, SRC, "-o", so]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     return so
 
 
-def load():
-    global _lib
-    if _lib is None:
-        lib = C.CDLL(build())
+def load(extra=()):
+    """The host build; `extra` are compile flags (SPLIT_ALL)."""
+    key = tuple(extra)
+    if key not in _libs:
+        name = "adj_host" + ("_split_all" if key else "")
+        lib = C.CDLL(build(key, name))
         p = C.c_void_p
         lib.adj_host_vjp.argtypes = [C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int,
                                      p, p, p, p, p, C.c_double, C.c_double, p, p, p, p, p, p,
@@ -47,39 +53,39 @@ def load():
         lib.adj_host_set_fibers.restype = C.c_int
         lib.adj_host_fiber_profile.argtypes = [p, p, p]
         lib.adj_host_fiber_profile.restype = None
-        _lib = lib
-    return _lib
+        _libs[key] = lib
+    return _libs[key]
 
 
-def fiber_profile():
+def fiber_profile(extra=()):
     """{task kind: (critical path ns, barriers on it, launches)} of the fiber
     runs since the last call."""
     ns = np.zeros(32)
     bar = np.zeros(32, dtype=np.int64)
     nl = np.zeros(32, dtype=np.int64)
-    load().adj_host_fiber_profile(ns.ctypes.data_as(C.c_void_p), bar.ctypes.data_as(C.c_void_p),
+    load(extra).adj_host_fiber_profile(ns.ctypes.data_as(C.c_void_p), bar.ctypes.data_as(C.c_void_p),
                                   nl.ctypes.data_as(C.c_void_p))
     return {k: (float(ns[k]), int(bar[k]), int(nl[k])) for k in range(32) if nl[k]}
 
 
-def set_fibers(on):
+def set_fibers(on, extra=()):
     """Lanes as fibers on one thread (on) or as threads; returns (diverged,
     barriers) for the calls since the last switch."""
     b = C.c_int64(0)
-    e = load().adj_host_set_fibers(1 if on else 0, C.byref(b))
+    e = load(extra).adj_host_set_fibers(1 if on else 0, C.byref(b))
     return bool(e), b.value
 
 
-def set_chunking(chunk_rows=512, max_chunks=32):
+def set_chunking(chunk_rows=512, max_chunks=32, extra=()):
     """Row chunking of tall merges for later calls (512 and 32 are the
     library's defaults)."""
-    load().adj_host_set_chunking(int(chunk_rows), int(max_chunks))
+    load(extra).adj_host_set_chunking(int(chunk_rows), int(max_chunks))
 
 
-def last_split():
+def last_split(extra=()):
     """(merges split over row chunks, chunks) in the last plan."""
     a, b = C.c_int(0), C.c_int(0)
-    load().adj_host_last_split(C.byref(a), C.byref(b))
+    load(extra).adj_host_last_split(C.byref(a), C.byref(b))
     return a.value, b.value
 
 
@@ -128,10 +134,10 @@ def records_from_oracle(fs):
             np.asarray(ranks, dtype=np.int32), dm, stride)
 
 
-def vjp(fs, w, ybar, nt=8, info=None, want=("w", "h", "x", "y")):
+def vjp(fs, w, ybar, nt=8, info=None, want=("w", "h", "x", "y"), extra=()):
     """(gw, gh, gX, gY) of <ybar, A~ w> through the host emulation; None
     (a null output pointer) for what is not in `want`."""
-    lib = load()
+    lib = load(extra)
     wl = fs.wl
     li, recs, ranks, dm, stride = info or records_from_oracle(fs)
     X = np.ascontiguousarray(np.asarray(wl["X"], dtype=np.float64).T)
@@ -157,10 +163,10 @@ def vjp(fs, w, ybar, nt=8, info=None, want=("w", "h", "x", "y")):
     return gw, (None if gh is None else float(gh[0])), gX, gY
 
 
-def forward(fs, X=None, Y=None, h=None, nt=1):
+def forward(fs, X=None, Y=None, h=None, nt=1, extra=()):
     """(U, S, Vt) of the frozen operator at points X, Y (point-major) and
     width h; the recorded ones by default."""
-    lib = load()
+    lib = load(extra)
     wl = fs.wl
     li, recs, ranks, dm, stride = records_from_oracle(fs)
     X = np.ascontiguousarray(np.asarray(wl["X"] if X is None else X, dtype=np.float64).T)
@@ -182,17 +188,18 @@ def forward(fs, X=None, Y=None, h=None, nt=1):
     return U[:r].T.copy(), S[:r].copy(), Vt[:r].T.copy()
 
 
-def build_tsan():
+def build_tsan(extra=()):
     """The stand-alone driver built with ThreadSanitizer."""
-    return _build_exe("adj_host_tsan", ["-fsanitize=thread"])
+    return _build_exe("adj_host_tsan" + ("_split_all" if extra else ""),
+                      ["-fsanitize=thread", *extra])
 
 
-def build_asan():
+def build_asan(extra=()):
     """The stand-alone driver built with AddressSanitizer and
     UndefinedBehaviorSanitizer (host code only)."""
-    return _build_exe("adj_host_asan", ["-fsanitize=address,undefined",
-                                        "-fno-sanitize-recover=undefined",
-                                        "-fno-omit-frame-pointer"])
+    return _build_exe("adj_host_asan" + ("_split_all" if extra else ""),
+                      ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                       "-fno-omit-frame-pointer", *extra])
 
 
 def _build_exe(name, flags):

@@ -140,7 +140,7 @@ struct HostExec {
     double crit = 0.0;
     int64_t crit_bar = 0;
     for (int g = 0; g < count; ++g) {
-      std::vector<double> red(nt, 0.0);
+      std::vector<double> red(3 * nt + ADJ_RED_EXTRA, 0.0);
       if (g_fibers && nt > 1) {
         Fibers f;
         if (!f.run(a, kind, base + g, red.data(), nt)) {

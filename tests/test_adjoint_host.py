@@ -180,25 +180,26 @@ def test_outputs_left_out_are_not_written():
                 assert g is None
 
 
-def test_workgroup_of_256_lanes_as_fibers():
+@pytest.mark.parametrize("extra", [(), AH.SPLIT_ALL], ids=["library", "jacobi_split_all"])
+def test_workgroup_of_256_lanes_as_fibers(extra):
     """The GPU's 256 lanes per workgroup, run as fibers: lane-count dependent
     paths (dot products shared by 256/j lanes, reductions over 256 partial
-    sums) and every barrier reached by all lanes, with and without row
-    chunks."""
+    sums, Jacobi pairs shared over lanes) and every barrier reached by all
+    lanes, with row chunks."""
     wl = G.make_gauss3d(n=200, m=180, h=0.7, leaf=50, tol=1e-6, d=8, cfg=52)
     fs = adj.FrozenStructure(wl)
     rng = np.random.default_rng(3)
     w = rng.standard_normal(wl["n"])
     yb = rng.standard_normal(wl["m"])
     ref = AH.vjp(fs, w, yb, nt=1)
-    AH.set_chunking(16, 32)
-    AH.set_fibers(True)
+    AH.set_chunking(16, 32, extra=extra)
+    AH.set_fibers(True, extra=extra)
     try:
-        got = AH.vjp(fs, w, yb, nt=256)
-        split = AH.last_split()[0]
+        got = AH.vjp(fs, w, yb, nt=256, extra=extra)
+        split = AH.last_split(extra)[0]
     finally:
-        diverged, barriers = AH.set_fibers(False)
-        AH.set_chunking()
+        diverged, barriers = AH.set_fibers(False, extra=extra)
+        AH.set_chunking(extra=extra)
     assert not diverged
     assert split > 0 and barriers > 0
     for a, r in zip(got, ref):
@@ -206,17 +207,19 @@ def test_workgroup_of_256_lanes_as_fibers():
         assert np.max(np.abs(a - r)) <= 1e-11 * max(1.0, np.max(np.abs(r)))
 
 
-@pytest.mark.parametrize("chunking", [None, (16, 32)])
-def test_no_data_race_under_thread_sanitizer(tmp_path, chunking):
+@pytest.mark.parametrize("chunking,nt,extra", [(None, 4, ()), ((16, 32), 4, ()),
+                                               ((16, 32), 32, AH.SPLIT_ALL)])
+def test_no_data_race_under_thread_sanitizer(tmp_path, chunking, nt, extra):
     # both merge shapes: wide first-level merges (45 rows), tall ones above;
-    # with small row chunks the tall ones run split
+    # with small row chunks the tall ones run split; with 32 lanes and every
+    # Jacobi SVD split, pairs are shared over lanes
     wl = G.make_gauss3d(n=200, m=180, h=0.7, leaf=50, tol=1e-6, d=8, cfg=52)
     fs = adj.FrozenStructure(wl)
     rng = np.random.default_rng(1)
     w = rng.standard_normal(wl["n"])
     yb = rng.standard_normal(wl["m"])
-    exe = AH.build_tsan()
-    rc, err, outs = AH.run_exe(exe, fs, w, yb, 4, str(tmp_path), chunking)
+    exe = AH.build_tsan(extra)
+    rc, err, outs = AH.run_exe(exe, fs, w, yb, nt, str(tmp_path), chunking)
     assert rc == 0, err[-4000:]
     assert "ThreadSanitizer" not in err
     ref = AH.vjp(fs, w, yb, nt=1)
@@ -224,15 +227,16 @@ def test_no_data_race_under_thread_sanitizer(tmp_path, chunking):
         assert np.max(np.abs(np.asarray(a) - np.asarray(r))) <= 1e-12 * max(1.0, np.max(np.abs(r)))
 
 
-@pytest.mark.parametrize("chunking", [None, (16, 32)])
-def test_no_memory_error_under_address_sanitizer(tmp_path, chunking):
+@pytest.mark.parametrize("chunking,nt,extra", [(None, 2, ()), ((16, 32), 2, ()),
+                                               ((16, 32), 32, AH.SPLIT_ALL)])
+def test_no_memory_error_under_address_sanitizer(tmp_path, chunking, nt, extra):
     wl = G.make_gauss3d(n=200, m=180, h=0.7, leaf=50, tol=1e-6, d=8, cfg=52)
     fs = adj.FrozenStructure(wl)
     rng = np.random.default_rng(2)
     w = rng.standard_normal(wl["n"])
     yb = rng.standard_normal(wl["m"])
-    exe = AH.build_asan()
-    rc, err, outs = AH.run_exe(exe, fs, w, yb, 2, str(tmp_path), chunking)
+    exe = AH.build_asan(extra)
+    rc, err, outs = AH.run_exe(exe, fs, w, yb, nt, str(tmp_path), chunking)
     assert rc == 0, err[-4000:]
     assert "Sanitizer" not in err and "runtime error" not in err
     ref = AH.vjp(fs, w, yb, nt=2)
@@ -240,10 +244,12 @@ def test_no_memory_error_under_address_sanitizer(tmp_path, chunking):
         assert np.max(np.abs(np.asarray(a) - np.asarray(r))) <= 1e-12 * max(1.0, np.max(np.abs(r)))
 
 
+@pytest.mark.parametrize("extra", [(), AH.SPLIT_ALL], ids=["library", "jacobi_split_all"])
 @pytest.mark.parametrize("name,chunk", [("n400", 16), ("n700", 8)])
-def test_merges_split_over_row_chunks(name, chunk):
+def test_merges_split_over_row_chunks(name, chunk, extra):
     """Tall merges run as row chunks (a two-level thin QR, per-chunk partial
-    sums): forced small chunks make every merge above the first level split."""
+    sums): forced small chunks make every merge above the first level split.
+    The second build shares every Jacobi pair over lanes."""
     wl = {"n400": lambda: G.make_gauss3d(n=400, m=360, h=0.7, leaf=100, tol=1e-6, d=8, cfg=51),
           "n700": lambda: G.make_gauss3d(n=700, m=650, h=0.6, leaf=90, tol=1e-5, d=16,
                                          cfg=53)}[name]()
@@ -253,13 +259,13 @@ def test_merges_split_over_row_chunks(name, chunk):
     b = rng.standard_normal(wl["m"])
     _, gw, gh, gX, gY = adj.frozen_gradients(fs, w, b)
     yb = _ybar(fs, w, b)
-    AH.set_chunking(chunk, 32)
+    AH.set_chunking(chunk, 32, extra=extra)
     try:
-        U, S, Vt = AH.forward(fs)
-        assert AH.last_split()[0] > 0
-        hw, hh, hX, hY = AH.vjp(fs, w, yb, nt=4)
+        U, S, Vt = AH.forward(fs, extra=extra)
+        assert AH.last_split(extra)[0] > 0
+        hw, hh, hX, hY = AH.vjp(fs, w, yb, nt=4, extra=extra)
     finally:
-        AH.set_chunking()
+        AH.set_chunking(extra=extra)
     A = fs.res.dense()
     assert np.linalg.norm((U * S) @ Vt.T - A) <= 1e-11 * np.linalg.norm(A)
     assert _rel(hw, gw) <= 1e-10
