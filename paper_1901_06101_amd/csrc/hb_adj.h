@@ -120,10 +120,11 @@ struct AdjMerge {
   int64_t Ub, Y, S;    // rows x p, k x p, p
   int64_t ws_f, ws_b;  // G == 1
   // G > 1: B and then each chunk's Q (rows x k), the chunks' R stacked and
-  // then their Q' (G k x k), Q' X (G k x k), per-chunk partial sums
+  // then their Q' (G k x k), Q' X (G k x k, each chunk forms its k rows),
+  // the SVD's left factor X (k x k), per-chunk partial sums
   // (G x (2 k rho + k)), and the reverse rule's J (k x rho), G Y^T (k x k)
   // and E2 (k x rho)
-  int64_t Bq, Rs, QX, part, Jm, H, E2;
+  int64_t Bq, Rs, QX, Xs, part, Jm, H, E2;
   int64_t ws_f2, ws_b2;
 };
 
@@ -999,13 +1000,13 @@ HBA_FN void adj_mch_fwd2(W& w, const AdjArgs& a, int mi) {
   const int k = M.k;
   const int64_t gk = (int64_t)M.G * k;
   double* D = a.D;
-  double* R = a.ws + M.ws_f2;  // k x k
-  double* Aw = R + k * k;
+  double* Aw = a.ws + M.ws_f2;  // k x k
   double* Yw = Aw + k * k;
-  double* hs = Yw + k * k;     // gk + k
-  wg_qr(w, gk, k, D + M.Rs, gk, D + M.Rs, gk, R, k, hs);
-  wg_svd(w, k, R, k, D + M.Y, k, D + M.S, Aw, Yw, hs);
-  wg_gemm(w, gk, k, k, 1.0, D + M.Rs, gk, 0, R, k, 0, 0.0, D + M.QX, gk);
+  double* hs = Yw + k * k;      // gk + k
+  // the stacked R's = Q' R; R goes to Xs, where the SVD R = X diag(s) Y^T
+  // leaves X
+  wg_qr(w, gk, k, D + M.Rs, gk, D + M.Rs, gk, D + M.Xs, k, hs);
+  wg_svd(w, k, D + M.Xs, k, D + M.Y, k, D + M.S, Aw, Yw, hs);
 }
 
 template <class W>
@@ -1018,8 +1019,10 @@ HBA_FN void adj_mch_fwd3(W& w, const AdjArgs& a, int ci) {
   const int64_t gk = (int64_t)M.G * k;
   const AdjSides sd = adj_sides(a, M);
   double* D = a.D;
-  wg_gemm(w, len, k, k, 1.0, D + M.Bq + Ch.p0, rows, 0, D + M.QX + (int64_t)Ch.c * k, gk, 0,
-          0.0, D + M.Ub + Ch.p0, rows);
+  // this chunk's k rows of Q' X, then its rows of Ub = Q_c (Q' X)_c
+  double* QXc = D + M.QX + (int64_t)Ch.c * k;
+  wg_gemm(w, k, k, k, 1.0, D + M.Rs + (int64_t)Ch.c * k, gk, 0, D + M.Xs, k, 0, 0.0, QXc, gk);
+  wg_gemm(w, len, k, k, 1.0, D + M.Bq + Ch.p0, rows, 0, QXc, gk, 0, 0.0, D + M.Ub + Ch.p0, rows);
   const AdjBlock& out = a.blocks[M.out];
   double* On = D + (M.horiz ? out.Vt : out.U);
   const int64_t a0 = Ch.o0, a1 = Ch.o1 < n1 ? Ch.o1 : n1;

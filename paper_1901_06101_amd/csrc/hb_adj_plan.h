@@ -248,6 +248,7 @@ inline int adj_plan(const AdjPlanIn& in, AdjPlan& P) {
         M.Bq = take(M.rows * k);
         M.Rs = take(gk * k);
         M.QX = take(gk * k);
+        M.Xs = take(k * k);
         M.part = take(M.G * (2 * k * rho + k));
         M.Jm = take(k * rho);
         M.H = take(k * k);
@@ -316,7 +317,7 @@ inline int adj_plan(const AdjPlanIn& in, AdjPlan& P) {
       else if (ph.kind == ADJ_MERGE_BWD)
         M.ws_b = piece(k * rho + 2 * p * rho + p * p + p * k + k * rho + M.rows * (rho + k));
       else if (ph.kind == ADJ_MCH_FWD2)
-        M.ws_f2 = piece(3 * k * k + (int64_t)M.G * k + k);
+        M.ws_f2 = piece(2 * k * k + (int64_t)M.G * k + k);
       else if (ph.kind == ADJ_MCH_BWD2)
         M.ws_b2 = piece(2 * k * rho + k * k);
     }
