@@ -202,13 +202,19 @@ def build_asan(extra=()):
                        "-fno-omit-frame-pointer", *extra])
 
 
+_exes = {}
+
+
 def _build_exe(name, flags):
-    os.makedirs(OUT, exist_ok=True)
-    exe = os.path.join(OUT, name)
-    cmd = ["g++", "-std=c++20", "-O1", "-g", *flags, "-pthread", "-DADJ_HOST_MAIN", SRC, "-o",
-           exe]
-    subprocess.run(cmd, check=True, capture_output=True, text=True)
-    return exe
+    """Builds the stand-alone driver once per process and flag set."""
+    if name not in _exes:
+        os.makedirs(OUT, exist_ok=True)
+        exe = os.path.join(OUT, name)
+        cmd = ["g++", "-std=c++20", "-O1", "-g", *flags, "-pthread", "-DADJ_HOST_MAIN", SRC,
+               "-o", exe]
+        subprocess.run(cmd, check=True, capture_output=True, text=True)
+        _exes[name] = exe
+    return _exes[name]
 
 
 def run_exe(exe, fs, w, ybar, nt, workdir, chunking=None):

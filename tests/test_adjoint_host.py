@@ -212,7 +212,8 @@ def test_workgroup_of_256_lanes_as_fibers(extra):
 def test_no_data_race_under_thread_sanitizer(tmp_path, chunking, nt, extra):
     # both merge shapes: wide first-level merges (45 rows), tall ones above;
     # with small row chunks the tall ones run split; with 32 lanes and every
-    # Jacobi SVD split, pairs are shared over lanes
+    # Jacobi SVD split, the leaf re-compressions' pairs (21 to 29 columns)
+    # are shared by two lanes each
     wl = G.make_gauss3d(n=200, m=180, h=0.7, leaf=50, tol=1e-6, d=8, cfg=52)
     fs = adj.FrozenStructure(wl)
     rng = np.random.default_rng(1)
