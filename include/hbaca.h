@@ -216,8 +216,9 @@ hb_status hbaca_apply(const hb_result* res, int64_t block, const void* in, void*
  * grad_points_col: DEVICE, n x dim FP64 in the layout of points_col.
  * Any gradient pointer may be NULL to skip it.  The call allocates its own
  * device workspace (the replayed factors, the saved blocks of every
- * iteration and merge, and the cotangents), runs on `stream` and
- * synchronises it before returning.  The replay assumes the frozen ranks sit at a gap
+ * iteration and merge, and the cotangents: about 11.3 GB for a 50000 x
+ * 50000 Gaussian with leaves of 1563 and root rank 63; HB_ENOMEM when it
+ * cannot), runs on `stream` and synchronises it before returning.  The replay assumes the frozen ranks sit at a gap
  * of the singular values (distinct kept values, separated from the dropped
  * ones); where they do not, the gradient is not defined and the result is
  * not finite.
