@@ -213,6 +213,7 @@ def adjoint(steps=3, warmup=1):
                         f"d={wl['d']} leaf={wl['leaf']}",
                steps=steps, warmup=warmup, rank=res.rank(0), compress_recording_ms=c_ms,
                apply_ms=a_ms, vjp_ms=v_ms, loss_and_gradient_ms=a_ms + v_ms,
+               vjp_over_compression=v_ms / c_ms,
                w_grad_vs_adjoint_apply_rel=check, gradients_finite=finite)
     _note(f"adjoint: vjp {v_ms:.1f} ms")
     res.close()
