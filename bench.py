@@ -241,6 +241,17 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
         return None
 
 
+def _finite(x):
+    """x with every non-finite float replaced by None (strict JSON)."""
+    if isinstance(x, float):
+        return x if x == x and abs(x) != float("inf") else None
+    if isinstance(x, dict):
+        return {k: _finite(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_finite(v) for v in x]
+    return x
+
+
 def _note(msg):
     """Progress of the run on stderr (stdout carries only the JSON line)."""
     print(f"bench: {msg}", file=sys.stderr, flush=True)
@@ -388,7 +399,7 @@ def main():
         out["comparisons"] = run_child("--comparisons")
     if not args.no_adjoint:
         out["adjoint"] = run_child("--adjoint")
-    print(json.dumps(out), flush=True)
+    print(json.dumps(_finite(out)), flush=True)
 
 
 if __name__ == "__main__":

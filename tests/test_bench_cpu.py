@@ -26,3 +26,14 @@ def test_cpu_baseline_fields():
     assert out["kind"] == "oracle" and out["unit"] == "ms"
     assert out["value"] > 0 and out["cores"] >= 1
     assert out["rank"] > 0 and out["sample"]
+
+
+def test_non_finite_values_become_null():
+    sys.path.insert(0, ROOT)
+    import json
+
+    import bench
+    out = bench._finite({"a": float("nan"), "b": [1.0, float("inf")], "c": {"d": -float("inf")},
+                         "e": 2, "f": "x", "g": 0.5})
+    assert out == {"a": None, "b": [1.0, None], "c": {"d": None}, "e": 2, "f": "x", "g": 0.5}
+    json.loads(json.dumps(out), parse_constant=lambda c: (_ for _ in ()).throw(ValueError(c)))
