@@ -37,3 +37,212 @@ def test_non_finite_values_become_null():
                          "e": 2, "f": "x", "g": 0.5})
     assert out == {"a": None, "b": [1.0, None], "c": {"d": None}, "e": 2, "f": "x", "g": 0.5}
     json.loads(json.dumps(out), parse_constant=lambda c: (_ for _ in ()).throw(ValueError(c)))
+
+
+def test_adjoint_leg_runs_against_a_stand_in_library(monkeypatch, capsys):
+    """The adjoint leg's own code (calls, timing, checks, JSON fields) run on
+    the CPU against a stand-in for the library whose result applies the
+    factors of a dense SVD; the library itself is tested on the GPU."""
+    import json
+    import types
+
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads
+    from workloads import generators as G
+
+    wl = G.make_gauss3d(n=120, m=100, h=0.7, leaf=30, tol=1e-6, d=8, cfg=71)
+
+    class StandIn:
+        def __init__(self, A):
+            U, S, Vt = np.linalg.svd(A, full_matrices=False)
+            r = int(np.sum(S > 1e-6 * S[0]))
+            self.U, self.S, self.V = (torch.tensor(U[:, :r]), torch.tensor(S[:r]),
+                                      torch.tensor(Vt[:r].T))
+
+        def rank(self, block=0):
+            return int(self.S.numel())
+
+        def apply(self, w, block=0, adjoint=False):
+            if adjoint:
+                return self.V @ (self.S * (self.U.T @ w))
+            return self.U @ (self.S * (self.V.T @ w))
+
+        def vjp(self, w, ybar, want=("w", "h", "x", "y")):
+            gw = self.apply(ybar, adjoint=True)
+            return gw, torch.zeros(1, dtype=torch.float64), torch.zeros(wl["m"], 3), \
+                torch.zeros(wl["n"], 3)
+
+        def close(self):
+            pass
+
+    A = np.exp(-((wl["X"][:, None, :] - wl["Y"][None, :, :]) ** 2).sum(-1) / wl["h"] ** 2)
+    fake = types.SimpleNamespace(
+        require_gpu=lambda: None,
+        params=lambda **kw: kw,
+        compress=lambda entry, p, X, Y, m, n, tol, d, leaf: StandIn(A))
+    monkeypatch.setitem(sys.modules, "paper_1901_06101_amd", fake)
+    monkeypatch.setattr(workloads, "make_config", lambda name, scale=1.0: wl)
+    orig_device = torch.device
+    monkeypatch.setattr(torch, "device", lambda *a, **k: orig_device("cpu"))
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    bench.adjoint(steps=2, warmup=1)
+    line = [s for s in capsys.readouterr().out.splitlines() if s.startswith("{")][-1]
+    out = json.loads(line)
+    for key in ("workload", "rank", "compress_recording_ms", "apply_ms", "vjp_ms",
+                "loss_and_gradient_ms", "vjp_over_compression", "w_grad_vs_adjoint_apply_rel",
+                "gradients_finite"):
+        assert key in out, key
+    assert out["w_grad_vs_adjoint_apply_rel"] == 0.0
+    assert out["gradients_finite"] is True
+
+
+def test_comparisons_leg_runs_against_a_stand_in_library(monkeypatch, capsys):
+    """The comparisons leg's own code (mixed against FP64, batched against one
+    call per block) run on the CPU against a stand-in for the library that
+    returns fixed small factors; the library itself is tested on the GPU."""
+    import json
+    import types
+
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads
+    from workloads import generators as G
+
+    rng = np.random.default_rng(3)
+    U0 = torch.tensor(np.linalg.qr(rng.standard_normal((40, 5)))[0])
+    V0 = torch.tensor(np.linalg.qr(rng.standard_normal((30, 5)))[0])
+    S0 = torch.tensor([5.0, 3.0, 1.0, 0.5, 0.1], dtype=torch.float64)
+
+    class StandIn:
+        def __init__(self, nblocks=1, shift=0.0):
+            self.nblocks = nblocks
+            self.shift = shift
+
+        def rank(self, block=0):
+            return 5
+
+        def factors(self, block=0):
+            return U0, S0 + self.shift, V0
+
+        def error(self, block=0, row_stride=1):
+            return 1e-14, 1.0
+
+        def close(self):
+            pass
+
+    fake = types.SimpleNamespace(
+        HB_PREC_FP64=0, HB_PREC_MIXED=1,
+        require_gpu=lambda: None,
+        params=lambda **kw: kw,
+        compress=lambda *a: StandIn(1, 1e-9 * a[1].get("precision", 0)),
+        compress_batched=lambda *a: StandIn(len(a[3])))
+    nb = 1024
+    cnt = np.full(nb, 2, dtype=np.int64)
+    off = np.arange(nb, dtype=np.int64) * 2
+    blocks = dict(X=rng.random((2 * nb, 3)), Y=rng.random((2 * nb, 3)) + 3.0, row_off=off,
+                  row_cnt=cnt, col_off=off, col_cnt=cnt, seed=3000, entry=2, tol=1e-4, d=8,
+                  leaf=64)
+    wl = G.make_gauss3d(n=60, leaf=30, cfg=72)
+    monkeypatch.setitem(sys.modules, "paper_1901_06101_amd", fake)
+    monkeypatch.setattr(workloads, "make_config", lambda name, scale=1.0: wl)
+    monkeypatch.setattr(G, "make_laplace_blocks", lambda nblocks, cfg: blocks)
+    orig_device = torch.device
+    monkeypatch.setattr(torch, "device", lambda *a, **k: orig_device("cpu"))
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    bench.comparisons(steps=1, warmup=1)
+    line = [s for s in capsys.readouterr().out.splitlines() if s.startswith("{")][-1]
+    out = json.loads(line)
+    mv = out["mixed_vs_fp64"]
+    assert mv["fp64_rank"] == 5 and mv["mixed_within_5tol"] is True
+    assert 0.0 < mv["mixed_vs_fp64_operator_rel_diff"] < 1e-8
+    bs = out["batched_vs_sequential"]
+    for key in ("sequential_fp64_ms", "batched_fp64_ms", "batched_mixed_ms",
+                "speedup_batched_fp64", "speedup_batched_mixed", "max_rel_err_rows7_fp64",
+                "max_rel_err_rows7_mixed", "mixed_within_5tol"):
+        assert key in bs, key
+
+
+def test_json_line_contract_with_a_stand_in_library(monkeypatch, capsys):
+    """main()'s line on the CPU with a stand-in library (the legs in child
+    processes switched off): the fields the line must carry, the roofline
+    object, and the CPU baseline from the oracle on a small workload."""
+    import json
+    import types
+
+    import torch
+
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads
+    from workloads import generators as G
+
+    wl = G.make_gauss3d(n=200, leaf=50, tol=1e-6, d=8, cfg=73)
+
+    class StandIn:
+        def stats(self):
+            return dict(ms_baca=1.0, resid_bytes=2e9, resid_flops=1e9, recompress_flops=1e9,
+                        merge_flops=2e9, ms_setup=0.1, ms_recompress=0.5, ms_merge=2.0,
+                        ms_total=3.6)
+
+        def error(self, block=0, row_stride=1):
+            return 1e-14, 1.0
+
+        def rank(self, block=0):
+            return 17
+
+        def close(self):
+            pass
+
+    fake = types.SimpleNamespace(HB_K_LOWRANK_SPIKES=4, require_gpu=lambda: None,
+                                 params=lambda **kw: kw, compress=lambda *a: StandIn())
+    monkeypatch.setitem(sys.modules, "paper_1901_06101_amd", fake)
+    monkeypatch.setattr(workloads, "make_config", lambda name, scale=1.0: wl)
+    orig_device = torch.device
+    monkeypatch.setattr(torch, "device", lambda *a, **k: orig_device("cpu"))
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    monkeypatch.setattr(bench, "copy_bandwidth", lambda torch: 5000.0)
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--steps", "2", "--warmup", "1",
+                                      "--no-comparisons", "--no-adjoint"])
+    bench.main()
+    lines = [s for s in capsys.readouterr().out.splitlines() if s.strip()]
+    assert len(lines) == 1
+    out = json.loads(lines[0])
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config"):
+        assert key in out, key
+    assert out["n_gpus"] == 1 and out["steps"] == 2 and out["warmup"] == 1
+    assert out["value"] == out["ms_per_step"] and out["higher_is_better"] is False
+    assert "workload" in out["config"]
+    rf = out["roofline"]
+    assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
+    assert abs(rf["achieved"] - 2000.0) < 1e-9 and abs(rf["frac"] - 0.25) < 1e-12
+    assert "traffic" in rf
+    cb = out["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1
+    assert "comparisons" not in out and "adjoint" not in out
+
+
+def test_a_failing_leg_becomes_an_error_object(monkeypatch):
+    sys.path.insert(0, ROOT)
+    import subprocess
+    import types
+
+    import bench
+
+    def failing(*a, **k):
+        return types.SimpleNamespace(returncode=1, stdout="no json here\n")
+
+    def slow(*a, **k):
+        raise subprocess.TimeoutExpired(cmd="bench.py", timeout=k.get("timeout", 1))
+
+    monkeypatch.setattr(subprocess, "run", failing)
+    assert "error" in bench.run_child("--adjoint")
+    monkeypatch.setattr(subprocess, "run", slow)
+    assert "timed out" in bench.run_child("--comparisons", timeout=5)["error"]
