@@ -3,7 +3,8 @@ leaves in FP32, FP64 merges per step) against the FP64 oracle per block.
 
 The bars are those of the single problems: the compressed operators agree
 to 5 tol relative (Frobenius norm of the difference, from the factors), and
-the ranks stay within 3 of the oracle's."""
+the ranks stay within max(3, 10 %) of the oracle's (FP32 residuals may
+choose other pivots)."""
 import pytest
 
 from workloads import generators as G
@@ -29,4 +30,4 @@ def test_mixed_batched_laplace_blocks(lib):
         U, S, Vh = factors_np(res, b)
         diff = lowrank_diff(U * S, Vh, ref.U * ref.S, ref.V.T)
         assert diff <= 5 * wl["tol"] * recon_norm(ref.U * ref.S, ref.V.T), b
-        assert abs(S.size - ref.rank) <= 3, (b, S.size, ref.rank)
+        assert abs(S.size - ref.rank) <= max(3, ref.rank // 10), (b, S.size, ref.rank)
