@@ -228,6 +228,21 @@ hb_status hbaca_vjp(const hb_result* res, const double* w, const double* ybar, d
                     void* stream);
 
 /*
+ * hbaca_vjp for FP32 vectors, as the differentiation workload draws w and b:
+ * w (n) and ybar (m) are widened to FP64 on the device, the frozen pipeline
+ * is replayed and reversed in FP64 exactly as by hbaca_vjp, and the
+ * w-gradient is rounded to FP32 into wbar (n).  hbar (1), points_row_bar
+ * (m x dim) and points_col_bar (n x dim) are FP64 as in hbaca_vjp.  All
+ * pointers are DEVICE; wbar, hbar and the point gradients may be NULL to
+ * skip them.  Same requirements, errors and workspace as hbaca_vjp, plus
+ * 8 (2n + m) bytes for the widened vectors; synchronises `stream` before
+ * returning.
+ */
+hb_status hbaca_adjoint(const hb_result* res, const float* w, const float* ybar, float* wbar,
+                        double* hbar, double* points_row_bar, double* points_col_bar,
+                        void* stream);
+
+/*
  * The frozen operator at new parameters: the pipeline recorded in `tape`
  * (same requirements as hbaca_vjp) replayed in FP64 with the same pivots
  * and ranks, at new points and a new Gaussian width, without any new

@@ -234,6 +234,28 @@ class Result:
                                      _ptr(gY), _stream()), "hbaca_vjp")
         return gw, gh, gX, gY
 
+    def adjoint(self, w, ybar, want=("w", "h", "x", "y")):
+        """vjp for FP32 vectors (hbaca_adjoint): w and ybar in FP32, the
+        w-gradient in FP32, the h and point gradients in FP64; None where
+        not in `want`."""
+        import torch
+        m, n = self.shape(0)
+        X = self._keep[0]
+        dim = int(X.shape[1])
+        w = w.to(dtype=torch.float32).contiguous()
+        ybar = ybar.to(dtype=torch.float32).contiguous()
+        if w.numel() != n or ybar.numel() != m:
+            raise ValueError(f"w of length {w.numel()} and ybar of length {ybar.numel()} "
+                             f"for a {m} x {n} operator")
+        f64 = dict(dtype=torch.float64, device=w.device)
+        gw = torch.empty((n,), dtype=torch.float32, device=w.device) if "w" in want else None
+        gh = torch.empty((1,), **f64) if "h" in want else None
+        gX = torch.empty((m, dim), **f64) if "x" in want else None
+        gY = torch.empty((n, dim), **f64) if "y" in want else None
+        B._check(self._lib.hbaca_adjoint(self._h, _ptr(w), _ptr(ybar), _ptr(gw), _ptr(gh),
+                                         _ptr(gX), _ptr(gY), _stream()), "hbaca_adjoint")
+        return gw, gh, gX, gY
+
     def recompute_frozen(self, X, Y, h, gauss_c=1.0):
         """The frozen operator (same pivots and ranks as this result, which
         needs record_tape=2) at new points X, Y and width h, as a new

@@ -22,7 +22,7 @@ EXPORTED = (
     "hbaca_compress", "hbaca_compress_batched", "hb_result_nblocks", "hb_result_rank",
     "hb_result_rows", "hb_result_cols", "hb_result_is_complex", "hb_result_copy",
     "hb_result_stats", "hb_result_nleaves", "hb_result_leaf_info", "hb_result_leaf_tape",
-    "hb_result_error", "hb_result_free", "hb_status_string", "hbaca_apply", "hbaca_vjp",
+    "hb_result_error", "hb_result_free", "hb_status_string", "hbaca_apply", "hbaca_vjp", "hbaca_adjoint",
     "hbaca_recompute_frozen", "hb_partition", "hb_result_leaf_frozen", "hb_result_merge_ranks",
 )
 
@@ -128,6 +128,8 @@ def load(path: str = LIB_PATH):
     lib.hbaca_apply.restype = C.c_int
     lib.hbaca_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hbaca_vjp.restype = C.c_int
+    lib.hbaca_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hbaca_adjoint.restype = C.c_int
     lib.hbaca_recompute_frozen.argtypes = [vp, C.POINTER(HbParams), vp, vp, vp, C.POINTER(vp)]
     lib.hbaca_recompute_frozen.restype = C.c_int
     lib.hb_partition.argtypes = [i64, i64, i32, i32, C.c_uint64, C.POINTER(i32), vp, vp]

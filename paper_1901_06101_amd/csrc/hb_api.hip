@@ -246,6 +246,17 @@ __global__ void aos_to_soa_kernel(const double* __restrict__ src, double* __rest
   for (int c = 0; c < dim; ++c) dst[(int64_t)c * npts + i] = src[i * dim + c];
 }
 
+// FP32 vectors to FP64 and back (the adjoint's FP32 entry point).
+__global__ void widen_kernel(const float* __restrict__ src, double* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (double)src[i];
+}
+
+__global__ void narrow_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
 // Compressed operator applied to a vector: y = U diag(S) Vh^H w, or its
 // adjoint w~ = Vh diag(S) U^H y.  First t_j = S_j sum_i conj(X(i, j)) v_i for
 // every column j of X (one workgroup per column, a deterministic tree sum),
@@ -2381,15 +2392,58 @@ hb_status hbaca_recompute_frozen(const hb_result* tape, const hb_params* params,
   }
 }
 
+// A result the adjoint can replay: a single real Gaussian problem compressed
+// with its frozen structure recorded.
+static hb_status vjp_check(const hb_result* r) {
+  if (r->entry != HB_K_GAUSS || r->scalar != 0) return HB_EUNSUPPORTED;
+  if (!r->fz_complete || r->fz_stride < 6 || r->problems.size() != 1) return HB_EINVAL;
+  return HB_OK;
+}
+
 hb_status hbaca_vjp(const hb_result* r, const double* w, const double* ybar, double* grad_w,
                     double* grad_h, double* grad_points_row, double* grad_points_col,
                     void* stream) {
   if (!r || !w || !ybar) return HB_EINVAL;
-  if (r->entry != HB_K_GAUSS || r->scalar != 0) return HB_EUNSUPPORTED;
-  if (!r->fz_complete || r->fz_stride < 6 || r->problems.size() != 1) return HB_EINVAL;
+  const hb_status ok = vjp_check(r);
+  if (ok != HB_OK) return ok;
   try {
     return vjp_run(r, w, ybar, grad_w, grad_h, grad_points_row, grad_points_col,
                    (hipStream_t)stream);
+  } catch (const HbError& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    return HB_ENOMEM;
+  }
+}
+
+hb_status hbaca_adjoint(const hb_result* r, const float* w, const float* ybar, float* wbar,
+                        double* hbar, double* points_row_bar, double* points_col_bar,
+                        void* stream) {
+  if (!r || !w || !ybar) return HB_EINVAL;
+  const hb_status ok = vjp_check(r);
+  if (ok != HB_OK) return ok;
+  try {
+    const hipStream_t st = (hipStream_t)stream;
+    const int64_t m = r->problems[0].m, n = r->problems[0].n;
+    DevMem mem;
+    mem.st = st;
+    double* wd = mem.get<double>((size_t)n);
+    double* yd = mem.get<double>((size_t)m);
+    double* gw = wbar ? mem.get<double>((size_t)n) : nullptr;
+    hipLaunchKernelGGL(widen_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, wd,
+                       n);
+    hipLaunchKernelGGL(widen_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, ybar,
+                       yd, m);
+    HB_HIP(hipGetLastError());
+    const hb_status vs = vjp_run(r, wd, yd, gw, hbar, points_row_bar, points_col_bar, st);
+    if (vs != HB_OK) return vs;
+    if (wbar) {
+      hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gw,
+                         wbar, n);
+      HB_HIP(hipGetLastError());
+      HB_HIP(hipStreamSynchronize(st));
+    }
+    return HB_OK;
   } catch (const HbError& e) {
     return e.st;
   } catch (const std::bad_alloc&) {

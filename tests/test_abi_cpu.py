@@ -90,6 +90,7 @@ def test_result_accessors_reject_null():
     assert lib.hb_result_copy(None, 0, None, None, None, None) == -1
     assert lib.hbaca_apply(None, 0, None, None, 0, None) == -1
     assert lib.hbaca_vjp(None, None, None, None, None, None, None, None) == -1
+    assert lib.hbaca_adjoint(None, None, None, None, None, None, None, None) == -1
     out = C.c_void_p(1234)
     assert lib.hbaca_recompute_frozen(None, None, None, None, None, C.byref(out)) == -1
     stride = C.c_int32(0)
