@@ -113,7 +113,9 @@ def comparisons(steps=5, warmup=1):
         fp64_ms=f_ms, mixed_ms=m_ms, speedup=f_ms / m_ms, fp64_rank=f_res.rank(0),
         mixed_rank=m_res.rank(0), fp64_rel_err_rows7=ef, mixed_rel_err_rows7=em,
         mixed_vs_fp64_operator_rel_diff=operator_rel_diff(f_res, m_res),
-        mixed_within_5tol=bool(em <= 5 * wl["tol"]))
+        mixed_within_5tol=bool(em <= 5 * wl["tol"]),
+        # the speedup counts only where both reach rel. error <= tol
+        speedup_counts=bool(ef <= wl["tol"] and em <= wl["tol"]))
     f_res.close()
     m_res.close()
     # one batched call against one call per block (Laplace blocks of the
@@ -156,7 +158,9 @@ def comparisons(steps=5, warmup=1):
         sequential_fp64_ms=s_ms, batched_fp64_ms=bf_ms, batched_mixed_ms=bm_ms,
         speedup_batched_fp64=s_ms / bf_ms, speedup_batched_mixed=s_ms / bm_ms,
         max_rel_err_rows7_fp64=ebf, max_rel_err_rows7_mixed=ebm,
-        mixed_within_5tol=bool(ebm <= 5 * wb["tol"]))
+        mixed_within_5tol=bool(ebm <= 5 * wb["tol"]),
+        speedup_fp64_counts=bool(ebf <= wb["tol"]),
+        speedup_mixed_counts=bool(ebf <= wb["tol"] and ebm <= wb["tol"]))
     print(json.dumps(out), flush=True)
 
 

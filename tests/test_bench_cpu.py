@@ -161,11 +161,13 @@ def test_comparisons_leg_runs_against_a_stand_in_library(monkeypatch, capsys):
     out = json.loads(line)
     mv = out["mixed_vs_fp64"]
     assert mv["fp64_rank"] == 5 and mv["mixed_within_5tol"] is True
+    assert mv["speedup_counts"] is True
     assert 0.0 < mv["mixed_vs_fp64_operator_rel_diff"] < 1e-8
     bs = out["batched_vs_sequential"]
     for key in ("sequential_fp64_ms", "batched_fp64_ms", "batched_mixed_ms",
                 "speedup_batched_fp64", "speedup_batched_mixed", "max_rel_err_rows7_fp64",
-                "max_rel_err_rows7_mixed", "mixed_within_5tol"):
+                "max_rel_err_rows7_mixed", "mixed_within_5tol", "speedup_fp64_counts",
+                "speedup_mixed_counts"):
         assert key in bs, key
 
 
