@@ -219,10 +219,14 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
     // g lanes share each of the j dot products (rows interleaved) when
     // j <= nt / 2; their partial sums meet in red
     const int g = j > 0 && w.nt / j >= 2 ? w.nt / j : 1;
-    // nq: the norm of column j as it stands
-    double part0 = 0.0;
-    for (int64_t l = w.tid; l < m; l += w.nt) part0 += Q[l + j * ldq] * Q[l + j * ldq];
-    double nq = sqrt(wg_sum(w, part0));
+    // nq: the norm of column j as it stands; for j > 0 the first pass
+    // always runs and forms it afresh, so it is taken here for j == 0 only
+    double nq = 0.0;
+    if (j == 0) {
+      double part0 = 0.0;
+      for (int64_t l = w.tid; l < m; l += w.nt) part0 += Q[l + j * ldq] * Q[l + j * ldq];
+      nq = sqrt(wg_sum(w, part0));
+    }
     for (int pass = 0; j > 0 && pass < 4; ++pass) {
       if (g == 1) {
         for (int i = w.tid; i < j; i += w.nt) {
