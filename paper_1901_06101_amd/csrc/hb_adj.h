@@ -216,11 +216,7 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
       for (int64_t i = w.tid; i < m; i += w.nt) Q[i + j * ldq] = A[i + j * lda];
     for (int e = w.tid; e < k; e += w.nt) R[e + j * ldr] = 0.0;
     w.sync();
-    // g lanes share each of the j dot products (rows interleaved) when
-    // j <= nt / 2; their partial sums meet in red
-    const int g = j > 0 && w.nt / j >= 2 ? w.nt / j : 1;
-    // nq: the norm of column j as it stands; for j > 0 the first pass
-    // always runs and forms it afresh, so it is taken here for j == 0 only
+    // nq: the norm of column j as it stands (for j > 0 the passes form it)
     double nq = 0.0;
     if (j == 0) {
       double part0 = 0.0;
@@ -228,27 +224,34 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
       nq = sqrt(wg_sum(w, part0));
     }
     for (int pass = 0; j > 0 && pass < 4; ++pass) {
+      // the dot products with the j earlier columns; pass 1 (which always
+      // follows pass 0) adds column j with itself, the norm pass 0 left,
+      // as h[j].  g lanes share each of the nd products (rows interleaved)
+      // when nd <= nt / 2; their partial sums meet in red
+      const int nd = pass == 1 ? j + 1 : j;
+      const int g = w.nt / nd >= 2 ? w.nt / nd : 1;
       if (g == 1) {
-        for (int i = w.tid; i < j; i += w.nt) {
+        for (int i = w.tid; i < nd; i += w.nt) {
           double s = 0.0;
           for (int64_t l = 0; l < m; ++l) s += Q[l + i * ldq] * Q[l + j * ldq];
           h[i] = s;
         }
       } else {
-        if (w.tid < j * g) {
-          const int i = w.tid % j, c = w.tid / j;
+        if (w.tid < nd * g) {
+          const int i = w.tid % nd, c = w.tid / nd;
           double s = 0.0;
           for (int64_t l = c; l < m; l += g) s += Q[l + i * ldq] * Q[l + j * ldq];
           w.red[w.tid] = s;
         }
         w.sync();
-        for (int i = w.tid; i < j; i += w.nt) {
+        for (int i = w.tid; i < nd; i += w.nt) {
           double s = 0.0;
-          for (int c = 0; c < g; ++c) s += w.red[i + c * j];
+          for (int c = 0; c < g; ++c) s += w.red[i + c * nd];
           h[i] = s;
         }
       }
       w.sync();
+      if (pass == 1) nq = sqrt(h[j]);
       for (int64_t l = w.tid; l < m; l += w.nt) {
         double s = Q[l + j * ldq];
         for (int i = 0; i < j; ++i) s -= Q[l + i * ldq] * h[i];
@@ -256,10 +259,11 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
       }
       for (int i = w.tid; i < j; i += w.nt) R[i + j * ldr] += h[i];
       w.sync();
+      if (pass == 0) continue;
       double pn = 0.0;
       for (int64_t l = w.tid; l < m; l += w.nt) pn += Q[l + j * ldq] * Q[l + j * ldq];
       const double nnow = sqrt(wg_sum(w, pn));
-      const bool again = pass == 0 || nnow < 0.5 * nq;
+      const bool again = nnow < 0.5 * nq;
       nq = nnow;
       if (!again) break;
     }
