@@ -28,7 +28,9 @@
 //   when P has at least as many rows as columns, the other when it has
 //   fewer).
 //
-// Every task runs on one workgroup.  `W` supplies the lane id `tid`, the
+// Every task runs on one workgroup; a tall merge is split into several
+// row-chunk tasks with small single-workgroup steps between them (see
+// "merges split over rows").  `W` supplies the lane id `tid`, the
 // lane count `nt`, a reduction array `red` of 3 nt + ADJ_RED_EXTRA doubles
 // and `sync()`, a barrier that every lane reaches.  Loops stride by nt over
 // disjoint outputs and a phase that reads another lane's output follows a
@@ -40,8 +42,8 @@
 #include <stdint.h>
 
 // hipcc compiles these tasks for the GPU (hb_adjoint.hip).  The tests also
-// compile them for the host, one thread per lane, to check them against
-// the oracle; the library itself has no host path.
+// compile them for the host, one thread or one fiber per lane, to check
+// them against the oracle; the library itself has no host path.
 #if defined(__HIPCC__)
 #define HBA_FN __device__ inline
 #else
