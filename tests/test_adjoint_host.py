@@ -383,3 +383,32 @@ def test_adjoint_reference_size_checks():
     assert abs(hh - dh) <= 1e-3 * abs(dh)
     for a, r in ((hw, dw), (hX, dX), (hY, dY)):
         assert _rel(a, r) <= 1e-3
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13, 14, 15, 16])
+def test_random_configurations_match_oracle(seed):
+    """Random sizes (m != n), leaf sizes, block sizes, tolerances, lane
+    counts (not powers of two too) and row chunks.  Bar 1e-9: near a
+    truncation, trailing singular values that sit close together amplify
+    rounding through 1/(s_j^2 - s_i^2); 1.0e-10 is the largest difference
+    seen over such draws, the same for every lane count and chunking."""
+    rng = np.random.default_rng(seed)
+    n, m = int(rng.integers(120, 500)), int(rng.integers(120, 500))
+    leaf, d = int(rng.integers(40, 160)), int(rng.choice([4, 8, 16]))
+    tol, h = float(rng.choice([1e-4, 1e-6, 1e-8])), float(rng.uniform(0.5, 0.9))
+    nt, chunk = int(rng.choice([1, 3, 8, 24])), int(rng.choice([0, 8, 32]))
+    wl = G.make_gauss3d(n=n, m=m, h=h, leaf=leaf, tol=tol, d=d, cfg=200 + seed)
+    fs = adj.FrozenStructure(wl)
+    w = rng.standard_normal(n)
+    b = rng.standard_normal(m)
+    _, gw, gh, gX, gY = adj.frozen_gradients(fs, w, b)
+    if chunk:
+        AH.set_chunking(chunk, 32)
+    try:
+        hw, hh, hX, hY = AH.vjp(fs, w, _ybar(fs, w, b), nt=nt)
+    finally:
+        AH.set_chunking()
+    assert _rel(hw, gw) <= 1e-9
+    assert abs(hh - gh) <= 1e-9 * abs(gh)
+    assert _rel(hX, gX) <= 1e-9
+    assert _rel(hY, gY) <= 1e-9
