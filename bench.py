@@ -277,36 +277,15 @@ def run_child(flag, timeout=300):
     return {"error": f"exit {r.returncode} (its messages are on stderr)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="helmholtz")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-comparisons", action="store_true")
-    ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--comparisons", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--adjoint", action="store_true", help=argparse.SUPPRESS)
-    args = ap.parse_args()
-    if args.comparisons:
-        comparisons()
-        return
-    if args.adjoint:
-        adjoint()
-        return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); how H-BACA would "
-              "shard over several GPUs is described in the design notes", file=sys.stderr)
-        sys.exit(2)
+def headline(args, wl):
+    """The timed compress calls on the headline workload: the measured
+    fields of the line."""
     import numpy as np
     import torch
 
     import paper_1901_06101_amd as hb
-    from workloads import make_config
 
     hb.require_gpu()
-    wl = make_config(args.workload)
     dev = torch.device("cuda:0")
     X = torch.tensor(wl["X"], device=dev) if wl.get("X") is not None else None
     Y = torch.tensor(wl["Y"], device=dev) if wl.get("Y") is not None else None
@@ -367,13 +346,52 @@ def main():
                                  peak_TFLOPs=FP64_PEAK_TFLOPS,
                                  frac=(tf / FP64_PEAK_TFLOPS) if tf is not None else None)
     out = {
-        "metric": METRIC,
         "value": ms,
+        "ms_per_step": ms,
+        "rank": rank,
+        "rel_err_rows7": rel_err,
+        "phases_ms": phases,
+        "roofline": roofline,
+        "phase_rates": phase_rates,
+    }
+    last.close()
+    _note(f"{wl['name']}: {ms:.2f} ms per compress")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="helmholtz")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparisons", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--comparisons", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--adjoint", action="store_true", help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.comparisons:
+        comparisons()
+        return
+    if args.adjoint:
+        adjoint()
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); how H-BACA would "
+              "shard over several GPUs is described in the design notes", file=sys.stderr)
+        sys.exit(2)
+    from workloads import make_config
+
+    wl = make_config(args.workload)
+    out = {
+        "metric": METRIC,
+        "value": None,
         "unit": "ms",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": None,
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
@@ -383,14 +401,12 @@ def main():
                                f"leaf={wl['leaf']}",
                    "precision": "plain FP64 (complex128 for Helmholtz)",
                    "parallelism": "single GPU"},
-        "rank": rank,
-        "rel_err_rows7": rel_err,
-        "phases_ms": phases,
-        "roofline": roofline,
-        "phase_rates": phase_rates,
     }
-    last.close()
-    _note(f"{wl['name']}: {ms:.2f} ms per compress")
+    try:
+        out.update(headline(args, wl))
+    except Exception as e:  # the line is still printed, with the failure
+        out["error"] = f"{type(e).__name__}: {e}"
+        _note(f"headline failed: {out['error']}")
     if not args.no_cpu_baseline:
         _note("CPU baseline (the oracle on the same workload)")
         try:

@@ -248,3 +248,31 @@ def test_a_failing_leg_becomes_an_error_object(monkeypatch):
     assert "error" in bench.run_child("--adjoint")
     monkeypatch.setattr(subprocess, "run", slow)
     assert "timed out" in bench.run_child("--comparisons", timeout=5)["error"]
+
+
+def test_a_failing_headline_still_prints_the_line(monkeypatch, capsys):
+    import json
+    import types
+
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads
+    from workloads import generators as G
+
+    wl = G.make_gauss3d(n=100, leaf=50, tol=1e-6, d=8, cfg=74)
+
+    def broken(*a, **k):
+        raise RuntimeError("device lost")
+
+    fake = types.SimpleNamespace(HB_K_LOWRANK_SPIKES=4, require_gpu=broken,
+                                 params=lambda **kw: kw, compress=broken)
+    monkeypatch.setitem(sys.modules, "paper_1901_06101_amd", fake)
+    monkeypatch.setattr(workloads, "make_config", lambda name, scale=1.0: wl)
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--no-comparisons", "--no-adjoint",
+                                      "--no-cpu-baseline"])
+    bench.main()
+    lines = [s for s in capsys.readouterr().out.splitlines() if s.strip()]
+    assert len(lines) == 1
+    out = json.loads(lines[0])
+    assert out["value"] is None and "device lost" in out["error"]
+    assert out["metric"] == bench.METRIC and out["n_gpus"] == 1
