@@ -203,26 +203,45 @@ HBA_FN void wg_gemm(W& w, int64_t m, int64_t n, int64_t k, double alpha, const d
   w.sync();
 }
 
+// The rows where column j can be nonzero: all m rows, or, for a stack of
+// upper-triangular blk x blk blocks (m a multiple of blk), rows
+// c blk + i with i <= j.  Index t < n maps to row (*this)(t).
+struct QrRows {
+  int64_t n, per, blk;
+  HBA_FN QrRows(int64_t m, int64_t b, int j)
+      : n(m), per(b > 0 && j + 1 < b ? j + 1 : 0), blk(b) {
+    if (per) n = (m / b) * per;
+  }
+  HBA_FN int64_t operator()(int64_t t) const { return per ? (t / per) * blk + t % per : t; }
+};
+
 // Thin QR of A (m x k, m >= k) by classical Gram-Schmidt with at least one
 // full re-orthogonalisation, and more (up to four passes) while a pass still
 // removes more than half of the column's norm, as happens for a column
 // nearly in the span of the earlier ones (Kahan and Parlett's criterion):
 // Q (m x k) with orthonormal columns, R (k x k) upper triangular with a
 // non-negative diagonal, A = Q R to working precision.  Q may be A itself
-// (same ld).  h: k doubles of scratch.
+// (same ld).  h: k doubles of scratch.  blk > 0 declares A a stack of
+// upper-triangular blk x blk blocks (blk = k): column j and every
+// combination of the earlier columns vanish on block rows below j, so the
+// loops skip those rows (the result is the same).
 template <class W>
 HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* Q, int64_t ldq,
-                  double* R, int64_t ldr, double* h) {
+                  double* R, int64_t ldr, double* h, int blk = 0) {
   for (int j = 0; j < k; ++j) {
     if (A != Q)
       for (int64_t i = w.tid; i < m; i += w.nt) Q[i + j * ldq] = A[i + j * lda];
     for (int e = w.tid; e < k; e += w.nt) R[e + j * ldr] = 0.0;
     w.sync();
+    const QrRows rows(m, blk, j);
     // nq: the norm of column j as it stands (for j > 0 the passes form it)
     double nq = 0.0;
     if (j == 0) {
       double part0 = 0.0;
-      for (int64_t l = w.tid; l < m; l += w.nt) part0 += Q[l + j * ldq] * Q[l + j * ldq];
+      for (int64_t t = w.tid; t < rows.n; t += w.nt) {
+        const int64_t l = rows(t);
+        part0 += Q[l + j * ldq] * Q[l + j * ldq];
+      }
       nq = sqrt(wg_sum(w, part0));
     }
     for (int pass = 0; j > 0 && pass < 4; ++pass) {
@@ -235,14 +254,20 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
       if (g == 1) {
         for (int i = w.tid; i < nd; i += w.nt) {
           double s = 0.0;
-          for (int64_t l = 0; l < m; ++l) s += Q[l + i * ldq] * Q[l + j * ldq];
+          for (int64_t t = 0; t < rows.n; ++t) {
+            const int64_t l = rows(t);
+            s += Q[l + i * ldq] * Q[l + j * ldq];
+          }
           h[i] = s;
         }
       } else {
         if (w.tid < nd * g) {
           const int i = w.tid % nd, c = w.tid / nd;
           double s = 0.0;
-          for (int64_t l = c; l < m; l += g) s += Q[l + i * ldq] * Q[l + j * ldq];
+          for (int64_t t = c; t < rows.n; t += g) {
+            const int64_t l = rows(t);
+            s += Q[l + i * ldq] * Q[l + j * ldq];
+          }
           w.red[w.tid] = s;
         }
         w.sync();
@@ -254,7 +279,8 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
       }
       w.sync();
       if (pass == 1) nq = sqrt(h[j]);
-      for (int64_t l = w.tid; l < m; l += w.nt) {
+      for (int64_t t = w.tid; t < rows.n; t += w.nt) {
+        const int64_t l = rows(t);
         double s = Q[l + j * ldq];
         for (int i = 0; i < j; ++i) s -= Q[l + i * ldq] * h[i];
         Q[l + j * ldq] = s;
@@ -263,7 +289,10 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
       w.sync();
       if (pass == 0) continue;
       double pn = 0.0;
-      for (int64_t l = w.tid; l < m; l += w.nt) pn += Q[l + j * ldq] * Q[l + j * ldq];
+      for (int64_t t = w.tid; t < rows.n; t += w.nt) {
+        const int64_t l = rows(t);
+        pn += Q[l + j * ldq] * Q[l + j * ldq];
+      }
       const double nnow = sqrt(wg_sum(w, pn));
       const bool again = nnow < 0.5 * nq;
       nq = nnow;
@@ -271,7 +300,7 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
     }
     const double nrm = nq;
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (int64_t l = w.tid; l < m; l += w.nt) Q[l + j * ldq] *= inv;
+    for (int64_t t = w.tid; t < rows.n; t += w.nt) Q[rows(t) + j * ldq] *= inv;
     if (w.tid == 0) R[j + j * ldr] = nrm;
     w.sync();
   }
@@ -1013,9 +1042,9 @@ HBA_FN void adj_mch_fwd2(W& w, const AdjArgs& a, int mi) {
   double* Aw = a.ws + M.ws_f2;  // k x k
   double* Yw = Aw + k * k;
   double* hs = Yw + k * k;      // gk + k
-  // the stacked R's = Q' R; R goes to Xs, where the SVD R = X diag(s) Y^T
-  // leaves X
-  wg_qr(w, gk, k, D + M.Rs, gk, D + M.Rs, gk, D + M.Xs, k, hs);
+  // the stacked R's (upper-triangular k x k blocks) = Q' R; R goes to Xs,
+  // where the SVD R = X diag(s) Y^T leaves X
+  wg_qr(w, gk, k, D + M.Rs, gk, D + M.Rs, gk, D + M.Xs, k, hs, k);
   wg_svd(w, k, D + M.Xs, k, D + M.Y, k, D + M.S, Aw, Yw, hs);
 }
 
