@@ -224,7 +224,7 @@ struct QrRows {
 // (same ld).  h: k doubles of scratch.  blk > 0 declares A a stack of
 // upper-triangular blk x blk blocks (blk = k): column j and every
 // combination of the earlier columns vanish on block rows below j, so the
-// loops skip those rows (the result is the same).
+// loops skip those rows (the same result up to the order of the sums).
 template <class W>
 HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* Q, int64_t ldq,
                   double* R, int64_t ldr, double* h, int blk = 0) {
