@@ -338,11 +338,11 @@ def headline(args, wl):
     # the leaf residual passes, the re-compression and the merges (the
     # library's counters) over each phase's device time
     phase_rates = {}
-    for name, flops, ms in (("leaf_residuals", st["resid_flops"], phases["ms_baca"]),
-                            ("recompression", st["recompress_flops"], phases["ms_recompress"]),
-                            ("merges", st["merge_flops"], phases["ms_merge"])):
-        tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else None
-        phase_rates[name] = dict(flops=flops, ms=ms, achieved_TFLOPs=tf,
+    for name, flops, phase_ms in (("leaf_residuals", st["resid_flops"], phases["ms_baca"]),
+                                  ("recompression", st["recompress_flops"], phases["ms_recompress"]),
+                                  ("merges", st["merge_flops"], phases["ms_merge"])):
+        tf = flops / (phase_ms * 1e-3) / 1e12 if phase_ms > 0 else None
+        phase_rates[name] = dict(flops=flops, ms=phase_ms, achieved_TFLOPs=tf,
                                  peak_TFLOPs=FP64_PEAK_TFLOPS,
                                  frac=(tf / FP64_PEAK_TFLOPS) if tf is not None else None)
     out = {

@@ -13,13 +13,25 @@ reflector H = I - beta v v^H maps the pivot's trailing part to alpha e_1 with
 alpha = -exp(i arg x_0) |x|, and is applied to every remaining column.  The
 number of steps is min(kmax, rows, columns).
 
+Reading for trailing norms at the rounding level: a trailing norm below
+NOISE times the largest column norm of the panel (taken at the first step)
+is no information about the column, only rounding left by the earlier
+reflectors.  Such norms count as zero, so the pick among them is a tie and
+goes to the lowest column position.  Without this, two correct runs of the
+method (here and on the GPU) would pick different noise columns whenever a
+block's numerical rank falls below d, and the picks that follow would part.
+The reflector itself is formed from the column's actual values.
+
 Pinned in the tests against a brute-force selection that recomputes every
 residual norm by least squares, and (for the full factorisation) against
-Q T = W(:, pivots).
+Q T = W(:, pivots); the rounding-level reading against exactly rank-deficient
+panels.
 """
 from __future__ import annotations
 
 import numpy as np
+
+NOISE = 1e-12
 
 
 def householder(x: np.ndarray):
@@ -70,11 +82,16 @@ def qrcp(M: np.ndarray, kmax: int) -> QRCPResult:
     steps = min(kmax, p, q)
     remaining = np.ones(q, dtype=bool)
     piv, tdiag, refl = [], [], []
+    ref2 = 0.0
     for t in range(steps):
         cols = np.nonzero(remaining)[0]
         sub = A[t:, cols]
         norm2 = np.sum(sub.real ** 2 + sub.imag ** 2, axis=0) if np.iscomplexobj(sub) \
             else np.sum(sub * sub, axis=0)
+        if t == 0:
+            ref2 = float(norm2.max())
+        else:  # rounding-level trailing norms count as zero
+            norm2 = np.where(norm2 < NOISE * NOISE * ref2, 0.0, norm2)
         j = int(cols[int(np.argmax(norm2))])  # first maximum = lowest position
         v, beta, alpha = householder(A[t:, j])
         if beta != 0.0:

@@ -1018,19 +1018,210 @@ static void run_merges_direct(Engine& E, std::vector<MergeJob>& jobs, DevMem& ou
   }
 }
 
-// Merges wider than the register TSQR tile: Householder QR of B by column
-// panels (communication-avoiding QR).  Panel p is factored by TSQR; the Q^H
-// of its tree is applied bottom-up to every later panel, whose top rows
-// become the coupling block R_{p,j} and whose other rows form the next
-// working matrix.  Q [X_r; 0] is applied top-down panel by panel with the
-// trailing rows of the later panels re-injected.
+// Householder QR of tall matrices wider than the register TSQR tile, by
+// column panels (communication-avoiding QR).  Panel p is factored by TSQR;
+// the Q^H of its tree is applied bottom-up to every later panel, whose top
+// rows become the coupling block R_{p,j} and whose other rows form the next
+// working matrix.  The inputs are only read.
+struct PanelQR {
+  size_t nj = 0;
+  int kcap = 0, qmax = 0;
+  std::vector<int> q, kk;
+  std::vector<int64_t> rows;
+  std::vector<std::vector<int64_t>> rows_at;  // working rows when panel p is factored
+  std::vector<std::vector<int>> stepsp;       // R rows contributed by panel p
+  std::vector<std::unique_ptr<Engine::Factored>> Fp;
+  std::vector<std::vector<int>> midx;         // matrix index of job a in panel p's trees
+  std::vector<int64_t> P;                     // rows of R (sum of the panel steps)
+  std::vector<char*> R;                       // R compacted: P x k, column-major, ld P
+  int pw(size_t a, int p) const { return std::min(kcap, kk[a] - p * kcap); }
+};
+
+// B_a: rows_a x k_a, column-major with ld rows_a.
+static void panel_qr_factor(Engine& E, const std::vector<const void*>& B,
+                            const std::vector<int64_t>& rows, const std::vector<int>& k,
+                            PanelQR& S) {
+  const size_t nj = B.size();
+  const size_t sb = E.sb();
+  S.nj = nj;
+  S.kcap = E.kcap();
+  S.kk = k;
+  S.rows = rows;
+  S.q.assign(nj, 0);
+  S.qmax = 0;
+  for (size_t a = 0; a < nj; ++a) {
+    S.q[a] = (k[a] + S.kcap - 1) / S.kcap;
+    S.qmax = std::max(S.qmax, S.q[a]);
+  }
+  S.rows_at.assign(nj, {});
+  S.stepsp.assign(nj, {});
+  S.Fp.clear();
+  S.Fp.resize(S.qmax);
+  S.midx.assign(S.qmax, std::vector<int>(nj, -1));
+  std::vector<std::vector<const void*>> pin(nj);
+  std::vector<int64_t> wrows(rows);
+  for (size_t a = 0; a < nj; ++a) {
+    pin[a].resize(S.q[a]);
+    for (int p = 0; p < S.q[a]; ++p) pin[a][p] = (const char*)B[a] + (size_t)p * S.kcap * rows[a] * sb;
+  }
+  // R is written during the sweep at its upper bound (k x k, ld k) and
+  // compacted to its P rows afterwards
+  std::vector<size_t> rsz(nj);
+  for (size_t a = 0; a < nj; ++a) rsz[a] = (size_t)k[a] * k[a] * sb;
+  std::vector<char*> Rbuf = E.tmp.carve(rsz);
+  {
+    size_t tot = 0;
+    for (size_t a = 0; a < nj; ++a) tot += (std::max<size_t>(rsz[a], 1) + 255) & ~(size_t)255;
+    HB_LAUNCH(hbk::zero_fill_launch(Rbuf[0], tot, E.st));
+  }
+  std::vector<int64_t> roff(nj, 0);
+  for (int p = 0; p < S.qmax; ++p) {
+    std::vector<QRNodeDev> mats;
+    std::vector<int64_t> mrows;
+    for (size_t a = 0; a < nj; ++a) {
+      if (p >= S.q[a]) continue;
+      if (wrows[a] == 0) {  // no rows left: this panel adds no R rows
+        S.rows_at[a].push_back(0);
+        S.stepsp[a].push_back(0);
+        continue;
+      }
+      QRNodeDev nd{};
+      nd.k = S.pw(a, p);
+      nd.P1 = pin[a][p];
+      nd.ld1 = wrows[a];
+      nd.n1 = nd.k;
+      nd.P2 = pin[a][p];
+      nd.ld2 = wrows[a];
+      S.midx[p][a] = (int)mats.size();
+      mats.push_back(nd);
+      mrows.push_back(wrows[a]);
+    }
+    S.Fp[p].reset(new Engine::Factored());
+    Engine::Factored& F = *S.Fp[p];
+    if (mats.empty()) continue;
+    E.factor(mats, mrows, F);
+    // R_pp into R, coupling blocks of later panels, next working matrices
+    std::vector<RCopyDev> rc;
+    for (size_t a = 0; a < nj; ++a) {
+      if (S.midx[p][a] < 0) continue;
+      const int i = S.midx[p][a];
+      const QRNodeDev& top = F.tb.levels[F.tb.top_level[i]][F.tb.top_index[i]];
+      S.rows_at[a].push_back(wrows[a]);
+      S.stepsp[a].push_back(top.steps);
+      RCopyDev c{};
+      c.store = top.store;
+      c.ab = top.ab;
+      c.p = top.steps;
+      c.k = top.k;
+      c.dst = Rbuf[a] + ((size_t)p * S.kcap * k[a] + roff[a]) * sb;
+      c.ld = k[a];
+      rc.push_back(c);
+    }
+    RCopyDev* drc = upload(E.tmp, rc, E.st);
+    HB_LAUNCH(hbk::rcopy_launch(E.scalar, drc, (int)rc.size(), F.store, F.alpha, E.st));
+    for (int j = p + 1; j < S.qmax; ++j) {
+      std::vector<const void*> zin(mats.size(), nullptr);
+      std::vector<int64_t> ldin(mats.size(), 1), ldtop(mats.size(), 1), ldtr(mats.size(), 1);
+      std::vector<int> kj(mats.size(), 0);
+      std::vector<void*> top(mats.size(), nullptr), trail(mats.size(), nullptr);
+      std::vector<size_t> tsz(mats.size(), 0);
+      std::vector<size_t> who;
+      for (size_t a = 0; a < nj; ++a)
+        if (S.midx[p][a] >= 0 && j < S.q[a]) who.push_back(a);
+      if (who.empty()) continue;
+      for (size_t a : who) {
+        const int i = S.midx[p][a];
+        tsz[i] = (size_t)(wrows[a] - S.stepsp[a][p]) * S.pw(a, j) * sb;
+      }
+      std::vector<char*> tb = E.tmp.carve(tsz);
+      for (size_t a : who) {
+        const int i = S.midx[p][a];
+        kj[i] = S.pw(a, j);
+        zin[i] = pin[a][j];
+        ldin[i] = wrows[a];
+        top[i] = Rbuf[a] + ((size_t)j * S.kcap * k[a] + roff[a]) * sb;
+        ldtop[i] = k[a];
+        trail[i] = tb[i];
+        ldtr[i] = wrows[a] - S.stepsp[a][p];
+      }
+      E.apply_h(F, zin, ldin, kj, top, ldtop, trail, ldtr);
+      for (size_t a : who) pin[a][j] = tb[S.midx[p][a]];
+    }
+    for (size_t a = 0; a < nj; ++a)
+      if (S.midx[p][a] >= 0) {
+        roff[a] += S.stepsp[a][p];
+        wrows[a] -= S.stepsp[a][p];
+      }
+  }
+  S.P = roff;
+  std::vector<size_t> csz(nj);
+  for (size_t a = 0; a < nj; ++a) csz[a] = (size_t)std::max<int64_t>(roff[a], 1) * k[a] * sb;
+  S.R = E.tmp.carve(csz);
+  std::vector<RCompactDev> rcj(nj);
+  for (size_t a = 0; a < nj; ++a) rcj[a] = RCompactDev{Rbuf[a], k[a], S.R[a], (int)roff[a], k[a]};
+  RCompactDev* drcj = upload(E.tmp, rcj, E.st);
+  HB_LAUNCH(hbk::rcompact_launch(E.scalar, drcj, (int)nj, E.st));
+}
+
+// Zout_a (rows_a x r_a, ld rows_a) = Q_a [Zin_a; 0], Zin_a: P_a x r_a with
+// leading dimension ldin_a.  Panel by panel from the last: Z_p = Q_p [rows
+// of Zin for panel p; Z_{p+1}], the later panels' rows re-injected below.
+static void panel_qr_apply(Engine& E, const PanelQR& S, const std::vector<const void*>& zin,
+                           const std::vector<int64_t>& ldin, const std::vector<int>& rr,
+                           const std::vector<void*>& zout) {
+  const size_t nj = S.nj;
+  const size_t sb = E.sb();
+  std::vector<const void*> znext(nj, nullptr);
+  std::vector<int64_t> ldnext(nj, 1);
+  for (int p = S.qmax - 1; p >= 0; --p) {
+    const Engine::Factored& F = *S.Fp[p];
+    const size_t nm = F.tb.kmat.size();
+    if (nm == 0) continue;
+    std::vector<const void*> zi(nm, nullptr), ztr(nm, nullptr);
+    std::vector<int64_t> li(nm, 1), lo(nm, 1), ltr(nm, 1);
+    std::vector<int> rc(nm, 0);
+    std::vector<void*> zo(nm, nullptr);
+    std::vector<size_t> zsz(nm, 0);
+    for (size_t a = 0; a < nj; ++a) {
+      const int i = S.midx[p][a];
+      if (i < 0 || rr[a] == 0) continue;
+      if (p > 0) zsz[i] = (size_t)S.rows_at[a][p] * rr[a] * sb;
+    }
+    std::vector<char*> zb = E.tmp.carve(zsz);
+    for (size_t a = 0; a < nj; ++a) {
+      const int i = S.midx[p][a];
+      if (i < 0 || rr[a] == 0) continue;
+      int64_t r0 = 0;
+      for (int pp = 0; pp < p; ++pp) r0 += S.stepsp[a][pp];
+      rc[i] = rr[a];
+      zi[i] = (const char*)zin[a] + (size_t)r0 * sb;
+      li[i] = ldin[a];
+      zo[i] = p == 0 ? zout[a] : (void*)zb[i];
+      lo[i] = S.rows_at[a][p];
+      if (p + 1 < S.q[a]) {
+        ztr[i] = znext[a];
+        ltr[i] = ldnext[a];
+      }
+    }
+    E.apply(F, zi, li, rc, zo, lo, &ztr, &ltr);
+    for (size_t a = 0; a < nj; ++a) {
+      const int i = S.midx[p][a];
+      if (i < 0 || rr[a] == 0) continue;
+      znext[a] = zo[i];
+      ldnext[a] = S.rows_at[a][p];
+    }
+  }
+}
+
+// Merges wider than the register TSQR tile: the panel QR of the materialised
+// B = [P1 S1, P2 S2], the SVD of its R, Q [X_r; 0] and the block product on
+// the other side.
 static void run_merges_caqr(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_mem) {
   const size_t nj = jobs.size();
   if (nj == 0) return;
   const size_t sb = E.sb();
-  const int kcap = E.kcap();
-  std::vector<int> q(nj), kk(nj);
-  int qmax = 0;
+  std::vector<int> kk(nj);
+  std::vector<int64_t> rows(nj);
   for (size_t a = 0; a < nj; ++a) {
     MergeJob& J = jobs[a];
     Block& B = *J.outP_owner;
@@ -1043,10 +1234,8 @@ static void run_merges_caqr(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_
     }
     B.r = 0;
     kk[a] = J.r1 + J.r2;
-    q[a] = (kk[a] + kcap - 1) / kcap;
-    qmax = std::max(qmax, q[a]);
+    rows[a] = J.rows;
   }
-  auto pw = [&](size_t a, int p) { return std::min(kcap, kk[a] - p * kcap); };
   // materialised B = [P1 S1, P2 S2]
   std::vector<size_t> bsz(nj);
   for (size_t a = 0; a < nj; ++a) bsz[a] = (size_t)jobs[a].rows * kk[a] * sb;
@@ -1062,130 +1251,20 @@ static void run_merges_caqr(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_
     ConcatDev* d = upload(E.tmp, cj, E.st);
     HB_LAUNCH(hbk::concat_launch(E.scalar, d, (int)nj, mm, 0, E.st));
   }
-  // working matrices of every panel: pointer + ld (rows of the working set)
-  std::vector<std::vector<const void*>> pin(nj);
-  std::vector<int64_t> wrows(nj);
-  for (size_t a = 0; a < nj; ++a) {
-    wrows[a] = jobs[a].rows;
-    pin[a].resize(q[a]);
-    for (int p = 0; p < q[a]; ++p) pin[a][p] = Bm[a] + (size_t)p * kcap * jobs[a].rows * sb;
-  }
-  std::vector<std::vector<int64_t>> rows_at(nj);   // working rows when panel p is factored
-  std::vector<std::vector<int>> stepsp(nj);        // R rows contributed by panel p
-  std::vector<std::unique_ptr<Engine::Factored>> Fp(qmax);
-  std::vector<std::vector<int>> midx(qmax, std::vector<int>(nj, -1));
-  // R rows: panel p starts at row sum(stepsp[<p]); allocate R after all panels
-  // are known - but coupling blocks are written during the sweep, so size R by
-  // its upper bound (sum of panel widths) and compact rows later.
-  std::vector<size_t> rsz(nj);
-  for (size_t a = 0; a < nj; ++a) rsz[a] = (size_t)kk[a] * kk[a] * sb;
-  std::vector<char*> Rbuf = E.tmp.carve(rsz);  // kk x kk, ld kk (rows beyond P stay unused)
-  {
-    size_t tot = 0;
-    for (size_t a = 0; a < nj; ++a) tot += (rsz[a] + 255) & ~(size_t)255;
-    HB_LAUNCH(hbk::zero_fill_launch(Rbuf[0], tot, E.st));
-  }
-  std::vector<int64_t> roff(nj, 0);            // current R row offset
-  for (int p = 0; p < qmax; ++p) {
-    std::vector<QRNodeDev> mats;
-    std::vector<int64_t> rows;
-    for (size_t a = 0; a < nj; ++a) {
-      if (p >= q[a]) continue;
-      if (wrows[a] == 0) {  // no rows left: this panel adds no R rows
-        rows_at[a].push_back(0);
-        stepsp[a].push_back(0);
-        continue;
-      }
-      QRNodeDev nd{};
-      nd.k = pw(a, p);
-      nd.P1 = pin[a][p];
-      nd.ld1 = wrows[a];
-      nd.n1 = nd.k;
-      nd.P2 = pin[a][p];
-      nd.ld2 = wrows[a];
-      midx[p][a] = (int)mats.size();
-      mats.push_back(nd);
-      rows.push_back(wrows[a]);
-    }
-    Fp[p].reset(new Engine::Factored());
-    Engine::Factored& F = *Fp[p];
-    if (mats.empty()) continue;
-    E.factor(mats, rows, F);
-    // R_pp into R, coupling blocks of later panels, next working matrices
-    std::vector<RCopyDev> rc;
-    for (size_t a = 0; a < nj; ++a) {
-      if (midx[p][a] < 0) continue;
-      const int i = midx[p][a];
-      const QRNodeDev& top = F.tb.levels[F.tb.top_level[i]][F.tb.top_index[i]];
-      rows_at[a].push_back(wrows[a]);
-      stepsp[a].push_back(top.steps);
-      RCopyDev c{};
-      c.store = top.store;
-      c.ab = top.ab;
-      c.p = top.steps;
-      c.k = top.k;
-      c.dst = Rbuf[a] + ((size_t)p * kcap * kk[a] + roff[a]) * sb;
-      c.ld = kk[a];
-      rc.push_back(c);
-    }
-    RCopyDev* drc = upload(E.tmp, rc, E.st);
-    HB_LAUNCH(hbk::rcopy_launch(E.scalar, drc, (int)rc.size(), F.store, F.alpha, E.st));
-    // later panels
-    for (int j = p + 1; j < qmax; ++j) {
-      std::vector<const void*> zin(mats.size(), nullptr);
-      std::vector<int64_t> ldin(mats.size(), 1), ldtop(mats.size(), 1), ldtr(mats.size(), 1);
-      std::vector<int> kj(mats.size(), 0);
-      std::vector<void*> top(mats.size(), nullptr), trail(mats.size(), nullptr);
-      std::vector<size_t> tsz(mats.size(), 0);
-      std::vector<size_t> who;
-      for (size_t a = 0; a < nj; ++a)
-        if (midx[p][a] >= 0 && j < q[a]) who.push_back(a);
-      if (who.empty()) continue;
-      for (size_t a : who) {
-        const int i = midx[p][a];
-        tsz[i] = (size_t)(wrows[a] - stepsp[a][p]) * pw(a, j) * sb;
-      }
-      std::vector<char*> tb = E.tmp.carve(tsz);
-      for (size_t a : who) {
-        const int i = midx[p][a];
-        kj[i] = pw(a, j);
-        zin[i] = pin[a][j];
-        ldin[i] = wrows[a];
-        top[i] = Rbuf[a] + ((size_t)j * kcap * kk[a] + roff[a]) * sb;
-        ldtop[i] = kk[a];
-        trail[i] = tb[i];
-        ldtr[i] = wrows[a] - stepsp[a][p];
-      }
-      E.apply_h(F, zin, ldin, kj, top, ldtop, trail, ldtr);
-      for (size_t a : who) pin[a][j] = tb[midx[p][a]];
-    }
-    for (size_t a = 0; a < nj; ++a)
-      if (midx[p][a] >= 0) {
-        roff[a] += stepsp[a][p];
-        wrows[a] -= stepsp[a][p];
-      }
-  }
-  // compact R (P x k, P = sum of panel steps) and its SVD
+  PanelQR S;
+  panel_qr_factor(E, std::vector<const void*>(Bm.begin(), Bm.end()), rows, kk, S);
   std::vector<SVDJobDev> sj(nj);
-  std::vector<size_t> csz(nj);
-  for (size_t a = 0; a < nj; ++a) csz[a] = (size_t)std::max<int64_t>(roff[a], 1) * kk[a] * sb;
-  std::vector<char*> Rc = E.tmp.carve(csz);
-  std::vector<RCompactDev> rcj(nj);
   for (size_t a = 0; a < nj; ++a) {
-    rcj[a] = RCompactDev{Rbuf[a], kk[a], Rc[a], (int)roff[a], kk[a]};
     SVDJobDev J{};
-    J.p = (int)roff[a];
+    J.p = (int)S.P[a];
     J.k = kk[a];
     J.from_node = 0;
-    J.R = Rc[a];
+    J.R = S.R[a];
     sj[a] = J;
   }
-  RCompactDev* drcj = upload(E.tmp, rcj, E.st);
-  HB_LAUNCH(hbk::rcompact_launch(E.scalar, drcj, (int)nj, E.st));
   std::vector<SvdOut> so;
   std::vector<int> rk;
   run_svds(E, sj, nullptr, nullptr, so, rk);
-  // outputs
   std::vector<size_t> osz;
   for (size_t a = 0; a < nj; ++a) {
     const int r = rk[a];
@@ -1197,7 +1276,10 @@ static void run_merges_caqr(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_
   std::vector<BlockGemmDev> gj;
   int64_t max_rows = 0;
   int max_rin = 0;
-  std::vector<char*> P(nj, nullptr);
+  std::vector<const void*> zin(nj, nullptr);
+  std::vector<int64_t> ldin(nj, 1);
+  std::vector<int> rr(nj, 0);
+  std::vector<void*> zout(nj, nullptr);
   std::vector<CopyDev> scp;
   for (size_t a = 0; a < nj; ++a) {
     MergeJob& J = jobs[a];
@@ -1205,17 +1287,21 @@ static void run_merges_caqr(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_
     const int r = rk[a];
     B.r = r;
     if (r == 0) continue;
-    P[a] = ob[3 * a];
+    void* P = ob[3 * a];
     void* O = ob[3 * a + 1];
     B.S = (double*)ob[3 * a + 2];
     scp.push_back(CopyDev{so[a].S, B.S, (int64_t)r * 8});
     if (J.p_is_u) {
-      B.U = P[a];
+      B.U = P;
       B.Vh = O;
     } else {
-      B.Vh = P[a];
+      B.Vh = P;
       B.U = O;
     }
+    zin[a] = so[a].Xr;
+    ldin[a] = so[a].p;
+    rr[a] = r;
+    zout[a] = P;
     BlockGemmDev bg{};
     bg.A1 = J.O1; bg.lda1 = J.n1; bg.n1 = (int)J.n1; bg.r1 = J.r1;
     bg.A2 = J.O2; bg.lda2 = J.n2; bg.n2 = (int)J.n2; bg.r2 = J.r2;
@@ -1226,49 +1312,7 @@ static void run_merges_caqr(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_
     max_rin = std::max(max_rin, J.r1 + J.r2);
   }
   copy_sigmas(E, scp);
-  // forward: Z_p = T_p [X_r(rows of panel p); Z_{p+1}]
-  std::vector<const void*> znext(nj, nullptr);
-  std::vector<int64_t> ldnext(nj, 1);
-  for (int p = qmax - 1; p >= 0; --p) {
-    Engine::Factored& F = *Fp[p];
-    const size_t nm = F.tb.kmat.size();
-    if (nm == 0) continue;
-    std::vector<const void*> zin(nm, nullptr), ztr(nm, nullptr);
-    std::vector<int64_t> ldin(nm, 1), ldout(nm, 1), ldtr(nm, 1);
-    std::vector<int> rr(nm, 0);
-    std::vector<void*> zout(nm, nullptr);
-    std::vector<size_t> zsz(nm, 0);
-    for (size_t a = 0; a < nj; ++a) {
-      const int i = midx[p][a];
-      if (i < 0 || rk[a] == 0) continue;
-      if (p > 0) zsz[i] = (size_t)rows_at[a][p] * rk[a] * sb;
-    }
-    std::vector<char*> zb = E.tmp.carve(zsz);
-    int64_t rof = 0;
-    for (size_t a = 0; a < nj; ++a) {
-      const int i = midx[p][a];
-      if (i < 0 || rk[a] == 0) continue;
-      int64_t r0 = 0;
-      for (int pp = 0; pp < p; ++pp) r0 += stepsp[a][pp];
-      (void)rof;
-      rr[i] = rk[a];
-      zin[i] = (const char*)so[a].Xr + (size_t)r0 * sb;
-      ldin[i] = so[a].p;
-      zout[i] = p == 0 ? (void*)P[a] : (void*)zb[i];
-      ldout[i] = rows_at[a][p];
-      if (p + 1 < q[a]) {
-        ztr[i] = znext[a];
-        ldtr[i] = ldnext[a];
-      }
-    }
-    E.apply(F, zin, ldin, rr, zout, ldout, &ztr, &ldtr);
-    for (size_t a = 0; a < nj; ++a) {
-      const int i = midx[p][a];
-      if (i < 0 || rk[a] == 0) continue;
-      znext[a] = zout[i];
-      ldnext[a] = rows_at[a][p];
-    }
-  }
+  panel_qr_apply(E, S, zin, ldin, rr, zout);
   if (!gj.empty()) {
     BlockGemmDev* dg = upload(E.tmp, gj, E.st);
     HB_LAUNCH(hbk::block_gemm_launch(E.scalar, dg, (int)gj.size(), (int)max_rows, max_rin, E.st));
@@ -1311,47 +1355,85 @@ struct RecJob {
 
 static void run_recompress_narrow(Engine& E, std::vector<RecJob>& jobs, DevMem& out_mem);
 
-// Leaves whose BACA rank exceeds the register TSQR tile: V^H is first
-// orthonormalised by a merge of the single block with no truncation above
-// the rounding level (V^H = Q X S Y^H, so U V = (U Y) S (Q X)^H), then
-// (U Y) S (Q X)^H is truncated at eps by a second single-block merge, whose
-// wide QR runs column panel by column panel.
+// Leaves whose BACA rank exceeds the register TSQR tile: the same steps as
+// the narrow route (Section "Blocked Adaptive Cross Approximation", the SVD
+// re-compression): Q_U T_U = QR(U), Q_V T_V = QR(V^H) by column panels,
+// M = T_U T_V^H, the truncated SVD of M, then U' = Q_U Y_r and
+// V'^H = Q_V X_r.  As on the narrow route the SVD is taken of
+// M^H = T_V T_U^H, so that the side that becomes the next merge's
+// orthonormal basis comes from the Jacobi iteration.
 static void run_recompress_wide(Engine& E, std::vector<RecJob>& jobs, DevMem& out_mem) {
-  if (jobs.empty()) return;
-  DevMem mid;
-  mid.st = E.st;
-  std::vector<Block> midb(jobs.size());
-  std::vector<MergeJob> j1, j2;
-  for (size_t i = 0; i < jobs.size(); ++i) {
-    const RecJob& R = jobs[i];
-    MergeJob J{};
-    J.rows = R.n0;
-    J.P1 = R.Vh; J.r1 = R.r; J.S1 = nullptr;
-    J.P2 = nullptr; J.r2 = 0; J.S2 = nullptr;
-    J.O1 = R.U; J.n1 = R.m0;
-    J.O2 = nullptr; J.n2 = 0;
-    J.p_is_u = false;
-    J.outP_owner = &midb[i];
-    j1.push_back(J);
+  const size_t nj = jobs.size();
+  if (nj == 0) return;
+  const size_t sb = E.sb();
+  std::vector<const void*> B(2 * nj);
+  std::vector<int64_t> rows(2 * nj);
+  std::vector<int> k(2 * nj);
+  for (size_t a = 0; a < nj; ++a) {
+    B[2 * a] = jobs[a].U;
+    rows[2 * a] = jobs[a].m0;
+    B[2 * a + 1] = jobs[a].Vh;
+    rows[2 * a + 1] = jobs[a].n0;
+    k[2 * a] = k[2 * a + 1] = jobs[a].r;
   }
-  const double eps = E.eps;
-  E.eps = 1e-14;
-  run_merges(E, j1, mid);
-  E.eps = eps;
-  for (size_t i = 0; i < jobs.size(); ++i) {
-    const Block& b = midb[i];
-    MergeJob J{};
-    J.rows = b.m;
-    J.P1 = b.U; J.r1 = b.r; J.S1 = b.S;
-    J.P2 = nullptr; J.r2 = 0; J.S2 = nullptr;
-    J.O1 = b.Vh; J.n1 = b.n;
-    J.O2 = nullptr; J.n2 = 0;
-    J.p_is_u = true;
-    J.outP_owner = jobs[i].out;
-    j2.push_back(J);
+  PanelQR S;
+  panel_qr_factor(E, B, rows, k, S);
+  // M^H = T_V T_U^H (P_V x P_U) per leaf
+  std::vector<size_t> msz(nj);
+  for (size_t a = 0; a < nj; ++a) msz[a] = (size_t)S.P[2 * a] * S.P[2 * a + 1] * sb;
+  std::vector<char*> MH = E.tmp.carve(msz);
+  std::vector<RRhDev> mj(nj);
+  std::vector<SVDJobDev> sj(nj);
+  int64_t mmax = 0;
+  for (size_t a = 0; a < nj; ++a) {
+    const int pv = (int)S.P[2 * a + 1], pu = (int)S.P[2 * a];
+    mj[a] = RRhDev{S.R[2 * a + 1], S.R[2 * a], MH[a], pv, pu, jobs[a].r, 0};
+    mmax = std::max<int64_t>(mmax, (int64_t)pv * pu);
+    SVDJobDev J{};
+    J.p = pv;
+    J.k = pu;
+    J.from_node = 0;
+    J.R = MH[a];
+    sj[a] = J;
   }
-  run_merges(E, j2, out_mem);
-  mid.release();
+  RRhDev* dmj = upload(E.tmp, mj, E.st);
+  HB_LAUNCH(hbk::rrh_launch(E.scalar, dmj, (int)nj, mmax, E.st));
+  std::vector<SvdOut> so;
+  std::vector<int> rk;
+  run_svds(E, sj, nullptr, nullptr, so, rk);
+  std::vector<size_t> osz;
+  for (size_t a = 0; a < nj; ++a) {
+    osz.push_back((size_t)jobs[a].m0 * rk[a] * sb);
+    osz.push_back((size_t)jobs[a].n0 * rk[a] * sb);
+    osz.push_back((size_t)rk[a] * 8);
+  }
+  std::vector<char*> ob = out_mem.carve(osz);
+  std::vector<const void*> zin(2 * nj, nullptr);
+  std::vector<int64_t> ldin(2 * nj, 1);
+  std::vector<int> rr(2 * nj, 0);
+  std::vector<void*> zout(2 * nj, nullptr);
+  std::vector<CopyDev> scp;
+  for (size_t a = 0; a < nj; ++a) {
+    Block& Bk = *jobs[a].out;
+    const int r = rk[a];
+    Bk.r = r;
+    if (r == 0) continue;
+    Bk.U = ob[3 * a];
+    Bk.Vh = ob[3 * a + 1];
+    Bk.S = (double*)ob[3 * a + 2];
+    scp.push_back(CopyDev{so[a].S, Bk.S, (int64_t)r * 8});
+    // M^H = X S Y^H  =>  M = Y S X^H: U side from Y, V side from X
+    zin[2 * a] = so[a].Yr;
+    ldin[2 * a] = so[a].k;
+    rr[2 * a] = r;
+    zout[2 * a] = Bk.U;
+    zin[2 * a + 1] = so[a].Xr;
+    ldin[2 * a + 1] = so[a].p;
+    rr[2 * a + 1] = r;
+    zout[2 * a + 1] = Bk.Vh;
+  }
+  copy_sigmas(E, scp);
+  panel_qr_apply(E, S, zin, ldin, rr, zout);
 }
 
 static void run_recompress(Engine& E, std::vector<RecJob>& jobs, DevMem& out_mem) {
@@ -1743,7 +1825,11 @@ static hb_status run(const CallSpec& c, hb_result** out) {
     lf.rank_baca = bo[s].rank;
     lf.iters = bo[s].iters;
     lf.status = bo[s].status;
-    if (bo[s].status != 0) return HB_ERANKCAP;
+    if (bo[s].status == 1) return HB_ERANKCAP;
+    if (bo[s].status != 0) {  // a pivot outside its candidate range (non-finite data)
+      hb_report("leaf BACA", bo[s].status, "pivot index outside the candidate range", __LINE__);
+      return HB_EDEVICE;
+    }
     if (P.record_tape) {
       lf.tape_rows.assign(h_rows.begin() + ld[s].tape_off, h_rows.begin() + ld[s].tape_off + lf.rank_baca);
       lf.tape_cols.assign(h_cols.begin() + ld[s].tape_off, h_cols.begin() + ld[s].tape_off + lf.rank_baca);
@@ -1928,6 +2014,18 @@ static hb_status run(const CallSpec& c, hb_result** out) {
           prev_mem->ptrs.clear();
           break;
         }
+        // The previous level's memory holds the finished roots of every
+        // problem whose tree ended there (L = l - 1); those move to the
+        // result, the rest of that memory is free for reuse.
+        {
+          bool holds_root = false;
+          for (size_t p = 0; p < np; ++p)
+            if (R->problems[p].L == l - 1) holds_root = true;
+          if (holds_root) {
+            for (void* q : prev_mem->ptrs) R->keep.ptrs.push_back(q);
+            prev_mem->ptrs.clear();
+          }
+        }
         prev_mem->release();
         // vertical: (tau, nu) from (tau_1, nu) and (tau_2, nu)
         std::unique_ptr<DevMem> vm(new DevMem());
@@ -1984,7 +2082,6 @@ static hb_status run(const CallSpec& c, hb_result** out) {
           }
         mems.push_back(std::move(vm));
         prev_mem = mems.back().get();
-        if (mems.size() > 1) mems.front()->release();
         tmp.release();
       }
       S.n_steps = step + 1;

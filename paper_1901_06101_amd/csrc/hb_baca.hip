@@ -25,6 +25,11 @@
 namespace {
 
 constexpr int NT = 512;
+// Trailing norms below this fraction of a panel's largest column norm are
+// rounding left by the earlier reflectors and count as zero in the pivot
+// choice (ties go to the lowest index), so that the picks do not depend on
+// the order of rounding.
+constexpr double QRCP_NOISE = 1e-12;
 constexpr int NW = NT / HB_WAVE;
 constexpr int LCH = 8;  // HBM loads issued together before their first use
 
@@ -156,6 +161,10 @@ __device__ __forceinline__ void qrcp_select(T (&x)[RPT][DMAX], int ncand_total, 
   bool picked[RPT];
 #pragma unroll
   for (int s = 0; s < RPT; ++s) picked[s] = false;
+  // the largest squared norm at the first step: later trailing norms below
+  // QRCP_NOISE of it are rounding only and count as zero (ties to the
+  // lowest index)
+  double zero2 = 0.0;
 #pragma unroll 1
   for (int st = 0; st < nsel; ++st) {
     const int bb = st & 1;
@@ -171,6 +180,7 @@ __device__ __forceinline__ void qrcp_select(T (&x)[RPT][DMAX], int ncand_total, 
           if (c >= st && c < nrow) nv += sc_abs2(x[s][c]);
         // a NaN norm (non-finite data) must still leave a valid winner
         if (!(nv == nv)) nv = 0.0;
+        if (nv < zero2) nv = 0.0;
         if (nv > bv || (nv == bv && i < bi)) {
           bv = nv;
           bi = i;
@@ -203,6 +213,7 @@ __device__ __forceinline__ void qrcp_select(T (&x)[RPT][DMAX], int ncand_total, 
         ww = w;
       }
     }
+    if (st == 0) zero2 = QRCP_NOISE * QRCP_NOISE * bv;
 #pragma unroll
     for (int s = 0; s < RPT; ++s)
       if (tid + s * NT == bi) picked[s] = true;
@@ -239,6 +250,15 @@ __device__ __forceinline__ void qrcp_select(T (&x)[RPT][DMAX], int ncand_total, 
   }
   // the chosen indices are read after the call
   __syncthreads();
+}
+
+// True when the first n entries of the LDS index list lie in [0, lim).  Every
+// thread reads the same entries after a barrier, so the answer is uniform
+// over the workgroup and a loop may be left on it.
+__device__ __forceinline__ bool pivots_in_range(const int* idx, int n, int lim) {
+  bool ok = true;
+  for (int c = 0; c < n; ++c) ok = ok && idx[c] >= 0 && idx[c] < lim;
+  return ok;
 }
 
 template <typename T, int DMAX, int RPT>
@@ -296,6 +316,13 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
     const int nJ = sNJ;
     if (r + min(nJ, m0 - r) > cap) {
       status = 1;
+      break;
+    }
+    // Every pivot index is checked before it addresses memory: a winner
+    // outside the candidate range (possible only with non-finite data) ends
+    // the leaf with status 2 instead of reading past the point arrays.
+    if (!pivots_in_range(sJ, nJ, n0)) {
+      status = 2;
       break;
     }
     // ------------------------------------------------ C_k = A(:,J) - U V(:,J)
@@ -379,6 +406,10 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
     const int nI = min(nJ, m0 - r);
     qrcp_select<T, DMAX, RPT>(x, m0, used_r, nJ, nI, sI, sPivW, redv, redi);
     // (the last select step ends with a barrier, so sI is visible)
+    if (!pivots_in_range(sI, nI, m0)) {
+      status = 2;
+      break;
+    }
 
     // ------------------------------------------------ R_k = A(I,:) - U(I,:) V
     if (tid < nI * dim) {
@@ -467,6 +498,7 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
         }
       }
       const int q = min(nI, nJ);
+      double zero2 = 0.0;  // rounding-level trailing norms count as zero
 #pragma unroll 1
       for (int st = 0; st < q; ++st) {
         double bv = -1.0;
@@ -476,9 +508,11 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
           for (int c = 0; c < DMAX; ++c)
             if (c >= st && c < nI) bv += sc_abs2(w[c]);
           if (!(bv == bv)) bv = 0.0;
+          if (bv < zero2) bv = 0.0;
         }
         int bi = rem ? lane : 0x7fffffff;
         wave_argmax(bv, bi);
+        if (st == 0) zero2 = QRCP_NOISE * QRCP_NOISE * bv;
         const int p = bi;
         // the pivot column goes through LDS to every lane of the wave
         if (lane == p) {
@@ -542,6 +576,10 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
     }
     __syncthreads();
     const int dk = sDK;
+    if (!pivots_in_range(sJbar, dk, nJ)) {
+      status = 2;
+      break;
+    }
     if (A.fz && A.fz_stride >= 3 + 3 * DMAX) {
       // the iteration's pivots in full, for a replay with frozen pivots
       int32_t* rec = A.fz + (int64_t)(L.it_off + iter) * A.fz_stride;

@@ -26,7 +26,7 @@ struct BacaLeafDev {
 struct BacaOutDev {
   int32_t rank;
   int32_t iters;
-  int32_t status;  // 0 ok, 1 factor capacity exhausted
+  int32_t status;  // 0 ok, 1 factor capacity exhausted, 2 a pivot outside its candidate range
   int32_t pad;
   double mu;
 };

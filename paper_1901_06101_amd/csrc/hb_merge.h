@@ -132,6 +132,16 @@ struct RCompactDev {
   int32_t P, k;
 };
 
+// M (pa x pb, column-major, ld pa) = A B^H for A (pa x k, ld pa) and
+// B (pb x k, ld pb), both upper trapezoidal: A(i, t) = 0 for t < i.
+struct RRhDev {
+  const void* A;
+  const void* B;
+  void* M;
+  int32_t pa, pb, k;
+  int32_t pad;
+};
+
 namespace hbk {
 // scalar: 0 double, 1 complex double
 int copy_list_launch(const CopyDev* jobs_dev, int njobs, hipStream_t st);
@@ -153,6 +163,7 @@ int tsqr_applyh_launch(int scalar, int kmax, const QRApplyHDev* jobs_dev, int nj
                        const void* store, const double* beta, hipStream_t st);
 int concat_launch(int scalar, const ConcatDev* jobs_dev, int njobs, int64_t max_m, int max_k,
                   hipStream_t st);
+int rrh_launch(int scalar, const RRhDev* jobs_dev, int njobs, int64_t max_entries, hipStream_t st);
 int tsqr_mc(int scalar, int kmax);
 int tsqr_kmax_for(int scalar, int k);
 }  // namespace hbk

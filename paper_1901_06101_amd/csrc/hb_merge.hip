@@ -339,6 +339,22 @@ __global__ void rcompact_kernel(const RCompactDev* __restrict__ jobs) {
   }
 }
 
+// One thread per entry of M = A B^H; the sum starts at max(i, j) since
+// both factors vanish left of their diagonal.
+template <typename T>
+__global__ void rrh_explicit_kernel(const RRhDev* __restrict__ jobs) {
+  const RRhDev J = jobs[blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)J.pa * J.pb) return;
+  const int i = (int)(e % J.pa), j = (int)(e / J.pa);
+  const T* A = (const T*)J.A;
+  const T* B = (const T*)J.B;
+  T acc = sc_zero<T>();
+  for (int t = max(i, j); t < J.k; ++t)
+    sc_fma(acc, A[(int64_t)t * J.pa + i], sc_conj(B[(int64_t)t * J.pb + j]));
+  ((T*)J.M)[e] = acc;
+}
+
 __global__ void zero_fill_kernel(uint64_t* p, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -617,6 +633,9 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
         bv = sWv[w];
         piv = sWi[w];
       }
+    // a candidate always exists (s < p); the clamp keeps LDS indexing in
+    // range even if non-finite data left no winner
+    if (piv < s || piv >= p) piv = s;
     const int cs = c_cur[s], cpv = c_cur[piv];
     if (tid < p) c_nxt[tid] = tid == s ? cpv : (tid == piv ? cs : c_cur[tid]);
     const T* vcol = B + (int64_t)cpv * ldb;
@@ -974,6 +993,17 @@ int rcopy_launch(int scalar, const RCopyDev* jobs, int n, const void* store, con
   else
     hipLaunchKernelGGL((rcopy_kernel<hb_cplx>), dim3(n), dim3(256), 0, st, jobs,
                        (const hb_cplx*)store, (const hb_cplx*)alpha);
+  return (int)hipGetLastError();
+}
+
+int rrh_launch(int scalar, const RRhDev* jobs, int n, int64_t max_entries, hipStream_t st) {
+  if (n == 0 || max_entries == 0) return 0;
+  if (n > 65535) return -1;
+  const dim3 g((unsigned)((max_entries + 255) / 256), (unsigned)n);
+  if (scalar == 0)
+    hipLaunchKernelGGL((rrh_explicit_kernel<double>), g, dim3(256), 0, st, jobs);
+  else
+    hipLaunchKernelGGL((rrh_explicit_kernel<hb_cplx>), g, dim3(256), 0, st, jobs);
   return (int)hipGetLastError();
 }
 

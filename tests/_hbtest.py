@@ -75,13 +75,21 @@ def recon_norm(X, Y):
 
 NOISE = 1e-12
 PICK_NOISE = 1e-11
+QRCP_ZERO = 1e-13
+NORM_RTOL = 1e-9
 
 
 def _determined(norms):
-    """A QRCP pick is unique only while its trailing norm is well above the
-    rounding level of its panel."""
+    """A QRCP pick is unique while its trailing norm is well above the
+    rounding level of its panel, or so far below it that both sides count
+    every remaining norm as zero and pick the lowest index (the reading of
+    rounding-level norms, QRCP_ZERO below the first pick).  Picks in the band
+    between may differ."""
     norms = np.asarray(norms)
-    return norms.size == 0 or norms.min() > PICK_NOISE * norms.max()
+    if norms.size == 0 or not norms.max() > 0.0:
+        return True
+    rel = norms / norms.max()
+    return not np.any((rel > QRCP_ZERO) & (rel <= PICK_NOISE))
 
 
 def compare_tape(gtape, ginfo, oinfo):
@@ -92,7 +100,8 @@ def compare_tape(gtape, ginfo, oinfo):
     first iteration whose row picks, or the column picks that produced its
     block J_k, were made among rounding-level trailing norms (an exactly
     low-rank residual), and a terminating iteration with nu < 1e-12 mu is
-    never compared: in both cases several choices are equally valid.
+    never compared: in both cases several choices are equally valid.  On
+    the compared iterations nu and mu must agree to NORM_RTOL as well.
     Returns None or a text describing the first difference."""
     its = oinfo["iters"]
     gdk = list(int(x) for x in gtape["dk"])
@@ -117,6 +126,16 @@ def compare_tape(gtape, ginfo, oinfo):
         return "column pivots differ"
     if nk == len(odk) and (len(gdk) != len(odk) or ginfo["rank_baca"] != oinfo["rank_baca"]):
         return f"iteration count differs: gpu {gdk} oracle {odk}"
+    # the norm estimates of eqs. (11)-(13) on the compared iterations: both
+    # sides form nu from Cholesky factors of Gram blocks, so they agree to
+    # rounding amplified by the Gram blocks' conditioning
+    gnu, gmu = np.asarray(gtape["nu"]), np.asarray(gtape["mu"])
+    for k in range(nk):
+        onu, omu = its[k]["nu"], its[k]["mu"]
+        if abs(gmu[k] - omu) > NORM_RTOL * omu:
+            return f"iteration {k}: mu gpu {gmu[k]:.17e} oracle {omu:.17e}"
+        if abs(gnu[k] - onu) > NORM_RTOL * onu + 1e-13 * omu:
+            return f"iteration {k}: nu gpu {gnu[k]:.17e} oracle {onu:.17e}"
     return None
 
 

@@ -1,14 +1,15 @@
 """Leaves whose BACA rank exceeds the register TSQR tile (128 real columns)
-take the two-merge re-compression (V^H orthonormalised without truncation,
-then an eps-truncated merge with column-panel QR).  The 8-D Gaussian mixture
-at tol 1e-6 has leaf ranks up to 224 and merge widths up to 470; the FP64
-result is held to the usual bars against the oracle."""
+take the column-panel route of the SVD re-compression (QR(U) and QR(V^H) by
+column panels, the truncated SVD of T_U T_V^H).  The 8-D Gaussian mixture at
+tol 1e-6 has leaf ranks up to 224 and merge widths up to 470; every leaf's
+pivot tape and the FP64 result are held to the usual bars against the
+oracle."""
 import numpy as np
 import pytest
 
 from workloads import generators as G
 
-from _hbtest import factors_np, lowrank_diff, recon_norm, run_gpu, run_oracle, say
+from _hbtest import compare_tape, factors_np, lowrank_diff, recon_norm, run_gpu, run_oracle, say
 
 pytestmark = pytest.mark.gpu
 
@@ -16,8 +17,14 @@ pytestmark = pytest.mark.gpu
 def test_wide_leaves_match_oracle(lib):
     wl = G.make_gauss_mixture(n=2000, leaf=250, tol=1e-6, d=16, cfg=44)
     say("[wide leaves] 8-D mixture 2000 x 2000, leaf 250, d 16, tol 1e-6")
-    res = run_gpu(lib, wl)
+    res = run_gpu(lib, wl, record_tape=1)
     _, ores = run_oracle(wl)
+    nb = 1 << ores.L
+    for li in range(res.nleaves):
+        info = res.leaf_info(li)
+        b = info["t"] * nb + info["v"]
+        msg = compare_tape(res.leaf_tape(li), info, ores.leaf_info[b])
+        assert msg is None, f"leaf {b}: {msg}"
     st = res.stats()
     say(f"  leaf BACA rank max {st['leaf_rank_baca_max']}; rank gpu {res.rank(0)} oracle {ores.rank}")
     assert st["leaf_rank_baca_max"] > 128  # the wide path did run

@@ -96,6 +96,30 @@ def test_qrcp_ties_go_to_lowest_position():
     assert res.piv[1] == 0
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_qrcp_rounding_level_norms_tie_to_lowest_position(cplx):
+    """An exactly rank-2 panel: after two steps every trailing norm is
+    rounding only (the reading counts it as zero), so the later picks are the
+    lowest remaining positions, whatever the rounding left behind.  A panel
+    whose third column is small but well above rounding keeps its greedy
+    pick."""
+    rng = np.random.default_rng(3)
+
+    def rnd(*s):
+        return rng.standard_normal(s) + (1j * rng.standard_normal(s) if cplx else 0)
+
+    M = rnd(6, 2) @ rnd(2, 12)
+    res = qrcp(M, 6)
+    assert set(res.piv[:2].tolist()) <= set(range(12))
+    rest = [c for c in range(12) if c not in res.piv[:2]]
+    assert res.piv[2:].tolist() == rest[:4]
+    assert np.all(np.abs(res.tdiag[2:]) < 1e-13 * np.abs(res.tdiag[0]))
+    # a third direction at 1e-9 of the panel is information, not rounding
+    M2 = M + 1e-9 * np.linalg.norm(M) * np.outer(rnd(6), np.eye(12)[7])
+    res2 = qrcp(M2, 3)
+    assert res2.piv[2] == 7 or 7 in res2.piv[:2]
+
+
 def test_jacobi_closed_forms():
     # diagonal
     s = oracle.jacobi_svd(np.diag([3.0, -1.0, 2.0]))[1]
@@ -147,6 +171,37 @@ def test_lrnorm_and_update_equal_dense_norms(cplx):
     mu2n = oracle.lrnorm_update(U, V, mu2, Uk, Vk, nu)
     full = np.linalg.norm(np.hstack([U, Uk]) @ np.vstack([V, Vk])) ** 2
     assert abs(mu2n - full) <= 1e-12 * full
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("where", ["U_zero_column", "V_zero_row", "U_repeated_column"])
+def test_lrnorm_cholesky_breakdown_fallback(cplx, where):
+    """Reading of a Cholesky breakdown in LRnorm (eqs. (11)-(12)): a Gram
+    matrix that is only positive semidefinite (a zero column of U_k, a zero
+    row of V_k, or a repeated column) stops the factorisation, and nu comes
+    from nu^2 = Re sum(G_U o conj(G_V)), which is ||U_k V_k||_F^2 exactly.
+    The breakdown is checked to happen, so the fallback branch is what runs;
+    a dropped conjugate or a transposed Gram matrix fails the complex cases."""
+    from oracle.baca import _chol_upper
+    rng = np.random.default_rng(11)
+
+    def rnd(*s):
+        return rng.standard_normal(s) + (1j * rng.standard_normal(s) if cplx else 0)
+
+    Uk, Vk = rnd(30, 4), rnd(4, 25)
+    if where == "U_zero_column":
+        Uk[:, 2] = 0.0
+    elif where == "V_zero_row":
+        Vk[1, :] = 0.0
+    else:
+        Uk[:, 3] = Uk[:, 0]
+        Uk[:, 1] = 0.0  # a repeated column alone may factor by rounding
+    GU = Uk.conj().T @ Uk
+    GV = Vk @ Vk.conj().T
+    assert _chol_upper(GU) is None or _chol_upper(GV) is None
+    nu = oracle.lrnorm(Uk, Vk)
+    ref = np.linalg.norm(Uk @ Vk)
+    assert abs(nu - ref) <= 1e-13 * ref
 
 
 def test_entries_closed_values():
