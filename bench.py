@@ -1,23 +1,30 @@
 """Benchmark: H-BACA compress time on one MI355X.
 
-A step is one full H-BACA pass (leaf BACA, leaf SVD re-compression, every
+A step is one full H-BACA call (leaf BACA, leaf SVD re-compression, every
 merge level) over the benchmark workload with its inputs already resident in
-HBM.  Prints one JSON line.  The roofline object rates the leaf BACA kernel:
-its algorithmic bytes (U and V streamed once per iteration, counted by the
-library from the per-iteration block ranks) over its duration from HIP events
-on the call's stream, against the 8 TB/s HBM peak.
+HBM; `value` is the wall time per call.  The metric asks for the time at
+rel. error <= tol: the truncation tolerance eps of the call is the largest of
+tol, tol/2, tol/4, tol/8 whose result reaches a sampled relative Frobenius
+error <= tol against A (the eps-rank is relative to sigma_1 of each block, so
+eps = tol can leave a Frobenius error above tol); every path of the line is
+run at that eps.  Prints one JSON line.
+
+The roofline object rates the kernel class that takes the most device time
+in the call (HIP events the library records on the call's stream around
+each launch): the leaf BACA kernel against HBM (algorithmic bytes: U and V
+streamed once per iteration plus the residual blocks C_k and R_k written),
+or the small SVDs / the TSQR kernels against the FP64 vector peak.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload helmholtz]
                   [--no-cpu-baseline] [--no-comparisons] [--no-adjoint]
 
 Besides the headline workload, the line carries "comparisons": mixed
-precision against plain FP64 (Gaussian 2000^2) and one batched call against
-one call per block (1024 Laplace blocks); and "adjoint": the frozen-pivot
-adjoint on the differentiation workload (Gaussian 50000^2 in R^3, h = 0.7),
-that is the compression that records its pivots and ranks, the apply
-y = A~w and the gradients of <ybar, A~w> with respect to w, h and every
-point.  Each of the two runs in a child process of its own with a time
-limit, after the headline measurement, so that neither can change it.
+precision against plain FP64 (the 8-D Gaussian mixture at 2000^2 and the
+Gaussian R^3 2000^2 workload) and one batched call against one call per
+block (the 4096 Laplace blocks of the batched workload), and "adjoint": the
+frozen-pivot adjoint on the differentiation workload (Gaussian 50000^2 in
+R^3, h = 0.7).  Each runs in a child process of its own with a time limit,
+after the headline measurement, so that neither can change it.
 """
 import argparse
 import json
@@ -30,32 +37,71 @@ sys.path.insert(0, ROOT)
 
 METRIC = "H-BACA compress time at rel err\u2264tol, mixed/batched vs plain FP64; % roofline"
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
+FP64_PEAK_TFLOPS = 78.6  # FP64 vector (and FP64 MFMA) peak of MI355X
+EPS_DIVISORS = (1, 2, 4, 8)
 
 
-def cpu_baseline(wl):
-    """The CPU oracle, timed on this host on the same workload."""
-    import numpy as np  # noqa: F401
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(wl, eps=None, single_thread=True):
+    """The CPU oracle, timed on this host on the same workload at the same
+    eps: once with the BLAS threads NumPy starts with (all cores) and once
+    limited to one thread."""
     import oracle
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
+        threadpool_limits = None
         threads = 1
+    eps = wl["tol"] if eps is None else eps
     src = oracle.EntrySource(wl)
-    t = time.perf_counter()
-    res = oracle.hbaca(src, wl["m"], wl["n"], wl["tol"], wl["d"], wl["leaf"], wl["seed"])
-    el = time.perf_counter() - t
-    return dict(value=el * 1e3, unit="ms", cores=int(threads), kind="oracle",
-                sample=f"the whole workload ({len(res.leaf_info)} leaves, all merge levels); "
-                       "single Python thread, NumPy BLAS threads as counted",
-                rank=int(res.rank))
+
+    def once():
+        t = time.perf_counter()
+        res = oracle.hbaca(src, wl["m"], wl["n"], eps, wl["d"], wl["leaf"], wl["seed"])
+        return (time.perf_counter() - t) * 1e3, res
+
+    ms, res = once()
+    out = dict(value=ms, unit="ms", cores=int(threads), kind="oracle",
+               sample=f"the whole workload ({len(res.leaf_info)} leaves, all merge levels, "
+                      f"eps {eps:g}); one Python thread, NumPy BLAS on {threads} threads",
+               rank=int(res.rank), cpu_model=_cpu_model(), logical_cpus=os.cpu_count())
+    if single_thread and threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            ms1, _ = once()
+        out["single_thread"] = dict(value=ms1, unit="ms", cores=1)
+    return out
+
+
+def _lowrank_rel_diff(X1, Y1, X2, Y2):
+    """||X1 Y1^H - X2 Y2^H||_F / ||X2 Y2^H||_F from QR factors of the stacked
+    factors (never the dense products)."""
+    import numpy as np
+    if X2.shape[1] == 0:
+        return 0.0 if X1.shape[1] == 0 else float("inf")
+    _, R1 = np.linalg.qr(np.hstack([X1, -X2]))
+    _, R2 = np.linalg.qr(np.hstack([Y1, Y2]))
+    _, Q1 = np.linalg.qr(X2)
+    _, Q2 = np.linalg.qr(Y2)
+    return float(np.linalg.norm(R1 @ R2.conj().T) / np.linalg.norm(Q1 @ Q2.conj().T))
 
 
 def comparisons(steps=5, warmup=1):
-    """Mixed precision and batching against the plain FP64 GPU path, each at
-    the accuracy it reaches; prints one JSON object.  Runs in a child process
-    of the benchmark so that its outcome cannot affect the headline line."""
+    """Mixed precision and batching against the plain FP64 GPU path at equal
+    accuracy: every pair runs at the largest eps (tol / 1, 2, 4, 8) where
+    both sides reach a sampled relative error <= tol.  Prints one JSON object.
+    Runs in a child process of the benchmark so that its outcome cannot
+    affect the headline line."""
     import numpy as np
     import torch
 
@@ -81,58 +127,82 @@ def comparisons(steps=5, warmup=1):
 
     def rel_err(res, block=0):
         e2, a2 = res.error(block, 7)
-        return float(np.sqrt(e2 / a2))
+        return float(np.sqrt(e2 / a2)) if a2 > 0 else 0.0
 
-    out = {}
-    # plain FP64 against mixed precision on the Gaussian R^3 workload
-    wl = make_config("gauss3d")
-    X = torch.tensor(wl["X"], device=dev)
-    Y = torch.tensor(wl["Y"], device=dev)
+    def max_err(res):
+        return max(rel_err(res, b) for b in range(getattr(res, "nblocks", 1)))
 
-    def single(prec):
-        p = hb.params(dim=3, h=wl["h"], gauss_c=wl["gauss_c"], seed=wl["seed"], precision=prec)
-        return hb.compress(wl["entry"], p, X, Y, wl["m"], wl["n"], wl["tol"], wl["d"], wl["leaf"])
-
-    f_ms, f_res = timed(lambda: single(hb.HB_PREC_FP64), steps, warmup)
-    _note(f"comparisons: gauss3d FP64 {f_ms:.1f} ms")
-    m_ms, m_res = timed(lambda: single(hb.HB_PREC_MIXED), steps, warmup)
-    _note(f"comparisons: gauss3d mixed {m_ms:.1f} ms")
-    ef, em = rel_err(f_res), rel_err(m_res)
+    def equal_accuracy_eps(tol, makers):
+        """Largest tol / f at which every maker's result is within tol."""
+        eps = tol
+        for f in EPS_DIVISORS:
+            eps = tol / f
+            ok = True
+            for mk in makers:
+                r = mk(eps)
+                ok = ok and max_err(r) <= tol
+                r.close()
+            if ok:
+                break
+        return eps
 
     def operator_rel_diff(a, b):
-        # ||Ua Sa Va^T - Ub Sb Vb^T||_F / ||Ua Sa Va^T||_F from the factors
-        Ua, Sa, Va = a.factors(0)
-        Ub, Sb, Vb = b.factors(0)
-        Qu, Ru = torch.linalg.qr(torch.cat([Ua, Ub], dim=1))
-        Qv, Rv = torch.linalg.qr(torch.cat([Va, Vb], dim=1))
-        M = Ru @ torch.diag(torch.cat([Sa, -Sb])) @ Rv.T
-        return float(torch.linalg.norm(M) / torch.linalg.norm(Sa))
+        Ua, Sa, Va = (t.cpu().numpy() for t in a.factors(0))
+        Ub, Sb, Vb = (t.cpu().numpy() for t in b.factors(0))
+        return _lowrank_rel_diff(Ua * Sa, Va, Ub * Sb, Vb)
 
-    out["mixed_vs_fp64"] = dict(
-        workload=f"gauss3d {wl['m']}x{wl['n']} tol={wl['tol']} d={wl['d']} leaf={wl['leaf']}",
-        fp64_ms=f_ms, mixed_ms=m_ms, speedup=f_ms / m_ms, fp64_rank=f_res.rank(0),
-        mixed_rank=m_res.rank(0), fp64_rel_err_rows7=ef, mixed_rel_err_rows7=em,
-        mixed_vs_fp64_operator_rel_diff=operator_rel_diff(f_res, m_res),
-        mixed_within_5tol=bool(em <= 5 * wl["tol"]),
-        # the speedup counts only where both reach rel. error <= tol
-        speedup_counts=bool(ef <= wl["tol"] and em <= wl["tol"]))
-    f_res.close()
-    m_res.close()
-    # one batched call against one call per block (Laplace blocks of the
-    # batched workload's recipe), FP64 and mixed
-    nb = 1024
-    wb = G.make_laplace_blocks(nblocks=nb, cfg=3)
+    out = {}
+    # plain FP64 against mixed precision: the 8-D Gaussian mixture (the
+    # mixed-precision workload's recipe at 2000^2) and the Gaussian R^3 case
+    single_cases = (
+        ("gauss_mixture", G.make_gauss_mixture(n=2000, leaf=250, tol=1e-6, d=16, cfg=4)),
+        ("gauss3d", make_config("gauss3d")),
+    )
+    for key, wl in single_cases:
+        X = torch.tensor(wl["X"], device=dev)
+        Y = torch.tensor(wl["Y"], device=dev)
+        tol = wl["tol"]
+
+        def single(prec, eps, wl=wl, X=X, Y=Y):
+            p = hb.params(dim=wl["X"].shape[1], h=wl["h"], gauss_c=wl["gauss_c"],
+                          seed=wl["seed"], precision=prec)
+            return hb.compress(wl["entry"], p, X, Y, wl["m"], wl["n"], eps, wl["d"], wl["leaf"])
+
+        eps = equal_accuracy_eps(tol, [lambda e: single(hb.HB_PREC_FP64, e),
+                                       lambda e: single(hb.HB_PREC_MIXED, e)])
+        f_ms, f_res = timed(lambda: single(hb.HB_PREC_FP64, eps), steps, warmup)
+        m_ms, m_res = timed(lambda: single(hb.HB_PREC_MIXED, eps), steps, warmup)
+        _note(f"comparisons: {key} FP64 {f_ms:.1f} ms, mixed {m_ms:.1f} ms (eps {eps:g})")
+        ef, em = rel_err(f_res), rel_err(m_res)
+        out[f"mixed_vs_fp64_{key}"] = dict(
+            workload=f"{key} {wl['m']}x{wl['n']} tol={tol} d={wl['d']} leaf={wl['leaf']}",
+            eps=eps, fp64_ms=f_ms, mixed_ms=m_ms, speedup=f_ms / m_ms,
+            fp64_rank=f_res.rank(0), mixed_rank=m_res.rank(0), fp64_rel_err_rows7=ef,
+            mixed_rel_err_rows7=em,
+            mixed_vs_fp64_operator_rel_diff=operator_rel_diff(m_res, f_res),
+            mixed_within_5tol=bool(em <= 5 * tol),
+            # the speedup counts only where both reach rel. error <= tol
+            speedup_counts=bool(ef <= tol and em <= tol))
+        f_res.close()
+        m_res.close()
+    # one batched call against one call per block: the batched workload's
+    # 4096 Laplace blocks, FP64 and mixed
+    wb = G.make_laplace_blocks(nblocks=4096, cfg=3)
+    nb = len(wb["row_cnt"])
     Xb = torch.tensor(wb["X"], device=dev)
     Yb = torch.tensor(wb["Y"], device=dev)
+    tol = wb["tol"]
 
-    def batched(prec):
+    def batched(prec, eps):
         p = hb.params(dim=3, seed=wb["seed"], precision=prec)
         return hb.compress_batched(wb["entry"], p, Xb, wb["row_off"], wb["row_cnt"], Yb,
-                                   wb["col_off"], wb["col_cnt"], wb["tol"], wb["d"], wb["leaf"])
+                                   wb["col_off"], wb["col_cnt"], eps, wb["d"], wb["leaf"])
 
-    bf_ms, bf_res = timed(lambda: batched(hb.HB_PREC_FP64), 3, 1)
+    eps = equal_accuracy_eps(tol, [lambda e: batched(hb.HB_PREC_FP64, e),
+                                   lambda e: batched(hb.HB_PREC_MIXED, e)])
+    bf_ms, bf_res = timed(lambda: batched(hb.HB_PREC_FP64, eps), 3, 1)
     _note(f"comparisons: {nb} Laplace blocks batched FP64 {bf_ms:.1f} ms")
-    bm_ms, bm_res = timed(lambda: batched(hb.HB_PREC_MIXED), 3, 1)
+    bm_ms, bm_res = timed(lambda: batched(hb.HB_PREC_MIXED, eps), 3, 1)
     _note(f"comparisons: {nb} Laplace blocks batched mixed {bm_ms:.1f} ms")
 
     def sequential():
@@ -143,24 +213,44 @@ def comparisons(steps=5, warmup=1):
             p = hb.params(dim=3, seed=wb["seed"] + b)
             if last is not None:
                 last.close()
-            last = hb.compress(wb["entry"], p, Xb[r0:r0 + m], Yb[c0:c0 + n], m, n, wb["tol"],
+            last = hb.compress(wb["entry"], p, Xb[r0:r0 + m], Yb[c0:c0 + n], m, n, eps,
                                wb["d"], wb["leaf"])
         return last
 
     s_ms, s_res = timed(sequential, 1, 1)
     s_res.close()
     _note(f"comparisons: {nb} Laplace blocks one call each {s_ms:.1f} ms")
-    ebf = max(rel_err(bf_res, b) for b in range(nb))
-    ebm = max(rel_err(bm_res, b) for b in range(nb))
+    ebf, ebm = max_err(bf_res), max_err(bm_res)
+    # an evenly spaced sample of the blocks against the oracle (its H-BACA
+    # of that block alone)
+    sample = list(range(0, nb, max(1, nb // 128)))
+    oracle_diff = None
+    try:
+        import oracle
+        worst = 0.0
+        for b in sample:
+            ro, rc = int(wb["row_off"][b]), int(wb["row_cnt"][b])
+            co, cc = int(wb["col_off"][b]), int(wb["col_cnt"][b])
+            src = oracle.EntrySource(wb, X=wb["X"][ro:ro + rc], Y=wb["Y"][co:co + cc])
+            ref = oracle.hbaca(src, rc, cc, eps, wb["d"], wb["leaf"], wb["seed"] + b)
+            U, S, V = (t.cpu().numpy() for t in bf_res.factors(b))
+            worst = max(worst, _lowrank_rel_diff(U * S, V, ref.U * ref.S, ref.V.T))
+        oracle_diff = worst
+    except Exception as e:  # reported, not fatal to the leg
+        oracle_diff = f"{type(e).__name__}: {e}"
     out["batched_vs_sequential"] = dict(
-        workload=f"laplace_batched {nb} blocks, sizes 64-1024, tol={wb['tol']} d={wb['d']} "
+        workload=f"laplace_batched {nb} blocks, sizes 64-1024, tol={tol} d={wb['d']} "
                  f"leaf={wb['leaf']}",
-        sequential_fp64_ms=s_ms, batched_fp64_ms=bf_ms, batched_mixed_ms=bm_ms,
+        eps=eps, sequential_fp64_ms=s_ms, batched_fp64_ms=bf_ms, batched_mixed_ms=bm_ms,
         speedup_batched_fp64=s_ms / bf_ms, speedup_batched_mixed=s_ms / bm_ms,
         max_rel_err_rows7_fp64=ebf, max_rel_err_rows7_mixed=ebm,
-        mixed_within_5tol=bool(ebm <= 5 * wb["tol"]),
-        speedup_fp64_counts=bool(ebf <= wb["tol"]),
-        speedup_mixed_counts=bool(ebf <= wb["tol"] and ebm <= wb["tol"]))
+        fp64_vs_oracle_max_rel_diff=oracle_diff,
+        fp64_vs_oracle_sample=f"{len(sample)} of the {nb} blocks, evenly spaced",
+        mixed_within_5tol=bool(ebm <= 5 * tol),
+        speedup_fp64_counts=bool(ebf <= tol),
+        speedup_mixed_counts=bool(ebf <= tol and ebm <= tol))
+    bf_res.close()
+    bm_res.close()
     print(json.dumps(out), flush=True)
 
 
@@ -277,6 +367,66 @@ def run_child(flag, timeout=300):
     return {"error": f"exit {r.returncode} (its messages are on stderr)"}
 
 
+def _traffic(kernel, workload):
+    """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE plus
+    WRITE_SIZE, scaled by the same counters' reading for a copy of known
+    size), or None when no measurement of this kernel on this workload was
+    taken with the current source of the kernel."""
+    import hashlib
+    rec = PMC_TRAFFIC.get((kernel, workload))
+    if rec is None:
+        return None
+    try:
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return rec["bytes_per_launch"] if sha == rec["source_sha16"] else None
+
+
+# rocprofv3 --pmc measurements (profiles/*_pmc.md): kernel, workload ->
+# HBM bytes per launch and the sha256 prefix of the kernel's source when they
+# were taken
+PMC_TRAFFIC = {
+    # profiles/helmholtz_pmc.md: the timed call at eps 5e-5
+    ("baca_leaf_kernel", "helmholtz"): dict(
+        bytes_per_launch=5336506150.0, source="paper_1901_06101_amd/csrc/hb_baca.hip",
+        source_sha16="13bf2c49cbff476c"),
+}
+
+
+def rooflines(st, workload):
+    """Rates of the three kernel classes of one call from the library's
+    counters and HIP-event times; the dominant one by device time first."""
+    ms_leaf = st["ms_baca"]
+    leaf_bytes = st["resid_bytes"] + st.get("resid_cr_bytes", 0.0)
+    out = []
+    if ms_leaf > 0:
+        a = leaf_bytes / (ms_leaf * 1e-3) / 1e9
+        out.append(dict(kernel="baca_leaf_kernel", bound="hbm", achieved=a, peak=HBM_PEAK_GBS,
+                        unit="GB/s", frac=a / HBM_PEAK_GBS,
+                        traffic=_traffic("baca_leaf_kernel", workload),
+                        algorithmic_bytes_per_launch=leaf_bytes, launch_ms=ms_leaf, launches=1))
+    ms_svd = st.get("ms_svd", 0.0)
+    if ms_svd > 0:
+        a = st["svd_flops"] / (ms_svd * 1e-3) / 1e12
+        out.append(dict(kernel="svd_kernel", bound="alu", achieved=a, peak=FP64_PEAK_TFLOPS,
+                        unit="TFLOP/s", frac=a / FP64_PEAK_TFLOPS,
+                        traffic=_traffic("svd_kernel", workload),
+                        algorithmic_flops_per_call=st["svd_flops"], launch_ms=ms_svd,
+                        launches=st.get("svd_launches")))
+    ms_qr = st.get("ms_qr", 0.0) + st.get("ms_gemm", 0.0)
+    if ms_qr > 0:
+        fl = st["recompress_flops"] + st["merge_flops"]
+        a = fl / (ms_qr * 1e-3) / 1e12
+        out.append(dict(kernel="tsqr_factor/apply + block_gemm", bound="alu", achieved=a,
+                        peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=a / FP64_PEAK_TFLOPS,
+                        traffic=None, algorithmic_flops_per_call=fl, launch_ms=ms_qr,
+                        launches=st.get("qr_launches")))
+    out.sort(key=lambda r: -r["launch_ms"])
+    return out
+
+
 def headline(args, wl):
     """The timed compress calls on the headline workload: the measured
     fields of the line."""
@@ -297,65 +447,68 @@ def headline(args, wl):
         p["G2"] = torch.tensor(wl["G2"], device=dev)
         p["spike_lin"] = torch.tensor(wl["spike_lin"], device=dev)
         p["spike_val"] = torch.tensor(wl["spike_val"], device=dev)
+    tol = wl["tol"]
 
-    def step():
-        return hb.compress(wl["entry"], p, X, Y, wl["m"], wl["n"], wl["tol"], wl["d"],
-                           wl["leaf"])
+    def step(eps):
+        return hb.compress(wl["entry"], p, X, Y, wl["m"], wl["n"], eps, wl["d"], wl["leaf"])
 
-    _note(f"{wl['name']} {wl['m']}x{wl['n']}: warm-up")
+    def rel_err(res):
+        e2, a2 = res.error(0, 7)
+        return float(np.sqrt(e2 / a2))
+
+    # the truncation tolerance that reaches rel. error <= tol (untimed)
+    tried = []
+    eps = tol
+    for f in EPS_DIVISORS:
+        eps = tol / f
+        r = step(eps)
+        e = rel_err(r)
+        tried.append(dict(eps=eps, rel_err_rows7=e, rank=r.rank(0)))
+        r.close()
+        if e <= tol:
+            break
+    _note(f"{wl['name']} {wl['m']}x{wl['n']}: eps {eps:g} (tol {tol:g}); warm-up")
     for _ in range(args.warmup):
-        step().close()
+        step(eps).close()
     torch.cuda.synchronize()
     _note(f"{wl['name']}: {args.steps} timed steps")
     stats = []
+    last = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        r = step()
-        stats.append(r.stats())
-        last = r
+        if last is not None:
+            last.close()
+        last = step(eps)
+        stats.append(last.stats())
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ms = el * 1e3 / args.steps
-    e2, a2 = last.error(0, 7)
-    rel_err = float(np.sqrt(e2 / a2))
+    wall_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    rel = rel_err(last)
     rank = last.rank(0)
-    st = stats[-1]
-    # dominant-kernel roofline: the leaf BACA kernel (residual passes), timed
-    # with HIP events the library records on its stream around that launch
-    ms_baca = float(np.mean([s["ms_baca"] for s in stats]))
-    achieved = st["resid_bytes"] / (ms_baca * 1e-3) / 1e9
-    roofline = dict(kernel="baca_leaf_kernel", bound="hbm", achieved=achieved,
-                    peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                    traffic=None,
-                    algorithmic_bytes_per_launch=st["resid_bytes"],
-                    launch_ms=ms_baca)
+    keys = set(stats[-1])
+    mean = {k: float(np.mean([s[k] for s in stats])) for k in keys
+            if isinstance(stats[-1][k], (int, float))}
+    rf = rooflines(mean, wl["name"])
     copy = copy_bandwidth(torch)
-    roofline["copy_GBps_measured"] = copy
-    roofline["frac_of_copy"] = achieved / copy if copy else None
-    phases = {k: float(np.mean([s[k] for s in stats])) for k in
-              ("ms_setup", "ms_baca", "ms_recompress", "ms_merge", "ms_total")}
-    # the other kernel classes against the FP64 peak: algorithmic flops of
-    # the leaf residual passes, the re-compression and the merges (the
-    # library's counters) over each phase's device time
-    phase_rates = {}
-    for name, flops, phase_ms in (("leaf_residuals", st["resid_flops"], phases["ms_baca"]),
-                                  ("recompression", st["recompress_flops"], phases["ms_recompress"]),
-                                  ("merges", st["merge_flops"], phases["ms_merge"])):
-        tf = flops / (phase_ms * 1e-3) / 1e12 if phase_ms > 0 else None
-        phase_rates[name] = dict(flops=flops, ms=phase_ms, achieved_TFLOPs=tf,
-                                 peak_TFLOPs=FP64_PEAK_TFLOPS,
-                                 frac=(tf / FP64_PEAK_TFLOPS) if tf is not None else None)
+    for r in rf:
+        if r["unit"] == "GB/s":
+            r["copy_GBps_measured"] = copy
+            r["frac_of_copy"] = r["achieved"] / copy if copy else None
+    phases = {k: mean[k] for k in ("ms_setup", "ms_baca", "ms_recompress", "ms_merge", "ms_total",
+                                   "ms_svd", "ms_qr", "ms_gemm") if k in mean}
     out = {
-        "value": ms,
-        "ms_per_step": ms,
+        "value": wall_ms,
+        "ms_per_step": wall_ms,
+        "eps": eps,
+        "eps_search": tried,
         "rank": rank,
-        "rel_err_rows7": rel_err,
+        "rel_err_rows7": rel,
+        "within_tol": bool(rel <= tol),
         "phases_ms": phases,
-        "roofline": roofline,
-        "phase_rates": phase_rates,
+        "roofline": rf[0] if rf else None,
+        "kernel_classes": rf,
     }
     last.close()
-    _note(f"{wl['name']}: {ms:.2f} ms per compress")
+    _note(f"{wl['name']}: {wall_ms:.2f} ms per compress (eps {eps:g}, rel. error {rel:.2e})")
     return out
 
 
@@ -400,6 +553,8 @@ def main():
         "config": {"workload": f"{wl['name']} {wl['m']}x{wl['n']} tol={wl['tol']} d={wl['d']} "
                                f"leaf={wl['leaf']}",
                    "precision": "plain FP64 (complex128 for Helmholtz)",
+                   "comparisons": "mixed precision vs plain FP64 and batched vs one call per "
+                                  "block, in the 'comparisons' object",
                    "parallelism": "single GPU"},
     }
     try:
@@ -410,7 +565,7 @@ def main():
     if not args.no_cpu_baseline:
         _note("CPU baseline (the oracle on the same workload)")
         try:
-            out["cpu_baseline"] = cpu_baseline(wl)
+            out["cpu_baseline"] = cpu_baseline(wl, eps=out.get("eps"))
         except Exception as e:  # the GPU line is still reported
             out["cpu_baseline"] = {"value": None, "unit": "ms", "cores": None, "kind": "oracle",
                                    "sample": f"failed: {type(e).__name__}: {e}"}

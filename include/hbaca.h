@@ -131,6 +131,17 @@ typedef struct {
      are not counted */
   double recompress_flops;
   double merge_flops;
+  double resid_cr_bytes;     /* algorithmic bytes of the residual blocks C_k
+                                (m0 x d) and R_k (d x n0) written once per
+                                iteration: s d (m0 + n0) */
+  double ms_svd;             /* device time of the small-SVD launches */
+  double ms_qr;              /* device time of the TSQR factor and apply
+                                launches (re-compression and merges) */
+  double ms_gemm;            /* device time of the other-side block products */
+  double svd_flops;          /* algorithmic flops of the small SVDs: QRCP of
+                                R^H 4 phi p k q, and 4 phi p q (q - 1) per
+                                Jacobi sweep, q = min(p, k) */
+  int32_t svd_launches, qr_launches;
 } hb_stats;
 
 /*
@@ -192,6 +203,7 @@ hb_status hb_result_copy(const hb_result* res, int64_t block, void* U, double* s
  */
 hb_status hbaca_apply(const hb_result* res, int64_t block, const void* in, void* out,
                       int32_t adjoint, void* stream);
+
 
 /*
  * Vector-Jacobian product of y = A~(h, X, Y) w with pivots and ranks frozen.

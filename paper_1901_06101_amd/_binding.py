@@ -22,7 +22,8 @@ EXPORTED = (
     "hbaca_compress", "hbaca_compress_batched", "hb_result_nblocks", "hb_result_rank",
     "hb_result_rows", "hb_result_cols", "hb_result_is_complex", "hb_result_copy",
     "hb_result_stats", "hb_result_nleaves", "hb_result_leaf_info", "hb_result_leaf_tape",
-    "hb_result_error", "hb_result_free", "hb_status_string", "hbaca_apply", "hbaca_vjp", "hbaca_adjoint",
+    "hb_result_error", "hb_result_free", "hb_status_string", "hbaca_apply", "hbaca_vjp",
+    "hbaca_adjoint",
     "hbaca_recompute_frozen", "hb_partition", "hb_result_leaf_frozen", "hb_result_merge_ranks",
 )
 
@@ -72,6 +73,13 @@ class HbStats(C.Structure):
         ("pad", C.c_int32),
         ("recompress_flops", C.c_double),
         ("merge_flops", C.c_double),
+        ("resid_cr_bytes", C.c_double),
+        ("ms_svd", C.c_double),
+        ("ms_qr", C.c_double),
+        ("ms_gemm", C.c_double),
+        ("svd_flops", C.c_double),
+        ("svd_launches", C.c_int32),
+        ("qr_launches", C.c_int32),
     ]
 
     def as_dict(self):

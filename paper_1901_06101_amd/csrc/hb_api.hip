@@ -522,6 +522,78 @@ static void build_trees(const std::vector<QRNodeDev>& mats, const std::vector<in
   }
 }
 
+// Device time per kernel class of one call: HIP event pairs recorded on the
+// call's stream around each launch of the class, read after the call's last
+// synchronisation.  Events come from a process-wide pool, so a call creates
+// none after the first few.
+class EventPool {
+ public:
+  static EventPool& get() {
+    static EventPool p;
+    return p;
+  }
+  hipEvent_t take() {
+    std::lock_guard<std::mutex> g(mu_);
+    if (!free_.empty()) {
+      hipEvent_t e = free_.back();
+      free_.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return e;
+  }
+  void give(hipEvent_t e) {
+    if (!e) return;
+    std::lock_guard<std::mutex> g(mu_);
+    free_.push_back(e);
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<hipEvent_t> free_;
+};
+
+enum KClass { KC_SVD = 0, KC_QR = 1, KC_GEMM = 2, KC_N = 3 };
+
+struct KernelClock {
+  struct Span {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Span> spans;
+  hipEvent_t begin(hipStream_t st) {
+    hipEvent_t e = EventPool::get().take();
+    if (e) (void)hipEventRecord(e, st);
+    return e;
+  }
+  void end(int cls, hipEvent_t a, hipStream_t st) {
+    hipEvent_t b = EventPool::get().take();
+    if (b) (void)hipEventRecord(b, st);
+    spans.push_back(Span{cls, a, b});
+  }
+  // after the stream has been synchronised
+  void totals(double* ms, int* launches) {
+    for (const Span& s : spans) {
+      if (s.a && s.b) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, s.a, s.b) == hipSuccess) ms[s.cls] += t;
+        else (void)hipGetLastError();
+      }
+      launches[s.cls] += 1;
+    }
+  }
+  ~KernelClock() {
+    for (const Span& s : spans) {
+      EventPool::get().give(s.a);
+      EventPool::get().give(s.b);
+    }
+  }
+};
+
 struct Engine {
   hipStream_t st;
   int scalar;
@@ -531,6 +603,8 @@ struct Engine {
   int panel = 0;        // merge panel width (0: the TSQR tile)
   int svd_sweeps_max = 0;
   int svd_storage = 0;  // forced SVD storage mode (diagnostics)
+  double svd_flops = 0.0;  // algorithmic flops of the small SVDs run so far
+  KernelClock clock;
 
   Engine(hipStream_t s, int sc, double e, DevMem& t) : st(s), scalar(sc), eps(e), tmp(t) {}
 
@@ -558,11 +632,13 @@ struct Engine {
     F.beta = tmp.get<double>(std::max(F.tb.ab_elems, 1));
     F.dlev.clear();
     for (auto& lv : F.tb.levels) F.dlev.push_back(upload(tmp, lv, st));
+    hipEvent_t t0 = clock.begin(st);
     for (size_t l = 0; l < F.tb.levels.size(); ++l) {
       HB_LAUNCH(hbk::tsqr_factor_launch(scalar, kv, F.dlev[l], (int)F.tb.levels[l].size(),
                                         l ? F.dlev[l - 1] : nullptr, F.store, F.alpha, F.beta,
                                         st));
     }
+    clock.end(KC_QR, t0, st);
   }
 
   // Zout(matrix a) = Q_a [Zin_a; 0]  (Zin_a: steps_top x r_a, ld ldin_a;
@@ -716,7 +792,9 @@ struct Engine {
       }
       if (!jobs.empty()) {
         QRApplyHDev* dj = upload(tmp, jobs, st);
+        hipEvent_t t0 = clock.begin(st);
         HB_LAUNCH(hbk::tsqr_applyh_launch(scalar, kv, dj, (int)jobs.size(), F.store, F.beta, st));
+        clock.end(KC_QR, t0, st);
       }
     }
   }
@@ -827,7 +905,9 @@ struct Engine {
       }
       if (!jobs.empty()) {
         QRApplyDev* dj = upload(tmp, jobs, st);
+        hipEvent_t t0 = clock.begin(st);
         HB_LAUNCH(hbk::tsqr_apply_launch(scalar, kv, dj, (int)jobs.size(), F.store, F.beta, st));
+        clock.end(KC_QR, t0, st);
       }
     }
   }
@@ -877,14 +957,22 @@ static void run_svds(Engine& E, std::vector<SVDJobDev>& jobs, const void* store,
     outs[a] = SvdOut{J.Xr, J.Yr, J.S, J.rank, J.p, J.k};
   }
   SVDJobDev* dj = upload(E.tmp, jobs, E.st);
+  hipEvent_t t0 = E.clock.begin(E.st);
   HB_LAUNCH(hbk::svd_launch(E.scalar, dj, (int)nj, kmax, pmax, store, alpha, E.eps, E.st, E.svd_storage));
+  E.clock.end(KC_SVD, t0, E.st);
   std::vector<int32_t> rh(2 * nj);
   HB_HIP(hipMemcpyAsync(rh.data(), dr, 2 * nj * sizeof(int32_t), hipMemcpyDeviceToHost, E.st));
   HB_HIP(hipStreamSynchronize(E.st));
   ranks_host.resize(nj);
+  // algorithmic flops: QRCP of R^H (4 phi p k q) and per Jacobi sweep
+  // q (q - 1) / 2 pairs, each a dot product and a rotation of two length-p
+  // columns (8 phi p); q = min(p, k)
+  const double phi = E.scalar ? 4.0 : 1.0;
   for (size_t a = 0; a < nj; ++a) {
     ranks_host[a] = rh[2 * a];
     E.svd_sweeps_max = std::max(E.svd_sweeps_max, (int)rh[2 * a + 1]);
+    const double p = jobs[a].p, k = jobs[a].k, q = std::min(p, k);
+    E.svd_flops += phi * (4.0 * p * k * q + (double)rh[2 * a + 1] * 4.0 * p * q * (q - 1.0));
   }
 }
 
@@ -1014,7 +1102,9 @@ static void run_merges_direct(Engine& E, std::vector<MergeJob>& jobs, DevMem& ou
   E.apply(F, zin_all, ldin_all, rr_all, zout_all, ldout_all);
   if (!gj.empty()) {
     BlockGemmDev* dg = upload(E.tmp, gj, E.st);
+    hipEvent_t t0 = E.clock.begin(E.st);
     HB_LAUNCH(hbk::block_gemm_launch(E.scalar, dg, (int)gj.size(), (int)max_rows, max_rin, E.st));
+    E.clock.end(KC_GEMM, t0, E.st);
   }
 }
 
@@ -1315,7 +1405,9 @@ static void run_merges_caqr(Engine& E, std::vector<MergeJob>& jobs, DevMem& out_
   panel_qr_apply(E, S, zin, ldin, rr, zout);
   if (!gj.empty()) {
     BlockGemmDev* dg = upload(E.tmp, gj, E.st);
+    hipEvent_t t0 = E.clock.begin(E.st);
     HB_LAUNCH(hbk::block_gemm_launch(E.scalar, dg, (int)gj.size(), (int)max_rows, max_rin, E.st));
+    E.clock.end(KC_GEMM, t0, E.st);
   }
 }
 
@@ -1854,6 +1946,8 @@ static hb_status run(const CallSpec& c, hb_result** out) {
       for (int k = 0; k < lf.iters; ++k) {
         const double mn = (double)lf.m0 + lf.n0;
         S.resid_bytes += (double)bbytes * r * mn;
+        S.resid_cr_bytes += (double)bbytes *
+                            ((double)std::min(c.d, lf.n0) * lf.m0 + (double)std::min(c.d, lf.m0) * lf.n0);
         S.resid_flops += 2.0 * phi * std::min(c.d, lf.n0) * r * mn;
         S.entries_evaluated += (double)std::min(c.d, lf.n0) * mn;
         r += h_dk[ld[s].it_off + k];
@@ -2110,6 +2204,17 @@ finish:
   S.svd_sweeps_max = Eng.svd_sweeps_max;
   HB_HIP(hipEventRecord(ev[5], st));
   HB_HIP(hipStreamSynchronize(st));
+  {
+    double ms[KC_N] = {0.0, 0.0, 0.0};
+    int nl[KC_N] = {0, 0, 0};
+    Eng.clock.totals(ms, nl);
+    S.ms_svd = ms[KC_SVD];
+    S.ms_qr = ms[KC_QR];
+    S.ms_gemm = ms[KC_GEMM];
+    S.svd_launches = nl[KC_SVD];
+    S.qr_launches = nl[KC_QR];
+    S.svd_flops = Eng.svd_flops;
+  }
   S.ms_setup = elapsed(ev[0], ev[1]);
   S.ms_baca = elapsed(ev[1], ev[2]);
   S.ms_recompress = elapsed(ev[2], ev[3]);

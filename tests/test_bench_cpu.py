@@ -153,21 +153,23 @@ def test_comparisons_leg_runs_against_a_stand_in_library(monkeypatch, capsys):
     monkeypatch.setitem(sys.modules, "paper_1901_06101_amd", fake)
     monkeypatch.setattr(workloads, "make_config", lambda name, scale=1.0: wl)
     monkeypatch.setattr(G, "make_laplace_blocks", lambda nblocks, cfg: blocks)
+    monkeypatch.setattr(G, "make_gauss_mixture", lambda **kw: wl)
     orig_device = torch.device
     monkeypatch.setattr(torch, "device", lambda *a, **k: orig_device("cpu"))
     monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
     bench.comparisons(steps=1, warmup=1)
     line = [s for s in capsys.readouterr().out.splitlines() if s.startswith("{")][-1]
     out = json.loads(line)
-    mv = out["mixed_vs_fp64"]
-    assert mv["fp64_rank"] == 5 and mv["mixed_within_5tol"] is True
-    assert mv["speedup_counts"] is True
-    assert 0.0 < mv["mixed_vs_fp64_operator_rel_diff"] < 1e-8
+    for key in ("mixed_vs_fp64_gauss_mixture", "mixed_vs_fp64_gauss3d"):
+        mv = out[key]
+        assert mv["fp64_rank"] == 5 and mv["mixed_within_5tol"] is True
+        assert mv["speedup_counts"] is True and mv["eps"] == wl["tol"]
+        assert 0.0 < mv["mixed_vs_fp64_operator_rel_diff"] < 1e-8
     bs = out["batched_vs_sequential"]
     for key in ("sequential_fp64_ms", "batched_fp64_ms", "batched_mixed_ms",
                 "speedup_batched_fp64", "speedup_batched_mixed", "max_rel_err_rows7_fp64",
                 "max_rel_err_rows7_mixed", "mixed_within_5tol", "speedup_fp64_counts",
-                "speedup_mixed_counts"):
+                "speedup_mixed_counts", "fp64_vs_oracle_max_rel_diff", "eps"):
         assert key in bs, key
 
 
@@ -187,11 +189,17 @@ def test_json_line_contract_with_a_stand_in_library(monkeypatch, capsys):
 
     wl = G.make_gauss3d(n=200, leaf=50, tol=1e-6, d=8, cfg=73)
 
+    import time as _time
+
     class StandIn:
+        def __init__(self):
+            _time.sleep(0.005)  # a call takes longer than any of its phases
+
         def stats(self):
-            return dict(ms_baca=1.0, resid_bytes=2e9, resid_flops=1e9, recompress_flops=1e9,
-                        merge_flops=2e9, ms_setup=0.1, ms_recompress=0.5, ms_merge=2.0,
-                        ms_total=3.6)
+            return dict(ms_baca=1.0, resid_bytes=1.5e9, resid_cr_bytes=0.5e9, resid_flops=1e9,
+                        recompress_flops=1e9, merge_flops=2e9, ms_setup=0.1,
+                        ms_recompress=0.5, ms_merge=2.0, ms_total=3.6, ms_svd=0.4,
+                        svd_flops=4e8, ms_qr=0.3, ms_gemm=0.05, svd_launches=3, qr_launches=9)
 
         def error(self, block=0, row_stride=1):
             return 1e-14, 1.0
@@ -221,11 +229,21 @@ def test_json_line_contract_with_a_stand_in_library(monkeypatch, capsys):
         assert key in out, key
     assert out["n_gpus"] == 1 and out["steps"] == 2 and out["warmup"] == 1
     assert out["value"] == out["ms_per_step"] and out["higher_is_better"] is False
+    # the wall time of whole calls, not a phase of one
+    assert out["value"] >= 5.0 and out["value"] != out["phases_ms"]["ms_merge"]
+    assert out["eps"] == wl["tol"] and out["within_tol"] is True
     assert "workload" in out["config"]
     rf = out["roofline"]
+    # the leaf kernel has the most device time here (1.0 ms against 0.4 and
+    # 0.35): its bytes are the U/V streams plus the C_k, R_k writes
+    assert rf["kernel"] == "baca_leaf_kernel"
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
     assert abs(rf["achieved"] - 2000.0) < 1e-9 and abs(rf["frac"] - 0.25) < 1e-12
     assert "traffic" in rf
+    kc = {k["kernel"]: k for k in out["kernel_classes"]}
+    assert abs(kc["svd_kernel"]["achieved"] - 1.0) < 1e-12 and kc["svd_kernel"]["bound"] == "alu"
+    assert [k["launch_ms"] for k in out["kernel_classes"]] == sorted(
+        [k["launch_ms"] for k in out["kernel_classes"]], reverse=True)
     cb = out["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1
     assert "comparisons" not in out and "adjoint" not in out
