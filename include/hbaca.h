@@ -204,6 +204,21 @@ hb_status hb_result_copy(const hb_result* res, int64_t block, void* U, double* s
 hb_status hbaca_apply(const hb_result* res, int64_t block, const void* in, void* out,
                       int32_t adjoint, void* stream);
 
+/*
+ * hbaca_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation and the same kernels, with the r per-column products held
+ * in a library-owned static device buffer of 64 KiB per GPU instead of an
+ * allocation.  The call allocates nothing.  Ranks whose products exceed
+ * 64 KiB (4096 complex, 8192 real) return HB_EUNSUPPORTED.  Every call on
+ * one GPU shares that buffer: calls that overlap on one GPU (concurrent
+ * streams or host threads) race and must be serialised by the caller.  The
+ * buffer is fully written before it is read, so no clearing is needed.
+ * Arguments, layouts and errors are those of hbaca_apply; HB_EDEVICE also
+ * when the buffer's device address cannot be obtained.
+ */
+hb_status hbaca_apply_noalloc(const hb_result* res, int64_t block, const void* in, void* out,
+                              int32_t adjoint, void* stream);
 
 /*
  * Vector-Jacobian product of y = A~(h, X, Y) w with pivots and ranks frozen.

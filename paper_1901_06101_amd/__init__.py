@@ -212,6 +212,17 @@ class Result:
                                        _stream()), "hbaca_apply")
         return out
 
+    def apply_noalloc(self, w, out, block=0, adjoint=False):
+        """apply() into the caller's device vector `out` through
+        hbaca_apply_noalloc, which allocates no device memory."""
+        m, n = self.shape(block)
+        if w.numel() != (m if adjoint else n) or out.numel() != (n if adjoint else m):
+            raise ValueError("vector lengths do not match the block")
+        B._check(self._lib.hbaca_apply_noalloc(self._h, block, _ptr(w), _ptr(out),
+                                               int(bool(adjoint)), _stream()),
+                 "hbaca_apply_noalloc")
+        return out
+
     def vjp(self, w, ybar, want=("w", "h", "x", "y")):
         """Gradients of <ybar, A~ w> with pivots and ranks frozen (needs a
         Gaussian result compressed with record_tape=2): (grad_w, grad_h,

@@ -22,8 +22,8 @@ EXPORTED = (
     "hbaca_compress", "hbaca_compress_batched", "hb_result_nblocks", "hb_result_rank",
     "hb_result_rows", "hb_result_cols", "hb_result_is_complex", "hb_result_copy",
     "hb_result_stats", "hb_result_nleaves", "hb_result_leaf_info", "hb_result_leaf_tape",
-    "hb_result_error", "hb_result_free", "hb_status_string", "hbaca_apply", "hbaca_vjp",
-    "hbaca_adjoint",
+    "hb_result_error", "hb_result_free", "hb_status_string", "hbaca_apply",
+    "hbaca_apply_noalloc", "hbaca_vjp", "hbaca_adjoint",
     "hbaca_recompute_frozen", "hb_partition", "hb_result_leaf_frozen", "hb_result_merge_ranks",
 )
 
@@ -134,6 +134,8 @@ def load(path: str = LIB_PATH):
     lib.hb_result_error.restype = C.c_int
     lib.hbaca_apply.argtypes = [vp, i64, vp, vp, i32, vp]
     lib.hbaca_apply.restype = C.c_int
+    lib.hbaca_apply_noalloc.argtypes = [vp, i64, vp, vp, i32, vp]
+    lib.hbaca_apply_noalloc.restype = C.c_int
     lib.hbaca_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hbaca_vjp.restype = C.c_int
     lib.hbaca_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]

@@ -2245,6 +2245,61 @@ static hb_status guarded(const CallSpec& c, hb_result** out) {
 // ============================================================== C ABI =======
 namespace {
 
+// The per-column products t = diag(S) X^H v of hbaca_apply live in this
+// buffer for hbaca_apply_noalloc (callers that cannot allocate).  Each
+// device holds its own copy until the process ends.
+constexpr size_t kApplyScratchBytes = 64 * 1024;
+static __device__ __align__(256) unsigned char scratch[kApplyScratchBytes];
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current (the array's name in host code is only a
+// host-side stand-in, never a device address).
+static void* apply_scratch_ptr() {
+  static std::mutex mu;
+  static std::vector<void*> ptrs;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+  std::lock_guard<std::mutex> g(mu);
+  if ((size_t)dev >= ptrs.size()) ptrs.resize((size_t)dev + 1, nullptr);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    ptrs[dev] = p;
+  }
+  return ptrs[dev];
+}
+
+// y = U diag(S) Vh^H v (adjoint 0) or Vh diag(S) U^H v (adjoint 1) with the
+// r products t held in `t` (any device buffer of r scalars).
+static hb_status apply_blocks(const Block& B, int scalar, const void* in, void* out, int adjoint,
+                              void* t, hipStream_t st) {
+  const int64_t nin = adjoint ? B.m : B.n, nout = adjoint ? B.n : B.m;
+  const size_t sb = scalar_bytes(scalar);
+  if (B.r == 0) {
+    if (nout > 0 && hbk::zero_fill_launch(out, (size_t)nout * sb, st) != 0) return HB_EDEVICE;
+    return HB_OK;
+  }
+  const void* X = adjoint ? B.U : B.Vh;  // reduced against the input
+  const void* Z = adjoint ? B.Vh : B.U;  // expanded into the output
+  const unsigned ng = (unsigned)((nout + AP_NT - 1) / AP_NT);
+  const size_t sh = (size_t)B.r * sb;
+  if (scalar == 0) {
+    hipLaunchKernelGGL(apply_reduce_kernel<double>, dim3(B.r), dim3(AP_NT), 0, st,
+                       (const double*)X, nin, B.r, B.S, (const double*)in, (double*)t);
+    hipLaunchKernelGGL(apply_expand_kernel<double>, dim3(ng), dim3(AP_NT), sh, st,
+                       (const double*)Z, nout, B.r, (const double*)t, (double*)out);
+  } else {
+    hipLaunchKernelGGL(apply_reduce_kernel<hb_cplx>, dim3(B.r), dim3(AP_NT), 0, st,
+                       (const hb_cplx*)X, nin, B.r, B.S, (const hb_cplx*)in, (hb_cplx*)t);
+    hipLaunchKernelGGL(apply_expand_kernel<hb_cplx>, dim3(ng), dim3(AP_NT), sh, st,
+                       (const hb_cplx*)Z, nout, B.r, (const hb_cplx*)t, (hb_cplx*)out);
+  }
+  return hipGetLastError() == hipSuccess ? HB_OK : HB_EDEVICE;
+}
+
 struct GpuAdjExec {
   const AdjArgs& a;
   hipStream_t st;
@@ -2510,33 +2565,29 @@ hb_status hbaca_apply(const hb_result* r, int64_t b, const void* in, void* out, 
   if (adjoint != 0 && adjoint != 1) return HB_EINVAL;
   const Block& B = r->out_blocks[b];
   hipStream_t st = (hipStream_t)stream;
-  const int64_t nin = adjoint ? B.m : B.n, nout = adjoint ? B.n : B.m;
   const size_t sb = scalar_bytes(r->scalar);
-  if (B.r == 0) {
-    if (nout > 0 && hbk::zero_fill_launch(out, (size_t)nout * sb, st) != 0) return HB_EDEVICE;
-    return HB_OK;
-  }
-  if ((size_t)B.r * sb > 64 * 1024) return HB_EUNSUPPORTED;
+  if (B.r == 0) return apply_blocks(B, r->scalar, in, out, adjoint, nullptr, st);
+  if ((size_t)B.r * sb > kApplyScratchBytes) return HB_EUNSUPPORTED;
   void* t = BlockCache::get().alloc((size_t)B.r * sb, st);
   if (!t) return HB_ENOMEM;
-  const void* X = adjoint ? B.U : B.Vh;  // reduced against the input
-  const void* Z = adjoint ? B.Vh : B.U;  // expanded into the output
-  const unsigned ng = (unsigned)((nout + AP_NT - 1) / AP_NT);
-  const size_t sh = (size_t)B.r * sb;
-  if (r->scalar == 0) {
-    hipLaunchKernelGGL(apply_reduce_kernel<double>, dim3(B.r), dim3(AP_NT), 0, st,
-                       (const double*)X, nin, B.r, B.S, (const double*)in, (double*)t);
-    hipLaunchKernelGGL(apply_expand_kernel<double>, dim3(ng), dim3(AP_NT), sh, st,
-                       (const double*)Z, nout, B.r, (const double*)t, (double*)out);
-  } else {
-    hipLaunchKernelGGL(apply_reduce_kernel<hb_cplx>, dim3(B.r), dim3(AP_NT), 0, st,
-                       (const hb_cplx*)X, nin, B.r, B.S, (const hb_cplx*)in, (hb_cplx*)t);
-    hipLaunchKernelGGL(apply_expand_kernel<hb_cplx>, dim3(ng), dim3(AP_NT), sh, st,
-                       (const hb_cplx*)Z, nout, B.r, (const hb_cplx*)t, (hb_cplx*)out);
-  }
-  const hipError_t e = hipGetLastError();
+  const hb_status s = apply_blocks(B, r->scalar, in, out, adjoint, t, st);
   BlockCache::get().release(t, st, false);
-  return e == hipSuccess ? HB_OK : HB_EDEVICE;
+  return s;
+}
+
+hb_status hbaca_apply_noalloc(const hb_result* r, int64_t b, const void* in, void* out,
+                              int32_t adjoint, void* stream) {
+  if (!r || b < 0 || b >= (int64_t)r->out_blocks.size() || !in || !out) return HB_EINVAL;
+  if (adjoint != 0 && adjoint != 1) return HB_EINVAL;
+  const Block& B = r->out_blocks[b];
+  hipStream_t st = (hipStream_t)stream;
+  if ((size_t)B.r * scalar_bytes(r->scalar) > kApplyScratchBytes) return HB_EUNSUPPORTED;
+  void* t = nullptr;
+  if (B.r > 0) {
+    t = apply_scratch_ptr();
+    if (!t) return HB_EDEVICE;
+  }
+  return apply_blocks(B, r->scalar, in, out, adjoint, t, st);
 }
 
 
