@@ -51,9 +51,16 @@ typedef enum {
                               paper's Gaussian kernel has gauss_c = 2 */
   HB_K_LAPLACE = 2,        /* 1 / |x - y|, real */
   HB_K_HELMHOLTZ3D = 3,    /* exp(i k |x - y|) / (4 pi |x - y|), complex */
-  HB_K_LOWRANK_SPIKES = 4  /* (G1 G2)(i, j) + spike(i, j), real: the paper's
+  HB_K_LOWRANK_SPIKES = 4, /* (G1 G2)(i, j) + spike(i, j), real: the paper's
                               product-of-random kernel plus sparse entries */
+  HB_K_EFIE2D = 5,         /* H_0^(2)(k |x - y|), the Hankel function of the
+                              second kind and order 0, complex: the paper's
+                              EFIE2D kernel (Section "Numerical Results") */
+  HB_K_POLYNOMIAL = 6      /* (x^T y + h)^2, real: the paper's polynomial
+                              kernel; dim up to HB_POLY_MAXDIM */
 } hb_entry_fn;
+
+#define HB_POLY_MAXDIM 256
 
 typedef enum {
   HB_PREC_FP64 = 0,  /* every step in FP64 (complex: FP64 pairs) */
@@ -66,10 +73,11 @@ typedef enum {
 } hb_precision;
 
 typedef struct {
-  int32_t dim;        /* point dimension (1..8); ignored by LOWRANK_SPIKES */
-  double h;           /* Gaussian width h > 0 */
+  int32_t dim;        /* point dimension (1..8; 1..HB_POLY_MAXDIM for
+                         POLYNOMIAL); ignored by LOWRANK_SPIKES */
+  double h;           /* Gaussian width h > 0; POLYNOMIAL: the shift h */
   double gauss_c;     /* Gaussian normalisation c > 0 */
-  double wavenumber;  /* Helmholtz k > 0 */
+  double wavenumber;  /* Helmholtz and EFIE2D k > 0 */
   /* LOWRANK_SPIKES only (device arrays): G1 is m x lr_rank row-major, G2 is
      lr_rank x n row-major; spike_lin holds n_spikes sorted linear indices
      i * n + j with values spike_val. */

@@ -9,6 +9,9 @@ The paper assumes any entry A(i, j) costs O(1) (Abstract; Section
 * Helmholtz exp(i k r) / (4 pi r), r = |x_i - y_j|   (complex).
 * Product of random factors G1 G2 (the paper's "Product-of-random" kernel)
   plus a sparse set of spikes (coherent entries).
+* EFIE2D    H_0^(2)(k |x_i - y_j|), the Hankel function of the second kind
+  and order 0 (complex), between points of two 2-D strips.
+* Polynomial (x_i^T y_j + h)^2.
 
 Every function evaluates a full sub-block A(I, J) for global index arrays.
 Parity: these are the plain definitions; the HIP side evaluates the same
@@ -18,7 +21,7 @@ from __future__ import annotations
 
 import numpy as np
 
-GAUSS, LAPLACE, HELMHOLTZ, LOWRANK_SPIKES = 1, 2, 3, 4
+GAUSS, LAPLACE, HELMHOLTZ, LOWRANK_SPIKES, EFIE2D, POLYNOMIAL = 1, 2, 3, 4, 5, 6
 
 
 class EntrySource:
@@ -37,7 +40,7 @@ class EntrySource:
         self.h = float(wl.get("h", 0.0))
         self.c = float(wl.get("gauss_c", 1.0))
         self.k = float(wl.get("wavenumber", 0.0))
-        self.is_complex = self.kind == HELMHOLTZ
+        self.is_complex = self.kind in (HELMHOLTZ, EFIE2D)
         self.dtype = np.complex128 if self.is_complex else np.float64
         if self.kind == LOWRANK_SPIKES:
             self.G1 = wl["G1"]
@@ -66,6 +69,11 @@ class EntrySource:
         if self.kind == HELMHOLTZ:
             r = np.sqrt(self._r2(I, J))
             return np.exp(1j * self.k * r) / (4.0 * np.pi * r)
+        if self.kind == EFIE2D:
+            from scipy.special import hankel2
+            return hankel2(0, self.k * np.sqrt(self._r2(I, J)))
+        if self.kind == POLYNOMIAL:
+            return (self.X[I] @ self.Y[J].T + self.h) ** 2
         if self.kind == LOWRANK_SPIKES:
             A = self.G1[I] @ self.G2[:, J]
             if self.spike_lin.size:

@@ -14,14 +14,15 @@ import ctypes as C
 import numpy as np
 
 from . import _binding as B
-from ._binding import (HB_K_GAUSS, HB_K_HELMHOLTZ3D, HB_K_LAPLACE,  # noqa: F401
-                       HB_K_LOWRANK_SPIKES, HB_PREC_FP64, HB_PREC_MIXED, HBACAError, HbParams,
-                       HbStats, load)
+from ._binding import (HB_K_EFIE2D, HB_K_GAUSS, HB_K_HELMHOLTZ3D,  # noqa: F401
+                       HB_K_LAPLACE, HB_K_LOWRANK_SPIKES, HB_K_POLYNOMIAL, HB_PREC_FP64,
+                       HB_PREC_MIXED, HBACAError, HbParams, HbStats, load)
 
 __all__ = ["compress", "compress_batched", "Result", "operator", "gaussian_operator",
            "partition", "require_gpu", "params", "load",
            "HBACAError", "HB_K_GAUSS", "HB_K_LAPLACE", "HB_K_HELMHOLTZ3D",
-           "HB_K_LOWRANK_SPIKES", "HB_PREC_FP64", "HB_PREC_MIXED"]
+           "HB_K_LOWRANK_SPIKES", "HB_K_EFIE2D", "HB_K_POLYNOMIAL", "HB_PREC_FP64",
+           "HB_PREC_MIXED"]
 
 
 def partition(m: int, n: int, leaf: int, d: int, seed: int):

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhbaca.so")
 HB_OK, HB_EINVAL, HB_ENOMEM, HB_EDEVICE, HB_ERANKCAP, HB_ENONFINITE, HB_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
 HB_K_GAUSS, HB_K_LAPLACE, HB_K_HELMHOLTZ3D, HB_K_LOWRANK_SPIKES = 1, 2, 3, 4
+HB_K_EFIE2D, HB_K_POLYNOMIAL = 5, 6
 HB_PREC_FP64, HB_PREC_MIXED = 0, 1
 
 EXPORTED = (

@@ -1677,7 +1677,8 @@ static hb_status validate(const CallSpec& c) {
   if (c.d < 1 || c.leaf < 1) return HB_EINVAL;
   if (c.d > 32) return HB_EUNSUPPORTED;
   if (p->precision != HB_PREC_FP64 && p->precision != HB_PREC_MIXED) return HB_EINVAL;
-  if (p->precision == HB_PREC_MIXED && c.entry == HB_K_HELMHOLTZ3D) return HB_EUNSUPPORTED;
+  if (p->precision == HB_PREC_MIXED && (c.entry == HB_K_HELMHOLTZ3D || c.entry == HB_K_EFIE2D))
+    return HB_EUNSUPPORTED;
   if (p->stop_after < 0 || p->stop_after > 2 + 2 * 30 || p->rank_cap < 0) return HB_EINVAL;
   if (p->record_tape < 0 || p->record_tape > 2) return HB_EINVAL;
   if (p->diag_panel < 0 || p->diag_panel > 128 || p->diag_svd_storage < 0 ||
@@ -1694,11 +1695,17 @@ static hb_status validate(const CallSpec& c) {
       [[fallthrough]];
     case HB_K_LAPLACE:
     case HB_K_HELMHOLTZ3D:
-      if (c.entry == HB_K_HELMHOLTZ3D) {
+    case HB_K_EFIE2D:
+      if (c.entry == HB_K_HELMHOLTZ3D || c.entry == HB_K_EFIE2D) {
         if (!std::isfinite(p->wavenumber)) return HB_ENONFINITE;
         if (!(p->wavenumber > 0.0)) return HB_EINVAL;
       }
       if (p->dim < 1 || p->dim > HB_MAXDIM) return HB_EINVAL;
+      if (!c.X || !c.Y) return HB_EINVAL;
+      break;
+    case HB_K_POLYNOMIAL:
+      if (!std::isfinite(p->h)) return HB_ENONFINITE;
+      if (p->dim < 1 || p->dim > HB_POLY_MAXDIM) return HB_EINVAL;
       if (!c.X || !c.Y) return HB_EINVAL;
       break;
     case HB_K_LOWRANK_SPIKES:
@@ -1735,7 +1742,7 @@ static hb_status run(const CallSpec& c, hb_result** out) {
   } evg{ev};
   HB_HIP(hipEventRecord(ev[0], st));
 
-  const int scalar = c.entry == HB_K_HELMHOLTZ3D ? 1 : 0;
+  const int scalar = (c.entry == HB_K_HELMHOLTZ3D || c.entry == HB_K_EFIE2D) ? 1 : 0;
   R->scalar = scalar;
   R->entry = c.entry;
   const size_t sbytes = scalar_bytes(scalar);
@@ -1759,7 +1766,11 @@ static hb_status run(const CallSpec& c, hb_result** out) {
     E.spike_val = P.spike_val;
     E.nspk = P.n_spikes;
   } else {
-    E.dim = P.dim;
+    // the polynomial kernel reads its coordinates by global index (any dim);
+    // the others preload at most HB_MAXDIM of them per point
+    E.dim = c.entry == HB_K_POLYNOMIAL ? 0 : P.dim;
+    E.pdim = c.entry == HB_K_POLYNOMIAL ? P.dim : 0;
+    E.poly_h = P.h;
     double* Xs = R->keep.get<double>((size_t)c.nx * P.dim);
     double* Ys = R->keep.get<double>((size_t)c.ny * P.dim);
     hipLaunchKernelGGL(aos_to_soa_kernel, dim3((c.nx + 255) / 256), dim3(256), 0, st, c.X, Xs,

@@ -5,13 +5,16 @@
 // structure-of-arrays: coordinate c of row point i is X[c * ldx + i].
 #pragma once
 
+#include "hb_bessel.h"
 #include "hb_common.h"
 
 enum hb_kind_dev {
-  HBK_GAUSS = 1,         // exp(-|x - y|^2 / (c h^2))
-  HBK_LAPLACE = 2,       // 1 / |x - y|
-  HBK_HELMHOLTZ = 3,     // exp(i k |x - y|) / (4 pi |x - y|)  (complex)
-  HBK_LOWRANK_SPIKES = 4 // (G1 G2)(i, j) + spike(i, j)
+  HBK_GAUSS = 1,          // exp(-|x - y|^2 / (c h^2))
+  HBK_LAPLACE = 2,        // 1 / |x - y|
+  HBK_HELMHOLTZ = 3,      // exp(i k |x - y|) / (4 pi |x - y|)  (complex)
+  HBK_LOWRANK_SPIKES = 4, // (G1 G2)(i, j) + spike(i, j)
+  HBK_EFIE2D = 5,         // H_0^(2)(k |x - y|) = J_0 - i Y_0  (complex)
+  HBK_POLYNOMIAL = 6      // (x^T y + h)^2
 };
 
 #define HB_MAXDIM 8
@@ -32,6 +35,10 @@ struct EntryDev {
   const int64_t* spike_lin;  // sorted i * n + j
   const double* spike_val;
   int nspk;
+  // polynomial kernel: the coordinates are read from X, Y by global index
+  // (pdim of them; dim is 0 so nothing is preloaded into registers)
+  int pdim;
+  double poly_h;
 };
 
 __device__ inline double kernel_r2(const double* x, const double* y, int dim) {
@@ -57,6 +64,13 @@ __device__ inline double spike_lookup(const EntryDev& P, int64_t i, int64_t j) {
   return P.spike_lin[lo] == key ? P.spike_val[lo] : 0.0;
 }
 
+// (x_i^T y_j + h) for the polynomial kernel, SoA coordinates by global index
+__device__ inline double poly_base(const EntryDev& P, int64_t i, int64_t j) {
+  double s = P.poly_h;
+  for (int c = 0; c < P.pdim; ++c) s = fma(P.X[(int64_t)c * P.ldx + i], P.Y[(int64_t)c * P.ldy + j], s);
+  return s;
+}
+
 // Entry for global row i / column j with their coordinates already loaded.
 template <typename T>
 __device__ inline T eval_entry(const EntryDev& P, int64_t i, int64_t j, const double* x,
@@ -69,6 +83,9 @@ __device__ inline double eval_entry<double>(const EntryDev& P, int64_t i, int64_
     return exp(kernel_r2(x, y, P.dim) * P.neg_inv_ch2);
   } else if (P.kind == HBK_LAPLACE) {
     return 1.0 / sqrt(kernel_r2(x, y, P.dim));
+  } else if (P.kind == HBK_POLYNOMIAL) {
+    const double b = poly_base(P, i, j);
+    return b * b;
   } else {  // HBK_LOWRANK_SPIKES
     double s = 0.0;
     const double* g1 = P.G1 + i * P.r0;
@@ -87,6 +104,9 @@ __device__ inline float eval_entry<float>(const EntryDev& P, int64_t i, int64_t 
     return expf((float)(kernel_r2(x, y, P.dim) * P.neg_inv_ch2));
   } else if (P.kind == HBK_LAPLACE) {
     return 1.0f / sqrtf((float)kernel_r2(x, y, P.dim));
+  } else if (P.kind == HBK_POLYNOMIAL) {
+    const float b = (float)poly_base(P, i, j);
+    return b * b;
   } else {
     double s = 0.0;
     const double* g1 = P.G1 + i * P.r0;
@@ -99,8 +119,14 @@ __device__ inline float eval_entry<float>(const EntryDev& P, int64_t i, int64_t 
 template <>
 __device__ inline hb_cplx eval_entry<hb_cplx>(const EntryDev& P, int64_t /*i*/, int64_t /*j*/,
                                               const double* x, const double* y) {
-  // Helmholtz free-space Green's function
   double r = sqrt(kernel_r2(x, y, P.dim));
+  if (P.kind == HBK_EFIE2D) {
+    // Hankel function of the second kind, order 0: J_0 - i Y_0
+    double jv, yv;
+    hb_bessel_j0y0(P.wavenumber * r, &jv, &yv);
+    return hb_cplx{jv, -yv};
+  }
+  // Helmholtz free-space Green's function
   double s, c;
   sincos(P.wavenumber * r, &s, &c);
   double a = 1.0 / (4.0 * M_PI * r);

@@ -226,6 +226,47 @@ def test_entries_closed_values():
     assert np.array_equal(D, ref)
 
 
+def test_efie2d_entries_against_hankel_closed_forms():
+    """EFIE2D entries H_0^(2)(k r) = J_0(k r) - i Y_0(k r) (Section "Numerical
+    Results", kernel 2), pinned without re-calling the library routine: the
+    first zeros of J_0 and Y_0 (2.404825557695773 and 0.8935769662791675,
+    Abramowitz and Stegun, Table 9.5) make the real and imaginary parts
+    vanish; for small arguments J_0 -> 1 and Y_0 ~ (2/pi)(ln(x/2) + gamma);
+    for large arguments H_0^(2)(x) ~ sqrt(2/(pi x)) exp(-i(x - pi/4)) (the
+    sign of the exponent tells the second kind from the first)."""
+    def entry(x, k=1.0):
+        X = np.array([[0.0, 0.0]])
+        Y = np.array([[x, 0.0]])
+        return EntrySource(dict(entry=5, X=X, Y=Y, wavenumber=k)).block([0], [0])[0, 0]
+
+    assert abs(entry(2.404825557695773).real) < 1e-15
+    assert abs(entry(0.8935769662791675).imag) < 1e-15
+    # the zero of J_0 through k and r: k = 2, r = x / 2
+    assert abs(entry(2.404825557695773 / 2, k=2.0).real) < 1e-15
+    x = 1e-6
+    h = entry(x)
+    assert abs(h.real - 1.0) < 1e-12
+    assert abs(-h.imag - (2 / np.pi) * (np.log(x / 2) + np.euler_gamma)) < 1e-10
+    x = 4000.0
+    asym = np.sqrt(2 / (np.pi * x)) * np.exp(-1j * (x - np.pi / 4))
+    assert abs(entry(x) - asym) < 1e-4 * abs(asym)
+
+
+def test_polynomial_entries_and_rank():
+    """(x^T y + h)^2 (Section "Numerical Results", kernel 5): a closed value,
+    and the rank of the matrix is at most D (D + 3) / 2 + 1, the dimension
+    of the quadratic polynomials in D variables."""
+    X = np.array([[1.0, 2.0]])
+    Y = np.array([[3.0, -1.0]])
+    v = EntrySource(dict(entry=6, X=X, Y=Y, h=0.5)).block([0], [0])[0, 0]
+    assert v == (3.0 - 2.0 + 0.5) ** 2
+    rng = np.random.default_rng(4)
+    for D in (2, 5):
+        wl = dict(entry=6, X=rng.random((60, D)), Y=rng.random((70, D)), h=0.2)
+        s = np.linalg.svd(EntrySource(wl).dense(), compute_uv=False)
+        assert np.sum(s > 1e-12 * s[0]) == D * (D + 3) // 2 + 1
+
+
 def test_cluster_tree_and_levels():
     assert oracle.tree_levels(2000, 2000, 250) == 3
     assert oracle.tree_levels(20000, 20000, 625) == 5

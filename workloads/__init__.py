@@ -13,5 +13,7 @@ from .generators import (  # noqa: F401
     make_lowrank_spikes,
     make_laplace_blocks,
     make_gauss_mixture,
+    make_efie2d_strips,
+    make_polynomial,
     CONFIG_NAMES,
 )

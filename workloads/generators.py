@@ -23,9 +23,11 @@ ENTRY_GAUSS = 1
 ENTRY_LAPLACE = 2
 ENTRY_HELMHOLTZ = 3
 ENTRY_LOWRANK_SPIKES = 4
+ENTRY_EFIE2D = 5
+ENTRY_POLYNOMIAL = 6
 
 CONFIG_NAMES = ("gauss3d", "helmholtz", "coherent", "laplace_batched",
-                "gauss_mixture", "gauss3d_adjoint")
+                "gauss_mixture", "gauss3d_adjoint", "efie2d", "polynomial")
 
 
 def kd_order(points: np.ndarray, min_size: int = 16) -> np.ndarray:
@@ -180,10 +182,48 @@ def make_gauss_mixture(n: int = 100000, dim: int = 8, ncent: int = 10,
                 leaf=leaf, seed=1000 * cfg + 2, complex=False)
 
 
+def make_efie2d_strips(n: int = 4000, m: int | None = None, ppw: float = 15.0,
+                       tol: float = 1e-4, d: int = 8, leaf: int = 250, cfg: int = 6) -> dict:
+    """EFIE2D kernel H_0^(2)(k r) between two parallel strips of length 1 at
+    distance 1 in the plane (y = 0 and y = 1), each carrying nodes drawn
+    uniformly along it and sorted (which is their KD order); k gives ``ppw``
+    points per wavelength on average on the longer strip, 2 pi max(m, n) /
+    ppw.  Random rather than evenly spaced nodes: the mirror symmetry of
+    evenly spaced strips makes pairs of residual rows of exactly equal norm,
+    ties that rounding would decide."""
+    m = n if m is None else m
+    k = 2.0 * math.pi * max(m, n) / ppw
+    X = np.zeros((m, 2))
+    Y = np.ones((n, 2))
+    X[:, 0] = np.sort(np.random.default_rng(1000 * cfg + 0).random(m))
+    Y[:, 0] = np.sort(np.random.default_rng(1000 * cfg + 1).random(n))
+    return dict(name="efie2d", entry=ENTRY_EFIE2D, X=X, Y=Y, m=m, n=n, h=0.0, gauss_c=0.0,
+                wavenumber=k, tol=tol, d=d, leaf=leaf, seed=1000 * cfg + 2, complex=True)
+
+
+def make_polynomial(n: int = 4000, dim: int = 16, h: float = 0.2, tol: float = 1e-4,
+                    d: int = 8, leaf: int = 500, cfg: int = 7) -> dict:
+    """Polynomial kernel (x^T y + h)^2 on 2n points uniform in [0, 1]^dim,
+    split at the median of the widest coordinate: the lower half gives the
+    rows, the upper half the columns (the off-diagonal block of the
+    KD-permuted 2n x 2n matrix); each half is KD-ordered.  The matrix has
+    rank at most dim (dim + 3) / 2 + 1 at every size: the constant-rank
+    regime of the paper's cost analysis."""
+    P = np.random.default_rng(1000 * cfg + 3).random((2 * n, dim))
+    ax = int(np.argmax(P.max(axis=0) - P.min(axis=0)))
+    order = np.argsort(P[:, ax], kind="stable")
+    X = P[order[:n]]
+    Y = P[order[n:]]
+    return dict(name="polynomial", entry=ENTRY_POLYNOMIAL, X=_kd(X), Y=_kd(Y), m=n, n=n, h=h,
+                gauss_c=0.0, wavenumber=0.0, tol=tol, d=d, leaf=leaf, seed=1000 * cfg + 2,
+                complex=False)
+
+
 def make_config(name: str, scale: float = 1.0) -> dict:
     """Workload by name at full size (scale=1) or shrunk in n (scale<1, at
     least a few leaves) for parity runs.  Names: gauss3d, helmholtz,
-    coherent, laplace_batched, gauss_mixture, gauss3d_adjoint."""
+    coherent, laplace_batched, gauss_mixture, gauss3d_adjoint, efie2d,
+    polynomial."""
     def sz(full, minimum):
         return max(minimum, int(round(full * scale)))
     if name == "gauss3d":
@@ -200,4 +240,8 @@ def make_config(name: str, scale: float = 1.0) -> dict:
         return make_gauss_mixture(n=sz(100000, 256), cfg=4)
     if name == "gauss3d_adjoint":
         return make_gauss3d(n=sz(50000, 64), h=0.7, leaf=1563, cfg=5)
+    if name == "efie2d":
+        return make_efie2d_strips(n=sz(4000, 64), cfg=6)
+    if name == "polynomial":
+        return make_polynomial(n=sz(8000, 64), cfg=7)
     raise KeyError(name)
