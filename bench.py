@@ -16,14 +16,16 @@ streamed once per iteration plus the residual blocks C_k and R_k written),
 or the small SVDs / the TSQR kernels against the FP64 vector peak.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload helmholtz]
-                  [--no-cpu-baseline] [--no-comparisons] [--no-adjoint]
+                  [--no-cpu-baseline] [--no-comparisons] [--no-adjoint] [--no-hodlr]
 
 Besides the headline workload, the line carries "comparisons": mixed
 precision against plain FP64 (the 8-D Gaussian mixture at 2000^2 and the
 Gaussian R^3 2000^2 workload) and one batched call against one call per
 block (the 4096 Laplace blocks of the batched workload), and "adjoint": the
 frozen-pivot adjoint on the differentiation workload (Gaussian 50000^2 in
-R^3, h = 0.7).  Each runs in a child process of its own with a time limit,
+R^3, h = 0.7), and "hodlr": a hierarchical matrix of a Gaussian kernel
+built with the batched path and its matrix-vector product.  Each runs in a
+child process of its own with a time limit,
 after the headline measurement, so that neither can change it.
 """
 import argparse
@@ -314,6 +316,61 @@ def adjoint(steps=3, warmup=1):
     print(json.dumps(out), flush=True)
 
 
+def hodlr(steps=5, warmup=1):
+    """A hierarchical (HODLR) matrix of the Gaussian kernel of 32768 points on
+    a space curve built with the batched H-BACA path (every off-diagonal block
+    of the cluster tree in one call), and its matrix-vector product; the
+    product is checked against the dense kernel on every 64th row.  Prints
+    one JSON object."""
+    import numpy as np
+    import torch
+
+    import paper_1901_06101_amd as hb
+    from workloads import generators as G
+
+    hb.require_gpu()
+    wl = G.make_hodlr_curve(N=32768)
+    N = wl["X"].shape[0]
+    X = torch.tensor(wl["X"], device="cuda")
+    p = hb.params(dim=3, h=wl["h"], gauss_c=wl["gauss_c"], seed=wl["seed"])
+
+    def build():
+        return hb.hodlr_build(wl["entry"], p, X, wl["nmin"], wl["tol"], wl["d"], wl["leaf"])
+
+    for _ in range(warmup):
+        build().close()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    H = None
+    for _ in range(steps):
+        if H is not None:
+            H.close()
+        H = build()
+    torch.cuda.synchronize()
+    b_ms = (time.perf_counter() - t) * 1e3 / steps
+    x = torch.tensor(np.random.default_rng(5).standard_normal(N), device="cuda")
+    H.matvec(x)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(20):
+        y = H.matvec(x)
+    torch.cuda.synchronize()
+    m_ms = (time.perf_counter() - t) * 1e3 / 20
+    rows = torch.arange(0, N, 64, device="cuda")
+    d2 = ((X[rows][:, None, :] - X[None, :, :]) ** 2).sum(-1)
+    yd = torch.exp(-d2 / (wl["gauss_c"] * wl["h"] ** 2)) @ x
+    err = float(torch.linalg.norm(y[rows] - yd) / torch.linalg.norm(yd))
+    ranks = [H.blocks.rank(b) for b in range(H.nblocks)]
+    out = dict(workload=f"hodlr_curve N={N} Gaussian h={wl['h']} nmin={wl['nmin']} "
+                        f"tol={wl['tol']} d={wl['d']} leaf={wl['leaf']}",
+               build_ms=b_ms, matvec_ms=m_ms, blocks=H.nblocks, leaves=H.nleaves,
+               max_block_rank=max(ranks), matvec_rel_err_rows64=err,
+               within_10tol=bool(err <= 10 * wl["tol"]))
+    _note(f"hodlr: build {b_ms:.1f} ms, matvec {m_ms:.3f} ms")
+    H.close()
+    print(json.dumps(out), flush=True)
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
     """Device-to-device copy rate in GB/s (bytes read plus bytes written),
     the measured counterpart of the HBM peak."""
@@ -521,14 +578,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparisons", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-hodlr", action="store_true")
     ap.add_argument("--comparisons", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--adjoint", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--hodlr", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.comparisons:
         comparisons()
         return
     if args.adjoint:
         adjoint()
+        return
+    if args.hodlr:
+        hodlr()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); how H-BACA would "
@@ -574,6 +636,8 @@ def main():
         out["comparisons"] = run_child("--comparisons")
     if not args.no_adjoint:
         out["adjoint"] = run_child("--adjoint")
+    if not args.no_hodlr:
+        out["hodlr"] = run_child("--hodlr")
     print(json.dumps(_finite(out)), flush=True)
 
 

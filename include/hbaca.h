@@ -314,6 +314,43 @@ hb_status hbaca_recompute_frozen(const hb_result* tape, const hb_params* params,
 hb_status hb_partition(int64_t m, int64_t n, int32_t leaf, int32_t d, uint64_t seed,
                        int32_t* L_out, int64_t* leaves, int32_t* j1);
 
+/*
+ * Hierarchical (HODLR) matrix of the kernel matrix of one point set with
+ * itself, built with H-BACA: the construction of hierarchical matrices the
+ * paper names as the method's use (Introduction; Section "Numerical
+ * Results" compresses one off-diagonal block of a KD-permuted kernel matrix
+ * and notes that the permutation yields a hierarchical representation).
+ *   points  N x dim row-major DEVICE array, already in KD order
+ *   nmin    leaf size: the cluster tree of [0, N) splits a node of s points
+ *           into ceil(s/2) and floor(s/2) down to the smallest depth whose
+ *           nodes hold at most nmin points
+ *   tol, d, leaf  as for hbaca_compress, for every off-diagonal block
+ * Both off-diagonal blocks A(c1, c2) and A(c2, c1) of every internal node
+ * are compressed in one hbaca_compress_batched pass (block p, numbered level
+ * by level from the root, nodes left to right, A(c1, c2) first, draws its
+ * first column blocks from params->seed + p); the diagonal blocks of the
+ * leaves are evaluated densely.  Real kernels finite at r = 0 only: GAUSS
+ * and POLYNOMIAL (others return HB_EUNSUPPORTED).  Synchronises `stream`.
+ * The object is library-owned until hb_hodlr_free.
+ */
+typedef struct hb_hodlr hb_hodlr; /* opaque */
+hb_status hb_hodlr_build(int entry_fn_id, const hb_params* params, const double* points, int64_t N,
+                         int32_t nmin, double tol, int32_t d, int32_t leaf, void* stream,
+                         hb_hodlr** out);
+/* The H-BACA result of the off-diagonal blocks (owned by the HODLR object;
+   block p in the order above; NULL when N <= nmin). */
+const hb_result* hb_hodlr_blocks(const hb_hodlr* h);
+int64_t hb_hodlr_nblocks(const hb_hodlr* h);
+int64_t hb_hodlr_nleaves(const hb_hodlr* h);
+/* level, row offset, row count, column offset, column count of block p. */
+hb_status hb_hodlr_block_info(const hb_hodlr* h, int64_t block, int64_t* info5);
+/* y = A_H x for DEVICE vectors of N FP64 entries (must not overlap): the
+   dense leaves, then the low-rank blocks level by level (the blocks of one
+   level cover disjoint rows, so the sums have a fixed order).  Asynchronous
+   on `stream`. */
+hb_status hb_hodlr_matvec(const hb_hodlr* h, const double* x, double* y, void* stream);
+void hb_hodlr_free(hb_hodlr* h);
+
 /* Statistics of the call (host struct). */
 hb_status hb_result_stats(const hb_result* res, hb_stats* out);
 

@@ -19,6 +19,7 @@ from ._binding import (HB_K_EFIE2D, HB_K_GAUSS, HB_K_HELMHOLTZ3D,  # noqa: F401
                        HB_PREC_MIXED, HBACAError, HbParams, HbStats, load)
 
 __all__ = ["compress", "compress_batched", "Result", "operator", "gaussian_operator",
+           "hodlr_build", "Hodlr",
            "partition", "require_gpu", "params", "load",
            "HBACAError", "HB_K_GAUSS", "HB_K_LAPLACE", "HB_K_HELMHOLTZ3D",
            "HB_K_LOWRANK_SPIKES", "HB_K_EFIE2D", "HB_K_POLYNOMIAL", "HB_PREC_FP64",
@@ -97,16 +98,19 @@ def _hb_params(p: dict, keep: list) -> HbParams:
 
 
 class Result:
-    """Owns an hb_result handle; frees it on close() or garbage collection."""
+    """Owns an hb_result handle; frees it on close() or garbage collection
+    (a view of a result another object owns frees nothing)."""
 
-    def __init__(self, handle, keep):
+    def __init__(self, handle, keep, owned=True):
         self._h = handle
         self._keep = keep
+        self._owned = owned
         self._lib = load()
 
     def close(self):
         if self._h:
-            self._lib.hb_result_free(self._h)
+            if self._owned:
+                self._lib.hb_result_free(self._h)
             self._h = None
 
     def __del__(self):
@@ -359,6 +363,68 @@ def compress(entry: int, p: dict, X, Y, m: int, n: int, tol: float, d: int, leaf
                             float(tol), int(d), int(leaf), _stream(), C.byref(out))
     B._check(st, "hbaca_compress")
     return Result(out, keep)
+
+
+class Hodlr:
+    """Owns an hb_hodlr handle (a HODLR matrix built with H-BACA)."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep
+        self._lib = load()
+        hb = self._lib.hb_hodlr_blocks(self._h)
+        # the off-diagonal blocks' H-BACA result, owned by the HODLR object
+        self.blocks = Result(C.c_void_p(hb), [self], owned=False) if hb else None
+
+    def close(self):
+        if self._h:
+            self.blocks = None
+            self._lib.hb_hodlr_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nblocks(self):
+        return int(self._lib.hb_hodlr_nblocks(self._h))
+
+    @property
+    def nleaves(self):
+        return int(self._lib.hb_hodlr_nleaves(self._h))
+
+    def block_info(self, b):
+        """(level, row_off, row_cnt, col_off, col_cnt) of off-diagonal block b."""
+        buf = (C.c_int64 * 5)()
+        B._check(self._lib.hb_hodlr_block_info(self._h, b, buf), "hb_hodlr_block_info")
+        return tuple(int(v) for v in buf)
+
+    def matvec(self, x, out=None):
+        """A_H x for a float64 device vector of N entries."""
+        import torch
+        x = x.to(dtype=torch.float64).contiguous()
+        if out is None:
+            out = torch.empty_like(x)
+        B._check(self._lib.hb_hodlr_matvec(self._h, _ptr(x), _ptr(out), _stream()),
+                 "hb_hodlr_matvec")
+        return out
+
+
+def hodlr_build(entry: int, p: dict, X, nmin: int, tol: float, d: int, leaf: int) -> Hodlr:
+    """HODLR matrix of the kernel matrix of the KD-ordered points X (N x dim,
+    float64 device tensor) with themselves; every off-diagonal block by
+    H-BACA in one batched pass, dense diagonal leaves of at most nmin."""
+    lib = load()
+    keep = [X]
+    hp = _hb_params(p, keep)
+    out = C.c_void_p()
+    st = lib.hb_hodlr_build(int(entry), C.byref(hp), _ptr(X), int(X.shape[0]), int(nmin),
+                            float(tol), int(d), int(leaf), _stream(), C.byref(out))
+    B._check(st, "hb_hodlr_build")
+    return Hodlr(out, keep)
 
 
 def compress_batched(entry: int, p: dict, X, row_off, row_cnt, Y, col_off, col_cnt, tol: float,

@@ -26,6 +26,8 @@ EXPORTED = (
     "hb_result_error", "hb_result_free", "hb_status_string", "hbaca_apply",
     "hbaca_apply_noalloc", "hbaca_vjp", "hbaca_adjoint",
     "hbaca_recompute_frozen", "hb_partition", "hb_result_leaf_frozen", "hb_result_merge_ranks",
+    "hb_hodlr_build", "hb_hodlr_blocks", "hb_hodlr_nblocks", "hb_hodlr_nleaves",
+    "hb_hodlr_block_info", "hb_hodlr_matvec", "hb_hodlr_free",
 )
 
 
@@ -137,6 +139,21 @@ def load(path: str = LIB_PATH):
     lib.hbaca_apply.restype = C.c_int
     lib.hbaca_apply_noalloc.argtypes = [vp, i64, vp, vp, i32, vp]
     lib.hbaca_apply_noalloc.restype = C.c_int
+    lib.hb_hodlr_build.argtypes = [C.c_int, C.POINTER(HbParams), vp, i64, i32, dbl, i32, i32, vp,
+                                   C.POINTER(vp)]
+    lib.hb_hodlr_build.restype = C.c_int
+    lib.hb_hodlr_blocks.argtypes = [vp]
+    lib.hb_hodlr_blocks.restype = vp
+    lib.hb_hodlr_nblocks.argtypes = [vp]
+    lib.hb_hodlr_nblocks.restype = i64
+    lib.hb_hodlr_nleaves.argtypes = [vp]
+    lib.hb_hodlr_nleaves.restype = i64
+    lib.hb_hodlr_block_info.argtypes = [vp, i64, vp]
+    lib.hb_hodlr_block_info.restype = C.c_int
+    lib.hb_hodlr_matvec.argtypes = [vp, vp, vp, vp]
+    lib.hb_hodlr_matvec.restype = C.c_int
+    lib.hb_hodlr_free.argtypes = [vp]
+    lib.hb_hodlr_free.restype = None
     lib.hbaca_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hbaca_vjp.restype = C.c_int
     lib.hbaca_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]

@@ -422,6 +422,27 @@ struct hb_result {
   double fz_h = 0.0, fz_c = 0.0;
 };
 
+struct hb_hodlr {
+  int64_t N = 0;
+  int levels = 0;                        // depth of the cluster tree
+  hb_result* blocks = nullptr;           // H-BACA of every off-diagonal block
+  std::vector<int> level;                // per block
+  std::vector<int64_t> roff, rcnt, coff, ccnt;
+  std::vector<std::vector<int>> by_level;  // block indices of each level
+  int64_t nleaves = 0;
+  void* leaves_dev = nullptr;            // HodlrLeafDev per leaf
+  std::vector<int64_t> leaf_off, leaf_size;
+  double* dense = nullptr;               // dense diagonal blocks
+  int64_t dense_elems = 0;
+  std::vector<void*> jobs_dev;           // HodlrJob arrays per level
+  std::vector<int> level_rmax;
+  std::vector<int64_t> level_rowmax;
+  int64_t t_elems = 0;                   // products per matvec
+  int64_t leaf_max = 0;
+  DevMem keep;                           // device memory of this object
+  ~hb_hodlr();
+};
+
 namespace {
 
 static size_t scalar_bytes(int scalar) { return scalar == 1 ? 16 : 8; }
@@ -2253,6 +2274,96 @@ static hb_status guarded(const CallSpec& c, hb_result** out) {
 
 }  // namespace
 
+// ------------------------------------------------------------ HODLR matrix ---
+// A hierarchical (HODLR) matrix of the kernel matrix of one KD-ordered point
+// set with itself: the cluster tree of [0, N) splits a node into ceil(s/2)
+// and floor(s/2) down to the depth whose nodes hold at most nmin points;
+// both off-diagonal blocks A(c1, c2), A(c2, c1) of every internal node are
+// compressed by H-BACA in one batched call, the leaves' diagonal blocks are
+// kept dense (the construction of hierarchical matrices the paper names as
+// the method's use; Introduction and Section "Numerical Results").
+struct HodlrJob {
+  const double* U;   // rows x r
+  const double* Vh;  // cols x r
+  const double* S;   // r
+  int64_t row0, rows, col0, cols;
+  int r;
+  int pad;
+  int64_t t_off;     // offset of this block's r products in t
+};
+
+// t[t_off + j] = S_j sum_i Vh(i, j) x[col0 + i]: one workgroup per (column
+// j, block), a fixed-order tree sum.
+__global__ __launch_bounds__(AP_NT) void hodlr_reduce_kernel(const HodlrJob* __restrict__ jobs,
+                                                             const double* __restrict__ x,
+                                                             double* __restrict__ t) {
+  const HodlrJob J = jobs[blockIdx.y];
+  const int j = blockIdx.x;
+  if (j >= J.r) return;
+  const double* v = J.Vh + (int64_t)j * J.cols;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < J.cols; i += AP_NT) acc = fma(v[i], x[J.col0 + i], acc);
+  acc = group_sum<64>(acc);
+  __shared__ double part[AP_NT / 64];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = part[0];
+    for (int w = 1; w < AP_NT / 64; ++w) sum += part[w];
+    t[J.t_off + j] = sum * J.S[j];
+  }
+}
+
+// y[row0 + i] += sum_j U(i, j) t[t_off + j]: one thread per row; the blocks
+// of one launch have disjoint rows (one tree level), so no atomics.
+__global__ __launch_bounds__(AP_NT) void hodlr_expand_kernel(const HodlrJob* __restrict__ jobs,
+                                                             const double* __restrict__ t,
+                                                             double* __restrict__ y) {
+  const HodlrJob J = jobs[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * AP_NT + threadIdx.x;
+  if (i >= J.rows) return;
+  double acc = 0.0;
+  for (int j = 0; j < J.r; ++j) acc = fma(J.U[(int64_t)j * J.rows + i], t[J.t_off + j], acc);
+  y[J.row0 + i] += acc;
+}
+
+struct HodlrLeafDev {
+  int64_t off, size, d_off;  // rows/columns [off, off + size); dense block at D + d_off
+};
+
+// D_l(i, j) = A(off + i, off + j), column-major: one thread per entry.
+__global__ void hodlr_dense_kernel(EntryDev E, const HodlrLeafDev* __restrict__ leaves,
+                                   double* __restrict__ D) {
+  const HodlrLeafDev L = leaves[blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= L.size * L.size) return;
+  const int64_t i = e % L.size, j = e / L.size;
+  double xi[HB_MAXDIM], yj[HB_MAXDIM];
+  for (int q = 0; q < HB_MAXDIM; ++q) {
+    xi[q] = q < E.dim ? E.X[(int64_t)q * E.ldx + L.off + i] : 0.0;
+    yj[q] = q < E.dim ? E.Y[(int64_t)q * E.ldy + L.off + j] : 0.0;
+  }
+  D[L.d_off + e] = eval_entry<double>(E, L.off + i, L.off + j, xi, yj);
+}
+
+// y[off + i] = sum_j D_l(i, j) x[off + j]: one thread per row of a leaf.
+__global__ __launch_bounds__(AP_NT) void hodlr_diag_kernel(const HodlrLeafDev* __restrict__ leaves,
+                                                           const double* __restrict__ D,
+                                                           const double* __restrict__ x,
+                                                           double* __restrict__ y) {
+  const HodlrLeafDev L = leaves[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * AP_NT + threadIdx.x;
+  if (i >= L.size) return;
+  const double* Dl = D + L.d_off;
+  double acc = 0.0;
+  for (int64_t j = 0; j < L.size; ++j) acc = fma(Dl[j * L.size + i], x[L.off + j], acc);
+  y[L.off + i] = acc;
+}
+
+hb_hodlr::~hb_hodlr() {
+  if (blocks) hb_result_free(blocks);
+}
+
 // ============================================================== C ABI =======
 namespace {
 
@@ -2831,6 +2942,181 @@ void hb_result_free(hb_result* r) {
   if (!r) return;
   (void)hipDeviceSynchronize();
   delete r;
+}
+
+hb_status hb_hodlr_build(int entry_fn_id, const hb_params* params, const double* points, int64_t N,
+                         int32_t nmin, double tol, int32_t d, int32_t leaf, void* stream,
+                         hb_hodlr** out) {
+  if (out) *out = nullptr;
+  if (!out || !params || !points || N < 1 || nmin < 1) return HB_EINVAL;
+  if (entry_fn_id != HB_K_GAUSS && entry_fn_id != HB_K_POLYNOMIAL) return HB_EUNSUPPORTED;
+  const hb_params& P = *params;
+  if (P.dim < 1 || P.dim > (entry_fn_id == HB_K_POLYNOMIAL ? HB_POLY_MAXDIM : HB_MAXDIM))
+    return HB_EINVAL;
+  if (!std::isfinite(P.h)) return HB_ENONFINITE;
+  if (entry_fn_id == HB_K_GAUSS && (!(P.h > 0.0) || !(P.gauss_c > 0.0))) return HB_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    std::unique_ptr<hb_hodlr> H(new hb_hodlr());
+    H->N = N;
+    H->keep.st = st;
+    H->keep.sync_free = true;
+    int Lh = 0;
+    while ((N + ((int64_t)1 << Lh) - 1) / ((int64_t)1 << Lh) > nmin) ++Lh;
+    H->levels = Lh;
+    const auto tree = cluster_tree(N, Lh);
+    H->by_level.assign(Lh, {});
+    for (int lev = 0; lev < Lh; ++lev)
+      for (size_t i = 0; i < tree[lev].size(); ++i) {
+        const Node c1 = tree[lev + 1][2 * i], c2 = tree[lev + 1][2 * i + 1];
+        for (int side = 0; side < 2; ++side) {
+          const Node a = side ? c2 : c1, b = side ? c1 : c2;
+          H->by_level[lev].push_back((int)H->level.size());
+          H->level.push_back(lev);
+          H->roff.push_back(a.off);
+          H->rcnt.push_back(a.size);
+          H->coff.push_back(b.off);
+          H->ccnt.push_back(b.size);
+        }
+      }
+    const size_t nb = H->level.size();
+    if (nb > 0) {
+      CallSpec c;
+      c.entry = entry_fn_id;
+      c.prm = params;
+      c.X = points;
+      c.Y = points;
+      c.nx = N;
+      c.ny = N;
+      c.roff = H->roff;
+      c.rcnt = H->rcnt;
+      c.coff = H->coff;
+      c.ccnt = H->ccnt;
+      c.tol = tol;
+      c.d = d;
+      c.leaf = leaf;
+      c.st = st;
+      c.batched = true;
+      const hb_status bs = guarded(c, &H->blocks);
+      if (bs != HB_OK) return bs;
+    }
+    // points as one array per coordinate for the dense leaves
+    EntryDev E{};
+    E.kind = entry_fn_id;
+    E.dim = entry_fn_id == HB_K_POLYNOMIAL ? 0 : P.dim;
+    E.pdim = entry_fn_id == HB_K_POLYNOMIAL ? P.dim : 0;
+    E.poly_h = P.h;
+    E.neg_inv_ch2 = entry_fn_id == HB_K_GAUSS ? -1.0 / (P.gauss_c * P.h * P.h) : 0.0;
+    double* Xs = H->keep.get<double>((size_t)N * P.dim);
+    hipLaunchKernelGGL(aos_to_soa_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+                       points, Xs, N, P.dim);
+    HB_HIP(hipGetLastError());
+    E.X = Xs;
+    E.Y = Xs;
+    E.ldx = N;
+    E.ldy = N;
+    // dense diagonal leaves
+    std::vector<HodlrLeafDev> lv;
+    for (const Node& nd : tree[Lh]) {
+      lv.push_back(HodlrLeafDev{nd.off, nd.size, H->dense_elems});
+      H->dense_elems += nd.size * nd.size;
+      H->leaf_off.push_back(nd.off);
+      H->leaf_size.push_back(nd.size);
+      H->leaf_max = std::max(H->leaf_max, nd.size);
+    }
+    H->nleaves = (int64_t)lv.size();
+    H->dense = H->keep.get<double>((size_t)std::max<int64_t>(H->dense_elems, 1));
+    HodlrLeafDev* dl = upload(H->keep, lv, st);
+    H->leaves_dev = dl;
+    if (H->nleaves > 65535) throw HbError{HB_EUNSUPPORTED};
+    hipLaunchKernelGGL(hodlr_dense_kernel,
+                       dim3((unsigned)((H->leaf_max * H->leaf_max + 255) / 256), (unsigned)H->nleaves),
+                       dim3(256), 0, st, E, dl, H->dense);
+    HB_HIP(hipGetLastError());
+    // the low-rank blocks of each level as apply jobs
+    H->jobs_dev.assign(Lh, nullptr);
+    H->level_rmax.assign(Lh, 0);
+    H->level_rowmax.assign(Lh, 0);
+    for (int lev = 0; lev < Lh; ++lev) {
+      std::vector<HodlrJob> jobs;
+      for (int b : H->by_level[lev]) {
+        const Block& B = H->blocks->out_blocks[b];
+        HodlrJob J{};
+        J.U = (const double*)B.U;
+        J.Vh = (const double*)B.Vh;
+        J.S = B.S;
+        J.row0 = H->roff[b];
+        J.rows = H->rcnt[b];
+        J.col0 = H->coff[b];
+        J.cols = H->ccnt[b];
+        J.r = B.r;
+        J.t_off = H->t_elems;
+        H->t_elems += B.r;
+        H->level_rmax[lev] = std::max(H->level_rmax[lev], B.r);
+        H->level_rowmax[lev] = std::max<int64_t>(H->level_rowmax[lev], J.rows);
+        jobs.push_back(J);
+      }
+      if (jobs.size() > 65535) throw HbError{HB_EUNSUPPORTED};
+      H->jobs_dev[lev] = upload(H->keep, jobs, st);
+    }
+    HB_HIP(hipStreamSynchronize(st));
+    *out = H.release();
+    return HB_OK;
+  } catch (const HbError& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    return HB_ENOMEM;
+  } catch (...) {
+    return HB_EDEVICE;
+  }
+}
+
+const hb_result* hb_hodlr_blocks(const hb_hodlr* h) { return h ? h->blocks : nullptr; }
+
+int64_t hb_hodlr_nblocks(const hb_hodlr* h) { return h ? (int64_t)h->level.size() : -1; }
+
+int64_t hb_hodlr_nleaves(const hb_hodlr* h) { return h ? h->nleaves : -1; }
+
+hb_status hb_hodlr_block_info(const hb_hodlr* h, int64_t b, int64_t* info5) {
+  if (!h || !info5 || b < 0 || b >= (int64_t)h->level.size()) return HB_EINVAL;
+  info5[0] = h->level[b];
+  info5[1] = h->roff[b];
+  info5[2] = h->rcnt[b];
+  info5[3] = h->coff[b];
+  info5[4] = h->ccnt[b];
+  return HB_OK;
+}
+
+hb_status hb_hodlr_matvec(const hb_hodlr* h, const double* x, double* y, void* stream) {
+  if (!h || !x || !y) return HB_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  double* t = nullptr;
+  if (h->t_elems > 0) {
+    t = (double*)BlockCache::get().alloc((size_t)h->t_elems * 8, st);
+    if (!t) return HB_ENOMEM;
+  }
+  hipLaunchKernelGGL(hodlr_diag_kernel,
+                     dim3((unsigned)((h->leaf_max + AP_NT - 1) / AP_NT), (unsigned)h->nleaves),
+                     dim3(AP_NT), 0, st, (const HodlrLeafDev*)h->leaves_dev, h->dense, x, y);
+  for (int lev = 0; lev < h->levels; ++lev) {
+    const unsigned nj = (unsigned)h->by_level[lev].size();
+    if (nj == 0 || h->level_rmax[lev] == 0) continue;
+    const HodlrJob* J = (const HodlrJob*)h->jobs_dev[lev];
+    hipLaunchKernelGGL(hodlr_reduce_kernel, dim3((unsigned)h->level_rmax[lev], nj), dim3(AP_NT), 0,
+                       st, J, x, t);
+    hipLaunchKernelGGL(hodlr_expand_kernel,
+                       dim3((unsigned)((h->level_rowmax[lev] + AP_NT - 1) / AP_NT), nj),
+                       dim3(AP_NT), 0, st, J, t, y);
+  }
+  const hipError_t e = hipGetLastError();
+  if (t) BlockCache::get().release(t, st, false);
+  return e == hipSuccess ? HB_OK : HB_EDEVICE;
+}
+
+void hb_hodlr_free(hb_hodlr* h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  delete h;
 }
 
 const char* hb_status_string(hb_status s) {

@@ -219,7 +219,7 @@ def test_json_line_contract_with_a_stand_in_library(monkeypatch, capsys):
     monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
     monkeypatch.setattr(bench, "copy_bandwidth", lambda torch: 5000.0)
     monkeypatch.setattr(sys, "argv", ["bench.py", "--steps", "2", "--warmup", "1",
-                                      "--no-comparisons", "--no-adjoint"])
+                                      "--no-comparisons", "--no-adjoint", "--no-hodlr"])
     bench.main()
     lines = [s for s in capsys.readouterr().out.splitlines() if s.strip()]
     assert len(lines) == 1
@@ -246,7 +246,7 @@ def test_json_line_contract_with_a_stand_in_library(monkeypatch, capsys):
         [k["launch_ms"] for k in out["kernel_classes"]], reverse=True)
     cb = out["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1
-    assert "comparisons" not in out and "adjoint" not in out
+    assert "comparisons" not in out and "adjoint" not in out and "hodlr" not in out
 
 
 def test_a_failing_leg_becomes_an_error_object(monkeypatch):
@@ -286,7 +286,7 @@ def test_a_failing_headline_still_prints_the_line(monkeypatch, capsys):
                                  params=lambda **kw: kw, compress=broken)
     monkeypatch.setitem(sys.modules, "paper_1901_06101_amd", fake)
     monkeypatch.setattr(workloads, "make_config", lambda name, scale=1.0: wl)
-    monkeypatch.setattr(sys, "argv", ["bench.py", "--no-comparisons", "--no-adjoint",
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--no-comparisons", "--no-adjoint", "--no-hodlr",
                                       "--no-cpu-baseline"])
     bench.main()
     lines = [s for s in capsys.readouterr().out.splitlines() if s.strip()]
@@ -294,3 +294,50 @@ def test_a_failing_headline_still_prints_the_line(monkeypatch, capsys):
     out = json.loads(lines[0])
     assert out["value"] is None and "device lost" in out["error"]
     assert out["metric"] == bench.METRIC and out["n_gpus"] == 1
+
+
+def test_hodlr_leg_runs_against_a_stand_in_library(monkeypatch, capsys):
+    """The HODLR leg's own code (build and matvec timing, the sampled check
+    against the dense kernel) on the CPU against a stand-in library whose
+    matvec is the dense product."""
+    import json
+    import types
+
+    import torch
+
+    sys.path.insert(0, ROOT)
+    import bench
+    from workloads import generators as G
+
+    small = G.make_hodlr_curve(N=300)
+
+    class StandIn:
+        def __init__(self, X, wl):
+            d2 = ((X[:, None, :] - X[None, :, :]) ** 2).sum(-1)
+            self.A = torch.exp(-d2 / (wl["gauss_c"] * wl["h"] ** 2))
+            self.nblocks, self.nleaves = 2, 2
+            self.blocks = types.SimpleNamespace(rank=lambda b: 7)
+
+        def matvec(self, x):
+            return self.A @ x
+
+        def close(self):
+            pass
+
+    fake = types.SimpleNamespace(
+        require_gpu=lambda: None, params=lambda **kw: kw,
+        hodlr_build=lambda entry, p, X, nmin, tol, d, leaf: StandIn(X, small))
+    monkeypatch.setitem(sys.modules, "paper_1901_06101_amd", fake)
+    monkeypatch.setattr(G, "make_hodlr_curve", lambda N: small)
+    orig_tensor = torch.tensor
+    monkeypatch.setattr(torch, "tensor", lambda *a, **k: orig_tensor(
+        *a, **{key: v for key, v in k.items() if key != "device"}))
+    orig_arange = torch.arange
+    monkeypatch.setattr(torch, "arange", lambda *a, **k: orig_arange(
+        *a, **{key: v for key, v in k.items() if key != "device"}))
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    bench.hodlr(steps=1, warmup=1)
+    line = [s for s in capsys.readouterr().out.splitlines() if s.startswith("{")][-1]
+    out = json.loads(line)
+    assert out["max_block_rank"] == 7 and out["blocks"] == 2
+    assert out["matvec_rel_err_rows64"] < 1e-14 and out["within_10tol"] is True

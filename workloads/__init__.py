@@ -15,5 +15,7 @@ from .generators import (  # noqa: F401
     make_gauss_mixture,
     make_efie2d_strips,
     make_polynomial,
+    make_hodlr_curve,
+    make_hodlr_polynomial,
     CONFIG_NAMES,
 )

@@ -219,6 +219,28 @@ def make_polynomial(n: int = 4000, dim: int = 16, h: float = 0.2, tol: float = 1
                 complex=False)
 
 
+def make_hodlr_curve(N: int = 32768, h: float = 0.25, nmin: int = 256, tol: float = 1e-6,
+                     d: int = 8, leaf: int = 256, cfg: int = 8) -> dict:
+    """One point set for a hierarchical matrix of the Gaussian kernel
+    exp(-|x - y|^2 / h^2) with itself: N points on the closed space curve
+    (cos t, sin t, 0.1 sin 3t), t uniform on [0, 2 pi), in KD order."""
+    t = np.random.default_rng(1000 * cfg + 0).random(N) * 2.0 * math.pi
+    X = np.stack([np.cos(t), np.sin(t), 0.1 * np.sin(3.0 * t)], axis=1)
+    return dict(name="hodlr_curve", entry=ENTRY_GAUSS, X=_kd(X), N=N, h=h, gauss_c=1.0,
+                wavenumber=0.0, nmin=nmin, tol=tol, d=d, leaf=leaf, seed=1000 * cfg + 2,
+                complex=False)
+
+
+def make_hodlr_polynomial(N: int = 4000, dim: int = 8, h: float = 0.2, nmin: int = 256,
+                          tol: float = 1e-6, d: int = 16, leaf: int = 256, cfg: int = 9) -> dict:
+    """One point set for a hierarchical matrix of the polynomial kernel
+    (x^T y + h)^2 with itself: N points uniform in [0, 1]^dim, KD order."""
+    X = np.random.default_rng(1000 * cfg + 0).random((N, dim))
+    return dict(name="hodlr_polynomial", entry=ENTRY_POLYNOMIAL, X=_kd(X), N=N, h=h,
+                gauss_c=0.0, wavenumber=0.0, nmin=nmin, tol=tol, d=d, leaf=leaf,
+                seed=1000 * cfg + 2, complex=False)
+
+
 def make_config(name: str, scale: float = 1.0) -> dict:
     """Workload by name at full size (scale=1) or shrunk in n (scale<1, at
     least a few leaves) for parity runs.  Names: gauss3d, helmholtz,
