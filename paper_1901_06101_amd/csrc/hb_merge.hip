@@ -37,6 +37,7 @@ __global__ __launch_bounds__(KMAX* NQ) __attribute__((amdgpu_waves_per_eu(1, 2))
                                                               T* __restrict__ alpha,
                                                               double* __restrict__ beta) {
   static_assert(NQ * SEG == MC_ALL, "chunk height");
+  static_assert(SEG % TQ_CH == 0, "register segments are read in chunks of TQ_CH");
   constexpr int MC = MC_ALL;
   const QRNodeDev N = nodes[blockIdx.x];
   const int tid = threadIdx.x;
@@ -176,6 +177,7 @@ __global__ __launch_bounds__(KMAX* NQ) __attribute__((amdgpu_waves_per_eu(1, 2))
   // reflector st is read from HBM one step ahead of its use (one element
   // per thread, MC <= NTH), so the load latency overlaps the previous step
   static_assert(MC <= NTH, "one reflector element per thread");
+  static_assert(SEG % TQ_CH == 0 && NQ * SEG == MC_ALL, "register segments of TQ_CH");
   auto vload = [&](int st) -> T {
     return (st >= 0 && tid >= st && tid < rows) ? store[J.store + (int64_t)st * MC + tid]
                                                 : sc_zero<T>();
@@ -247,6 +249,7 @@ __global__ __launch_bounds__(KMAX* NQ) __attribute__((amdgpu_waves_per_eu(1, 2))
   }
   // reflector st is read from HBM one step ahead of its use
   static_assert(MC <= NTH, "one reflector element per thread");
+  static_assert(SEG % TQ_CH == 0 && NQ * SEG == MC_ALL, "register segments of TQ_CH");
   auto vload = [&](int st) -> T {
     return (st < steps && tid >= st && tid < rows) ? store[J.store + (int64_t)st * MC + tid]
                                                    : sc_zero<T>();
@@ -506,6 +509,98 @@ __device__ __forceinline__ int jacobi_rounds(T* A, int lda, int p, int k, int K,
   return sweep + 1;
 }
 
+// The same rounds with each pair's two columns held in registers for the
+// whole round: G lanes own elements gl, gl + G, ... (EPL per lane) of both
+// columns, load them once, form the dot product and both squared norms in
+// one pass, rotate in registers, and store back only when they rotated.
+// This halves the LDS traffic of a round (the columns are read once, not
+// once for the dot product and again for the update) and needs no norm
+// bookkeeping across rounds.  Used when a column fits in G * EPL elements;
+// a group takes the pairs grp, grp + SVD_NT / G, ... of a round in turn.
+template <typename T, int G, int EPL>
+__device__ __forceinline__ int jacobi_rounds_reg(T* A, int lda, int p, int k, int K, double tol,
+                                                 double negl, int* sRot) {
+  const int tid = threadIdx.x;
+  const int grp = tid / G, gl = tid % G;
+  constexpr int ngrp = SVD_NT / G;
+  const int npairs = K / 2;
+  const double tol2 = tol * tol;
+  int sweep = 0;
+  for (; sweep < 60; ++sweep) {
+    if (tid == 0) *sRot = 0;
+    __syncthreads();
+    for (int t = 0; t < K - 1; ++t) {
+      for (int pi = grp; pi < npairs; pi += ngrp) {
+        int a, b;
+        if (pi == 0) {
+          a = 0;
+          b = 1 + (t % (K - 1));
+        } else {
+          a = 1 + (t + pi) % (K - 1);
+          b = 1 + (t - pi + (K - 1)) % (K - 1);
+        }
+        if (a > b) {
+          const int tmp = a; a = b; b = tmp;
+        }
+        if (b < k) {  // b == k is the padding column of an odd k
+          T* xa = A + (int64_t)a * lda;
+          T* xb = A + (int64_t)b * lda;
+          T u[EPL], v[EPL];
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) {
+            const int i = gl + e * G;
+            const int ic = i < p ? i : p - 1;
+            const T uu = xa[ic], vv = xb[ic];
+            u[e] = i < p ? uu : sc_zero<T>();
+            v[e] = i < p ? vv : sc_zero<T>();
+          }
+          T g = sc_zero<T>();
+          double al = 0.0, bt = 0.0;
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) {
+            sc_cfma(g, u[e], v[e]);
+            al += sc_abs2(u[e]);
+            bt += sc_abs2(v[e]);
+          }
+          g = group_sum_sc<G, T>(g);
+          al = group_sum<G>(al);
+          bt = group_sum<G>(bt);
+          // a column below the rounding level of R cannot move any singular
+          // value that a truncation can see: leave it alone
+          const double g2 = sc_abs2(g);
+          if (al > negl && bt > negl && g2 > tol2 * al * bt) {
+            const double ag = sqrt(g2);
+            const double iag = 1.0 / ag;
+            const T ph = sc_scale(g, iag);
+            const double zeta = 0.5 * (bt - al) * iag;
+            const double az = fabs(zeta);
+            double tt = az > 1.0e150 ? 0.5 / az : 1.0 / (az + sqrt(1.0 + az * az));
+            if (zeta < 0.0) tt = -tt;
+            const double c = rsqrt(1.0 + tt * tt), sn = c * tt;
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+              const int i = gl + e * G;
+              const T vv = sc_mulc(v[e], ph);  // y * conj(phase)
+              const T na = sc_sub(sc_scale(u[e], c), sc_scale(vv, sn));
+              const T nb = sc_add(sc_scale(u[e], sn), sc_scale(vv, c));
+              if (i < p) {
+                xa[i] = na;
+                xb[i] = nb;
+              }
+            }
+            if (gl == 0) *sRot = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    const int rot = *sRot;
+    __syncthreads();
+    if (!rot) break;
+  }
+  return sweep + 1;
+}
+
 // Small SVD of R (p x k), preconditioned as in the one-sided Jacobi SVD of
 // Drmac and Veselic (2008): a QR factorisation with column pivoting of R^H,
 //   R^H P = Q2 R2   (R2 upper trapezoidal, q = min(p, k) rows),
@@ -724,12 +819,26 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
   int sweeps = 0;
   if (q >= 2) {
     const int npairs = Q / 2;
-    const int gp = p <= 16 ? 2 : (p <= 32 ? 4 : 8);
-    const int gk = npairs * 8 <= SVD_NT ? 8 : (npairs * 4 <= SVD_NT ? 4 : 2);
-    const int g = gp < gk ? gp : gk;
-    if (g == 8) sweeps = jacobi_rounds<T, 8>(W, ldw, p, q, Q, tol, negl, jn, &sRot);
-    else if (g == 4) sweeps = jacobi_rounds<T, 4>(W, ldw, p, q, Q, tol, negl, jn, &sRot);
-    else sweeps = jacobi_rounds<T, 2>(W, ldw, p, q, Q, tol, negl, jn, &sRot);
+    // register-resident rounds whenever a column fits in a group's
+    // registers: 8 lanes per pair up to 128 rows, 16 up to 256, 32 up to 512
+    if (p <= 8 * 4) {
+      sweeps = jacobi_rounds_reg<T, 8, 4>(W, ldw, p, q, Q, tol, negl, &sRot);
+    } else if (p <= 8 * 8) {
+      sweeps = jacobi_rounds_reg<T, 8, 8>(W, ldw, p, q, Q, tol, negl, &sRot);
+    } else if (p <= 8 * 16) {
+      sweeps = jacobi_rounds_reg<T, 8, 16>(W, ldw, p, q, Q, tol, negl, &sRot);
+    } else if (p <= 16 * 16) {
+      sweeps = jacobi_rounds_reg<T, 16, 16>(W, ldw, p, q, Q, tol, negl, &sRot);
+    } else if (p <= 32 * 16) {
+      sweeps = jacobi_rounds_reg<T, 32, 16>(W, ldw, p, q, Q, tol, negl, &sRot);
+    } else {
+      const int gp = p <= 16 ? 2 : (p <= 32 ? 4 : 8);
+      const int gk = npairs * 8 <= SVD_NT ? 8 : (npairs * 4 <= SVD_NT ? 4 : 2);
+      const int g = gp < gk ? gp : gk;
+      if (g == 8) sweeps = jacobi_rounds<T, 8>(W, ldw, p, q, Q, tol, negl, jn, &sRot);
+      else if (g == 4) sweeps = jacobi_rounds<T, 4>(W, ldw, p, q, Q, tol, negl, jn, &sRot);
+      else sweeps = jacobi_rounds<T, 2>(W, ldw, p, q, Q, tol, negl, jn, &sRot);
+    }
   }
   __syncthreads();
   // ---- singular values: column norms, sorted descending (ties by index)
@@ -873,13 +982,13 @@ int tsqr_factor_launch(int scalar, int kmax, const QRNodeDev* nodes, int n,
   if (n == 0) return 0;
   if (scalar == 0) {
     if (kmax == 16) return fac<double, 16, 32, 8>(nodes, n, below, store, alpha, beta, st);
-    if (kmax == 32) return fac<double, 32, 16, 16>(nodes, n, below, store, alpha, beta, st);
-    if (kmax == 64) return fac<double, 64, 8, 32>(nodes, n, below, store, alpha, beta, st);
-    if (kmax == 128) return fac<double, 128, 4, 64>(nodes, n, below, store, alpha, beta, st);
+    if (kmax == 32) return fac<double, 32, 32, 8>(nodes, n, below, store, alpha, beta, st);
+    if (kmax == 64) return fac<double, 64, 16, 16>(nodes, n, below, store, alpha, beta, st);
+    if (kmax == 128) return fac<double, 128, 8, 32>(nodes, n, below, store, alpha, beta, st);
   } else {
     if (kmax == 16) return fac<hb_cplx, 16, 32, 8>(nodes, n, below, store, alpha, beta, st);
-    if (kmax == 32) return fac<hb_cplx, 32, 16, 16>(nodes, n, below, store, alpha, beta, st);
-    if (kmax == 64) return fac<hb_cplx, 64, 8, 32>(nodes, n, below, store, alpha, beta, st);
+    if (kmax == 32) return fac<hb_cplx, 32, 32, 8>(nodes, n, below, store, alpha, beta, st);
+    if (kmax == 64) return fac<hb_cplx, 64, 16, 16>(nodes, n, below, store, alpha, beta, st);
   }
   return -1;
 }
@@ -897,13 +1006,13 @@ int tsqr_apply_launch(int scalar, int kmax, const QRApplyDev* jobs, int n, const
   if (n == 0) return 0;
   if (scalar == 0) {
     if (kmax == 16) return app<double, 16, 32, 8>(jobs, n, store, beta, st);
-    if (kmax == 32) return app<double, 32, 16, 16>(jobs, n, store, beta, st);
-    if (kmax == 64) return app<double, 64, 8, 32>(jobs, n, store, beta, st);
-    if (kmax == 128) return app<double, 128, 4, 64>(jobs, n, store, beta, st);
+    if (kmax == 32) return app<double, 32, 32, 8>(jobs, n, store, beta, st);
+    if (kmax == 64) return app<double, 64, 16, 16>(jobs, n, store, beta, st);
+    if (kmax == 128) return app<double, 128, 8, 32>(jobs, n, store, beta, st);
   } else {
     if (kmax == 16) return app<hb_cplx, 16, 32, 8>(jobs, n, store, beta, st);
-    if (kmax == 32) return app<hb_cplx, 32, 16, 16>(jobs, n, store, beta, st);
-    if (kmax == 64) return app<hb_cplx, 64, 8, 32>(jobs, n, store, beta, st);
+    if (kmax == 32) return app<hb_cplx, 32, 32, 8>(jobs, n, store, beta, st);
+    if (kmax == 64) return app<hb_cplx, 64, 16, 16>(jobs, n, store, beta, st);
   }
   return -1;
 }
@@ -962,13 +1071,13 @@ int tsqr_applyh_launch(int scalar, int kmax, const QRApplyHDev* jobs, int n, con
   if (n == 0) return 0;
   if (scalar == 0) {
     if (kmax == 16) return apph<double, 16, 32, 8>(jobs, n, store, beta, st);
-    if (kmax == 32) return apph<double, 32, 16, 16>(jobs, n, store, beta, st);
-    if (kmax == 64) return apph<double, 64, 8, 32>(jobs, n, store, beta, st);
-    if (kmax == 128) return apph<double, 128, 4, 64>(jobs, n, store, beta, st);
+    if (kmax == 32) return apph<double, 32, 32, 8>(jobs, n, store, beta, st);
+    if (kmax == 64) return apph<double, 64, 16, 16>(jobs, n, store, beta, st);
+    if (kmax == 128) return apph<double, 128, 8, 32>(jobs, n, store, beta, st);
   } else {
     if (kmax == 16) return apph<hb_cplx, 16, 32, 8>(jobs, n, store, beta, st);
-    if (kmax == 32) return apph<hb_cplx, 32, 16, 16>(jobs, n, store, beta, st);
-    if (kmax == 64) return apph<hb_cplx, 64, 8, 32>(jobs, n, store, beta, st);
+    if (kmax == 32) return apph<hb_cplx, 32, 32, 8>(jobs, n, store, beta, st);
+    if (kmax == 64) return apph<hb_cplx, 64, 16, 16>(jobs, n, store, beta, st);
   }
   return -1;
 }
