@@ -18,7 +18,8 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 from workloads import make_config  # noqa: E402
 
-WORKLOADS = {"helmholtz": "helmholtz_20000.json", "gauss3d": "gauss3d_2000.json"}
+WORKLOADS = {"helmholtz": "helmholtz_20000.json", "gauss3d": "gauss3d_2000.json",
+             "coherent": "coherent_20000.json"}
 
 
 def sampled_error(src, res, stride=7):

@@ -20,7 +20,7 @@ def _script():
     return mod
 
 
-@pytest.mark.parametrize("name", ["gauss3d", "helmholtz"])
+@pytest.mark.parametrize("name", ["gauss3d", "helmholtz", "coherent"])
 def test_golden_values_reproduce(name):
     mg = _script()
     with open(os.path.join(HERE, mg.WORKLOADS[name])) as f:
