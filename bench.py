@@ -493,6 +493,9 @@ def headline(args, wl):
     import paper_1901_06101_amd as hb
 
     hb.require_gpu()
+    # the library's TSQR autotuner (untimed): picks the lane layout of each
+    # thin-QR width from measured times before the headline calls
+    tune = hb.autotune() if hasattr(hb, "autotune") else None
     dev = torch.device("cuda:0")
     X = torch.tensor(wl["X"], device=dev) if wl.get("X") is not None else None
     Y = torch.tensor(wl["Y"], device=dev) if wl.get("Y") is not None else None
@@ -563,6 +566,7 @@ def headline(args, wl):
         "phases_ms": phases,
         "roofline": rf[0] if rf else None,
         "kernel_classes": rf,
+        "autotune_tsqr_layouts": tune["table"] if tune else None,
     }
     last.close()
     _note(f"{wl['name']}: {wall_ms:.2f} ms per compress (eps {eps:g}, rel. error {rel:.2e})")

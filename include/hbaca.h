@@ -351,6 +351,24 @@ hb_status hb_hodlr_block_info(const hb_hodlr* h, int64_t block, int64_t* info5);
 hb_status hb_hodlr_matvec(const hb_hodlr* h, const double* x, double* y, void* stream);
 void hb_hodlr_free(hb_hodlr* h);
 
+/*
+ * Autotuner of the thin-QR (TSQR) kernels that the re-compression and the
+ * merges use.  Each width (16, 32, 64, 128 columns; 128 real only) has two
+ * lane layouts (a node on K x NQ lanes, or on twice as many with half the
+ * rows each); this call times both, factor and apply, on synthetic batches
+ * of 1 node (the top of a tree) and 256 nodes (its bottom) and keeps the
+ * faster for each (scalar type, width, batch size) in a process-wide table
+ * that later calls use.  Both layouts give the same reflectors up to the
+ * order of their partial sums.  Call it with no other library work in
+ * flight (the table is shared).  Allocates and frees its own synthetic
+ * data; synchronises `stream`.
+ *   table  16 int32 (may be NULL): [scalar][width 16/32/64/128][batch
+ *          1 / 256] -> layout 0 or 1
+ *   us     32 doubles (may be NULL): the measured microseconds per factor
+ *          plus apply, [scalar][width][batch][layout]
+ */
+hb_status hb_autotune(void* stream, int32_t* table, double* us);
+
 /* Statistics of the call (host struct). */
 hb_status hb_result_stats(const hb_result* res, hb_stats* out);
 

@@ -19,7 +19,7 @@ from ._binding import (HB_K_EFIE2D, HB_K_GAUSS, HB_K_HELMHOLTZ3D,  # noqa: F401
                        HB_PREC_MIXED, HBACAError, HbParams, HbStats, load)
 
 __all__ = ["compress", "compress_batched", "Result", "operator", "gaussian_operator",
-           "hodlr_build", "Hodlr",
+           "hodlr_build", "Hodlr", "autotune",
            "partition", "require_gpu", "params", "load",
            "HBACAError", "HB_K_GAUSS", "HB_K_LAPLACE", "HB_K_HELMHOLTZ3D",
            "HB_K_LOWRANK_SPIKES", "HB_K_EFIE2D", "HB_K_POLYNOMIAL", "HB_PREC_FP64",
@@ -411,6 +411,17 @@ class Hodlr:
         B._check(self._lib.hb_hodlr_matvec(self._h, _ptr(x), _ptr(out), _stream()),
                  "hb_hodlr_matvec")
         return out
+
+
+def autotune():
+    """Runs the library's TSQR autotuner (hb_autotune) on the current stream;
+    returns {"table": [...16], "us": [...32]} (see include/hbaca.h)."""
+    lib = load()
+    table = np.zeros(16, dtype=np.int32)
+    us = np.zeros(32, dtype=np.float64)
+    B._check(lib.hb_autotune(_stream(), table.ctypes.data_as(C.c_void_p),
+                             us.ctypes.data_as(C.c_void_p)), "hb_autotune")
+    return dict(table=table.tolist(), us=us.tolist())
 
 
 def hodlr_build(entry: int, p: dict, X, nmin: int, tol: float, d: int, leaf: int) -> Hodlr:

@@ -27,7 +27,7 @@ EXPORTED = (
     "hbaca_apply_noalloc", "hbaca_vjp", "hbaca_adjoint",
     "hbaca_recompute_frozen", "hb_partition", "hb_result_leaf_frozen", "hb_result_merge_ranks",
     "hb_hodlr_build", "hb_hodlr_blocks", "hb_hodlr_nblocks", "hb_hodlr_nleaves",
-    "hb_hodlr_block_info", "hb_hodlr_matvec", "hb_hodlr_free",
+    "hb_hodlr_block_info", "hb_hodlr_matvec", "hb_hodlr_free", "hb_autotune",
 )
 
 
@@ -154,6 +154,8 @@ def load(path: str = LIB_PATH):
     lib.hb_hodlr_matvec.restype = C.c_int
     lib.hb_hodlr_free.argtypes = [vp]
     lib.hb_hodlr_free.restype = None
+    lib.hb_autotune.argtypes = [vp, vp, vp]
+    lib.hb_autotune.restype = C.c_int
     lib.hbaca_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hbaca_vjp.restype = C.c_int
     lib.hbaca_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]

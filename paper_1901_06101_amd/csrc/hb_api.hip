@@ -1916,6 +1916,7 @@ static hb_status run(const CallSpec& c, hb_result** out) {
   }
   A.eps = c.tol;
   A.nleaves = (int32_t)nleaves;
+  A.queue = tmp.get<int32_t>(2);
   HB_HIP(hipEventRecord(ev[1], st));
   HB_LAUNCH(hbk::baca_launch(bscalar, dmax, rpt_v, A, st));
   HB_HIP(hipEventRecord(ev[2], st));
@@ -3066,6 +3067,15 @@ hb_status hb_hodlr_build(int entry_fn_id, const hb_params* params, const double*
     return e.st;
   } catch (const std::bad_alloc&) {
     return HB_ENOMEM;
+  } catch (...) {
+    return HB_EDEVICE;
+  }
+}
+
+hb_status hb_autotune(void* stream, int32_t* table, double* us) {
+  try {
+    const int e = hbk::tsqr_autotune((hipStream_t)stream, table, us);
+    return e == 0 ? HB_OK : HB_EDEVICE;
   } catch (...) {
     return HB_EDEVICE;
   }

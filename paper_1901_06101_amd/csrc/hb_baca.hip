@@ -21,6 +21,7 @@
 #include "hb_common.h"
 #include "hb_entries.h"
 #include "hb_internal.h"
+#include "hb_merge.h"
 
 namespace {
 
@@ -261,13 +262,14 @@ __device__ __forceinline__ bool pivots_in_range(const int* idx, int n, int lim) 
   return ok;
 }
 
+// BACA of leaf `li` by the whole workgroup.
 template <typename T, int DMAX, int RPT>
-__global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
+__device__ __forceinline__ void baca_leaf(const BacaArgs& A, const int li) {
   using C = GramCfg<T, DMAX>;
   using TA = typename acc_type<T>::type;  // FP32 data accumulate in FP64
   constexpr int TILE = 32;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const BacaLeafDev L = A.leaves[blockIdx.x];
+  const BacaLeafDev L = A.leaves[li];
   const int m0 = L.m0, n0 = L.n0, cap = L.cap;
   const int rmax = min(m0, n0);
   T* __restrict__ U = (T*)A.U + L.u_off;
@@ -769,7 +771,24 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
     o.status = status;
     o.pad = 0;
     o.mu = sqrt(mu2);
-    A.out[blockIdx.x] = o;
+    A.out[li] = o;
+  }
+}
+
+// One persistent launch over all leaves: each workgroup takes the next leaf
+// from an atomic counter (the leaves are ordered largest first) until none
+// is left, so every wave reaches the exit once the counter passes nleaves.
+template <typename T, int DMAX, int RPT>
+__global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
+  __shared__ int sNext;
+  for (;;) {
+    if (threadIdx.x == 0) sNext = atomicAdd(A.queue, 1);
+    __syncthreads();
+    const int li = sNext;
+    if (li >= A.nleaves) break;
+    baca_leaf<T, DMAX, RPT>(A, li);
+    // every thread has read sNext and left the leaf's LDS before the next take
+    __syncthreads();
   }
 }
 
@@ -777,9 +796,24 @@ __global__ __launch_bounds__(NT) void baca_leaf_kernel(BacaArgs A) {
 
 namespace hbk {
 
+// Workgroups of the persistent launch: as many as fit on the device at once
+// (occupancy per CU times the CU count), at most one per leaf.
 template <typename T, int DMAX, int RPT>
 static int launch_one(const BacaArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((baca_leaf_kernel<T, DMAX, RPT>), dim3(a.nleaves), dim3(NT), 0, st, a);
+  static int resident = 0;  // per instantiation, computed on first use
+  if (resident == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, baca_leaf_kernel<T, DMAX, RPT>, NT, 0) !=
+            hipSuccess)
+      return (int)hipGetLastError();
+    resident = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+  }
+  const int grid = a.nleaves < resident ? a.nleaves : resident;
+  int e = zero_fill_launch(a.queue, sizeof(int32_t) * 2, st);
+  if (e != 0) return e;
+  hipLaunchKernelGGL((baca_leaf_kernel<T, DMAX, RPT>), dim3(grid), dim3(NT), 0, st, a);
   return (int)hipGetLastError();
 }
 

@@ -52,6 +52,9 @@ struct BacaArgs {
   double eps;
   int32_t nleaves;
   int32_t fz_stride;  // 3 + 3 DMAX when fz is set
+  // work queue of the persistent launch: the next leaf index to take (the
+  // leaves are ordered largest first); zero before the launch
+  int32_t* queue;
 };
 
 // host launchers (defined in the .hip files)

@@ -165,5 +165,6 @@ int concat_launch(int scalar, const ConcatDev* jobs_dev, int njobs, int64_t max_
                   hipStream_t st);
 int rrh_launch(int scalar, const RRhDev* jobs_dev, int njobs, int64_t max_entries, hipStream_t st);
 int tsqr_mc(int scalar, int kmax);
+int tsqr_autotune(hipStream_t st, int* table, double* us);
 int tsqr_kmax_for(int scalar, int k);
 }  // namespace hbk

@@ -12,6 +12,8 @@
 #include "hb_common.h"
 #include "hb_merge.h"
 
+#include <vector>
+
 #include <algorithm>
 
 namespace {
@@ -976,23 +978,6 @@ static int fac(const QRNodeDev* nodes, int n, const QRNodeDev* below, void* stor
   return (int)hipGetLastError();
 }
 
-int tsqr_factor_launch(int scalar, int kmax, const QRNodeDev* nodes, int n,
-                       const QRNodeDev* below, void* store, void* alpha, double* beta,
-                       hipStream_t st) {
-  if (n == 0) return 0;
-  if (scalar == 0) {
-    if (kmax == 16) return fac<double, 16, 32, 8>(nodes, n, below, store, alpha, beta, st);
-    if (kmax == 32) return fac<double, 32, 32, 8>(nodes, n, below, store, alpha, beta, st);
-    if (kmax == 64) return fac<double, 64, 16, 16>(nodes, n, below, store, alpha, beta, st);
-    if (kmax == 128) return fac<double, 128, 8, 32>(nodes, n, below, store, alpha, beta, st);
-  } else {
-    if (kmax == 16) return fac<hb_cplx, 16, 32, 8>(nodes, n, below, store, alpha, beta, st);
-    if (kmax == 32) return fac<hb_cplx, 32, 32, 8>(nodes, n, below, store, alpha, beta, st);
-    if (kmax == 64) return fac<hb_cplx, 64, 16, 16>(nodes, n, below, store, alpha, beta, st);
-  }
-  return -1;
-}
-
 template <typename T, int KMAX, int NQ, int SEG>
 static int app(const QRApplyDev* jobs, int n, const void* store, const double* beta,
                hipStream_t st) {
@@ -1001,20 +986,193 @@ static int app(const QRApplyDev* jobs, int n, const void* store, const double* b
   return (int)hipGetLastError();
 }
 
+template <typename T, int KMAX, int NQ, int SEG>
+static int apph(const QRApplyHDev* jobs, int n, const void* store, const double* beta,
+                hipStream_t st) {
+  hipLaunchKernelGGL((tsqr_applyh_kernel<T, KMAX, NQ, SEG>), dim3(n), dim3(KMAX * NQ), 0, st,
+                     jobs, (const T*)store, beta);
+  return (int)hipGetLastError();
+}
+
+// Lane layouts of the TSQR kernels of one width: layout 0 gives a node
+// KMAX * NQ lanes with SEG rows each, layout 1 twice the lanes with half the
+// rows (16 columns have a single layout).  Which one is faster depends on
+// the width and on how many nodes a launch holds (one node at the top of a
+// tree, hundreds at the bottom); the choice per (scalar, width, batch size)
+// is a table that tsqr_autotune fills by timing both, and that starts at
+// layout 1.  Both layouts compute the same reflectors up to the order of
+// their partial sums.
+static int g_tsqr_layout[2][4][2] = {{{1, 1}, {1, 1}, {1, 1}, {1, 1}},
+                                      {{1, 1}, {1, 1}, {1, 1}, {1, 1}}};
+
+static int kidx(int kmax) { return kmax == 16 ? 0 : kmax == 32 ? 1 : kmax == 64 ? 2 : 3; }
+static int nbucket(int n) { return n < 64 ? 0 : 1; }
+
+#define HB_TSQR_DISPATCH(FN, ...)                                                     \
+  do {                                                                                \
+    const int lay = g_tsqr_layout[scalar ? 1 : 0][kidx(kmax)][nbucket(n)];            \
+    if (scalar == 0) {                                                                \
+      if (kmax == 16) return FN<double, 16, 32, 8>(__VA_ARGS__);                      \
+      if (kmax == 32) return lay ? FN<double, 32, 32, 8>(__VA_ARGS__)                 \
+                                 : FN<double, 32, 16, 16>(__VA_ARGS__);               \
+      if (kmax == 64) return lay ? FN<double, 64, 16, 16>(__VA_ARGS__)                \
+                                 : FN<double, 64, 8, 32>(__VA_ARGS__);                \
+      if (kmax == 128) return lay ? FN<double, 128, 8, 32>(__VA_ARGS__)               \
+                                  : FN<double, 128, 4, 64>(__VA_ARGS__);              \
+    } else {                                                                          \
+      if (kmax == 16) return FN<hb_cplx, 16, 32, 8>(__VA_ARGS__);                     \
+      if (kmax == 32) return lay ? FN<hb_cplx, 32, 32, 8>(__VA_ARGS__)                \
+                                 : FN<hb_cplx, 32, 16, 16>(__VA_ARGS__);              \
+      if (kmax == 64) return lay ? FN<hb_cplx, 64, 16, 16>(__VA_ARGS__)               \
+                                 : FN<hb_cplx, 64, 8, 32>(__VA_ARGS__);               \
+    }                                                                                 \
+  } while (0)
+
+int tsqr_factor_launch(int scalar, int kmax, const QRNodeDev* nodes, int n,
+                       const QRNodeDev* below, void* store, void* alpha, double* beta,
+                       hipStream_t st) {
+  if (n == 0) return 0;
+  HB_TSQR_DISPATCH(fac, nodes, n, below, store, alpha, beta, st);
+  return -1;
+}
+
 int tsqr_apply_launch(int scalar, int kmax, const QRApplyDev* jobs, int n, const void* store,
                       const double* beta, hipStream_t st) {
   if (n == 0) return 0;
-  if (scalar == 0) {
-    if (kmax == 16) return app<double, 16, 32, 8>(jobs, n, store, beta, st);
-    if (kmax == 32) return app<double, 32, 32, 8>(jobs, n, store, beta, st);
-    if (kmax == 64) return app<double, 64, 16, 16>(jobs, n, store, beta, st);
-    if (kmax == 128) return app<double, 128, 8, 32>(jobs, n, store, beta, st);
-  } else {
-    if (kmax == 16) return app<hb_cplx, 16, 32, 8>(jobs, n, store, beta, st);
-    if (kmax == 32) return app<hb_cplx, 32, 32, 8>(jobs, n, store, beta, st);
-    if (kmax == 64) return app<hb_cplx, 64, 16, 16>(jobs, n, store, beta, st);
-  }
+  HB_TSQR_DISPATCH(app, jobs, n, store, beta, st);
   return -1;
+}
+
+int tsqr_applyh_launch(int scalar, int kmax, const QRApplyHDev* jobs, int n, const void* store,
+                       const double* beta, hipStream_t st) {
+  if (n == 0) return 0;
+  HB_TSQR_DISPATCH(apph, jobs, n, store, beta, st);
+  return -1;
+}
+#undef HB_TSQR_DISPATCH
+
+__global__ void tune_fill_kernel(double* x, int64_t n, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  // a fixed pseudo-random fill (SplitMix64 of the index), values in [-1, 1)
+  uint64_t z = seed + (uint64_t)i * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  x[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// Times both lane layouts of the factor and apply kernels on synthetic
+// level-0 batches (1 node: the top of a tree; 256 nodes: its bottom) of
+// every width and scalar type, and keeps the faster in g_tsqr_layout.
+// Writes the table to `table` (2 x 4 x 2 ints, may be null) and the
+// measured times in microseconds to `us` (2 x 4 x 2 x 2, may be null).
+int tsqr_autotune(hipStream_t st, int* table, double* us) {
+  const int MC = MC_ALL;
+  const int batches[2] = {1, 256};
+  const int kmaxs[4] = {16, 32, 64, 128};
+  const size_t maxk = 128, maxn = 256;
+  double *B = nullptr, *store = nullptr, *alpha = nullptr, *beta = nullptr, *Z = nullptr;
+  QRNodeDev* dn = nullptr;
+  QRApplyDev* dj = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int err = 0;
+  auto ok = [&](hipError_t e) {
+    if (e != hipSuccess && err == 0) err = (int)e;
+    return err == 0;
+  };
+  const size_t belems = maxn * MC * maxk * 2;  // complex counts twice
+  if (!ok(hipMalloc(&B, belems * 8)) || !ok(hipMalloc(&store, belems * 8)) ||
+      !ok(hipMalloc(&alpha, maxn * maxk * 16)) || !ok(hipMalloc(&beta, maxn * maxk * 8)) ||
+      !ok(hipMalloc(&Z, belems * 8)) || !ok(hipMalloc(&dn, maxn * sizeof(QRNodeDev))) ||
+      !ok(hipMalloc(&dj, maxn * sizeof(QRApplyDev))) || !ok(hipEventCreate(&e0)) ||
+      !ok(hipEventCreate(&e1))) {
+  } else {
+    hipLaunchKernelGGL(tune_fill_kernel, dim3((unsigned)((belems + 255) / 256)), dim3(256), 0, st,
+                       B, (int64_t)belems, 12345ull);
+    ok(hipGetLastError());
+    for (int sc = 0; sc < 2 && err == 0; ++sc)
+      for (int ki = 0; ki < 4 && err == 0; ++ki) {
+        const int k = kmaxs[ki];
+        if (sc == 1 && k == 128) continue;
+        for (int bi = 0; bi < 2 && err == 0; ++bi) {
+          const int n = batches[bi];
+          const size_t sb = sc ? 16 : 8;
+          std::vector<QRNodeDev> nodes(n);
+          std::vector<QRApplyDev> jobs(n);
+          for (int a = 0; a < n; ++a) {
+            QRNodeDev nd{};
+            nd.rows = MC;
+            nd.k = k;
+            nd.steps = k < MC ? k : MC;
+            nd.level0 = 1;
+            nd.P1 = (const char*)B + (size_t)a * MC * k * sb;
+            nd.P2 = nd.P1;
+            nd.ld1 = nd.ld2 = MC;
+            nd.n1 = k;
+            nd.store = (int64_t)a * MC * k;
+            nd.ab = a * k;
+            nodes[a] = nd;
+            QRApplyDev J{};
+            J.rows = MC;
+            J.steps = nd.steps;
+            J.r = k;
+            J.store = nd.store;
+            J.ab = nd.ab;
+            J.Zin = (const char*)B + (size_t)a * MC * k * sb;
+            J.ldin = MC;
+            J.Zout = (char*)Z + (size_t)a * MC * k * sb;
+            J.ldout = MC;
+            jobs[a] = J;
+          }
+          if (!ok(hipMemcpyAsync(dn, nodes.data(), n * sizeof(QRNodeDev), hipMemcpyHostToDevice,
+                                 st)) ||
+              !ok(hipMemcpyAsync(dj, jobs.data(), n * sizeof(QRApplyDev), hipMemcpyHostToDevice,
+                                 st)))
+            break;
+          double best = 0.0;
+          int pick = 1;
+          for (int lay = 0; lay < 2 && err == 0; ++lay) {
+            g_tsqr_layout[sc][ki][bi] = lay;
+            // warm-up, then three timed factor + apply pairs
+            int le = tsqr_factor_launch(sc, k, dn, n, nullptr, store, alpha, beta, st);
+            if (le == 0) le = tsqr_apply_launch(sc, k, dj, n, store, beta, st);
+            if (le != 0) {
+              err = le;
+              break;
+            }
+            ok(hipEventRecord(e0, st));
+            for (int rep = 0; rep < 3 && le == 0; ++rep) {
+              le = tsqr_factor_launch(sc, k, dn, n, nullptr, store, alpha, beta, st);
+              if (le == 0) le = tsqr_apply_launch(sc, k, dj, n, store, beta, st);
+            }
+            if (le != 0) {
+              err = le;
+              break;
+            }
+            ok(hipEventRecord(e1, st));
+            ok(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            ok(hipEventElapsedTime(&ms, e0, e1));
+            const double t = ms * 1e3 / 3.0;
+            if (us) us[((sc * 4 + ki) * 2 + bi) * 2 + lay] = t;
+            if (lay == 0 || t < best) {
+              best = t;
+              pick = lay;
+            }
+          }
+          g_tsqr_layout[sc][ki][bi] = pick;
+        }
+      }
+  }
+  if (table)
+    for (int i = 0; i < 16; ++i) table[i] = (&g_tsqr_layout[0][0][0])[i];
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  for (void* q : {(void*)B, (void*)store, (void*)alpha, (void*)beta, (void*)Z, (void*)dn, (void*)dj})
+    if (q) (void)hipFree(q);
+  return err;
 }
 
 int svd_launch(int scalar, const SVDJobDev* jobs, int n, int kmax_batch, int pmax_batch,
@@ -1056,30 +1214,6 @@ int block_gemm_launch(int scalar, const BlockGemmDev* jobs, int n, int max_rows,
   else
     hipLaunchKernelGGL((block_gemm_kernel<hb_cplx>), grid, dim3(BG_NT), sh, st, jobs, max_rin);
   return (int)hipGetLastError();
-}
-
-template <typename T, int KMAX, int NQ, int SEG>
-static int apph(const QRApplyHDev* jobs, int n, const void* store, const double* beta,
-                hipStream_t st) {
-  hipLaunchKernelGGL((tsqr_applyh_kernel<T, KMAX, NQ, SEG>), dim3(n), dim3(KMAX * NQ), 0, st,
-                     jobs, (const T*)store, beta);
-  return (int)hipGetLastError();
-}
-
-int tsqr_applyh_launch(int scalar, int kmax, const QRApplyHDev* jobs, int n, const void* store,
-                       const double* beta, hipStream_t st) {
-  if (n == 0) return 0;
-  if (scalar == 0) {
-    if (kmax == 16) return apph<double, 16, 32, 8>(jobs, n, store, beta, st);
-    if (kmax == 32) return apph<double, 32, 32, 8>(jobs, n, store, beta, st);
-    if (kmax == 64) return apph<double, 64, 16, 16>(jobs, n, store, beta, st);
-    if (kmax == 128) return apph<double, 128, 8, 32>(jobs, n, store, beta, st);
-  } else {
-    if (kmax == 16) return apph<hb_cplx, 16, 32, 8>(jobs, n, store, beta, st);
-    if (kmax == 32) return apph<hb_cplx, 32, 32, 8>(jobs, n, store, beta, st);
-    if (kmax == 64) return apph<hb_cplx, 64, 16, 16>(jobs, n, store, beta, st);
-  }
-  return -1;
 }
 
 int concat_launch(int scalar, const ConcatDev* jobs, int n, int64_t max_m, int, hipStream_t st) {

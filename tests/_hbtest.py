@@ -76,6 +76,7 @@ def recon_norm(X, Y):
 PICK_NOISE = 1e-11
 QRCP_ZERO = 1e-13
 NU_DECIDED = 1e-7
+PICK_FLOOR = 1e-11
 MU_RTOL = 1e-9
 NU_RTOL = 1e-6
 
@@ -101,8 +102,12 @@ def determined_iterations(oinfo):
     (see _determined), or whose new block has nu < NU_DECIDED * mu: its
     residual panels are differences of entries some 1 / NU_DECIDED times
     larger, so their rounding (about 1e-16 mu) reaches 1e-9 of the panel and
-    picks closer than that are a tie.  An iteration with d_k = 0 ends the
-    leaf and is counted like the others."""
+    picks closer than that are a tie; likewise an iteration with a pick
+    (among the rows I_k(1:d_k), or the columns that made J_k) whose trailing
+    norm is below PICK_FLOOR * mu: rounding of order 1e-16 mu then moves
+    that norm by 1e-5 of itself or more, enough to reorder close rows or
+    columns (neighbouring nodes on the EFIE2D strips).  An iteration with
+    d_k = 0 ends the leaf and is counted like the others."""
     its = oinfo["iters"]
     nk = 0
     for k, it in enumerate(its):
@@ -112,6 +117,16 @@ def determined_iterations(oinfo):
             break
         if it["dk"] > 0 and it["nu"] < NU_DECIDED * max(it["mu"], 1e-300):
             break
+        # a trailing norm this close to the rounding of the matrix scale
+        # (mu) decides nothing: two close rows or columns may trade places
+        floor = PICK_FLOOR * max(it["mu"], its[k - 1]["mu"] if k else 0.0)
+        sel = np.asarray(it["sel_I"])[:max(it["dk"], 1)]
+        if sel.size and np.any((sel > QRCP_ZERO * sel.max()) & (sel < floor)):
+            break
+        if k > 0:
+            sj = np.asarray(its[k - 1]["sel_J"])
+            if sj.size and np.any((sj > QRCP_ZERO * sj.max()) & (sj < floor)):
+                break
         nk += 1
     return nk
 
