@@ -37,13 +37,15 @@ Instrumentation (no effect on the arithmetic): every iteration records its
 pivots, d_k, nu, mu, the trailing norms of the row picks (sel_I) and of the
 column picks that chose the next block (sel_J), and the whole blocks I_k,
 J_k with the pivot order of QR(W_k, eps) (Iblock, Jblock, piv), which is
-what a replay with frozen pivots needs.
+what a replay with frozen pivots needs; with the strong selector also the
+swaps and decision margins of both selections (swaps_I, margin_I, swaps_J,
+margin_J).
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .qrcp import qrcp
+from .qrcp import qrcp, strong_select
 
 
 def _chol_upper(G: np.ndarray):
@@ -102,10 +104,24 @@ class LeafResult:
         return self.U.shape[1]
 
 
+def _select(M: np.ndarray, d: int, selector: int, f: float):
+    """Pivots of the d-pick selection of eqs. (6)-(7) on panel M, the QRCP
+    trailing norms of the greedy picks, the swaps made and the decision
+    margin: selector 0 is greedy QRCP (the paper's choice), 1 the strong
+    rank-revealing selection (QRCP then Gu-Eisenstat swaps, threshold f)."""
+    if selector == 0:
+        res = qrcp(M, d)
+        return res.piv, np.abs(res.tdiag), 0, np.inf
+    ss = strong_select(M, d, f)
+    return ss.piv, np.abs(ss.qr.tdiag), ss.swaps, ss.margin
+
+
 def baca_leaf(block, m0: int, n0: int, d: int, eps: float, J1: np.ndarray,
-              record: bool = True) -> LeafResult:
+              record: bool = True, selector: int = 0, select_f: float = 2.0) -> LeafResult:
     """BACA of the m0 x n0 leaf whose entries ``block(I, J)`` returns for
-    leaf-local index arrays.  ``J1`` is the first column block."""
+    leaf-local index arrays.  ``J1`` is the first column block.  ``selector``
+    picks the row and column selection (0 greedy QRCP, 1 strong
+    rank-revealing with swap threshold ``select_f``)."""
     probe = block(np.zeros(0, dtype=np.int64), np.zeros(0, dtype=np.int64))
     dt = probe.dtype
     U = np.zeros((m0, 0), dtype=dt)
@@ -131,8 +147,8 @@ def baca_leaf(block, m0: int, n0: int, d: int, eps: float, J1: np.ndarray,
         Pr = allr[~used_r]
         if Pr.size == 0:
             break
-        selI = qrcp(C[Pr, :].conj().T, d)
-        I = Pr[selI.piv]
+        pivI, normsI, swI, marI = _select(C[Pr, :].conj().T, d, selector, select_f)
+        I = Pr[pivI]
         ops["qrcp_flops"] += 4 * phi * J.size * Pr.size * I.size
         # (3) residual row block R_k = A(I_k, :) - U(I_k, :) V
         R = block(I, allc) - U[I, :] @ V
@@ -152,8 +168,10 @@ def baca_leaf(block, m0: int, n0: int, d: int, eps: float, J1: np.ndarray,
             if record:
                 iters.append(dict(I=np.zeros(0, np.int64), J=np.zeros(0, np.int64),
                                   dk=0, nu=0.0, mu=float(np.sqrt(mu2)), r=r,
-                                  sel_I=np.abs(selI.tdiag), sel_J=np.zeros(0),
-                                  Iblock=I.copy(), Jblock=J.copy(), piv=full.piv.copy()))
+                                  sel_I=normsI, sel_J=np.zeros(0),
+                                  Iblock=I.copy(), Jblock=J.copy(), piv=full.piv.copy(),
+                                  swaps_I=swI, margin_I=marI, swaps_J=0,
+                                  margin_J=np.inf))
             break
         jbar = full.piv[:dk]
         Uk = C[:, jbar]
@@ -173,15 +191,18 @@ def baca_leaf(block, m0: int, n0: int, d: int, eps: float, J1: np.ndarray,
         mu = float(np.sqrt(mu2))
         if record:
             iters.append(dict(I=I[:dk].copy(), J=J[jbar].copy(), dk=dk, nu=nu,
-                              mu=mu, r=U.shape[1], sel_I=np.abs(selI.tdiag),
+                              mu=mu, r=U.shape[1], sel_I=normsI,
                               sel_J=np.zeros(0), Iblock=I.copy(), Jblock=J.copy(),
-                              piv=full.piv.copy()))
+                              piv=full.piv.copy(), swaps_I=swI, margin_I=marI,
+                              swaps_J=0, margin_J=np.inf))
         # (8) stopping test, then the next column block (eq. (7))
         if nu < eps * mu or Pc.size == 0 or U.shape[1] >= rmax:
             break
-        selJ = qrcp(R[:, Pc], d)
+        pivJ, normsJ, swJ, marJ = _select(R[:, Pc], d, selector, select_f)
         if record:
-            iters[-1]["sel_J"] = np.abs(selJ.tdiag)
-        ops["qrcp_flops"] += 4 * phi * I.size * Pc.size * selJ.piv.size
-        J = Pc[selJ.piv]
+            iters[-1]["sel_J"] = normsJ
+            iters[-1]["swaps_J"] = swJ
+            iters[-1]["margin_J"] = marJ
+        ops["qrcp_flops"] += 4 * phi * I.size * Pc.size * pivJ.size
+        J = Pc[pivJ]
     return LeafResult(U, V, iters, ops)

@@ -161,8 +161,11 @@ class HBACAResult:
 
 
 def hbaca(src: EntrySource, m: int, n: int, eps: float, d: int, leaf: int,
-          seed: int, keep_leaf_factors: bool = False) -> HBACAResult:
-    """H-BACA (Algorithm 3) of the m x n matrix whose entries ``src`` gives."""
+          seed: int, keep_leaf_factors: bool = False, selector: int = 0,
+          select_f: float = 2.0) -> HBACAResult:
+    """H-BACA (Algorithm 3) of the m x n matrix whose entries ``src`` gives.
+    ``selector``/``select_f`` choose the leaves' pivot selection (see
+    baca_leaf)."""
     L = tree_levels(m, n, leaf)
     rows = cluster_tree(m, L)[L]
     cols = cluster_tree(n, L)[L]
@@ -180,7 +183,7 @@ def hbaca(src: EntrySource, m: int, n: int, eps: float, d: int, leaf: int,
                 return src.block(np.asarray(I) + ra, np.asarray(J) + ca)
 
             J1 = first_column_block(seed, b, cs, d)
-            res = baca_leaf(blk, rs, cs, d, eps, J1)
+            res = baca_leaf(blk, rs, cs, d, eps, J1, selector=selector, select_f=select_f)
             for key in res.ops:
                 ops[key] += res.ops[key]
             rb = res.rank
@@ -188,7 +191,8 @@ def hbaca(src: EntrySource, m: int, n: int, eps: float, d: int, leaf: int,
             blkres = recompress(res.U, res.V, eps)
             leaves[(t, v)] = blkres
             info = dict(rank_baca=rb, rank=blkres[1].size, iters=res.iters,
-                        m0=rs, n0=cs, row0=ra, col0=ca)
+                        m0=rs, n0=cs, row0=ra, col0=ca,
+                        swaps=sum(it["swaps_I"] + it["swaps_J"] for it in res.iters))
             if keep_leaf_factors:
                 info["U"], info["V"] = res.U, res.V
             leaf_info[b] = info

@@ -26,12 +26,35 @@ Pinned in the tests against a brute-force selection that recomputes every
 residual norm by least squares, and (for the full factorisation) against
 Q T = W(:, pivots); the rounding-level reading against exactly rank-deficient
 panels.
+
+``strong_select`` is the alternative selector the paper names beside QRCP
+(Section "Blocked Adaptive Cross Approximation": strong rank-revealing QR):
+greedy QRCP followed by the column swaps of Gu and Eisenstat (SIAM J. Sci.
+Comput. 17 (1996), "Efficient algorithms for computing a strong
+rank-revealing QR factorization").  Readings, since the paper gives no
+details:
+
+* k is the number of leading QRCP picks whose trailing norm is above the
+  rounding level (the reading above); the panel has numerical rank k, so the
+  trailing block R22 of the pivoted QR counts as zero and Gu and Eisenstat's
+  swap test reduces to |W(i, j)| > f for W = R11^-1 R12, the coefficients of
+  every other candidate column in the basis of the k chosen ones (a least
+  squares solve, exact when the chosen columns span the panel).  Swapping
+  chosen column i for candidate j multiplies |det R11| (the volume of the
+  chosen columns) by |W(i, j)|;
+* each round takes the largest |W(i, j)| (ties to the lowest candidate
+  position, then the lowest i), swaps in place (candidate j takes the slot
+  of chosen column i, so the pick order is otherwise kept) while it exceeds
+  f > 1, at most SWAP_CAP * k times;
+* the remaining picks past k (rounding-level norms, a tie) are the lowest
+  positions not chosen, as QRCP's reading gives them.
 """
 from __future__ import annotations
 
 import numpy as np
 
 NOISE = 1e-12
+SWAP_CAP = 4
 
 
 def householder(x: np.ndarray):
@@ -57,11 +80,12 @@ class QRCPResult:
     ``T[:k, :k]`` is the leading upper-triangular block T11.
     """
 
-    def __init__(self, piv, tdiag, refl, T):
+    def __init__(self, piv, tdiag, refl, T, nz=0):
         self.piv = piv
         self.tdiag = tdiag
         self.refl = refl
         self.T = T
+        self.nz = nz  # leading picks whose trailing norm is above the rounding level
 
     def apply_qh(self, B: np.ndarray, nsteps: int | None = None) -> np.ndarray:
         """Q^H B using the first ``nsteps`` reflectors (all by default)."""
@@ -83,6 +107,7 @@ def qrcp(M: np.ndarray, kmax: int) -> QRCPResult:
     remaining = np.ones(q, dtype=bool)
     piv, tdiag, refl = [], [], []
     ref2 = 0.0
+    nz, noise_reached = 0, False
     for t in range(steps):
         cols = np.nonzero(remaining)[0]
         sub = A[t:, cols]
@@ -93,6 +118,10 @@ def qrcp(M: np.ndarray, kmax: int) -> QRCPResult:
         else:  # rounding-level trailing norms count as zero
             norm2 = np.where(norm2 < NOISE * NOISE * ref2, 0.0, norm2)
         j = int(cols[int(np.argmax(norm2))])  # first maximum = lowest position
+        if norm2.max() > 0.0 and not noise_reached:
+            nz += 1
+        else:
+            noise_reached = True
         v, beta, alpha = householder(A[t:, j])
         if beta != 0.0:
             w = v.conj() @ A[t:, cols]
@@ -105,4 +134,53 @@ def qrcp(M: np.ndarray, kmax: int) -> QRCPResult:
         refl.append((v, beta))
     order = piv + [c for c in range(q) if remaining[c]]
     T = A[:steps, order] if steps else np.zeros((0, q), dtype=A.dtype)
-    return QRCPResult(np.array(piv, dtype=np.int64), np.array(tdiag), refl, T)
+    return QRCPResult(np.array(piv, dtype=np.int64), np.array(tdiag), refl, T, nz)
+
+
+class StrongSelection:
+    """Picks of ``strong_select``, the swaps made, and the smallest relative
+    margin of its decisions: (|W|max - f) / f or (f - |W|max) / f at every
+    round, and (|W|max - runner-up) / |W|max at every swap.  A margin near
+    the rounding level means another correct run may decide otherwise."""
+
+    def __init__(self, piv, qr, swaps, margin):
+        self.piv = piv
+        self.qr = qr
+        self.swaps = swaps
+        self.margin = margin
+
+
+def strong_select(M: np.ndarray, kmax: int, f: float) -> StrongSelection:
+    """Strong rank-revealing selection of at most ``kmax`` columns of M:
+    greedy QRCP, then Gu-Eisenstat swaps with threshold f > 1."""
+    if not f > 1.0:
+        raise ValueError("the swap threshold f must exceed 1")
+    res = qrcp(M, kmax)
+    piv = [int(c) for c in res.piv]
+    k = res.nz
+    q = M.shape[1]
+    S = piv[:k]
+    swaps, margin = 0, np.inf
+    while k > 0 and swaps < SWAP_CAP * k:
+        chosen = set(S)
+        rest = np.array([c for c in range(q) if c not in chosen], dtype=np.int64)
+        if rest.size == 0:
+            break
+        W = np.linalg.lstsq(M[:, S], M[:, rest], rcond=None)[0]  # k x |rest|
+        A = np.abs(W)
+        # the largest entry; ties to the lowest candidate position, then the
+        # lowest chosen slot (column-major scan of A)
+        flat = A.T.ravel()
+        pos = int(np.argmax(flat))
+        best = float(flat[pos])
+        j, i = divmod(pos, k)
+        if best <= f:
+            margin = min(margin, (f - best) / f)
+            break
+        second = float(np.max(np.delete(flat, pos))) if flat.size > 1 else 0.0
+        margin = min(margin, (best - f) / f, (best - second) / best)
+        S[i] = int(rest[j])
+        swaps += 1
+    chosen = set(S)
+    noise = [c for c in range(q) if c not in chosen][:len(piv) - k]
+    return StrongSelection(np.array(S + noise, dtype=np.int64), res, swaps, margin)
