@@ -17,6 +17,7 @@ or the small SVDs / the TSQR kernels against the FP64 vector peak.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload helmholtz]
                   [--no-cpu-baseline] [--no-comparisons] [--no-adjoint] [--no-hodlr]
+                  [--no-sweep]
 
 Besides the headline workload, the line carries "comparisons": mixed
 precision against plain FP64 (the 8-D Gaussian mixture at 2000^2 and the
@@ -24,7 +25,9 @@ Gaussian R^3 2000^2 workload) and one batched call against one call per
 block (the 4096 Laplace blocks of the batched workload), and "adjoint": the
 frozen-pivot adjoint on the differentiation workload (Gaussian 50000^2 in
 R^3, h = 0.7), and "hodlr": a hierarchical matrix of a Gaussian kernel
-built with the batched path and its matrix-vector product.  Each runs in a
+built with the batched path and its matrix-vector product, and "sweep": time,
+rank and error over leaf counts and block sizes d on four kernels (the
+paper's efficiency study, Fig. 5).  Each runs in a
 child process of its own with a time limit,
 after the headline measurement, so that neither can change it.
 """
@@ -371,6 +374,94 @@ def hodlr(steps=5, warmup=1):
     print(json.dumps(out), flush=True)
 
 
+def _device_workload(hb, wl, **kw):
+    """Device points and the parameter dict of a workload."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    X = torch.tensor(wl["X"], device=dev) if wl.get("X") is not None else None
+    Y = torch.tensor(wl["Y"], device=dev) if wl.get("Y") is not None else None
+    p = hb.params(dim=(wl["X"].shape[1] if wl.get("X") is not None else 0), h=wl.get("h", 0.0),
+                  gauss_c=wl.get("gauss_c", 1.0), wavenumber=wl.get("wavenumber", 0.0),
+                  seed=wl["seed"], **kw)
+    if wl["entry"] == hb.HB_K_LOWRANK_SPIKES:
+        p["G1"] = torch.tensor(wl["G1"], device=dev)
+        p["G2"] = torch.tensor(wl["G2"], device=dev)
+        p["spike_lin"] = torch.tensor(np.asarray(wl["spike_lin"], np.int64), device=dev)
+        p["spike_val"] = torch.tensor(np.asarray(wl["spike_val"], np.float64), device=dev)
+    return X, Y, p
+
+
+def sweep(reps=2):
+    """Time, rank and error of H-BACA for varying leaf counts n_b = 4^L and
+    block sizes d, mirroring the paper's efficiency study (Section
+    "Numerical Results", Fig. 5), on the 8-D Gaussian mixture (the Gaussian
+    data-set runs), the polynomial kernel (constant-rank regime), a product
+    of random factors, and the EFIE2D strips (increasing-rank regime); then,
+    per workload, greedy QRCP against the strong rank-revealing selection
+    at one (L, d).  Prints one JSON object."""
+    import numpy as np
+    import torch
+
+    import paper_1901_06101_amd as hb
+    from workloads import generators as G
+
+    hb.require_gpu()
+    cases = [
+        ("gauss_mixture_20000_eps1e-2",
+         G.make_gauss_mixture(n=20000, tol=1e-2, d=16, cfg=4), (4, 5, 6), 5),
+        ("polynomial_8000_eps1e-4", G.make_polynomial(n=8000, tol=1e-4), (2, 3, 4, 5), 4),
+        ("product_of_random_8000_r100",
+         G.make_lowrank_spikes(n=8000, rank=100, n_spikes=0, tol=1e-4, cfg=10), (2, 3, 4, 5), 4),
+        ("efie2d_4000_eps1e-4", G.make_efie2d_strips(n=4000, tol=1e-4), (1, 2, 3, 4), 3),
+    ]
+
+    def timed(wl, X, Y, p, d, leaf):
+        def call():
+            return hb.compress(wl["entry"], p, X, Y, wl["m"], wl["n"], wl["tol"], d, leaf)
+        call().close()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps - 1):
+            call().close()
+        r = call()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / reps
+        e2, a2 = r.error(0, 7)
+        st = r.stats()
+        row = dict(ms=ms, rank=r.rank(0), rel_err_rows7=float(np.sqrt(e2 / a2)),
+                   swaps=st["select_swaps"], leaf_rank_max=st["leaf_rank_max"],
+                   phases_ms={k: st[k] for k in ("ms_baca", "ms_recompress", "ms_merge",
+                                                 "ms_svd", "ms_qr", "ms_gemm")})
+        r.close()
+        return row
+
+    out = {}
+    for name, wl, levels, Lsel in cases:
+        X, Y, p = _device_workload(hb, wl)
+        rows = []
+        for L in levels:
+            leaf = -(-max(wl["m"], wl["n"]) // (1 << L))
+            for d in (1, 8, 16, 32):
+                try:
+                    rows.append(dict(L=L, n_b=4 ** L, leaf=leaf, d=d,
+                                     **timed(wl, X, Y, p, d, leaf)))
+                except Exception as e:  # a size the build does not take
+                    rows.append(dict(L=L, n_b=4 ** L, leaf=leaf, d=d,
+                                     error=f"{type(e).__name__}: {e}"))
+        leaf = -(-max(wl["m"], wl["n"]) // (1 << Lsel))
+        sel = []
+        for f in (None, 2.0, 1.05):
+            kw = {} if f is None else dict(selector=hb.HB_SEL_STRONG, select_f=f)
+            X, Y, p = _device_workload(hb, wl, **kw)
+            sel.append(dict(selector="qrcp" if f is None else "strong", f=f,
+                            **timed(wl, X, Y, p, 16, leaf)))
+        out[name] = dict(tol=wl["tol"], m=wl["m"], n=wl["n"], rows=rows,
+                         selectors=dict(L=Lsel, leaf=leaf, d=16, rows=sel))
+        _note(f"sweep: {name} done")
+    print(json.dumps(_finite(out)), flush=True)
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
     """Device-to-device copy rate in GB/s (bytes read plus bytes written),
     the measured counterpart of the HBM peak."""
@@ -496,17 +587,7 @@ def headline(args, wl):
     # the library's TSQR autotuner (untimed): picks the lane layout of each
     # thin-QR width from measured times before the headline calls
     tune = hb.autotune() if hasattr(hb, "autotune") else None
-    dev = torch.device("cuda:0")
-    X = torch.tensor(wl["X"], device=dev) if wl.get("X") is not None else None
-    Y = torch.tensor(wl["Y"], device=dev) if wl.get("Y") is not None else None
-    p = hb.params(dim=(wl["X"].shape[1] if wl.get("X") is not None else 0), h=wl.get("h", 0.0),
-                  gauss_c=wl.get("gauss_c", 1.0), wavenumber=wl.get("wavenumber", 0.0),
-                  seed=wl["seed"])
-    if wl["entry"] == hb.HB_K_LOWRANK_SPIKES:
-        p["G1"] = torch.tensor(wl["G1"], device=dev)
-        p["G2"] = torch.tensor(wl["G2"], device=dev)
-        p["spike_lin"] = torch.tensor(wl["spike_lin"], device=dev)
-        p["spike_val"] = torch.tensor(wl["spike_val"], device=dev)
+    X, Y, p = _device_workload(hb, wl)
     tol = wl["tol"]
 
     def step(eps):
@@ -583,6 +664,8 @@ def main():
     ap.add_argument("--no-comparisons", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-hodlr", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--comparisons", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--adjoint", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--hodlr", action="store_true", help=argparse.SUPPRESS)
@@ -595,6 +678,9 @@ def main():
         return
     if args.hodlr:
         hodlr()
+        return
+    if args.sweep:
+        sweep()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); how H-BACA would "
@@ -642,6 +728,8 @@ def main():
         out["adjoint"] = run_child("--adjoint")
     if not args.no_hodlr:
         out["hodlr"] = run_child("--hodlr")
+    if not args.no_sweep:
+        out["sweep"] = run_child("--sweep")
     print(json.dumps(_finite(out)), flush=True)
 
 

@@ -72,6 +72,25 @@ typedef enum {
                         HB_EUNSUPPORTED. */
 } hb_precision;
 
+/*
+ * Selection of the skeleton rows I_k and columns J_{k+1} in the leaf BACA
+ * (Algorithm 2, eqs. (6)-(7)).  The paper uses greedy QRCP and names strong
+ * rank-revealing QR as an alternative (Section "Blocked Adaptive Cross
+ * Approximation").
+ *   HB_SEL_QRCP    greedy QRCP (trailing norms below 1e-12 of the panel's
+ *                  largest count as zero; ties to the lowest index)
+ *   HB_SEL_STRONG  greedy QRCP, then the swaps of Gu and Eisenstat's strong
+ *                  rank-revealing QR: with k the picks above the rounding
+ *                  level and W = R11^-1 R12 the coefficients of every other
+ *                  candidate in the basis of the k chosen panel columns,
+ *                  while max |W(i, j)| > select_f the candidate j replaces
+ *                  chosen column i in place (ties: lowest j, then lowest i),
+ *                  at most 4 k swaps; the picks past k are then the lowest
+ *                  free indices.  Each swap multiplies the volume of the
+ *                  chosen columns by |W(i, j)| > select_f.
+ */
+typedef enum { HB_SEL_QRCP = 0, HB_SEL_STRONG = 1 } hb_selector;
+
 typedef struct {
   int32_t dim;        /* point dimension (1..8; 1..HB_POLY_MAXDIM for
                          POLYNOMIAL); ignored by LOWRANK_SPIKES */
@@ -110,6 +129,9 @@ typedef struct {
   int32_t diag_svd_storage; /* diagnostics: 0 default (the small SVD's
                           matrices in LDS when they fit); 1 keep them in HBM;
                           2 behaves as 0 */
+  int32_t selector;    /* hb_selector; 0 (greedy QRCP) for a zeroed struct */
+  double select_f;     /* HB_SEL_STRONG: swap threshold, finite and > 1
+                          (HB_EINVAL otherwise); ignored by HB_SEL_QRCP */
 } hb_params;
 
 typedef struct hb_result hb_result; /* opaque */
@@ -150,6 +172,7 @@ typedef struct {
                                 R^H 4 phi p k q, and 4 phi p q (q - 1) per
                                 Jacobi sweep, q = min(p, k) */
   int32_t svd_launches, qr_launches;
+  int64_t select_swaps;      /* swaps made by HB_SEL_STRONG over all leaves */
 } hb_stats;
 
 /*

@@ -38,8 +38,8 @@ pivots, d_k, nu, mu, the trailing norms of the row picks (sel_I) and of the
 column picks that chose the next block (sel_J), and the whole blocks I_k,
 J_k with the pivot order of QR(W_k, eps) (Iblock, Jblock, piv), which is
 what a replay with frozen pivots needs; with the strong selector also the
-swaps and decision margins of both selections (swaps_I, margin_I, swaps_J,
-margin_J).
+swaps and decision margins of both selections (swaps_I, margin_I, flip_I,
+swaps_J, margin_J, flip_J).
 """
 from __future__ import annotations
 
@@ -107,13 +107,14 @@ class LeafResult:
 def _select(M: np.ndarray, d: int, selector: int, f: float):
     """Pivots of the d-pick selection of eqs. (6)-(7) on panel M, the QRCP
     trailing norms of the greedy picks, the swaps made and the decision
-    margin: selector 0 is greedy QRCP (the paper's choice), 1 the strong
-    rank-revealing selection (QRCP then Gu-Eisenstat swaps, threshold f)."""
+    measures (margin, flip) of strong_select: selector 0 is greedy QRCP (the
+    paper's choice), 1 the strong rank-revealing selection (QRCP then
+    Gu-Eisenstat swaps, threshold f)."""
     if selector == 0:
         res = qrcp(M, d)
-        return res.piv, np.abs(res.tdiag), 0, np.inf
+        return res.piv, np.abs(res.tdiag), 0, (np.inf, np.inf)
     ss = strong_select(M, d, f)
-    return ss.piv, np.abs(ss.qr.tdiag), ss.swaps, ss.margin
+    return ss.piv, np.abs(ss.qr.tdiag), ss.swaps, (ss.margin, ss.flip)
 
 
 def baca_leaf(block, m0: int, n0: int, d: int, eps: float, J1: np.ndarray,
@@ -170,8 +171,8 @@ def baca_leaf(block, m0: int, n0: int, d: int, eps: float, J1: np.ndarray,
                                   dk=0, nu=0.0, mu=float(np.sqrt(mu2)), r=r,
                                   sel_I=normsI, sel_J=np.zeros(0),
                                   Iblock=I.copy(), Jblock=J.copy(), piv=full.piv.copy(),
-                                  swaps_I=swI, margin_I=marI, swaps_J=0,
-                                  margin_J=np.inf))
+                                  swaps_I=swI, margin_I=marI[0], flip_I=marI[1],
+                                  swaps_J=0, margin_J=np.inf, flip_J=np.inf))
             break
         jbar = full.piv[:dk]
         Uk = C[:, jbar]
@@ -193,8 +194,8 @@ def baca_leaf(block, m0: int, n0: int, d: int, eps: float, J1: np.ndarray,
             iters.append(dict(I=I[:dk].copy(), J=J[jbar].copy(), dk=dk, nu=nu,
                               mu=mu, r=U.shape[1], sel_I=normsI,
                               sel_J=np.zeros(0), Iblock=I.copy(), Jblock=J.copy(),
-                              piv=full.piv.copy(), swaps_I=swI, margin_I=marI,
-                              swaps_J=0, margin_J=np.inf))
+                              piv=full.piv.copy(), swaps_I=swI, margin_I=marI[0],
+                              flip_I=marI[1], swaps_J=0, margin_J=np.inf, flip_J=np.inf))
         # (8) stopping test, then the next column block (eq. (7))
         if nu < eps * mu or Pc.size == 0 or U.shape[1] >= rmax:
             break
@@ -202,7 +203,8 @@ def baca_leaf(block, m0: int, n0: int, d: int, eps: float, J1: np.ndarray,
         if record:
             iters[-1]["sel_J"] = normsJ
             iters[-1]["swaps_J"] = swJ
-            iters[-1]["margin_J"] = marJ
+            iters[-1]["margin_J"] = marJ[0]
+            iters[-1]["flip_J"] = marJ[1]
         ops["qrcp_flops"] += 4 * phi * I.size * Pc.size * pivJ.size
         J = Pc[pivJ]
     return LeafResult(U, V, iters, ops)

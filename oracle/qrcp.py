@@ -138,16 +138,26 @@ def qrcp(M: np.ndarray, kmax: int) -> QRCPResult:
 
 
 class StrongSelection:
-    """Picks of ``strong_select``, the swaps made, and the smallest relative
-    margin of its decisions: (|W|max - f) / f or (f - |W|max) / f at every
-    round, and (|W|max - runner-up) / |W|max at every swap.  A margin near
-    the rounding level means another correct run may decide otherwise."""
+    """Picks of ``strong_select``, the swaps made, and two measures of how
+    firmly its decisions were taken (instrumentation only):
 
-    def __init__(self, piv, qr, swaps, margin):
+    * margin: the smallest relative margin, (|W|max - f) / f or
+      (f - |W|max) / f at every round and (|W|max - runner-up) / |W|max at
+      every swap;
+    * flip: the smallest panel perturbation that could reverse a decision,
+      estimated per round as delta * sigma_min(M_S) / (1 + sqrt(k) |W|max),
+      delta the absolute margin of the round: a change dM of the panel
+      changes W by about M_S^+ (dM_rest - dM_S W).
+
+    A decision whose flip is near the rounding of the panel's entries may go
+    the other way in another correct run."""
+
+    def __init__(self, piv, qr, swaps, margin, flip):
         self.piv = piv
         self.qr = qr
         self.swaps = swaps
         self.margin = margin
+        self.flip = flip
 
 
 def strong_select(M: np.ndarray, kmax: int, f: float) -> StrongSelection:
@@ -160,7 +170,7 @@ def strong_select(M: np.ndarray, kmax: int, f: float) -> StrongSelection:
     k = res.nz
     q = M.shape[1]
     S = piv[:k]
-    swaps, margin = 0, np.inf
+    swaps, margin, flip = 0, np.inf, np.inf
     while k > 0 and swaps < SWAP_CAP * k:
         chosen = set(S)
         rest = np.array([c for c in range(q) if c not in chosen], dtype=np.int64)
@@ -174,13 +184,17 @@ def strong_select(M: np.ndarray, kmax: int, f: float) -> StrongSelection:
         pos = int(np.argmax(flat))
         best = float(flat[pos])
         j, i = divmod(pos, k)
+        smin = float(np.linalg.svd(M[:, S], compute_uv=False)[-1])
+        scale = smin / (1.0 + np.sqrt(k) * best)
         if best <= f:
             margin = min(margin, (f - best) / f)
+            flip = min(flip, (f - best) * scale)
             break
         second = float(np.max(np.delete(flat, pos))) if flat.size > 1 else 0.0
         margin = min(margin, (best - f) / f, (best - second) / best)
+        flip = min(flip, min(best - f, best - second) * scale)
         S[i] = int(rest[j])
         swaps += 1
     chosen = set(S)
     noise = [c for c in range(q) if c not in chosen][:len(piv) - k]
-    return StrongSelection(np.array(S + noise, dtype=np.int64), res, swaps, margin)
+    return StrongSelection(np.array(S + noise, dtype=np.int64), res, swaps, margin, flip)

@@ -16,14 +16,15 @@ import numpy as np
 from . import _binding as B
 from ._binding import (HB_K_EFIE2D, HB_K_GAUSS, HB_K_HELMHOLTZ3D,  # noqa: F401
                        HB_K_LAPLACE, HB_K_LOWRANK_SPIKES, HB_K_POLYNOMIAL, HB_PREC_FP64,
-                       HB_PREC_MIXED, HBACAError, HbParams, HbStats, load)
+                       HB_PREC_MIXED, HB_SEL_QRCP, HB_SEL_STRONG, HBACAError, HbParams,
+                       HbStats, load)
 
 __all__ = ["compress", "compress_batched", "Result", "operator", "gaussian_operator",
            "hodlr_build", "Hodlr", "autotune",
            "partition", "require_gpu", "params", "load",
            "HBACAError", "HB_K_GAUSS", "HB_K_LAPLACE", "HB_K_HELMHOLTZ3D",
            "HB_K_LOWRANK_SPIKES", "HB_K_EFIE2D", "HB_K_POLYNOMIAL", "HB_PREC_FP64",
-           "HB_PREC_MIXED"]
+           "HB_PREC_MIXED", "HB_SEL_QRCP", "HB_SEL_STRONG"]
 
 
 def partition(m: int, n: int, leaf: int, d: int, seed: int):
@@ -62,11 +63,12 @@ def _stream():
 
 def params(dim=3, h=1.0, gauss_c=1.0, wavenumber=0.0, seed=0, rank_cap=0, record_tape=0,
            stop_after=0, G1=None, G2=None, spike_lin=None, spike_val=None, diag_panel=0,
-           diag_svd_storage=0, precision=B.HB_PREC_FP64) -> dict:
+           diag_svd_storage=0, precision=B.HB_PREC_FP64, selector=0, select_f=2.0) -> dict:
     return dict(dim=dim, h=h, gauss_c=gauss_c, wavenumber=wavenumber, seed=seed,
                 rank_cap=rank_cap, record_tape=record_tape, stop_after=stop_after, G1=G1,
                 G2=G2, spike_lin=spike_lin, spike_val=spike_val, diag_panel=diag_panel,
-                diag_svd_storage=diag_svd_storage, precision=precision)
+                diag_svd_storage=diag_svd_storage, precision=precision, selector=selector,
+                select_f=select_f)
 
 
 def _hb_params(p: dict, keep: list) -> HbParams:
@@ -94,6 +96,8 @@ def _hb_params(p: dict, keep: list) -> HbParams:
     hp.stop_after = int(p.get("stop_after", 0))
     hp.diag_panel = int(p.get("diag_panel", 0))
     hp.diag_svd_storage = int(p.get("diag_svd_storage", 0))
+    hp.selector = int(p.get("selector", 0))
+    hp.select_f = float(p.get("select_f", 2.0))
     return hp
 
 

@@ -18,6 +18,7 @@ HB_OK, HB_EINVAL, HB_ENOMEM, HB_EDEVICE, HB_ERANKCAP, HB_ENONFINITE, HB_EUNSUPPO
 HB_K_GAUSS, HB_K_LAPLACE, HB_K_HELMHOLTZ3D, HB_K_LOWRANK_SPIKES = 1, 2, 3, 4
 HB_K_EFIE2D, HB_K_POLYNOMIAL = 5, 6
 HB_PREC_FP64, HB_PREC_MIXED = 0, 1
+HB_SEL_QRCP, HB_SEL_STRONG = 0, 1
 
 EXPORTED = (
     "hbaca_compress", "hbaca_compress_batched", "hb_result_nblocks", "hb_result_rank",
@@ -50,6 +51,8 @@ class HbParams(C.Structure):
         ("stop_after", C.c_int32),
         ("diag_panel", C.c_int32),
         ("diag_svd_storage", C.c_int32),
+        ("selector", C.c_int32),
+        ("select_f", C.c_double),
     ]
 
 
@@ -83,6 +86,7 @@ class HbStats(C.Structure):
         ("svd_flops", C.c_double),
         ("svd_launches", C.c_int32),
         ("qr_launches", C.c_int32),
+        ("select_swaps", C.c_int64),
     ]
 
     def as_dict(self):

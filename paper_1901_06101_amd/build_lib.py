@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhbaca.so")
-SOURCES = ["hb_baca.hip", "hb_merge.hip", "hb_adjoint.hip", "hb_api.hip"]
+SOURCES = ["hb_baca.hip", "hb_baca_strong.hip", "hb_merge.hip", "hb_adjoint.hip", "hb_api.hip"]
 ARCH = os.environ.get("HB_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

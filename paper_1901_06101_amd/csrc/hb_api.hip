@@ -1705,6 +1705,9 @@ static hb_status validate(const CallSpec& c) {
   if (p->diag_panel < 0 || p->diag_panel > 128 || p->diag_svd_storage < 0 ||
       p->diag_svd_storage > 2)
     return HB_EINVAL;
+  if (p->selector != HB_SEL_QRCP && p->selector != HB_SEL_STRONG) return HB_EINVAL;
+  if (p->selector == HB_SEL_STRONG && !(std::isfinite(p->select_f) && p->select_f > 1.0))
+    return HB_EINVAL;
   for (size_t b = 0; b < c.rcnt.size(); ++b) {
     if (c.rcnt[b] < 1 || c.ccnt[b] < 1 || c.roff[b] < 0 || c.coff[b] < 0) return HB_EINVAL;
     if (c.roff[b] + c.rcnt[b] > c.nx || c.coff[b] + c.ccnt[b] > c.ny) return HB_EINVAL;
@@ -1917,6 +1920,8 @@ static hb_status run(const CallSpec& c, hb_result** out) {
   A.eps = c.tol;
   A.nleaves = (int32_t)nleaves;
   A.queue = tmp.get<int32_t>(2);
+  A.selector = P.selector;
+  A.select_f = P.select_f;
   HB_HIP(hipEventRecord(ev[1], st));
   HB_LAUNCH(hbk::baca_launch(bscalar, dmax, rpt_v, A, st));
   HB_HIP(hipEventRecord(ev[2], st));
@@ -1968,6 +1973,7 @@ static hb_status run(const CallSpec& c, hb_result** out) {
     S.leaf_rank_baca_max = std::max(S.leaf_rank_baca_max, lf.rank_baca);
     S.iters_max = std::max(S.iters_max, lf.iters);
     S.iters_total += lf.iters;
+    S.select_swaps += bo[s].swaps;
   }
   // algorithmic counters of the residual passes (iteration k streams r_{k-1}
   // columns of U and V once and evaluates d (m0 + n0) entries)

@@ -27,7 +27,7 @@ struct BacaOutDev {
   int32_t rank;
   int32_t iters;
   int32_t status;  // 0 ok, 1 factor capacity exhausted, 2 a pivot outside its candidate range
-  int32_t pad;
+  int32_t swaps;   // swaps made by the strong rank-revealing selection
   double mu;
 };
 
@@ -55,12 +55,18 @@ struct BacaArgs {
   // work queue of the persistent launch: the next leaf index to take (the
   // leaves are ordered largest first); zero before the launch
   int32_t* queue;
+  // pivot selection of eqs. (6)-(7): 0 greedy QRCP, 1 QRCP then strong
+  // rank-revealing swaps while a coefficient exceeds select_f
+  int32_t selector;
+  double select_f;
 };
 
 // host launchers (defined in the .hip files)
 namespace hbk {
 int baca_launch(int scalar /*0 f64, 1 c128, 2 f32*/, int dmax, int rpt, const BacaArgs& a,
                 hipStream_t st);
+// the same with the strong rank-revealing selection (a.selector == 1)
+int baca_launch_strong(int scalar, int dmax, int rpt, const BacaArgs& a, hipStream_t st);
 // one launch of the adjoint tasks of one kind (AdjTaskKind), tasks
 // base .. base + count - 1
 int adj_launch(int kind, int base, int count, const AdjArgs& a, hipStream_t st);

@@ -42,10 +42,11 @@ def run_gpu(hb, wl, **kw):
     return hb.compress(wl["entry"], p, X, Y, wl["m"], wl["n"], wl["tol"], wl["d"], wl["leaf"])
 
 
-def run_oracle(wl, keep_leaf_factors=False):
+def run_oracle(wl, keep_leaf_factors=False, selector=0, select_f=2.0):
     src = oracle.EntrySource(wl)
     return src, oracle.hbaca(src, wl["m"], wl["n"], wl["tol"], wl["d"], wl["leaf"], wl["seed"],
-                             keep_leaf_factors=keep_leaf_factors)
+                             keep_leaf_factors=keep_leaf_factors, selector=selector,
+                             select_f=select_f)
 
 
 def factors_np(res, block=0):
@@ -79,6 +80,8 @@ NU_DECIDED = 1e-7
 PICK_FLOOR = 1e-11
 MU_RTOL = 1e-9
 NU_RTOL = 1e-6
+SWAP_DECIDED = 1e-6
+SWAP_FLIP = 1e-15
 
 
 def _determined(norms):
@@ -106,14 +109,30 @@ def determined_iterations(oinfo):
     (among the rows I_k(1:d_k), or the columns that made J_k) whose trailing
     norm is below PICK_FLOOR * mu: rounding of order 1e-16 mu then moves
     that norm by 1e-5 of itself or more, enough to reorder close rows or
-    columns (neighbouring nodes on the EFIE2D strips).  An iteration with
-    d_k = 0 ends the leaf and is counted like the others."""
+    columns (neighbouring nodes on the EFIE2D strips).  With the strong
+    rank-revealing selector the comparison also stops at an iteration whose
+    row selection, or the column selection that made J_k, took a swap
+    decision within SWAP_DECIDED (relative) of the threshold f or of the
+    runner-up coefficient, or one that a change of the panel's entries by
+    less than SWAP_FLIP * mu could reverse (the oracle's flip estimate:
+    the margin times the smallest singular value of the chosen columns):
+    the residual panels carry rounding of about 1e-16 mu, and graded panels
+    (the EFIE2D strips) have chosen columns with singular values far below
+    mu.  An iteration with d_k = 0 ends the leaf and is counted like the
+    others."""
     its = oinfo["iters"]
     nk = 0
     for k, it in enumerate(its):
         if not _determined(it["sel_I"]):
             break
         if k > 0 and not _determined(its[k - 1]["sel_J"]):
+            break
+        mu_k = max(it["mu"], its[k - 1]["mu"] if k else 0.0)
+        if it.get("margin_I", np.inf) < SWAP_DECIDED or \
+                it.get("flip_I", np.inf) < SWAP_FLIP * mu_k:
+            break
+        if k > 0 and (its[k - 1].get("margin_J", np.inf) < SWAP_DECIDED or
+                      its[k - 1].get("flip_J", np.inf) < SWAP_FLIP * mu_k):
             break
         if it["dk"] > 0 and it["nu"] < NU_DECIDED * max(it["mu"], 1e-300):
             break
@@ -152,6 +171,21 @@ def divergence_nu(gtape, oinfo):
     else:
         return 0.0 if len(gdk) == len(its) else float(its[-1]["nu"])
     return float(sum(x["nu"] for x in its[k:]))
+
+
+def rounding_sensitivity(wl, **kw):
+    """How far the oracle's own H-BACA result moves when its input points
+    are perturbed at the rounding level (relative 2^-52, seeded): the
+    reconstruction difference of the two oracle runs.  Two correct FP64 runs
+    that round differently cannot be expected to agree more closely than a
+    few times this; graded problems (the EFIE2D strips with large leaves)
+    amplify rounding through the truncations well past 1e-10."""
+    _, a = run_oracle(wl, **kw)
+    w2 = dict(wl)
+    rng = np.random.default_rng(12345)
+    w2["X"] = wl["X"] * (1.0 + 2.0 ** -52 * rng.standard_normal(wl["X"].shape))
+    _, b = run_oracle(w2, **kw)
+    return lowrank_diff(a.U * a.S, a.V.conj().T, b.U * b.S, b.V.conj().T)
 
 
 def parity_bar(ref_norm, diverged_nu=0.0):
@@ -199,13 +233,13 @@ def compare_tape(gtape, ginfo, oinfo):
     return None
 
 
-def check_mixed(lib, case, wl):
+def check_mixed(lib, case, wl, selector=0, select_f=2.0):
     """Mixed precision against the FP64 oracle on the same inputs: operator
     difference and error against A within 5 tol, ranks close."""
     tol = wl["tol"]
     say(f"[mixed] {case}: m={wl['m']} n={wl['n']} d={wl['d']} leaf={wl['leaf']} tol={tol}")
-    res = run_gpu(lib, wl, precision=lib.HB_PREC_MIXED)
-    src, ores = run_oracle(wl)
+    res = run_gpu(lib, wl, precision=lib.HB_PREC_MIXED, selector=selector, select_f=select_f)
+    src, ores = run_oracle(wl, selector=selector, select_f=select_f)
     U, S, Vh = factors_np(res)
     assert U.dtype == np.float64 and Vh.dtype == np.float64
     ref = recon_norm(ores.U * ores.S, ores.V.conj().T)

@@ -219,7 +219,8 @@ def test_json_line_contract_with_a_stand_in_library(monkeypatch, capsys):
     monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
     monkeypatch.setattr(bench, "copy_bandwidth", lambda torch: 5000.0)
     monkeypatch.setattr(sys, "argv", ["bench.py", "--steps", "2", "--warmup", "1",
-                                      "--no-comparisons", "--no-adjoint", "--no-hodlr"])
+                                      "--no-comparisons", "--no-adjoint", "--no-hodlr",
+                                      "--no-sweep"])
     bench.main()
     lines = [s for s in capsys.readouterr().out.splitlines() if s.strip()]
     assert len(lines) == 1
@@ -286,7 +287,7 @@ def test_a_failing_headline_still_prints_the_line(monkeypatch, capsys):
                                  params=lambda **kw: kw, compress=broken)
     monkeypatch.setitem(sys.modules, "paper_1901_06101_amd", fake)
     monkeypatch.setattr(workloads, "make_config", lambda name, scale=1.0: wl)
-    monkeypatch.setattr(sys, "argv", ["bench.py", "--no-comparisons", "--no-adjoint", "--no-hodlr",
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--no-comparisons", "--no-adjoint", "--no-hodlr", "--no-sweep",
                                       "--no-cpu-baseline"])
     bench.main()
     lines = [s for s in capsys.readouterr().out.splitlines() if s.strip()]
