@@ -126,9 +126,13 @@ typedef struct {
   int32_t diag_panel;  /* diagnostics: 0 default; > 0 merges wider than this
                           many columns use the column-panel QR with panels of
                           this width (1..128 real, 1..64 complex) */
-  int32_t diag_svd_storage; /* diagnostics: 0 default (the small SVD's
-                          matrices in LDS when they fit); 1 keep them in HBM;
-                          2 behaves as 0 */
+  int32_t diag_svd_storage; /* diagnostics: 0 default (small batches of
+                          wide matrices on several workgroups each, otherwise
+                          one workgroup per matrix with its matrices in LDS
+                          when they fit); 1 one workgroup, matrices in HBM;
+                          2 one workgroup, in LDS when they fit; 3 several
+                          workgroups wherever the shape allows (p >= k,
+                          p <= 512), else as 2 */
   int32_t selector;    /* hb_selector; 0 (greedy QRCP) for a zeroed struct */
   double select_f;     /* HB_SEL_STRONG: swap threshold, finite and > 1
                           (HB_EINVAL otherwise); ignored by HB_SEL_QRCP */

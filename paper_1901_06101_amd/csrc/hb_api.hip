@@ -964,22 +964,57 @@ static void run_svds(Engine& E, std::vector<SVDJobDev>& jobs, const void* store,
     sz.push_back(p * k * E.sb());
     sz.push_back(k * k * E.sb());
     sz.push_back(p * k * E.sb());   // HBM workspace (R2^H)
+    sz.push_back(p * 4);            // preconditioner row permutation
   }
   std::vector<char*> bufs = E.tmp.carve(sz);
   for (size_t a = 0; a < nj; ++a) {
     SVDJobDev& J = jobs[a];
-    J.A = bufs[6 * a + 0];
-    J.S = (double*)bufs[6 * a + 1];
-    J.perm = (int32_t*)bufs[6 * a + 2];
+    J.A = bufs[7 * a + 0];
+    J.S = (double*)bufs[7 * a + 1];
+    J.perm = (int32_t*)bufs[7 * a + 2];
     J.rank = dr + 2 * a;
-    J.Xr = bufs[6 * a + 3];
-    J.Yr = bufs[6 * a + 4];
-    J.W = bufs[6 * a + 5];
+    J.Xr = bufs[7 * a + 3];
+    J.Yr = bufs[7 * a + 4];
+    J.W = bufs[7 * a + 5];
+    J.cperm = (int32_t*)bufs[7 * a + 6];
     outs[a] = SvdOut{J.Xr, J.Yr, J.S, J.rank, J.p, J.k};
   }
   SVDJobDev* dj = upload(E.tmp, jobs, E.st);
+  // The multi-workgroup SVD takes batches of a few wide matrices (the top
+  // merge levels), where one workgroup per matrix runs about k / 32 pairs
+  // after one another in every round and leaves most of the chip idle: B
+  // workgroups per matrix, when every matrix suits it (p >= k, p <= 512)
+  // and the batch is small.  Storage mode 3 forces it wherever the shape
+  // allows; 1 and 2 keep one workgroup per matrix.
+  int wideB = 0;
+  if (E.svd_storage == 0 || E.svd_storage == 3) {
+    for (size_t a = 0; a < nj; ++a) {
+      const int b = hbk::svd_wide_blocks(E.scalar, jobs[a].p, jobs[a].k);
+      if (b == 0) {
+        wideB = 0;
+        break;
+      }
+      wideB = std::max(wideB, b);
+    }
+    // automatic: only matrices wider than 160 columns (below that one
+    // workgroup's rounds cost about as much as the rounds and grid
+    // synchronisations of several), and at most 256 workgroups
+    if (E.svd_storage == 0 && ((int64_t)nj * wideB > 256 || kmax <= 160)) wideB = 0;
+    if (wideB > 0 && !hbk::svd_wide_fits(E.scalar, (int)nj, wideB, pmax)) wideB = 0;
+  }
   hipEvent_t t0 = E.clock.begin(E.st);
-  HB_LAUNCH(hbk::svd_launch(E.scalar, dj, (int)nj, kmax, pmax, store, alpha, E.eps, E.st, E.svd_storage));
+  const int storage = E.svd_storage == 3 ? 2 : E.svd_storage;
+  if (wideB > 0) {
+    // the preconditioner on one workgroup per matrix, then the sweeps on B
+    void* work = E.tmp.alloc(hbk::svd_wide_work_bytes((int)nj, wideB));
+    HB_LAUNCH(hbk::svd_launch(E.scalar, dj, (int)nj, kmax, pmax, store, alpha, E.eps, E.st,
+                              storage, true));
+    HB_LAUNCH(hbk::svd_wide_launch(E.scalar, dj, (int)nj, wideB, pmax, store, alpha, E.eps, work,
+                                   E.st));
+  } else {
+    HB_LAUNCH(hbk::svd_launch(E.scalar, dj, (int)nj, kmax, pmax, store, alpha, E.eps, E.st,
+                              storage));
+  }
   E.clock.end(KC_SVD, t0, E.st);
   std::vector<int32_t> rh(2 * nj);
   HB_HIP(hipMemcpyAsync(rh.data(), dr, 2 * nj * sizeof(int32_t), hipMemcpyDeviceToHost, E.st));
@@ -1703,7 +1738,7 @@ static hb_status validate(const CallSpec& c) {
   if (p->stop_after < 0 || p->stop_after > 2 + 2 * 30 || p->rank_cap < 0) return HB_EINVAL;
   if (p->record_tape < 0 || p->record_tape > 2) return HB_EINVAL;
   if (p->diag_panel < 0 || p->diag_panel > 128 || p->diag_svd_storage < 0 ||
-      p->diag_svd_storage > 2)
+      p->diag_svd_storage > 3)
     return HB_EINVAL;
   if (p->selector != HB_SEL_QRCP && p->selector != HB_SEL_STRONG) return HB_EINVAL;
   if (p->selector == HB_SEL_STRONG && !(std::isfinite(p->select_f) && p->select_f > 1.0))

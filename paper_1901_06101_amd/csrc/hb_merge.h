@@ -89,6 +89,8 @@ struct SVDJobDev {
   void* Xr;        // p x k output: left singular vectors, sorted (ld p)
   void* Yr;        // k x k output: first r columns = right singular vectors
                    // R^H X_r diag(1/S_r) (ld k)
+  int32_t* cperm;  // p ints: the row permutation of the preconditioner, kept
+                   // for the multi-workgroup Jacobi (may be null otherwise)
 };
 
 // Batched device-to-device copies (one workgroup per entry).
@@ -156,7 +158,7 @@ int tsqr_apply_launch(int scalar, int kmax, const QRApplyDev* jobs_dev, int njob
                       const void* store, const double* beta, hipStream_t st);
 int svd_launch(int scalar, const SVDJobDev* jobs_dev, int njobs, int kmax_batch, int pmax_batch,
                const void* store, const void* alpha, double eps, hipStream_t st,
-               int force_storage = 0);
+               int force_storage = 0, bool precond_only = false);
 int block_gemm_launch(int scalar, const BlockGemmDev* jobs_dev, int njobs, int max_rows,
                       int max_r, hipStream_t st);
 int tsqr_applyh_launch(int scalar, int kmax, const QRApplyHDev* jobs_dev, int njobs,
@@ -164,6 +166,16 @@ int tsqr_applyh_launch(int scalar, int kmax, const QRApplyHDev* jobs_dev, int nj
 int concat_launch(int scalar, const ConcatDev* jobs_dev, int njobs, int64_t max_m, int max_k,
                   hipStream_t st);
 int rrh_launch(int scalar, const RRhDev* jobs_dev, int njobs, int64_t max_entries, hipStream_t st);
+// Multi-workgroup Jacobi SVD (cooperative launch) of jobs with p >= k, after
+// svd_launch(..., precond_only = true) has left each job's preconditioned
+// W = R2^H in its W workspace and the row permutation in cperm: workgroups
+// per matrix (0: not suited), whether the grid can be co-resident,
+// workspace bytes, and the launch (-2: not co-resident).
+int svd_wide_blocks(int scalar, int p, int k);
+bool svd_wide_fits(int scalar, int njobs, int B, int pmax);
+size_t svd_wide_work_bytes(int njobs, int B);
+int svd_wide_launch(int scalar, const SVDJobDev* jobs_dev, int njobs, int B, int pmax,
+                    const void* store, const void* alpha, double eps, void* work, hipStream_t st);
 int tsqr_mc(int scalar, int kmax);
 int tsqr_autotune(hipStream_t st, int* table, double* us);
 int tsqr_kmax_for(int scalar, int k);

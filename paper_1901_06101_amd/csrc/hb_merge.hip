@@ -12,6 +12,8 @@
 #include "hb_common.h"
 #include "hb_merge.h"
 
+#include <hip/hip_cooperative_groups.h>
+
 #include <vector>
 
 #include <algorithm>
@@ -644,7 +646,8 @@ __host__ __device__ inline size_t svd_aux_bytes(int p, int k) {
 template <typename T, bool INLDS>
 __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict__ jobs,
                                                      const T* __restrict__ store,
-                                                     const T* __restrict__ alpha, double eps) {
+                                                     const T* __restrict__ alpha, double eps,
+                                                     int precond_only) {
   const SVDJobDev Jb = jobs[blockIdx.x];
   const int p = Jb.p, k = Jb.k, tid = threadIdx.x;
   const int q = p < k ? p : k;
@@ -800,6 +803,11 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
     const int i = e % p, a = e / p;
     Wg[e] = i >= a ? sc_conj(B[(int64_t)cfin[i] * ldb + a]) : sc_zero<T>();
   }
+  if (precond_only) {
+    // the multi-workgroup Jacobi takes over from W and the permutation
+    for (int i = tid; i < p; i += SVD_NT) Jb.cperm[i] = cfin[i];
+    return;
+  }
   __syncthreads();
   if (INLDS) {
     for (int e = tid; e < p * q; e += SVD_NT) W[(int64_t)(e / p) * ldw + (e % p)] = Wg[e];
@@ -907,6 +915,262 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
     for (int t = gl; t <= tmax; t += G) sc_cfma(acc, Rat(t, i), x[t]);
     acc = group_sum_sc<G, T>(acc);
     if (gl == 0) Yr[(int64_t)pos * k + i] = sc_scale(acc, 1.0 / sN[pos]);
+  }
+}
+
+// ------------------------------------------- multi-workgroup Jacobi SVD ---
+// The same SVD for a few large R (the top merge levels), with the Jacobi
+// sweeps spread over B workgroups per matrix in one cooperative launch.  The
+// single-workgroup kernel first computes the preconditioned W = R2^H (the
+// QRCP of R^H, p x q with q = k here since p >= k) and its row permutation;
+// this kernel runs one-sided Jacobi on the k columns of W, cut into 2B
+// blocks of NB columns.  A sweep is 2B - 1 rounds of the round-robin
+// tournament over the blocks; in a round each workgroup loads its two blocks
+// into LDS, rotates the column pairs across them (in round 0 also the pairs
+// inside each block), writes them back, and the grid synchronises.  Every
+// column pair meets once per sweep; sweeps end when a whole sweep rotated
+// nothing.  The rotation rule, tolerance and rounding-level cut-off are those
+// of the single-workgroup rounds, and so are the outputs: X = P U from the
+// normalised columns, Y_r = R^H X_r / S_r.
+constexpr int WS_NT = 512;
+
+template <typename T> struct WideCfg;
+template <> struct WideCfg<double> { static constexpr int NB = 16; };   // 32 lanes per pair
+template <> struct WideCfg<hb_cplx> { static constexpr int NB = 8; };   // 64 lanes per pair
+constexpr int WS_PMAX = 512;
+
+// Rotates the column pair (ca, cb) of the LDS block L (column stride ldl)
+// with G lanes, each holding EPL entries in registers.  Returns true (in
+// every lane of the group) when the pair was rotated.
+template <typename T, int G, int EPL>
+__device__ __forceinline__ bool wide_pair(T* L, int ldl, int p, int ca, int cb, int gl, double tol2,
+                                          double negl) {
+  T* xa = L + (int64_t)ca * ldl;
+  T* xb = L + (int64_t)cb * ldl;
+  T u[EPL], v[EPL];
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    const int i = gl + e * G;
+    const int ic = i < p ? i : p - 1;
+    const T uu = xa[ic], vv = xb[ic];
+    u[e] = i < p ? uu : sc_zero<T>();
+    v[e] = i < p ? vv : sc_zero<T>();
+  }
+  T g = sc_zero<T>();
+  double al = 0.0, bt = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    sc_cfma(g, u[e], v[e]);
+    al += sc_abs2(u[e]);
+    bt += sc_abs2(v[e]);
+  }
+  g = group_sum_sc<G, T>(g);
+  al = group_sum<G>(al);
+  bt = group_sum<G>(bt);
+  const double g2 = sc_abs2(g);
+  if (!(al > negl && bt > negl && g2 > tol2 * al * bt)) return false;
+  const double ag = sqrt(g2);
+  const double iag = 1.0 / ag;
+  const T ph = sc_scale(g, iag);
+  const double zeta = 0.5 * (bt - al) * iag;
+  const double az = fabs(zeta);
+  double tt = az > 1.0e150 ? 0.5 / az : 1.0 / (az + sqrt(1.0 + az * az));
+  if (zeta < 0.0) tt = -tt;
+  const double c = rsqrt(1.0 + tt * tt), sn = c * tt;
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    const int i = gl + e * G;
+    const T vv = sc_mulc(v[e], ph);  // y * conj(phase)
+    const T na = sc_sub(sc_scale(u[e], c), sc_scale(vv, sn));
+    const T nb = sc_add(sc_scale(u[e], sn), sc_scale(vv, c));
+    if (i < p) {
+      xa[i] = na;
+      xb[i] = nb;
+    }
+  }
+  return true;
+}
+
+// jobs[j] runs on workgroups j * B .. j * B + B - 1.  work: 3 ints of sweep
+// flags (zero on entry) followed by njobs * B doubles of partial norms.
+template <typename T>
+__global__ __launch_bounds__(WS_NT) void svd_wide_kernel(const SVDJobDev* __restrict__ jobs, int B,
+                                                         const T* __restrict__ store,
+                                                         const T* __restrict__ alpha, double eps,
+                                                         int* __restrict__ flags,
+                                                         double* __restrict__ parts) {
+  namespace cg = cooperative_groups;
+  constexpr int NB = WideCfg<T>::NB;
+  constexpr int G = WS_NT / NB;
+  constexpr int EPL = (WS_PMAX + G - 1) / G;
+  const cg::grid_group grid = cg::this_grid();
+  const int job = blockIdx.x / B, w = blockIdx.x % B;
+  const SVDJobDev Jb = jobs[job];
+  const int p = Jb.p, k = Jb.k, tid = threadIdx.x;
+  const int grp = tid / G, gl = tid % G;
+  extern __shared__ unsigned char smem_raw[];
+  T* L = (T*)smem_raw;  // 2 NB columns of p entries
+  const int ldl = p;
+  __shared__ int sRotW;
+  __shared__ double sPart[WS_NT / 64];
+  __shared__ int sR;
+  T* M = (T*)Jb.W;  // W = R2^H, p x k, ld p (rotated in place)
+  QRNodeDev N;
+  N.store = Jb.store;
+  N.ab = Jb.ab;
+  auto Rat = [&](int i, int j) -> T {
+    return Jb.from_node ? node_R<T>(store, alpha, N, i, j) : ((const T*)Jb.R)[(int64_t)j * p + i];
+  };
+  // ---- the partial Frobenius norm of W (columns w, w + B, ...)
+  double f2 = 0.0;
+  for (int j = w; j < k; j += B)
+    for (int i = tid; i < p; i += WS_NT) f2 += sc_abs2(M[(int64_t)j * p + i]);
+  f2 = wave_sum(f2);
+  if ((tid & 63) == 0) sPart[tid >> 6] = f2;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int q = 0; q < WS_NT / 64; ++q) s += sPart[q];
+    parts[blockIdx.x] = s;
+    sRotW = 0;
+  }
+  grid.sync();
+  // the same sum in every workgroup of the job (fixed order: deterministic)
+  f2 = 0.0;
+  for (int q = 0; q < B; ++q) f2 += parts[job * B + q];
+  const double negl = 1.0e-32 * (double)(p > 1 ? p : 1) * f2;
+  const double tol = 4.0e-16 * (p > 4 ? (double)p : 4.0);
+  const double tol2 = tol * tol;
+  const int nblk = 2 * B, R1 = nblk - 1;
+  int sweep = 0;
+  for (; sweep < 60; ++sweep) {
+    if (blockIdx.x == 0 && tid == 0) flags[(sweep + 1) % 3] = 0;
+    for (int t = 0; t < R1; ++t) {
+      // the round-robin pairing of the blocks (block nblk - 1 stays put)
+      int ba, bb;
+      if (w == 0) {
+        ba = t;
+        bb = nblk - 1;
+      } else {
+        ba = (t + w) % R1;
+        bb = (t - w + R1) % R1;
+      }
+      // local column c < NB: block ba, else block bb; columns past k load
+      // as zero and never rotate (their norm is not above negl)
+      for (int e = tid; e < 2 * NB * p; e += WS_NT) {
+        const int c = e / p, i = e % p;
+        const int gc = (c < NB ? ba * NB + c : bb * NB + c - NB);
+        L[(int64_t)c * ldl + i] = gc < k ? M[(int64_t)gc * p + i] : sc_zero<T>();
+      }
+      __syncthreads();
+      bool rot = false;
+      if (t == 0) {
+        // every pair of the 2 NB local columns (circle method)
+        constexpr int K = 2 * NB;
+        for (int u = 0; u < K - 1; ++u) {
+          int a, b;
+          if (grp == 0) {
+            a = 0;
+            b = 1 + (u % (K - 1));
+          } else {
+            a = 1 + (u + grp) % (K - 1);
+            b = 1 + (u - grp + (K - 1)) % (K - 1);
+          }
+          rot |= wide_pair<T, G, EPL>(L, ldl, p, a, b, gl, tol2, negl);
+          __syncthreads();
+        }
+      } else {
+        // the pairs across the two blocks
+        for (int u = 0; u < NB; ++u) {
+          rot |= wide_pair<T, G, EPL>(L, ldl, p, grp, NB + (grp + u) % NB, gl, tol2, negl);
+          __syncthreads();
+        }
+      }
+      if (rot && gl == 0) sRotW = 1;
+      for (int e = tid; e < 2 * NB * p; e += WS_NT) {
+        const int c = e / p, i = e % p;
+        const int gc = (c < NB ? ba * NB + c : bb * NB + c - NB);
+        if (gc < k) M[(int64_t)gc * p + i] = L[(int64_t)c * ldl + i];
+      }
+      __syncthreads();
+      if (tid == 0 && sRotW) {
+        atomicAdd(&flags[sweep % 3], 1);
+        sRotW = 0;
+      }
+      grid.sync();
+    }
+    const int any = __atomic_load_n(&flags[sweep % 3], __ATOMIC_RELAXED);
+    if (any == 0) break;
+  }
+  // ---- singular values (column norms) sorted descending, the eps-rank:
+  // workgroup 0 of the job
+  __shared__ double sN[WS_PMAX];
+  __shared__ int sPerm[WS_PMAX];
+  if (w == 0) {
+    double* sNrm = (double*)smem_raw;  // k norms (the LDS block is free now)
+    for (int j = grp; j < k; j += NB) {
+      const T* x = M + (int64_t)j * p;
+      double s2 = 0.0;
+      for (int i = gl; i < p; i += G) s2 += sc_abs2(x[i]);
+      s2 = group_sum<G>(s2);
+      if (gl == 0) sNrm[j] = (s2 == s2 && s2 <= 1.0e300) ? sqrt(s2) : 0.0;
+    }
+    __syncthreads();
+    for (int j = tid; j < k; j += WS_NT) {
+      const double sj = sNrm[j];
+      int pos = 0;
+      for (int i = 0; i < k; ++i) {
+        const double si = sNrm[i];
+        if (si > sj || (si == sj && i < j)) ++pos;
+      }
+      sPerm[pos] = j;
+      sN[pos] = sj;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double s1 = k > 0 ? sN[0] : 0.0;
+      int r = 0;
+      if (s1 > 0.0)
+        while (r < k && sN[r] >= eps * s1) ++r;
+      Jb.rank[0] = r;
+      Jb.rank[1] = sweep + 1;
+    }
+    for (int j = tid; j < k; j += WS_NT) {
+      Jb.S[j] = sN[j];
+      Jb.perm[j] = sPerm[j];
+    }
+  }
+  grid.sync();
+  // ---- X = P U: X(cperm[i], pos) = W(i, perm[pos]) / S(pos);
+  // Y_r = R^H X_r / S_r; the output columns are shared out over the job's
+  // workgroups
+  if (tid == 0) sR = Jb.rank[0];
+  for (int j = tid; j < k; j += WS_NT) {
+    sN[j] = Jb.S[j];
+    sPerm[j] = Jb.perm[j];
+  }
+  __syncthreads();
+  const int r = sR;
+  const int* cperm = Jb.cperm;
+  T* Xr = (T*)Jb.Xr;
+  for (int pos = w; pos < k; pos += B) {
+    const double sv = sN[pos];
+    const T* x = M + (int64_t)sPerm[pos] * p;
+    for (int i = tid; i < p; i += WS_NT)
+      Xr[(int64_t)pos * p + cperm[i]] = sv > 0.0 ? sc_scale(x[i], 1.0 / sv) : sc_zero<T>();
+  }
+  grid.sync();
+  T* Yr = (T*)Jb.Yr;
+  for (int pos = w; pos < r; pos += B) {
+    const double sv = sN[pos];
+    const T* x = Xr + (int64_t)pos * p;
+    for (int i = grp; i < k; i += NB) {
+      const int tmax = Jb.from_node ? (i < p - 1 ? i : p - 1) : p - 1;
+      T acc = sc_zero<T>();
+      for (int tt = gl; tt <= tmax; tt += G) sc_cfma(acc, Rat(tt, i), x[tt]);
+      acc = group_sum_sc<G, T>(acc);
+      if (gl == 0) Yr[(int64_t)pos * k + i] = sc_scale(acc, 1.0 / sv);
+    }
   }
 }
 
@@ -1177,7 +1441,7 @@ int tsqr_autotune(hipStream_t st, int* table, double* us) {
 
 int svd_launch(int scalar, const SVDJobDev* jobs, int n, int kmax_batch, int pmax_batch,
                const void* store, const void* alpha, double eps, hipStream_t st,
-               int force_storage) {
+               int force_storage, bool precond_only) {
   if (n == 0) return 0;
   if (kmax_batch > 512 || pmax_batch > 512) return -1;
   const size_t sb = scalar == 0 ? 8 : 16;
@@ -1191,7 +1455,7 @@ int svd_launch(int scalar, const SVDJobDev* jobs, int n, int kmax_batch, int pma
     if (sh > 64 * 1024)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     hipLaunchKernelGGL(kern, dim3(n), dim3(SVD_NT), sh, st, jobs, (const TT*)store, (const TT*)alpha,
-                       eps);
+                       eps, precond_only ? 1 : 0);
   };
   if (scalar == 0) {
     if (in_lds) go(svd_kernel<double, true>, 0.0);
@@ -1201,6 +1465,58 @@ int svd_launch(int scalar, const SVDJobDev* jobs, int n, int kmax_batch, int pma
     else go(svd_kernel<hb_cplx, false>, hb_cplx{});
   }
   return (int)hipGetLastError();
+}
+
+// Workgroups per matrix of the multi-workgroup SVD for a width k (0 when the
+// shape does not suit it: p < k or p > WS_PMAX, or a single block pair).
+int svd_wide_blocks(int scalar, int p, int k) {
+  const int nb = scalar == 0 ? WideCfg<double>::NB : WideCfg<hb_cplx>::NB;
+  if (p < k || p > WS_PMAX || k <= 2 * nb) return 0;
+  return (k + 2 * nb - 1) / (2 * nb);
+}
+
+// Cooperative launch of svd_wide_kernel over njobs * B workgroups.  work
+// holds 3 ints and njobs * B doubles (svd_wide_work_bytes).  Returns -2 when
+// the grid cannot be co-resident (svd_wide_fits tells beforehand), a HIP
+// error code otherwise, 0 on success.
+size_t svd_wide_work_bytes(int njobs, int B) { return 16 + (size_t)njobs * B * 8; }
+
+static const void* wide_kernel(int scalar) {
+  return scalar == 0 ? (const void*)svd_wide_kernel<double> : (const void*)svd_wide_kernel<hb_cplx>;
+}
+static size_t wide_lds(int scalar, int pmax) {
+  const int nb = scalar == 0 ? WideCfg<double>::NB : WideCfg<hb_cplx>::NB;
+  return (size_t)2 * nb * pmax * (scalar == 0 ? 8 : 16);
+}
+
+bool svd_wide_fits(int scalar, int njobs, int B, int pmax) {
+  const void* kern = wide_kernel(scalar);
+  const size_t sh = wide_lds(scalar, pmax);
+  if (sh > 64 * 1024)
+    (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WS_NT, sh) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return (int64_t)njobs * B <= (int64_t)cus * per_cu;
+}
+
+int svd_wide_launch(int scalar, const SVDJobDev* jobs, int njobs, int B, int pmax,
+                    const void* store, const void* alpha, double eps, void* work, hipStream_t st) {
+  if (njobs == 0) return 0;
+  if (!svd_wide_fits(scalar, njobs, B, pmax)) return -2;
+  const void* kern = wide_kernel(scalar);
+  const size_t sh = wide_lds(scalar, pmax);
+  int e = zero_fill_launch(work, 16, st);
+  if (e != 0) return e;
+  int* flags = (int*)work;
+  double* parts = (double*)((char*)work + 16);
+  void* args[] = {(void*)&jobs, (void*)&B, (void*)&store, (void*)&alpha, (void*)&eps,
+                  (void*)&flags, (void*)&parts};
+  return (int)hipLaunchCooperativeKernel(kern, dim3(njobs * B), dim3(WS_NT), args, sh, st);
 }
 
 int block_gemm_launch(int scalar, const BlockGemmDev* jobs, int n, int max_rows, int max_rin,

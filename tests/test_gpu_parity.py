@@ -124,15 +124,46 @@ def test_column_panel_qr_matches_oracle(lib, case, panel):
     assert diff <= 1e-10 * recon_norm(ores.U * ores.S, ores.V.conj().T)
 
 
-@pytest.mark.parametrize("storage", [1, 2])
+@pytest.mark.parametrize("storage", [1, 2, 3])
 def test_svd_storage_modes_agree(lib, storage):
-    """The small SVD gives the same result with its matrices in HBM or in LDS."""
+    """The small SVD gives the same result with its matrices in HBM or in LDS,
+    and on several workgroups per matrix."""
     wl = FULL_CASES["gauss3d_ragged"]()
     say(f"[svd storage] mode {storage}")
     a = factors_np(run_gpu(lib, wl))
     b = factors_np(run_gpu(lib, wl, diag_svd_storage=storage))
     assert a[1].size == b[1].size
     assert np.allclose(a[1], b[1], rtol=0, atol=1e-12 * a[1][0])
+
+
+WIDE_SVD_CASES = {
+    "gauss3d_ragged": lambda: G.make_gauss3d(n=1100, m=900, leaf=140, d=8, cfg=21),
+    "helmholtz_1200": lambda: G.make_helmholtz_plates(n=1200, leaf=300, cfg=2),
+    "polynomial_2000": lambda: G.make_polynomial(n=2000, leaf=250, tol=1e-4, d=8),
+    "lowrank_r90_tol1e10": lambda: _lowrank(900, 800, 90, tol=1e-10, leaf=200),
+}
+
+
+@pytest.mark.parametrize("case", sorted(WIDE_SVD_CASES))
+def test_multi_workgroup_svd_matches_oracle(lib, case):
+    """Every SVD whose shape allows it (p >= k, p <= 512, more than one block
+    pair) on several workgroups (storage mode 3): the result against the
+    oracle at the FP64 bars."""
+    wl = WIDE_SVD_CASES[case]()
+    say(f"[multi-workgroup SVD] {case}: m={wl['m']} n={wl['n']} d={wl['d']} leaf={wl['leaf']}")
+    res = run_gpu(lib, wl, diag_svd_storage=3)
+    _, ores = run_oracle(wl)
+    U, S, Vh = factors_np(res)
+    st = res.stats()
+    say(f"  rank gpu {S.size} oracle {ores.rank}; step ranks {st['step_rank_max']}; "
+        f"sweeps max {st['svd_sweeps_max']}")
+    assert max(st["step_rank_max"]) > 16  # merges wide enough for several blocks
+    assert S.size == ores.rank
+    assert np.allclose(S, ores.S, rtol=0, atol=1e-10 * ores.S[0])
+    ref = recon_norm(ores.U * ores.S, ores.V.conj().T)
+    diff = lowrank_diff(U * S, Vh, ores.U * ores.S, ores.V.conj().T)
+    say(f"  reconstruction difference {diff / ref:.2e}")
+    assert diff <= 1e-10 * ref
 
 
 def test_zero_matrix_rank_zero(lib):
