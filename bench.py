@@ -43,7 +43,7 @@ sys.path.insert(0, ROOT)
 METRIC = "H-BACA compress time at rel err\u2264tol, mixed/batched vs plain FP64; % roofline"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6  # FP64 vector (and FP64 MFMA) peak of MI355X
-EPS_DIVISORS = (1, 2, 4, 8)
+EPS_DIVISORS = (1, 1.25, 1.6, 2, 4, 8)
 
 
 def _cpu_model():

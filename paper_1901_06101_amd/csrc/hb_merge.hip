@@ -389,6 +389,11 @@ __global__ void copy_list_kernel(const CopyDev* __restrict__ jobs) {
 // normalised final columns are the left singular vectors X (orthonormal to
 // the sweep tolerance) and the kept right vectors follow as R^H X_r / S_r.
 constexpr int SVD_NT = 512;
+// A sweep whose rotations all had |a_i^H a_j| <= JAC_QUAD |a_i| |a_j| leaves
+// the columns orthogonal to about JAC_QUAD^2 (one-sided Jacobi converges
+// quadratically), far inside the sweep tolerance: the sweeps end there
+// instead of running one more sweep that would rotate nothing.
+constexpr double JAC_QUAD = 1.0e-8;
 
 template <typename T, int G>
 __device__ __forceinline__ int jacobi_rounds(T* A, int lda, int p, int k, int K, double tol, double negl,
@@ -418,7 +423,10 @@ __device__ __forceinline__ int jacobi_rounds(T* A, int lda, int p, int k, int K,
       s2 = group_sum<G>(s2);
       if (gl == 0) nrm[j] = s2;
     }
-    if (tid == 0) *sRot = 0;
+    if (tid == 0) {
+      sRot[0] = 0;
+      sRot[1] = 0;
+    }
     __syncthreads();
     for (int t = 0; t < K - 1; ++t) {
       for (int pi = grp; pi < npairs; pi += ngrp) {
@@ -500,15 +508,16 @@ __device__ __forceinline__ int jacobi_rounds(T* A, int lda, int p, int k, int K,
           if (gl == 0) {
             nrm[a] = na;
             nrm[b] = nb;
-            *sRot = 1;
+            sRot[0] = 1;
+            if (g2 > JAC_QUAD * JAC_QUAD * al * bt) sRot[1] = 1;
           }
         }
       }
       __syncthreads();
     }
-    const int rot = *sRot;
+    const int rot = sRot[0], big = sRot[1];
     __syncthreads();
-    if (!rot) break;
+    if (!rot || !big) break;
   }
   return sweep + 1;
 }
@@ -531,7 +540,10 @@ __device__ __forceinline__ int jacobi_rounds_reg(T* A, int lda, int p, int k, in
   const double tol2 = tol * tol;
   int sweep = 0;
   for (; sweep < 60; ++sweep) {
-    if (tid == 0) *sRot = 0;
+    if (tid == 0) {
+      sRot[0] = 0;
+      sRot[1] = 0;
+    }
     __syncthreads();
     for (int t = 0; t < K - 1; ++t) {
       for (int pi = grp; pi < npairs; pi += ngrp) {
@@ -592,15 +604,18 @@ __device__ __forceinline__ int jacobi_rounds_reg(T* A, int lda, int p, int k, in
                 xb[i] = nb;
               }
             }
-            if (gl == 0) *sRot = 1;
+            if (gl == 0) {
+              sRot[0] = 1;
+              if (g2 > JAC_QUAD * JAC_QUAD * al * bt) sRot[1] = 1;
+            }
           }
         }
       }
       __syncthreads();
     }
-    const int rot = *sRot;
+    const int rot = sRot[0], big = sRot[1];
     __syncthreads();
-    if (!rot) break;
+    if (!rot || !big) break;
   }
   return sweep + 1;
 }
@@ -653,7 +668,7 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
   const int q = p < k ? p : k;
   const int lane = tid & 63, wid = tid >> 6;
   extern __shared__ unsigned char smem_raw[];
-  __shared__ int sRot;
+  __shared__ int sRot[2];
   __shared__ int sR;
   __shared__ double sWv[SVD_NT / 64];
   __shared__ int sWi[SVD_NT / 64];
@@ -832,22 +847,22 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
     // register-resident rounds whenever a column fits in a group's
     // registers: 8 lanes per pair up to 128 rows, 16 up to 256, 32 up to 512
     if (p <= 8 * 4) {
-      sweeps = jacobi_rounds_reg<T, 8, 4>(W, ldw, p, q, Q, tol, negl, &sRot);
+      sweeps = jacobi_rounds_reg<T, 8, 4>(W, ldw, p, q, Q, tol, negl, sRot);
     } else if (p <= 8 * 8) {
-      sweeps = jacobi_rounds_reg<T, 8, 8>(W, ldw, p, q, Q, tol, negl, &sRot);
+      sweeps = jacobi_rounds_reg<T, 8, 8>(W, ldw, p, q, Q, tol, negl, sRot);
     } else if (p <= 8 * 16) {
-      sweeps = jacobi_rounds_reg<T, 8, 16>(W, ldw, p, q, Q, tol, negl, &sRot);
+      sweeps = jacobi_rounds_reg<T, 8, 16>(W, ldw, p, q, Q, tol, negl, sRot);
     } else if (p <= 16 * 16) {
-      sweeps = jacobi_rounds_reg<T, 16, 16>(W, ldw, p, q, Q, tol, negl, &sRot);
+      sweeps = jacobi_rounds_reg<T, 16, 16>(W, ldw, p, q, Q, tol, negl, sRot);
     } else if (p <= 32 * 16) {
-      sweeps = jacobi_rounds_reg<T, 32, 16>(W, ldw, p, q, Q, tol, negl, &sRot);
+      sweeps = jacobi_rounds_reg<T, 32, 16>(W, ldw, p, q, Q, tol, negl, sRot);
     } else {
       const int gp = p <= 16 ? 2 : (p <= 32 ? 4 : 8);
       const int gk = npairs * 8 <= SVD_NT ? 8 : (npairs * 4 <= SVD_NT ? 4 : 2);
       const int g = gp < gk ? gp : gk;
-      if (g == 8) sweeps = jacobi_rounds<T, 8>(W, ldw, p, q, Q, tol, negl, jn, &sRot);
-      else if (g == 4) sweeps = jacobi_rounds<T, 4>(W, ldw, p, q, Q, tol, negl, jn, &sRot);
-      else sweeps = jacobi_rounds<T, 2>(W, ldw, p, q, Q, tol, negl, jn, &sRot);
+      if (g == 8) sweeps = jacobi_rounds<T, 8>(W, ldw, p, q, Q, tol, negl, jn, sRot);
+      else if (g == 4) sweeps = jacobi_rounds<T, 4>(W, ldw, p, q, Q, tol, negl, jn, sRot);
+      else sweeps = jacobi_rounds<T, 2>(W, ldw, p, q, Q, tol, negl, jn, sRot);
     }
   }
   __syncthreads();
@@ -940,11 +955,12 @@ template <> struct WideCfg<hb_cplx> { static constexpr int NB = 8; };   // 64 la
 constexpr int WS_PMAX = 512;
 
 // Rotates the column pair (ca, cb) of the LDS block L (column stride ldl)
-// with G lanes, each holding EPL entries in registers.  Returns true (in
-// every lane of the group) when the pair was rotated.
+// with G lanes, each holding EPL entries in registers.  Returns (in every
+// lane of the group) 0 when the pair was not rotated, 1 when it was, 2 when
+// it was and its cosine exceeded JAC_QUAD.
 template <typename T, int G, int EPL>
-__device__ __forceinline__ bool wide_pair(T* L, int ldl, int p, int ca, int cb, int gl, double tol2,
-                                          double negl) {
+__device__ __forceinline__ int wide_pair(T* L, int ldl, int p, int ca, int cb, int gl, double tol2,
+                                         double negl) {
   T* xa = L + (int64_t)ca * ldl;
   T* xb = L + (int64_t)cb * ldl;
   T u[EPL], v[EPL];
@@ -968,7 +984,7 @@ __device__ __forceinline__ bool wide_pair(T* L, int ldl, int p, int ca, int cb, 
   al = group_sum<G>(al);
   bt = group_sum<G>(bt);
   const double g2 = sc_abs2(g);
-  if (!(al > negl && bt > negl && g2 > tol2 * al * bt)) return false;
+  if (!(al > negl && bt > negl && g2 > tol2 * al * bt)) return 0;
   const double ag = sqrt(g2);
   const double iag = 1.0 / ag;
   const T ph = sc_scale(g, iag);
@@ -988,11 +1004,12 @@ __device__ __forceinline__ bool wide_pair(T* L, int ldl, int p, int ca, int cb, 
       xb[i] = nb;
     }
   }
-  return true;
+  return g2 > JAC_QUAD * JAC_QUAD * al * bt ? 2 : 1;
 }
 
-// jobs[j] runs on workgroups j * B .. j * B + B - 1.  work: 3 ints of sweep
-// flags (zero on entry) followed by njobs * B doubles of partial norms.
+// jobs[j] runs on workgroups j * B .. j * B + B - 1.  work: 3 + 3 ints of
+// sweep flags (rotations; rotations above JAC_QUAD), zero on entry, then
+// njobs * B doubles of partial norms at byte 32.
 template <typename T>
 __global__ __launch_bounds__(WS_NT) void svd_wide_kernel(const SVDJobDev* __restrict__ jobs, int B,
                                                          const T* __restrict__ store,
@@ -1044,7 +1061,10 @@ __global__ __launch_bounds__(WS_NT) void svd_wide_kernel(const SVDJobDev* __rest
   const int nblk = 2 * B, R1 = nblk - 1;
   int sweep = 0;
   for (; sweep < 60; ++sweep) {
-    if (blockIdx.x == 0 && tid == 0) flags[(sweep + 1) % 3] = 0;
+    if (blockIdx.x == 0 && tid == 0) {
+      flags[(sweep + 1) % 3] = 0;
+      flags[3 + (sweep + 1) % 3] = 0;
+    }
     for (int t = 0; t < R1; ++t) {
       // the round-robin pairing of the blocks (block nblk - 1 stays put)
       int ba, bb;
@@ -1063,7 +1083,7 @@ __global__ __launch_bounds__(WS_NT) void svd_wide_kernel(const SVDJobDev* __rest
         L[(int64_t)c * ldl + i] = gc < k ? M[(int64_t)gc * p + i] : sc_zero<T>();
       }
       __syncthreads();
-      bool rot = false;
+      int rot = 0;
       if (t == 0) {
         // every pair of the 2 NB local columns (circle method)
         constexpr int K = 2 * NB;
@@ -1076,17 +1096,17 @@ __global__ __launch_bounds__(WS_NT) void svd_wide_kernel(const SVDJobDev* __rest
             a = 1 + (u + grp) % (K - 1);
             b = 1 + (u - grp + (K - 1)) % (K - 1);
           }
-          rot |= wide_pair<T, G, EPL>(L, ldl, p, a, b, gl, tol2, negl);
+          rot = max(rot, wide_pair<T, G, EPL>(L, ldl, p, a, b, gl, tol2, negl));
           __syncthreads();
         }
       } else {
         // the pairs across the two blocks
         for (int u = 0; u < NB; ++u) {
-          rot |= wide_pair<T, G, EPL>(L, ldl, p, grp, NB + (grp + u) % NB, gl, tol2, negl);
+          rot = max(rot, wide_pair<T, G, EPL>(L, ldl, p, grp, NB + (grp + u) % NB, gl, tol2, negl));
           __syncthreads();
         }
       }
-      if (rot && gl == 0) sRotW = 1;
+      if (rot && gl == 0) atomicMax(&sRotW, rot);
       for (int e = tid; e < 2 * NB * p; e += WS_NT) {
         const int c = e / p, i = e % p;
         const int gc = (c < NB ? ba * NB + c : bb * NB + c - NB);
@@ -1095,12 +1115,14 @@ __global__ __launch_bounds__(WS_NT) void svd_wide_kernel(const SVDJobDev* __rest
       __syncthreads();
       if (tid == 0 && sRotW) {
         atomicAdd(&flags[sweep % 3], 1);
+        if (sRotW > 1) atomicAdd(&flags[3 + sweep % 3], 1);
         sRotW = 0;
       }
       grid.sync();
     }
     const int any = __atomic_load_n(&flags[sweep % 3], __ATOMIC_RELAXED);
-    if (any == 0) break;
+    const int big = __atomic_load_n(&flags[3 + sweep % 3], __ATOMIC_RELAXED);
+    if (any == 0 || big == 0) break;
   }
   // ---- singular values (column norms) sorted descending, the eps-rank:
   // workgroup 0 of the job
@@ -1479,7 +1501,7 @@ int svd_wide_blocks(int scalar, int p, int k) {
 // holds 3 ints and njobs * B doubles (svd_wide_work_bytes).  Returns -2 when
 // the grid cannot be co-resident (svd_wide_fits tells beforehand), a HIP
 // error code otherwise, 0 on success.
-size_t svd_wide_work_bytes(int njobs, int B) { return 16 + (size_t)njobs * B * 8; }
+size_t svd_wide_work_bytes(int njobs, int B) { return 32 + (size_t)njobs * B * 8; }
 
 static const void* wide_kernel(int scalar) {
   return scalar == 0 ? (const void*)svd_wide_kernel<double> : (const void*)svd_wide_kernel<hb_cplx>;
@@ -1510,10 +1532,10 @@ int svd_wide_launch(int scalar, const SVDJobDev* jobs, int njobs, int B, int pma
   if (!svd_wide_fits(scalar, njobs, B, pmax)) return -2;
   const void* kern = wide_kernel(scalar);
   const size_t sh = wide_lds(scalar, pmax);
-  int e = zero_fill_launch(work, 16, st);
+  int e = zero_fill_launch(work, 32, st);
   if (e != 0) return e;
   int* flags = (int*)work;
-  double* parts = (double*)((char*)work + 16);
+  double* parts = (double*)((char*)work + 32);
   void* args[] = {(void*)&jobs, (void*)&B, (void*)&store, (void*)&alpha, (void*)&eps,
                   (void*)&flags, (void*)&parts};
   return (int)hipLaunchCooperativeKernel(kern, dim3(njobs * B), dim3(WS_NT), args, sh, st);
