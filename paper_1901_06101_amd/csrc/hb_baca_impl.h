@@ -483,8 +483,6 @@ __device__ __forceinline__ void baca_leaf(const BacaArgs& A, const int li) {
   const int rmax = min(m0, n0);
   T* __restrict__ U = (T*)A.U + L.u_off;
   T* __restrict__ Vh = (T*)A.V + L.v_off;
-  T* __restrict__ Cg = (T*)A.C + L.c_off;
-  T* __restrict__ Rg = (T*)A.R + L.r_off;
   const double eps = A.eps;
   const int dim = A.E.dim;
 
@@ -524,6 +522,14 @@ __device__ __forceinline__ void baca_leaf(const BacaArgs& A, const int li) {
   int r = 0, iter = 0, status = 0, swaps = 0;
 
   while (true) {
+    // The residual blocks' bases are taken anew in every iteration: the
+    // empty asm hides that they do not change, so the compiler does not keep
+    // the per-column addresses (2 RPT DMAX 64-bit values) live across
+    // iterations, where they spilled to scratch.
+    uint64_t cbase = (uint64_t)((T*)A.C + L.c_off), rbase = (uint64_t)((T*)A.R + L.r_off);
+    asm volatile("" : "+v"(cbase), "+v"(rbase));
+    T* __restrict__ Cg = (T*)cbase;
+    T* __restrict__ Rg = (T*)rbase;
     const int nJ = sNJ;
     if (r + min(nJ, m0 - r) > cap) {
       status = 1;
