@@ -516,10 +516,10 @@ def run_child(flag, timeout=300):
 
 
 def _traffic(kernel, workload):
-    """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE plus
-    WRITE_SIZE, scaled by the same counters' reading for a copy of known
-    size), or None when no measurement of this kernel on this workload was
-    taken with the current source of the kernel."""
+    """HBM bytes of one call's launches of a kernel class, measured with
+    rocprofv3 --pmc (FETCH_SIZE plus WRITE_SIZE, scaled by the same
+    counters' reading for a copy of known size), or None when no measurement
+    of this class on this workload was taken with its current source."""
     import hashlib
     rec = PMC_TRAFFIC.get((kernel, workload))
     if rec is None:
@@ -529,17 +529,23 @@ def _traffic(kernel, workload):
             sha = hashlib.sha256(f.read()).hexdigest()[:16]
     except OSError:
         return None
-    return rec["bytes_per_launch"] if sha == rec["source_sha16"] else None
+    return rec["bytes_per_call"] if sha == rec["source_sha16"] else None
 
 
-# rocprofv3 --pmc measurements (profiles/*_pmc.md): kernel, workload ->
-# HBM bytes per launch and the sha256 prefix of the kernel's source when they
-# were taken
+# rocprofv3 --pmc measurements (profiles/helmholtz_pmc.md): kernel class,
+# workload -> HBM bytes of one call (FETCH_SIZE x 1024 x 2.0 + WRITE_SIZE x
+# 1024 x 1.0, the factors of a 1 GiB copy) and the sha256 prefix of the
+# classes' kernel source when they were taken
 PMC_TRAFFIC = {
-    # profiles/helmholtz_pmc.md: the timed call at eps 5e-5
     ("baca_leaf_kernel", "helmholtz"): dict(
-        bytes_per_launch=5336506150.0, source="paper_1901_06101_amd/csrc/hb_baca.hip",
-        source_sha16="13bf2c49cbff476c"),
+        bytes_per_call=4595917952.0, source="paper_1901_06101_amd/csrc/hb_baca_impl.h",
+        source_sha16="d3e6be78bec97795"),
+    ("svd_kernel", "helmholtz"): dict(
+        bytes_per_call=45833376.0, source="paper_1901_06101_amd/csrc/hb_merge.hip",
+        source_sha16="f8160f24912fffb4"),
+    ("tsqr_factor/apply + block_gemm", "helmholtz"): dict(
+        bytes_per_call=4406327872.0, source="paper_1901_06101_amd/csrc/hb_merge.hip",
+        source_sha16="f8160f24912fffb4"),
 }
 
 
@@ -569,7 +575,8 @@ def rooflines(st, workload):
         a = fl / (ms_qr * 1e-3) / 1e12
         out.append(dict(kernel="tsqr_factor/apply + block_gemm", bound="alu", achieved=a,
                         peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=a / FP64_PEAK_TFLOPS,
-                        traffic=None, algorithmic_flops_per_call=fl, launch_ms=ms_qr,
+                        traffic=_traffic("tsqr_factor/apply + block_gemm", workload),
+                        algorithmic_flops_per_call=fl, launch_ms=ms_qr,
                         launches=st.get("qr_launches")))
     out.sort(key=lambda r: -r["launch_ms"])
     return out
