@@ -744,13 +744,12 @@ __device__ __forceinline__ void baca_leaf(const BacaArgs& A, const int li) {
           for (int c = 0; c < DMAX; ++c) sPcol[c] = w[c];
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        T pc[DMAX];
-#pragma unroll
-        for (int c = 0; c < DMAX; ++c) pc[c] = sPcol[c];
+        // the pivot column is read from LDS where it is used (every lane
+        // reads the same address): a register copy of it spilled
         double sig2 = 0.0;
 #pragma unroll
         for (int c = 0; c < DMAX; ++c)
-          if (c >= st && c < nI) sig2 += sc_abs2(pc[c]);
+          if (c >= st && c < nI) sig2 += sc_abs2(sPcol[c]);
         const double sigma = sqrt(sig2);
         const T x0 = sPcol[st];
         T alpha = sc_zero<T>();
@@ -764,12 +763,12 @@ __device__ __forceinline__ void baca_leaf(const BacaArgs& A, const int li) {
           T ww = sc_zero<T>();
 #pragma unroll
           for (int c = 0; c < DMAX; ++c)
-            if (c >= st && c < nI) sc_cfma(ww, c == st ? v0 : pc[c], w[c]);
+            if (c >= st && c < nI) sc_cfma(ww, c == st ? v0 : sPcol[c], w[c]);
           const bool upd = rem && lane != p && beta != 0.0;
 #pragma unroll
           for (int c = 0; c < DMAX; ++c) {
-            if (upd && c >= st && c < nI) sc_axpy_neg(w[c], beta, c == st ? v0 : pc[c], ww);
-            if (lane == 0 && c >= st && c < nI) sRefl[st * DMAX + c] = (c == st) ? v0 : pc[c];
+            if (upd && c >= st && c < nI) sc_axpy_neg(w[c], beta, c == st ? v0 : sPcol[c], ww);
+            if (lane == 0 && c >= st && c < nI) sRefl[st * DMAX + c] = (c == st) ? v0 : sPcol[c];
           }
         }
         if (lane == p) {
