@@ -519,33 +519,40 @@ def _traffic(kernel, workload):
     """HBM bytes of one call's launches of a kernel class, measured with
     rocprofv3 --pmc (FETCH_SIZE plus WRITE_SIZE, scaled by the same
     counters' reading for a copy of known size), or None when no measurement
-    of this class on this workload was taken with its current source."""
+    of this class on this workload was taken with its current kernel source
+    and launching code."""
     import hashlib
     rec = PMC_TRAFFIC.get((kernel, workload))
     if rec is None:
         return None
+    h = hashlib.sha256()
     try:
-        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()[:16]
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
     except OSError:
         return None
+    sha = h.hexdigest()[:16]
     return rec["bytes_per_call"] if sha == rec["source_sha16"] else None
 
 
 # rocprofv3 --pmc measurements (profiles/helmholtz_pmc.md): kernel class,
 # workload -> HBM bytes of one call (FETCH_SIZE x 1024 x 2.0 + WRITE_SIZE x
 # 1024 x 1.0, the factors of a 1 GiB copy) and the sha256 prefix of the
-# classes' kernel source when they were taken
+# class's kernel source and of the launching code when they were taken
 PMC_TRAFFIC = {
     ("baca_leaf_kernel", "helmholtz"): dict(
-        bytes_per_call=4595917952.0, source="paper_1901_06101_amd/csrc/hb_baca_impl.h",
-        source_sha16="d3e6be78bec97795"),
+        bytes_per_call=4543075072.0,
+        sources=("paper_1901_06101_amd/csrc/hb_baca_impl.h", "paper_1901_06101_amd/csrc/hb_api.hip"),
+        source_sha16="5277296daff1247e"),
     ("svd_kernel", "helmholtz"): dict(
-        bytes_per_call=45833376.0, source="paper_1901_06101_amd/csrc/hb_merge.hip",
-        source_sha16="f8160f24912fffb4"),
+        bytes_per_call=75940512.0,
+        sources=("paper_1901_06101_amd/csrc/hb_merge.hip", "paper_1901_06101_amd/csrc/hb_api.hip"),
+        source_sha16="1356a8e730ae3305"),
     ("tsqr_factor/apply + block_gemm", "helmholtz"): dict(
-        bytes_per_call=4406327872.0, source="paper_1901_06101_amd/csrc/hb_merge.hip",
-        source_sha16="f8160f24912fffb4"),
+        bytes_per_call=4402420256.0,
+        sources=("paper_1901_06101_amd/csrc/hb_merge.hip", "paper_1901_06101_amd/csrc/hb_api.hip"),
+        source_sha16="1356a8e730ae3305"),
 }
 
 

@@ -996,10 +996,14 @@ static void run_svds(Engine& E, std::vector<SVDJobDev>& jobs, const void* store,
       }
       wideB = std::max(wideB, b);
     }
-    // automatic: only matrices wider than 160 columns (below that one
-    // workgroup's rounds cost about as much as the rounds and grid
-    // synchronisations of several), and at most 256 workgroups
-    if (E.svd_storage == 0 && ((int64_t)nj * wideB > 256 || kmax <= 160)) wideB = 0;
+    // automatic: matrices wider than 160 columns, or batches of one or two
+    // (the top merges) of at least 64 columns, and at most 256 workgroups.
+    // Measured: below 160 columns several workgroups lose to one when the
+    // batch has four or more matrices, and win for one or two (Gauss 3-D
+    // 2000^2: small-SVD time 16.2 -> 13.2 ms; Helmholtz 20000^2: 6.9 -> 6.5).
+    if (E.svd_storage == 0 &&
+        ((int64_t)nj * wideB > 256 || (kmax <= 160 && !(nj <= 2 && kmax >= 64))))
+      wideB = 0;
     if (wideB > 0 && !hbk::svd_wide_fits(E.scalar, (int)nj, wideB, pmax)) wideB = 0;
   }
   hipEvent_t t0 = E.clock.begin(E.st);
