@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -37,6 +38,9 @@ struct HbError {
 };
 // With HB_VERBOSE set in the environment, every failing HIP call or launch
 // and every unsupported size is reported on stderr with its source line.
+// set once the runtime has refused a cooperative launch in this process
+static std::atomic<bool> g_coop_refused{false};
+
 static void hb_report(const char* what, int code, const char* detail, int line) {
   static const bool on = std::getenv("HB_VERBOSE") != nullptr;
   if (on) std::fprintf(stderr, "[hbaca] %s failed (%d: %s) at hb_api.hip:%d\n", what, code, detail, line);
@@ -1005,6 +1009,7 @@ static void run_svds(Engine& E, std::vector<SVDJobDev>& jobs, const void* store,
         ((int64_t)nj * wideB > 256 || (kmax <= 160 && !(nj <= 2 && kmax >= 64))))
       wideB = 0;
     if (wideB > 0 && !hbk::svd_wide_fits(E.scalar, (int)nj, wideB, pmax)) wideB = 0;
+    if (g_coop_refused.load(std::memory_order_relaxed)) wideB = 0;
   }
   hipEvent_t t0 = E.clock.begin(E.st);
   const int storage = E.svd_storage == 3 ? 2 : E.svd_storage;
@@ -1013,8 +1018,20 @@ static void run_svds(Engine& E, std::vector<SVDJobDev>& jobs, const void* store,
     void* work = E.tmp.alloc(hbk::svd_wide_work_bytes((int)nj, wideB));
     HB_LAUNCH(hbk::svd_launch(E.scalar, dj, (int)nj, kmax, pmax, store, alpha, E.eps, E.st,
                               storage, true));
-    HB_LAUNCH(hbk::svd_wide_launch(E.scalar, dj, (int)nj, wideB, pmax, store, alpha, E.eps, work,
-                                   E.st));
+    const int we = hbk::svd_wide_launch(E.scalar, dj, (int)nj, wideB, pmax, store, alpha, E.eps,
+                                        work, E.st);
+    if (we != 0) {
+      // The runtime can refuse a cooperative launch that fits (error 401 was
+      // seen while another process on the device had made cooperative
+      // launches). The preconditioner read the inputs only, so the
+      // one-workgroup SVD starts over from them; the process keeps to it.
+      hb_report("cooperative SVD launch (falling back to one workgroup per matrix)", we,
+                we > 0 ? hipGetErrorString((hipError_t)we) : "grid does not fit", __LINE__);
+      (void)hipGetLastError();
+      g_coop_refused.store(true, std::memory_order_relaxed);
+      HB_LAUNCH(hbk::svd_launch(E.scalar, dj, (int)nj, kmax, pmax, store, alpha, E.eps, E.st,
+                                storage));
+    }
   } else {
     HB_LAUNCH(hbk::svd_launch(E.scalar, dj, (int)nj, kmax, pmax, store, alpha, E.eps, E.st,
                               storage));
