@@ -16,10 +16,12 @@
 #include <cstdlib>
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -196,14 +198,100 @@ static T* upload(DevMem& mem, const std::vector<T>& v, hipStream_t st) {
   return d;
 }
 
+// The descriptors of several launches, sent to the device in one copy before
+// the first of them: a copy queued between two kernels leaves the device idle
+// while it runs.  Launches are recorded as callbacks and issued by run(),
+// after the copy; at() gives the device address of a descriptor array there.
+struct Batch {
+  std::vector<unsigned char> h;
+  unsigned char* d = nullptr;
+  std::vector<std::function<void()>> launches;
+  template <typename T>
+  size_t add(const std::vector<T>& v) {
+    static_assert(std::is_trivially_copyable<T>::value, "descriptors are copied bytewise");
+    const size_t o = (h.size() + 255) & ~(size_t)255;
+    h.resize(o + std::max<size_t>(v.size(), 1) * sizeof(T));
+    if (!v.empty()) std::memcpy(h.data() + o, v.data(), v.size() * sizeof(T));
+    return o;
+  }
+  template <typename T> T* at(size_t o) const { return (T*)(d + o); }
+  void then(std::function<void()> f) { launches.push_back(std::move(f)); }
+  void run(DevMem& mem, hipStream_t st) {
+    if (!h.empty()) {
+      d = (unsigned char*)mem.alloc(h.size());
+      HB_HIP(hipMemcpyAsync(d, h.data(), h.size(), hipMemcpyHostToDevice, st));
+    }
+    for (auto& f : launches) f();
+    h.clear();
+    launches.clear();
+    d = nullptr;
+  }
+};
+
+// Copies `bytes` from the device to `dst` after the stream's work, and waits:
+// through a pinned buffer of the calling thread (grown as needed, kept for
+// the life of the thread), so the copy is one transfer rather than a staged
+// one.
+static void d2h_sync(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  static thread_local void* pin = nullptr;
+  static thread_local size_t cap = 0;
+  if (bytes > cap) {
+    const size_t want = std::max<size_t>(bytes, 64 * 1024);
+    void* p = nullptr;
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) == hipSuccess) {
+      if (pin) (void)hipHostFree(pin);  // idle: every use waits for its copy
+      pin = p;
+      cap = want;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  if (bytes <= cap) {
+    HB_HIP(hipMemcpyAsync(pin, src, bytes, hipMemcpyDeviceToHost, st));
+    HB_HIP(hipStreamSynchronize(st));
+    std::memcpy(dst, pin, bytes);
+  } else {
+    HB_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+    HB_HIP(hipStreamSynchronize(st));
+  }
+}
+
 // ------------------------------------------------------------ SplitMix64 ---
 // J_1 of leaf b: SplitMix64 (Steele, Lea and Flood 2014) from
 // seed + b * 0x632BE59BD9B4E019, partial Fisher-Yates over 0..n0-1.
 static void first_column_block(uint64_t seed, uint64_t b, int n0, int d, int32_t* out) {
   const int q = std::min(d, n0);
   uint64_t s = seed + b * 0x632BE59BD9B4E019ull;
-  std::vector<int32_t> perm(n0);
-  for (int i = 0; i < n0; ++i) perm[i] = i;
+  // q steps of a Fisher-Yates shuffle of 0..n0-1 touch at most 2q positions:
+  // those are kept as (position, value) pairs (in the whole array when q is
+  // large), every other position holds its own index
+  const int QS = 32;
+  int32_t pos[2 * QS], val[2 * QS];
+  std::vector<int32_t> perm;
+  if (q > QS) {
+    perm.resize(n0);
+    for (int i = 0; i < n0; ++i) perm[i] = i;
+  }
+  int nt = 0;
+  auto get = [&](int i) {
+    if (!perm.empty()) return perm[i];
+    for (int k = 0; k < nt; ++k)
+      if (pos[k] == i) return val[k];
+    return (int32_t)i;
+  };
+  auto put = [&](int i, int32_t v) {
+    if (!perm.empty()) {
+      perm[i] = v;
+      return;
+    }
+    for (int k = 0; k < nt; ++k)
+      if (pos[k] == i) {
+        val[k] = v;
+        return;
+      }
+    pos[nt] = i;
+    val[nt++] = v;
+  };
   for (int t = 0; t < q; ++t) {
     s += 0x9E3779B97F4A7C15ull;
     uint64_t z = s;
@@ -211,9 +299,11 @@ static void first_column_block(uint64_t seed, uint64_t b, int n0, int d, int32_t
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
     const int j = t + (int)(z % (uint64_t)(n0 - t));
-    std::swap(perm[t], perm[j]);
+    const int32_t vt = get(t), vj = get(j);
+    put(t, vj);
+    put(j, vt);
   }
-  for (int t = 0; t < q; ++t) out[t] = perm[t];
+  for (int t = 0; t < q; ++t) out[t] = get(t);
 }
 
 // ------------------------------------------------------------ trees --------
@@ -468,6 +558,7 @@ struct MergeJob {
 
 struct TreeBuild {
   std::vector<std::vector<QRNodeDev>> levels;  // per level, all trees concatenated
+  std::vector<std::vector<int>> nmat;          // per level, the matrix of every node
   std::vector<int> top_level, top_index;       // per matrix
   std::vector<int> kmat;                       // per matrix
   size_t store_elems = 0;
@@ -475,20 +566,34 @@ struct TreeBuild {
 };
 
 // Builds TSQR trees for a list of tall matrices given by their level-0 sources.
+// The nodes of every level are laid out matrix by matrix in the order `ord`
+// (all matrices in index order when it is empty).
 static void build_trees(const std::vector<QRNodeDev>& mats, const std::vector<int64_t>& rows,
-                        TreeBuild& tb) {
+                        TreeBuild& tb, const std::vector<int>& ord = {}) {
   const int MC = 256;
   const size_t nm = mats.size();
   tb.top_level.assign(nm, -1);
   tb.top_index.assign(nm, -1);
   tb.kmat.assign(nm, 0);
-  std::vector<std::vector<int>> cur(nm);  // node indices at the current level per matrix
+  std::vector<int> seq(ord);
+  if (seq.empty())
+    for (size_t a = 0; a < nm; ++a) seq.push_back((int)a);
+  // a matrix's nodes are contiguous on every level: first index and count
+  std::vector<int> first(nm, 0), count(nm, 0);
   tb.levels.clear();
   tb.levels.emplace_back();
-  for (size_t a = 0; a < nm; ++a) {
+  tb.nmat.clear();
+  tb.nmat.emplace_back();
+  size_t n0 = 0;
+  for (const int a : seq)
+    if (mats[a].k > 0 && rows[a] > 0) n0 += (size_t)((rows[a] + MC - 1) / MC);
+  tb.levels[0].reserve(n0);
+  tb.nmat[0].reserve(n0);
+  for (const int a : seq) {
     const int k = mats[a].k;
     tb.kmat[a] = k;
     if (k == 0 || rows[a] == 0) continue;
+    first[a] = (int)tb.levels[0].size();
     for (int64_t r0 = 0; r0 < rows[a]; r0 += MC) {
       QRNodeDev nd = mats[a];
       nd.row0 = mats[a].row0 + r0;
@@ -499,50 +604,57 @@ static void build_trees(const std::vector<QRNodeDev>& mats, const std::vector<in
       tb.store_elems += (size_t)MC * k;
       nd.ab = tb.ab_elems;
       tb.ab_elems += k;
-      cur[a].push_back((int)tb.levels[0].size());
       tb.levels[0].push_back(nd);
+      tb.nmat[0].push_back(a);
+      ++count[a];
     }
   }
   int lev = 0;
   while (true) {
     bool any = false;
     std::vector<QRNodeDev> next;
-    for (size_t a = 0; a < nm; ++a) {
-      if (cur[a].empty()) continue;
-      if (cur[a].size() == 1) {
+    std::vector<int> next_mat;
+    const std::vector<QRNodeDev>& below = tb.levels[lev];
+    for (const int a : seq) {
+      if (count[a] == 0) continue;
+      if (count[a] == 1) {
         if (tb.top_level[a] < 0) {
           tb.top_level[a] = lev;
-          tb.top_index[a] = cur[a][0];
+          tb.top_index[a] = first[a];
         }
-        cur[a].clear();
+        count[a] = 0;
         continue;
       }
       any = true;
       const int k = tb.kmat[a];
       const int g = std::max(2, MC / k);
-      std::vector<int> nxt;
-      for (size_t c0 = 0; c0 < cur[a].size(); c0 += g) {
-        const int nc = (int)std::min<size_t>(g, cur[a].size() - c0);
+      const int nfirst = (int)next.size();
+      int ncount = 0;
+      for (int c0 = 0; c0 < count[a]; c0 += g) {
+        const int nc = std::min(g, count[a] - c0);
         int rws = 0;
-        for (int c = 0; c < nc; ++c) rws += tb.levels[lev][cur[a][c0 + c]].steps;
+        for (int c = 0; c < nc; ++c) rws += below[first[a] + c0 + c].steps;
         QRNodeDev nd{};
         nd.rows = rws;
         nd.k = k;
         nd.steps = std::min(rws, k);
         nd.level0 = 0;
-        nd.child0 = cur[a][c0];
+        nd.child0 = first[a] + c0;
         nd.nchild = nc;
         nd.store = (int64_t)tb.store_elems;
         tb.store_elems += (size_t)MC * k;
         nd.ab = tb.ab_elems;
         tb.ab_elems += k;
-        nxt.push_back((int)next.size());
         next.push_back(nd);
+        next_mat.push_back(a);
+        ++ncount;
       }
-      cur[a] = nxt;
+      first[a] = nfirst;
+      count[a] = ncount;
     }
     if (!any) break;
-    tb.levels.push_back(next);
+    tb.levels.push_back(std::move(next));
+    tb.nmat.push_back(std::move(next_mat));
     ++lev;
   }
 }
@@ -641,29 +753,67 @@ struct Engine {
   struct Factored {
     TreeBuild tb;
     std::vector<QRNodeDev*> dlev;
+    // owner matrix of every node, offsets of the trailing rows, first chunk row
+    // of every matrix: the tree walks of the applies, done once (walk())
+    mutable std::vector<std::vector<int>> owner;
+    mutable std::vector<std::vector<int64_t>> tofs;
+    mutable std::vector<int64_t> first_row;
     void* store = nullptr;
     void* alpha = nullptr;
     double* beta = nullptr;
   };
 
-  void factor(const std::vector<QRNodeDev>& mats, const std::vector<int64_t>& rows, Factored& F) {
-    build_trees(mats, rows, F.tb);
-    int kmax = 1;
-    for (int k : F.tb.kmat) kmax = std::max(kmax, k);
-    const int kv = hbk::tsqr_kmax_for(scalar, kmax);
-    if (kv < 0) throw HbError{HB_EUNSUPPORTED};
+  // With a batch, the launches join it (issued by its run()); without, they
+  // are issued here.
+  void factor(const std::vector<QRNodeDev>& mats, const std::vector<int64_t>& rows, Factored& F,
+              Batch* batch = nullptr) {
+    // Every matrix takes the narrowest register tile that holds its width:
+    // the trees are laid out narrowest class first, and each level is
+    // launched once per class over its run of nodes (a batch of mostly
+    // narrow matrices with a few wider ones keeps the narrow tile for most).
+    const size_t nm = mats.size();
+    std::vector<int> kvm(nm, 0), ord(nm);
+    for (size_t a = 0; a < nm; ++a) {
+      ord[a] = (int)a;
+      if (mats[a].k == 0) continue;
+      kvm[a] = hbk::tsqr_kmax_for(scalar, mats[a].k);
+      if (kvm[a] < 0) throw HbError{HB_EUNSUPPORTED};
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return kvm[x] < kvm[y]; });
+    build_trees(mats, rows, F.tb, ord);
+    struct Seg {
+      int level, first, count, kv;
+    };
+    std::vector<Seg> segs;
+    for (size_t l = 0; l < F.tb.levels.size(); ++l) {
+      const std::vector<int>& nmat = F.tb.nmat[l];
+      for (size_t i = 0; i < nmat.size();) {
+        size_t j = i + 1;
+        while (j < nmat.size() && kvm[nmat[j]] == kvm[nmat[i]]) ++j;
+        segs.push_back(Seg{(int)l, (int)i, (int)(j - i), kvm[nmat[i]]});
+        i = j;
+      }
+    }
     F.store = tmp.alloc(std::max<size_t>(F.tb.store_elems, 1) * sb());
     F.alpha = tmp.alloc(std::max(F.tb.ab_elems, 1) * sb());
     F.beta = tmp.get<double>(std::max(F.tb.ab_elems, 1));
-    F.dlev.clear();
-    for (auto& lv : F.tb.levels) F.dlev.push_back(upload(tmp, lv, st));
-    hipEvent_t t0 = clock.begin(st);
-    for (size_t l = 0; l < F.tb.levels.size(); ++l) {
-      HB_LAUNCH(hbk::tsqr_factor_launch(scalar, kv, F.dlev[l], (int)F.tb.levels[l].size(),
-                                        l ? F.dlev[l - 1] : nullptr, F.store, F.alpha, F.beta,
-                                        st));
-    }
-    clock.end(KC_QR, t0, st);
+    Batch local;
+    Batch& B = batch ? *batch : local;
+    std::vector<size_t> off;
+    for (auto& lv : F.tb.levels) off.push_back(B.add(lv));
+    B.then([this, &F, &B, off, segs]() {
+      F.dlev.clear();
+      for (size_t o : off) F.dlev.push_back(B.at<QRNodeDev>(o));
+      hipEvent_t t0 = clock.begin(st);
+      for (const Seg& g : segs) {
+        const int l = g.level;
+        HB_LAUNCH(hbk::tsqr_factor_launch(scalar, g.kv, F.dlev[l] + g.first, g.count,
+                                          l ? F.dlev[l - 1] : nullptr, F.store, F.alpha, F.beta,
+                                          st));
+      }
+      clock.end(KC_QR, t0, st);
+    });
+    if (!batch) local.run(tmp, st);
   }
 
   // Zout(matrix a) = Q_a [Zin_a; 0]  (Zin_a: steps_top x r_a, ld ldin_a;
@@ -675,12 +825,12 @@ struct Engine {
   void apply(const Factored& F, const std::vector<const void*>& zin, const std::vector<int64_t>& ldin,
              const std::vector<int>& rr, const std::vector<void*>& zout,
              const std::vector<int64_t>& ldout, const std::vector<const void*>* ztr = nullptr,
-             const std::vector<int64_t>* ldtr = nullptr) {
+             const std::vector<int64_t>* ldtr = nullptr, Batch* batch = nullptr) {
     const int kcap = scalar == 0 ? 128 : 64;
     int rmax = 0;
     for (int r : rr) rmax = std::max(rmax, r);
     if (rmax <= kcap) {
-      apply_cols(F, zin, ldin, rr, zout, ldout, ztr, ldtr);
+      apply_cols(F, zin, ldin, rr, zout, ldout, ztr, ldtr, batch);
       return;
     }
     for (int c0 = 0; c0 < rmax; c0 += kcap) {
@@ -694,7 +844,19 @@ struct Engine {
         zo[a] = (char*)zout[a] + (size_t)c0 * ldout[a] * sb();
         if (ztr && (*ztr)[a]) zt[a] = (const char*)(*ztr)[a] + (size_t)c0 * (*ldtr)[a] * sb();
       }
-      apply_cols(F, zi, ldin, rc, zo, ldout, ztr ? &zt : nullptr, ldtr);
+      apply_cols(F, zi, ldin, rc, zo, ldout, ztr ? &zt : nullptr, ldtr, batch);
+    }
+  }
+
+  // the tree walks the applies need (host only; once per factorisation)
+  static void walk(const Factored& F) {
+    if (!F.owner.empty() || F.tb.levels.empty()) return;
+    F.owner = owners(F.tb);
+    F.tofs = trailing_offsets(F.tb, F.owner);
+    F.first_row.assign(F.tb.kmat.size(), -1);
+    for (size_t id = 0; id < F.tb.levels[0].size(); ++id) {
+      const int a = F.owner[0][id];
+      if (a >= 0 && F.first_row[a] < 0) F.first_row[a] = F.tb.levels[0][id].row0;
     }
   }
 
@@ -742,7 +904,8 @@ struct Engine {
   void apply_h(const Factored& F, const std::vector<const void*>& zin,
                const std::vector<int64_t>& ldin, const std::vector<int>& kk,
                const std::vector<void*>& top, const std::vector<int64_t>& ldtop,
-               const std::vector<void*>& trail, const std::vector<int64_t>& ldtrail) {
+               const std::vector<void*>& trail, const std::vector<int64_t>& ldtrail,
+               Batch* batch = nullptr) {
     const auto& tb = F.tb;
     const int nlev = (int)tb.levels.size();
     const size_t nm = tb.kmat.size();
@@ -750,8 +913,9 @@ struct Engine {
     for (size_t a = 0; a < nm; ++a) kmx = std::max(kmx, kk[a]);
     const int kv = hbk::tsqr_kmax_for(scalar, kmx);
     if (kv < 0) throw HbError{HB_EUNSUPPORTED};
-    auto owner = owners(tb);
-    auto toff = trailing_offsets(tb, owner);
+    walk(F);
+    const auto& owner = F.owner;
+    const auto& toff = F.tofs;
     // stacked input buffers of levels >= 1
     std::vector<std::vector<char*>> sbuf(nlev);
     for (int l = 1; l < nlev; ++l) {
@@ -778,11 +942,10 @@ struct Engine {
           off += tb.levels[l - 1][nd.child0 + c].steps;
         }
       }
-    std::vector<int64_t> first_row(nm, -1);
-    for (size_t id = 0; id < tb.levels[0].size(); ++id) {
-      const int a = owner[0][id];
-      if (a >= 0 && first_row[a] < 0) first_row[a] = tb.levels[0][id].row0;
-    }
+    const auto& first_row = F.first_row;
+    Batch local;
+    Batch& B = batch ? *batch : local;
+    std::vector<std::pair<size_t, int>> lv;  // (descriptor offset, jobs) per level
     for (int l = 0; l < nlev; ++l) {
       std::vector<QRApplyHDev> jobs;
       for (size_t id = 0; id < tb.levels[l].size(); ++id) {
@@ -815,19 +978,24 @@ struct Engine {
         J.ldtr = ldtrail[a];
         jobs.push_back(J);
       }
-      if (!jobs.empty()) {
-        QRApplyHDev* dj = upload(tmp, jobs, st);
-        hipEvent_t t0 = clock.begin(st);
-        HB_LAUNCH(hbk::tsqr_applyh_launch(scalar, kv, dj, (int)jobs.size(), F.store, F.beta, st));
-        clock.end(KC_QR, t0, st);
-      }
+      if (!jobs.empty()) lv.emplace_back(B.add(jobs), (int)jobs.size());
     }
+    if (!lv.empty())
+      B.then([this, &F, &B, lv, kv]() {
+        hipEvent_t t0 = clock.begin(st);
+        for (const auto& e : lv)
+          HB_LAUNCH(hbk::tsqr_applyh_launch(scalar, kv, B.at<QRApplyHDev>(e.first), e.second,
+                                            F.store, F.beta, st));
+        clock.end(KC_QR, t0, st);
+      });
+    if (!batch) local.run(tmp, st);
   }
 
   void apply_cols(const Factored& F, const std::vector<const void*>& zin,
                   const std::vector<int64_t>& ldin, const std::vector<int>& rr,
                   const std::vector<void*>& zout, const std::vector<int64_t>& ldout,
-                  const std::vector<const void*>* ztr, const std::vector<int64_t>* ldtr) {
+                  const std::vector<const void*>* ztr, const std::vector<int64_t>* ldtr,
+                  Batch* batch) {
     const auto& tb = F.tb;
     const int nlev = (int)tb.levels.size();
     const size_t nm = tb.kmat.size();
@@ -835,24 +1003,13 @@ struct Engine {
     for (size_t a = 0; a < nm; ++a) rmax = std::max(rmax, rr[a]);
     const int kv = hbk::tsqr_kmax_for(scalar, rmax);
     if (kv < 0) throw HbError{HB_EUNSUPPORTED};
-    // map node -> (matrix) and the input/output of every node, top down
-    std::vector<std::vector<int>> owner(nlev);
-    for (int l = 0; l < nlev; ++l) owner[l].assign(tb.levels[l].size(), -1);
-    for (size_t a = 0; a < nm; ++a) {
-      if (tb.top_level[a] < 0) continue;
-      // walk down marking ownership
-      std::vector<int> cur{tb.top_index[a]};
-      for (int l = tb.top_level[a]; l >= 0; --l) {
-        std::vector<int> nx;
-        for (int id : cur) {
-          owner[l][id] = (int)a;
-          if (l > 0)
-            for (int c = 0; c < tb.levels[l][id].nchild; ++c) nx.push_back(tb.levels[l][id].child0 + c);
-        }
-        cur = nx;
-      }
-    }
-    auto tofs = trailing_offsets(tb, owner);
+    // node -> matrix, then the input/output of every node, top down
+    walk(F);
+    const auto& owner = F.owner;
+    const auto& tofs = F.tofs;
+    Batch local;
+    Batch& B = batch ? *batch : local;
+    std::vector<std::pair<size_t, int>> lv;  // (descriptor offset, jobs) per level
     // per node Zin pointer/ld and Zout pointer/ld
     std::vector<std::vector<const void*>> nin(nlev);
     std::vector<std::vector<int64_t>> nldin(nlev);
@@ -915,26 +1072,25 @@ struct Engine {
       if (l == 0) {
         // level-0 chunks write rows [chunk offset, ...) of their matrix
         size_t j = 0;
-        std::vector<int64_t> first_row(nm, -1);
-        for (size_t id = 0; id < tb.levels[0].size(); ++id) {
-          const int a = owner[0][id];
-          if (a >= 0 && first_row[a] < 0) first_row[a] = tb.levels[0][id].row0;
-        }
         for (size_t id = 0; id < tb.levels[0].size(); ++id) {
           const int a = owner[0][id];
           if (a < 0 || rr[a] == 0) continue;
-          const int64_t off = tb.levels[0][id].row0 - first_row[a];
+          const int64_t off = tb.levels[0][id].row0 - F.first_row[a];
           jobs[j].Zout = (char*)zout[a] + (size_t)off * sb();
           ++j;
         }
       }
-      if (!jobs.empty()) {
-        QRApplyDev* dj = upload(tmp, jobs, st);
-        hipEvent_t t0 = clock.begin(st);
-        HB_LAUNCH(hbk::tsqr_apply_launch(scalar, kv, dj, (int)jobs.size(), F.store, F.beta, st));
-        clock.end(KC_QR, t0, st);
-      }
+      if (!jobs.empty()) lv.emplace_back(B.add(jobs), (int)jobs.size());
     }
+    if (!lv.empty())
+      B.then([this, &F, &B, lv, kv]() {
+        hipEvent_t t0 = clock.begin(st);
+        for (const auto& e : lv)
+          HB_LAUNCH(hbk::tsqr_apply_launch(scalar, kv, B.at<QRApplyDev>(e.first), e.second,
+                                           F.store, F.beta, st));
+        clock.end(KC_QR, t0, st);
+      });
+    if (!batch) local.run(tmp, st);
   }
 };
 
@@ -947,11 +1103,17 @@ struct SvdOut {
   int p, k;
 };
 
+// `batch` holds launches queued before the SVDs (they and the SVDs go out
+// with one descriptor copy); `overlap` runs on the host while the device
+// works, before the ranks are read back.
 static void run_svds(Engine& E, std::vector<SVDJobDev>& jobs, const void* store, const void* alpha,
-                     std::vector<SvdOut>& outs, std::vector<int>& ranks_host) {
+                     std::vector<SvdOut>& outs, std::vector<int>& ranks_host,
+                     Batch* batch = nullptr, const std::function<void()>& overlap = nullptr) {
   const size_t nj = jobs.size();
   outs.assign(nj, SvdOut{});
   if (nj == 0) {
+    if (batch) batch->run(E.tmp, E.st);
+    if (overlap) overlap();
     ranks_host.clear();
     return;
   }
@@ -983,7 +1145,9 @@ static void run_svds(Engine& E, std::vector<SVDJobDev>& jobs, const void* store,
     J.cperm = (int32_t*)bufs[7 * a + 6];
     outs[a] = SvdOut{J.Xr, J.Yr, J.S, J.rank, J.p, J.k};
   }
-  SVDJobDev* dj = upload(E.tmp, jobs, E.st);
+  Batch local;
+  Batch& B = batch ? *batch : local;
+  const size_t joff = B.add(jobs);
   // The multi-workgroup SVD takes batches of a few wide matrices (the top
   // merge levels), where one workgroup per matrix runs about k / 32 pairs
   // after one another in every round and leaves most of the chip idle: B
@@ -1011,8 +1175,10 @@ static void run_svds(Engine& E, std::vector<SVDJobDev>& jobs, const void* store,
     if (wideB > 0 && !hbk::svd_wide_fits(E.scalar, (int)nj, wideB, pmax)) wideB = 0;
     if (g_coop_refused.load(std::memory_order_relaxed)) wideB = 0;
   }
-  hipEvent_t t0 = E.clock.begin(E.st);
   const int storage = E.svd_storage == 3 ? 2 : E.svd_storage;
+  B.then([&]() {
+  SVDJobDev* dj = B.at<SVDJobDev>(joff);
+  hipEvent_t t0 = E.clock.begin(E.st);
   if (wideB > 0) {
     // the preconditioner on one workgroup per matrix, then the sweeps on B
     void* work = E.tmp.alloc(hbk::svd_wide_work_bytes((int)nj, wideB));
@@ -1037,9 +1203,11 @@ static void run_svds(Engine& E, std::vector<SVDJobDev>& jobs, const void* store,
                               storage));
   }
   E.clock.end(KC_SVD, t0, E.st);
+  });
+  B.run(E.tmp, E.st);
+  if (overlap) overlap();
   std::vector<int32_t> rh(2 * nj);
-  HB_HIP(hipMemcpyAsync(rh.data(), dr, 2 * nj * sizeof(int32_t), hipMemcpyDeviceToHost, E.st));
-  HB_HIP(hipStreamSynchronize(E.st));
+  d2h_sync(rh.data(), dr, 2 * nj * sizeof(int32_t), E.st);
   ranks_host.resize(nj);
   // algorithmic flops: QRCP of R^H (4 phi p k q) and per Jacobi sweep
   // q (q - 1) / 2 pairs, each a dot product and a rotation of two length-p
@@ -1053,10 +1221,14 @@ static void run_svds(Engine& E, std::vector<SVDJobDev>& jobs, const void* store,
   }
 }
 
-static void copy_sigmas(Engine& E, const std::vector<CopyDev>& cp) {
+static void copy_sigmas(Engine& E, const std::vector<CopyDev>& cp, Batch* batch = nullptr) {
   if (cp.empty()) return;
-  CopyDev* d = upload(E.tmp, cp, E.st);
-  HB_LAUNCH(hbk::copy_list_launch(d, (int)cp.size(), E.st));
+  Batch local;
+  Batch& B = batch ? *batch : local;
+  const size_t off = B.add(cp);
+  const int n = (int)cp.size();
+  B.then([&E, &B, off, n]() { HB_LAUNCH(hbk::copy_list_launch(B.at<CopyDev>(off), n, E.st)); });
+  if (!batch) local.run(E.tmp, E.st);
 }
 
 // Truncated SVD of the horizontal (p_is_u) or vertical concatenation of two
@@ -1089,7 +1261,8 @@ static void run_merges_direct(Engine& E, std::vector<MergeJob>& jobs, DevMem& ou
     rows.push_back(J.rows);
   }
   Engine::Factored F;
-  E.factor(mats, rows, F);
+  E.factor(mats, rows, F);  // at once: the device factors while the host plans the SVDs
+  Batch pre;
   std::vector<SVDJobDev> sj;
   for (size_t a = 0; a < mats.size(); ++a) {
     const QRNodeDev& top = F.tb.levels[F.tb.top_level[a]][F.tb.top_index[a]];
@@ -1103,7 +1276,7 @@ static void run_merges_direct(Engine& E, std::vector<MergeJob>& jobs, DevMem& ou
   }
   std::vector<SvdOut> so;
   std::vector<int> rk;
-  run_svds(E, sj, F.store, F.alpha, so, rk);
+  run_svds(E, sj, F.store, F.alpha, so, rk, &pre, [&F]() { Engine::walk(F); });
   // allocate outputs
   std::vector<const void*> zin;
   std::vector<int64_t> ldin, ldout;
@@ -1175,14 +1348,20 @@ static void run_merges_direct(Engine& E, std::vector<MergeJob>& jobs, DevMem& ou
       ++c;
     }
   }
-  copy_sigmas(E, scp);
-  E.apply(F, zin_all, ldin_all, rr_all, zout_all, ldout_all);
+  Batch post;
+  copy_sigmas(E, scp, &post);
+  E.apply(F, zin_all, ldin_all, rr_all, zout_all, ldout_all, nullptr, nullptr, &post);
   if (!gj.empty()) {
-    BlockGemmDev* dg = upload(E.tmp, gj, E.st);
-    hipEvent_t t0 = E.clock.begin(E.st);
-    HB_LAUNCH(hbk::block_gemm_launch(E.scalar, dg, (int)gj.size(), (int)max_rows, max_rin, E.st));
-    E.clock.end(KC_GEMM, t0, E.st);
+    const size_t goff = post.add(gj);
+    const int ng = (int)gj.size();
+    post.then([&]() {
+      hipEvent_t t0 = E.clock.begin(E.st);
+      HB_LAUNCH(hbk::block_gemm_launch(E.scalar, post.at<BlockGemmDev>(goff), ng, (int)max_rows,
+                                       max_rin, E.st));
+      E.clock.end(KC_GEMM, t0, E.st);
+    });
   }
+  post.run(E.tmp, E.st);
 }
 
 // Householder QR of tall matrices wider than the register TSQR tile, by
@@ -1646,7 +1825,8 @@ static void run_recompress_narrow(Engine& E, std::vector<RecJob>& jobs, DevMem& 
   }
   if (live.empty()) return;
   Engine::Factored F;
-  E.factor(mats, rows, F);
+  E.factor(mats, rows, F);  // at once: the device factors while the host plans the rest
+  Batch pre;
   const size_t nl = live.size();
   std::vector<QRNodeDev> topU(nl), topV(nl);
   std::vector<void*> Mptr(nl);
@@ -1675,19 +1855,24 @@ static void run_recompress_narrow(Engine& E, std::vector<RecJob>& jobs, DevMem& 
       sj[i].R = mb[i];
     }
   }
-  QRNodeDev* dU = upload(E.tmp, topV, E.st);  // first factor of M^H
-  QRNodeDev* dV = upload(E.tmp, topU, E.st);
-  void** dM = upload(E.tmp, Mptr, E.st);
-  if (E.scalar == 0)
-    hipLaunchKernelGGL((rrh_kernel<double>), dim3(nl), dim3(256), 0, E.st, dU, dV,
-                       (const double*)F.store, (const double*)F.alpha, (double* const*)dM);
-  else
-    hipLaunchKernelGGL((rrh_kernel<hb_cplx>), dim3(nl), dim3(256), 0, E.st, dU, dV,
-                       (const hb_cplx*)F.store, (const hb_cplx*)F.alpha, (hb_cplx* const*)dM);
-  HB_HIP(hipGetLastError());
+  const size_t oU = pre.add(topV);  // first factor of M^H
+  const size_t oV = pre.add(topU);
+  const size_t oM = pre.add(Mptr);
+  pre.then([&]() {
+    QRNodeDev* dU = pre.at<QRNodeDev>(oU);
+    QRNodeDev* dV = pre.at<QRNodeDev>(oV);
+    void** dM = pre.at<void*>(oM);
+    if (E.scalar == 0)
+      hipLaunchKernelGGL((rrh_kernel<double>), dim3(nl), dim3(256), 0, E.st, dU, dV,
+                         (const double*)F.store, (const double*)F.alpha, (double* const*)dM);
+    else
+      hipLaunchKernelGGL((rrh_kernel<hb_cplx>), dim3(nl), dim3(256), 0, E.st, dU, dV,
+                         (const hb_cplx*)F.store, (const hb_cplx*)F.alpha, (hb_cplx* const*)dM);
+    HB_HIP(hipGetLastError());
+  });
   std::vector<SvdOut> so;
   std::vector<int> rk;
-  run_svds(E, sj, F.store, F.alpha, so, rk);
+  run_svds(E, sj, F.store, F.alpha, so, rk, &pre, [&F]() { Engine::walk(F); });
   std::vector<int> rr(mats.size(), 0);
   std::vector<const void*> zin(mats.size(), nullptr);
   std::vector<int64_t> ldin(mats.size(), 1), ldout(mats.size(), 1);
@@ -1723,8 +1908,10 @@ static void run_recompress_narrow(Engine& E, std::vector<RecJob>& jobs, DevMem& 
     zout[2 * i + 1] = B.Vh;
     ldout[2 * i + 1] = J.n0;
   }
-  copy_sigmas(E, scp);
-  E.apply(F, zin, ldin, rr, zout, ldout);
+  Batch post;
+  copy_sigmas(E, scp, &post);
+  E.apply(F, zin, ldin, rr, zout, ldout, nullptr, nullptr, &post);
+  post.run(E.tmp, E.st);
 }
 
 // ---------------------------------------------------------- the pipeline ---
@@ -1812,14 +1999,17 @@ static hb_status run(const CallSpec& c, hb_result** out) {
   R->keep.sync_free = true;
   DevMem tmp;
   tmp.st = st;
-  hipEvent_t ev[6];
-  for (auto& e : ev) HB_HIP(hipEventCreate(&e));
+  hipEvent_t ev[6] = {};
   struct EvGuard {
     hipEvent_t* e;
     ~EvGuard() {
-      for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]);
+      for (int i = 0; i < 6; ++i) EventPool::get().give(e[i]);
     }
   } evg{ev};
+  for (auto& e : ev) {
+    e = EventPool::get().take();
+    if (!e) throw HbError{HB_EDEVICE};
+  }
   HB_HIP(hipEventRecord(ev[0], st));
 
   const int scalar = (c.entry == HB_K_HELMHOLTZ3D || c.entry == HB_K_EFIE2D) ? 1 : 0;
