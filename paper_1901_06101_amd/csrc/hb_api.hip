@@ -262,36 +262,16 @@ static void d2h_sync(void* dst, const void* src, size_t bytes, hipStream_t st) {
 static void first_column_block(uint64_t seed, uint64_t b, int n0, int d, int32_t* out) {
   const int q = std::min(d, n0);
   uint64_t s = seed + b * 0x632BE59BD9B4E019ull;
-  // q steps of a Fisher-Yates shuffle of 0..n0-1 touch at most 2q positions:
-  // those are kept as (position, value) pairs (in the whole array when q is
-  // large), every other position holds its own index
-  const int QS = 32;
-  int32_t pos[2 * QS], val[2 * QS];
-  std::vector<int32_t> perm;
-  if (q > QS) {
+  // q steps of a Fisher-Yates shuffle of 0..n0-1, on an identity array kept
+  // per thread: the swaps are undone afterwards, so a call costs O(q)
+  static thread_local std::vector<int32_t> perm;
+  static thread_local std::vector<int32_t> js;
+  if ((int)perm.size() < n0) {
+    const int old = (int)perm.size();
     perm.resize(n0);
-    for (int i = 0; i < n0; ++i) perm[i] = i;
+    for (int i = old; i < n0; ++i) perm[i] = i;
   }
-  int nt = 0;
-  auto get = [&](int i) {
-    if (!perm.empty()) return perm[i];
-    for (int k = 0; k < nt; ++k)
-      if (pos[k] == i) return val[k];
-    return (int32_t)i;
-  };
-  auto put = [&](int i, int32_t v) {
-    if (!perm.empty()) {
-      perm[i] = v;
-      return;
-    }
-    for (int k = 0; k < nt; ++k)
-      if (pos[k] == i) {
-        val[k] = v;
-        return;
-      }
-    pos[nt] = i;
-    val[nt++] = v;
-  };
+  if ((int)js.size() < q) js.resize(q);
   for (int t = 0; t < q; ++t) {
     s += 0x9E3779B97F4A7C15ull;
     uint64_t z = s;
@@ -299,11 +279,11 @@ static void first_column_block(uint64_t seed, uint64_t b, int n0, int d, int32_t
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
     const int j = t + (int)(z % (uint64_t)(n0 - t));
-    const int32_t vt = get(t), vj = get(j);
-    put(t, vj);
-    put(j, vt);
+    js[t] = j;
+    std::swap(perm[t], perm[j]);
   }
-  for (int t = 0; t < q; ++t) out[t] = get(t);
+  for (int t = 0; t < q; ++t) out[t] = perm[t];
+  for (int t = q - 1; t >= 0; --t) std::swap(perm[t], perm[js[t]]);
 }
 
 // ------------------------------------------------------------ trees --------

@@ -763,98 +763,46 @@ __global__ __launch_bounds__(SVD_NT) void svd_kernel(const SVDJobDev* __restrict
       be = 1.0 / (sig * (sig + sqrt(sc_abs2(x0))));
     }
     const T v0 = sc_sub(x0, al);
-    // Up to NCH row chunks of the reflector (v0 in row s, the pivot column
-    // below it) are read once per step into registers, and each trailing
-    // column once: the dot product and the update then run from registers,
-    // in the same order of operations as the streaming form below.
-    constexpr int NCH = 2;
-    const int nch = (k - s + CH * G - 1) / (CH * G);
-    if (nch <= NCH) {
-      T ur[NCH][CH];
+    for (int j = s + 1 + grp; j < p; j += NGRP) {
+      T* col = B + (int64_t)(j == piv ? cs : c_cur[j]) * ldb;
+      T w = sc_zero<T>();
+      for (int i0 = s + gl; i0 < k; i0 += CH * G) {
+        T u[CH], v[CH];
 #pragma unroll
-      for (int h = 0; h < NCH; ++h)
-        if (h < nch) {
-#pragma unroll
-          for (int c = 0; c < CH; ++c) {
-            const int i = s + gl + h * CH * G + c * G;
-            const T u = vcol[min(i, k - 1)];
-            ur[h][c] = i == s ? v0 : u;
-          }
+        for (int c = 0; c < CH; ++c) {
+          const int i = min(i0 + c * G, k - 1);
+          u[c] = vcol[i];
+          v[c] = col[i];
         }
-      for (int j = s + 1 + grp; j < p; j += NGRP) {
-        T* col = B + (int64_t)(j == piv ? cs : c_cur[j]) * ldb;
-        T vr[NCH][CH];
-        T w = sc_zero<T>();
 #pragma unroll
-        for (int h = 0; h < NCH; ++h)
-          if (h < nch) {
-#pragma unroll
-            for (int c = 0; c < CH; ++c) vr[h][c] = col[min(s + gl + h * CH * G + c * G, k - 1)];
-#pragma unroll
-            for (int c = 0; c < CH; ++c)
-              if (s + gl + h * CH * G + c * G < k) sc_cfma(w, ur[h][c], vr[h][c]);
-          }
-        w = group_sum_sc<G, T>(w);
-        double n2 = 0.0;
-#pragma unroll
-        for (int h = 0; h < NCH; ++h)
-          if (h < nch) {
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-              const int i = s + gl + h * CH * G + c * G;
-              if (i < k) {
-                T x = vr[h][c];
-                if (be != 0.0) sc_axpy_neg(x, be, ur[h][c], w);
-                col[i] = x;
-                if (i > s) n2 += sc_abs2(x);
-              }
-            }
-          }
-        n2 = group_sum<G>(n2);
-        if (gl == 0) n_nxt[j] = n2;
+        for (int c = 0; c < CH; ++c) {
+          const int i = i0 + c * G;
+          if (i < k) sc_cfma(w, i == s ? v0 : u[c], v[c]);
+        }
       }
-    } else {
-      for (int j = s + 1 + grp; j < p; j += NGRP) {
-        T* col = B + (int64_t)(j == piv ? cs : c_cur[j]) * ldb;
-        T w = sc_zero<T>();
-        for (int i0 = s + gl; i0 < k; i0 += CH * G) {
-          T u[CH], v[CH];
+      w = group_sum_sc<G, T>(w);
+      double n2 = 0.0;
+      for (int i0 = s + gl; i0 < k; i0 += CH * G) {
+        T u[CH], v[CH];
 #pragma unroll
-          for (int c = 0; c < CH; ++c) {
-            const int i = min(i0 + c * G, k - 1);
-            u[c] = vcol[i];
-            v[c] = col[i];
-          }
+        for (int c = 0; c < CH; ++c) {
+          const int i = min(i0 + c * G, k - 1);
+          u[c] = vcol[i];
+          v[c] = col[i];
+        }
 #pragma unroll
-          for (int c = 0; c < CH; ++c) {
-            const int i = i0 + c * G;
-            if (i < k) sc_cfma(w, i == s ? v0 : u[c], v[c]);
+        for (int c = 0; c < CH; ++c) {
+          const int i = i0 + c * G;
+          if (i < k) {
+            T x = v[c];
+            if (be != 0.0) sc_axpy_neg(x, be, i == s ? v0 : u[c], w);
+            col[i] = x;
+            if (i > s) n2 += sc_abs2(x);
           }
         }
-        w = group_sum_sc<G, T>(w);
-        double n2 = 0.0;
-        for (int i0 = s + gl; i0 < k; i0 += CH * G) {
-          T u[CH], v[CH];
-#pragma unroll
-          for (int c = 0; c < CH; ++c) {
-            const int i = min(i0 + c * G, k - 1);
-            u[c] = vcol[i];
-            v[c] = col[i];
-          }
-#pragma unroll
-          for (int c = 0; c < CH; ++c) {
-            const int i = i0 + c * G;
-            if (i < k) {
-              T x = v[c];
-              if (be != 0.0) sc_axpy_neg(x, be, i == s ? v0 : u[c], w);
-              col[i] = x;
-              if (i > s) n2 += sc_abs2(x);
-            }
-          }
-        }
-        n2 = group_sum<G>(n2);
-        if (gl == 0) n_nxt[j] = n2;
       }
+      n2 = group_sum<G>(n2);
+      if (gl == 0) n_nxt[j] = n2;
     }
     __syncthreads();
     // the pivot column is not touched after its step: its entry s becomes
