@@ -49,6 +49,11 @@ struct GramCfg {
   // rows per staged chunk: the staging buffers hold at most 2048 + 1024
   // elements, and every chunk costs two barriers and one HBM round trip
   static constexpr int GCH = (2048 / GT < 1024 / DMAX) ? 2048 / GT : 1024 / DMAX;
+  // row strides of the staged chunks, one element longer than a row: the
+  // transposing stores of consecutive lanes (consecutive rows) then fall in
+  // different LDS banks instead of all in one
+  static constexpr int XLD = GT + 1;
+  static constexpr int KLD = DMAX + 1;
 };
 
 // G[tt * DMAX + c] = sum_i conj(X(i, t0 + tt)) * X(i, k0 + c), tt < tw, c < dk.
@@ -91,12 +96,12 @@ __device__ __forceinline__ void gram_tile(const T* __restrict__ X, int64_t ld, i
 #pragma unroll
     for (int u = 0; u < NX; ++u) {
       const int e = tid + u * NT;
-      if (e < C::GCH * C::GT) sXs[(e % C::GCH) * C::GT + e / C::GCH] = vx[u];
+      if (e < C::GCH * C::GT) sXs[(e % C::GCH) * C::XLD + e / C::GCH] = vx[u];
     }
 #pragma unroll
     for (int u = 0; u < NK; ++u) {
       const int e = tid + u * NT;
-      if (e < C::GCH * DMAX) sKs[(e % C::GCH) * DMAX + e / C::GCH] = vk[u];
+      if (e < C::GCH * DMAX) sKs[(e % C::GCH) * C::KLD + e / C::GCH] = vk[u];
     }
     __syncthreads();
 #pragma unroll 4
@@ -104,9 +109,9 @@ __device__ __forceinline__ void gram_tile(const T* __restrict__ X, int64_t ld, i
       const int ii = wid * (C::GCH / NW) + q;
       T xa[4], kb[2];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) xa[a] = sXs[ii * C::GT + 4 * tb + a];
+      for (int a = 0; a < 4; ++a) xa[a] = sXs[ii * C::XLD + 4 * tb + a];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) kb[b] = sKs[ii * DMAX + 2 * cb + b];
+      for (int b = 0; b < 2; ++b) kb[b] = sKs[ii * C::KLD + 2 * cb + b];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -501,8 +506,8 @@ __device__ __forceinline__ void baca_leaf(const BacaArgs& A, const int li) {
   __shared__ double sTabs[DMAX];
   __shared__ double sPts[DMAX * HB_MAXDIM];
   __shared__ T sTile[DMAX * TILE];
-  __shared__ T sXs[C::GCH * C::GT];
-  __shared__ T sKs[C::GCH * DMAX];
+  __shared__ T sXs[C::GCH * C::XLD];
+  __shared__ T sKs[C::GCH * C::KLD];
   __shared__ TA sG[C::GT * DMAX];
   __shared__ TA sGU[C::GT * DMAX];
   __shared__ TA sGUd[DMAX * DMAX];
