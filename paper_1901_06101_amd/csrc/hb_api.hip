@@ -210,8 +210,10 @@ struct Batch {
   size_t add(const std::vector<T>& v) {
     static_assert(std::is_trivially_copyable<T>::value, "descriptors are copied bytewise");
     const size_t o = (h.size() + 255) & ~(size_t)255;
-    h.resize(o + std::max<size_t>(v.size(), 1) * sizeof(T));
-    if (!v.empty()) std::memcpy(h.data() + o, v.data(), v.size() * sizeof(T));
+    h.insert(h.end(), o - h.size(), (unsigned char)0);
+    const unsigned char* p = (const unsigned char*)v.data();
+    if (v.empty()) h.insert(h.end(), sizeof(T), (unsigned char)0);
+    else h.insert(h.end(), p, p + v.size() * sizeof(T));
     return o;
   }
   template <typename T> T* at(size_t o) const { return (T*)(d + o); }
@@ -255,6 +257,14 @@ static void d2h_sync(void* dst, const void* src, size_t bytes, hipStream_t st) {
     HB_HIP(hipStreamSynchronize(st));
   }
 }
+
+// Applies through trees of more nodes than this issue every tree level as soon
+// as its descriptors are built (the host prepares the next level while the
+// device runs this one); smaller ones send all levels in one copy.
+constexpr size_t kApplyBatchNodes = 512;
+// TSQR factor levels of at least this many nodes (the CUs of the device) are
+// launched once per register-width class
+constexpr size_t kSplitNodes = 256;
 
 // ------------------------------------------------------------ SplitMix64 ---
 // J_1 of leaf b: SplitMix64 (Steele, Lea and Flood 2014) from
@@ -545,6 +555,12 @@ struct TreeBuild {
   int ab_elems = 0;
 };
 
+static size_t tree_nodes(const TreeBuild& tb) {
+  size_t n = 0;
+  for (const auto& lv : tb.levels) n += lv.size();
+  return n;
+}
+
 // Builds TSQR trees for a list of tall matrices given by their level-0 sources.
 // The nodes of every level are laid out matrix by matrix in the order `ord`
 // (all matrices in index order when it is empty).
@@ -748,7 +764,7 @@ struct Engine {
   void factor(const std::vector<QRNodeDev>& mats, const std::vector<int64_t>& rows, Factored& F,
               Batch* batch = nullptr) {
     // Every matrix takes the narrowest register tile that holds its width:
-    // the trees are laid out narrowest class first, and each level is
+    // the trees are laid out narrowest class first, and a large level is
     // launched once per class over its run of nodes (a batch of mostly
     // narrow matrices with a few wider ones keeps the narrow tile for most).
     const size_t nm = mats.size();
@@ -759,14 +775,30 @@ struct Engine {
       kvm[a] = hbk::tsqr_kmax_for(scalar, mats[a].k);
       if (kvm[a] < 0) throw HbError{HB_EUNSUPPORTED};
     }
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return kvm[x] < kvm[y]; });
+    {
+      // stable counting sort by width class (0, 16, 32, 64, 128 columns)
+      auto cls = [](int kv) { return kv == 0 ? 0 : kv == 16 ? 1 : kv == 32 ? 2 : kv == 64 ? 3 : 4; };
+      size_t start[6] = {0, 0, 0, 0, 0, 0};
+      for (size_t a = 0; a < nm; ++a) ++start[cls(kvm[a]) + 1];
+      for (int c = 0; c < 5; ++c) start[c + 1] += start[c];
+      for (size_t a = 0; a < nm; ++a) ord[start[cls(kvm[a])]++] = (int)a;
+    }
     build_trees(mats, rows, F.tb, ord);
     struct Seg {
       int level, first, count, kv;
     };
+    // A level with fewer nodes than the device has CUs is one launch at the
+    // widest tile of the level: its launches would run one after another,
+    // each as long as its slowest node.
     std::vector<Seg> segs;
     for (size_t l = 0; l < F.tb.levels.size(); ++l) {
       const std::vector<int>& nmat = F.tb.nmat[l];
+      if (nmat.size() < kSplitNodes) {
+        int kvl = 0;
+        for (int a : nmat) kvl = std::max(kvl, kvm[a]);
+        if (!nmat.empty()) segs.push_back(Seg{(int)l, 0, (int)nmat.size(), kvl});
+        continue;
+      }
       for (size_t i = 0; i < nmat.size();) {
         size_t j = i + 1;
         while (j < nmat.size() && kvm[nmat[j]] == kvm[nmat[i]]) ++j;
@@ -923,8 +955,9 @@ struct Engine {
         }
       }
     const auto& first_row = F.first_row;
+    const bool stream = tree_nodes(tb) > kApplyBatchNodes;
     Batch local;
-    Batch& B = batch ? *batch : local;
+    Batch& B = batch && !stream ? *batch : local;
     std::vector<std::pair<size_t, int>> lv;  // (descriptor offset, jobs) per level
     for (int l = 0; l < nlev; ++l) {
       std::vector<QRApplyHDev> jobs;
@@ -958,7 +991,15 @@ struct Engine {
         J.ldtr = ldtrail[a];
         jobs.push_back(J);
       }
-      if (!jobs.empty()) lv.emplace_back(B.add(jobs), (int)jobs.size());
+      if (jobs.empty()) continue;
+      if (stream) {
+        QRApplyHDev* dj = upload(tmp, jobs, st);
+        hipEvent_t t0 = clock.begin(st);
+        HB_LAUNCH(hbk::tsqr_applyh_launch(scalar, kv, dj, (int)jobs.size(), F.store, F.beta, st));
+        clock.end(KC_QR, t0, st);
+      } else {
+        lv.emplace_back(B.add(jobs), (int)jobs.size());
+      }
     }
     if (!lv.empty())
       B.then([this, &F, &B, lv, kv]() {
@@ -968,7 +1009,7 @@ struct Engine {
                                             F.store, F.beta, st));
         clock.end(KC_QR, t0, st);
       });
-    if (!batch) local.run(tmp, st);
+    if (&B == &local) local.run(tmp, st);
   }
 
   void apply_cols(const Factored& F, const std::vector<const void*>& zin,
@@ -987,8 +1028,9 @@ struct Engine {
     walk(F);
     const auto& owner = F.owner;
     const auto& tofs = F.tofs;
+    const bool stream = tree_nodes(tb) > kApplyBatchNodes;
     Batch local;
-    Batch& B = batch ? *batch : local;
+    Batch& B = batch && !stream ? *batch : local;
     std::vector<std::pair<size_t, int>> lv;  // (descriptor offset, jobs) per level
     // per node Zin pointer/ld and Zout pointer/ld
     std::vector<std::vector<const void*>> nin(nlev);
@@ -1060,7 +1102,15 @@ struct Engine {
           ++j;
         }
       }
-      if (!jobs.empty()) lv.emplace_back(B.add(jobs), (int)jobs.size());
+      if (jobs.empty()) continue;
+      if (stream) {
+        QRApplyDev* dj = upload(tmp, jobs, st);
+        hipEvent_t t0 = clock.begin(st);
+        HB_LAUNCH(hbk::tsqr_apply_launch(scalar, kv, dj, (int)jobs.size(), F.store, F.beta, st));
+        clock.end(KC_QR, t0, st);
+      } else {
+        lv.emplace_back(B.add(jobs), (int)jobs.size());
+      }
     }
     if (!lv.empty())
       B.then([this, &F, &B, lv, kv]() {
@@ -1070,7 +1120,7 @@ struct Engine {
                                            F.store, F.beta, st));
         clock.end(KC_QR, t0, st);
       });
-    if (!batch) local.run(tmp, st);
+    if (&B == &local) local.run(tmp, st);
   }
 };
 
