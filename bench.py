@@ -542,17 +542,17 @@ def _traffic(kernel, workload):
 # class's kernel source and of the launching code when they were taken
 PMC_TRAFFIC = {
     ("baca_leaf_kernel", "helmholtz"): dict(
-        bytes_per_call=4541525824.0,
+        bytes_per_call=4541736960.0,
         sources=("paper_1901_06101_amd/csrc/hb_baca_impl.h", "paper_1901_06101_amd/csrc/hb_api.hip"),
-        source_sha16="14b146b2e5ffd9b4"),
+        source_sha16="10e5910127b3a721"),
     ("svd_kernel", "helmholtz"): dict(
-        bytes_per_call=75901344.0,
+        bytes_per_call=75899296.0,
         sources=("paper_1901_06101_amd/csrc/hb_merge.hip", "paper_1901_06101_amd/csrc/hb_api.hip"),
-        source_sha16="1abe9543a5655540"),
+        source_sha16="eef343bb99435d33"),
     ("tsqr_factor/apply + block_gemm", "helmholtz"): dict(
-        bytes_per_call=4407293152.0,
+        bytes_per_call=4403266144.0,
         sources=("paper_1901_06101_amd/csrc/hb_merge.hip", "paper_1901_06101_amd/csrc/hb_api.hip"),
-        source_sha16="1abe9543a5655540"),
+        source_sha16="eef343bb99435d33"),
 }
 
 
