@@ -542,17 +542,17 @@ def _traffic(kernel, workload):
 # class's kernel source and of the launching code when they were taken
 PMC_TRAFFIC = {
     ("baca_leaf_kernel", "helmholtz"): dict(
-        bytes_per_call=4541736960.0,
+        bytes_per_call=4543716896.0,
         sources=("paper_1901_06101_amd/csrc/hb_baca_impl.h", "paper_1901_06101_amd/csrc/hb_api.hip"),
-        source_sha16="10e5910127b3a721"),
+        source_sha16="31bf566d39b4e826"),
     ("svd_kernel", "helmholtz"): dict(
-        bytes_per_call=75899296.0,
+        bytes_per_call=75910304.0,
         sources=("paper_1901_06101_amd/csrc/hb_merge.hip", "paper_1901_06101_amd/csrc/hb_api.hip"),
-        source_sha16="eef343bb99435d33"),
+        source_sha16="c5e0c98aeef6d9b6"),
     ("tsqr_factor/apply + block_gemm", "helmholtz"): dict(
-        bytes_per_call=4403266144.0,
+        bytes_per_call=4404459744.0,
         sources=("paper_1901_06101_amd/csrc/hb_merge.hip", "paper_1901_06101_amd/csrc/hb_api.hip"),
-        source_sha16="eef343bb99435d33"),
+        source_sha16="c5e0c98aeef6d9b6"),
 }
 
 

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -233,7 +234,8 @@ struct Batch {
 // Copies `bytes` from the device to `dst` after the stream's work, and waits:
 // through a pinned buffer of the calling thread (grown as needed, kept for
 // the life of the thread), so the copy is one transfer rather than a staged
-// one.
+// one.  The wait polls an event for up to 3 ms before it blocks: a rank
+// read-back sits between two dependent launches, and polling wakes sooner.
 static void d2h_sync(void* dst, const void* src, size_t bytes, hipStream_t st) {
   static thread_local void* pin = nullptr;
   static thread_local size_t cap = 0;
@@ -250,7 +252,30 @@ static void d2h_sync(void* dst, const void* src, size_t bytes, hipStream_t st) {
   }
   if (bytes <= cap) {
     HB_HIP(hipMemcpyAsync(pin, src, bytes, hipMemcpyDeviceToHost, st));
-    HB_HIP(hipStreamSynchronize(st));
+    static thread_local hipEvent_t ev = nullptr;
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      ev = nullptr;
+    }
+    bool done = false;
+    if (ev && hipEventRecord(ev, st) == hipSuccess) {
+      const auto t0 = std::chrono::steady_clock::now();
+      while (true) {
+        const hipError_t q = hipEventQuery(ev);
+        if (q == hipSuccess) {
+          done = true;
+          break;
+        }
+        if (q != hipErrorNotReady) {  // the blocking wait below reports it
+          (void)hipGetLastError();
+          break;
+        }
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(3000)) break;
+      }
+    } else {
+      (void)hipGetLastError();
+    }
+    if (!done) HB_HIP(hipStreamSynchronize(st));
     std::memcpy(dst, pin, bytes);
   } else {
     HB_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
