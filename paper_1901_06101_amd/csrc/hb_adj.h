@@ -247,8 +247,9 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
     for (int pass = 0; j > 0 && pass < 4; ++pass) {
       // the dot products with the j earlier columns; pass 1 (which always
       // follows pass 0) adds column j with itself, the norm pass 0 left,
-      // as h[j].  g lanes share each of the nd products (rows interleaved)
-      // when nd <= nt / 2; their partial sums meet in red
+      // as h[j].  g adjacent lanes share each of the nd products (rows
+      // interleaved, so neighbouring lanes read neighbouring rows) when
+      // nd <= nt / 2; their partial sums meet in red
       const int nd = pass == 1 ? j + 1 : j;
       const int g = w.nt / nd >= 2 ? w.nt / nd : 1;
       if (g == 1) {
@@ -262,7 +263,7 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
         }
       } else {
         if (w.tid < nd * g) {
-          const int i = w.tid % nd, c = w.tid / nd;
+          const int i = w.tid / g, c = w.tid % g;
           double s = 0.0;
           for (int64_t t = c; t < rows.n; t += g) {
             const int64_t l = rows(t);
@@ -273,7 +274,7 @@ HBA_FN void wg_qr(W& w, int64_t m, int k, const double* A, int64_t lda, double* 
         w.sync();
         for (int i = w.tid; i < nd; i += w.nt) {
           double s = 0.0;
-          for (int c = 0; c < g; ++c) s += w.red[i + c * nd];
+          for (int c = 0; c < g; ++c) s += w.red[i * g + c];
           h[i] = s;
         }
       }
